@@ -1,0 +1,170 @@
+"""Pins of the dense oracle (Gram, loss, optimal means, gradient, posterior mean).
+
+* The loss against scipy's multivariate-normal log-density on the same Gram
+  matrix (fixed means): L = -2 log p(y) - N log(2 pi).
+* The block structure of Theorem "Fast MTGP computations": with V the
+  normalised Walsh-Hadamard matrix (DSEQ) or bit-reversal followed by the DFT
+  (LAT), V^dagger Ktilde V has tall blocks made of stacked diagonals, with
+  Lambda_tt' 1 = sqrt(n_t') V_(m_t)^dagger (Ktilde_tt')_(:,0) and frequency f of
+  the larger task coupled to f mod n_t' of the smaller; diagonal blocks'
+  eigenvalues are that transform of the first column; Lambda is Hermitian.
+* Equal sample sizes: the optimal means are the per-task sample means.
+* Central finite differences of L for the gradient, fixed and profiled means.
+* Posterior mean interpolates the data as xi -> 0, and with tau = tau_hat the
+  Bayesian-cubature identity E alpha = 0 holds (last sentence of the
+  multitask Bayesian cubature theorem).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.stats
+
+from oracle import dense, points as pts
+from _designs import tiny
+
+
+def _bitrev(j, m):
+    return int(format(j, f"0{m}b")[::-1], 2) if m > 0 else 0
+
+
+def _vdag(family, m):
+    n = 1 << m
+    if family == "dseq":
+        return sla.hadamard(n).astype(np.float64) / math.sqrt(n)
+    P = np.zeros((n, n))
+    for j in range(n):
+        P[j, _bitrev(j, m)] = 1.0
+    F = np.exp(-2j * np.pi * np.outer(np.arange(n), np.arange(n)) / n)
+    return F @ P / math.sqrt(n)
+
+
+@pytest.mark.parametrize("family", ["dseq", "lat"])
+@pytest.mark.parametrize("m", [[3, 3, 3], [3, 2, 1], [4, 4, 2]])
+def test_block_structure(family, m):
+    w = tiny(family, len(m), m, 2, seed=7)
+    X = pts.task_points(w)
+    K = dense.gram(w, X=X)
+    n = [1 << v for v in m]
+    off = np.concatenate([[0], np.cumsum(n)])
+    Vd = [_vdag(family, v) for v in m]
+    for t in range(len(m)):
+        for s in range(len(m)):
+            Kb = K[off[t]:off[t + 1], off[s]:off[s + 1]]
+            Lam = Vd[t] @ Kb @ Vd[s].conj().T
+            scale = np.abs(Kb).max()
+            if n[t] >= n[s]:
+                lam = math.sqrt(n[s]) * (Vd[t] @ Kb[:, 0])
+                expect = np.zeros_like(Lam)
+                for f in range(n[t]):
+                    expect[f, f % n[s]] = lam[f]
+            else:
+                lam = math.sqrt(n[t]) * (Vd[s] @ Kb[0, :])
+                expect = np.zeros_like(Lam)
+                for g in range(n[s]):
+                    expect[g % n[t], g] = np.conj(lam[g])
+            np.testing.assert_allclose(Lam, expect, rtol=0, atol=1e-12 * scale * n[t])
+            if t == s:
+                ev = np.sort(np.linalg.eigvalsh(Kb))
+                np.testing.assert_allclose(np.sort(lam.real), ev, rtol=0, atol=1e-12 * scale * n[t])
+                assert np.abs(lam.imag).max() < 1e-12 * scale * n[t]
+
+
+@pytest.mark.parametrize("family", ["dseq", "lat"])
+def test_gram_symmetric_pd(family):
+    w = tiny(family, 3, [5, 4, 4], 3, seed=2)
+    K = dense.gram(w)
+    assert np.array_equal(K, K.T)
+    assert np.linalg.eigvalsh(K).min() > 0
+
+
+@pytest.mark.parametrize("family", ["dseq", "lat"])
+def test_loss_matches_mvn_logpdf(family):
+    w = tiny(family, 2, [5, 4], 2, seed=3, profile=False)
+    X = pts.task_points(w)
+    y = dense.targets(w, np.random.default_rng(0), X)
+    r = dense.nll(w, y, X=X)
+    K = dense.gram(w, X=X)
+    mean = dense.summing_matrix([32, 16]).T @ w.theta["tau"]
+    lp = scipy.stats.multivariate_normal(mean=mean, cov=K).logpdf(y)
+    N = K.shape[0]
+    assert abs(r["L"] - (-2 * lp - N * math.log(2 * math.pi))) < 1e-9 * (abs(r["quad"]) + abs(r["logdet"]))
+    assert abs(r["nll"] + lp) < 1e-9 * abs(lp)
+
+
+@pytest.mark.parametrize("family", ["dseq", "lat"])
+def test_equal_sizes_tau_hat_is_sample_mean(family):
+    w = tiny(family, 3, [6, 6, 6], 2, seed=4)
+    X = pts.task_points(w)
+    y = dense.targets(w, np.random.default_rng(1), X)
+    r = dense.nll(w, y, X=X)
+    np.testing.assert_allclose(r["tau_hat"], y.reshape(3, -1).mean(axis=1), rtol=1e-10, atol=1e-12)
+
+
+def _pack(theta, keys):
+    return np.concatenate([np.atleast_1d(np.asarray(theta[k], dtype=np.float64)).ravel() for k in keys])
+
+
+LOG_KEYS = {"gamma", "eta", "b", "xi", "zeta"}
+
+
+def _unpack(vec, theta, keys):
+    out = dict(theta)
+    i = 0
+    for k in keys:
+        shape = np.shape(theta[k])
+        size = int(np.prod(shape)) if shape else 1
+        v = vec[i:i + size]
+        out[k] = float(v[0]) if not shape else v.reshape(shape)
+        i += size
+    return out
+
+
+@pytest.mark.parametrize("family,adaptive,profile,m", [
+    ("dseq", False, True, [4, 4]), ("dseq", True, False, [4, 3, 2]),
+    ("lat", False, False, [4, 4, 4]), ("lat", False, True, [4, 2])])
+def test_gradient_central_differences(family, adaptive, profile, m):
+    w = tiny(family, len(m), m, 2, adaptive=adaptive, seed=9, profile=profile, xi=1e-2)
+    X = pts.task_points(w)
+    y = dense.targets(w, np.random.default_rng(2), X)
+    g, _ = dense.grad(w, y, X=X)
+    keys = ["tau", "gamma", "eta"] + (["b"] if adaptive else []) + ["xi", "B", "zeta"]
+    # FD in the parameterisation of the gradient: log for positive parameters
+    base = {k: (np.log(w.theta[k]) if k in LOG_KEYS else np.asarray(w.theta[k], dtype=np.float64))
+            for k in keys}
+    vec = _pack(base, keys)
+    gvec = _pack(g, keys)
+    h = 1e-5
+
+    def L_of(v):
+        th = _unpack(v, base, keys)
+        th = {k: (np.exp(th[k]) if k in LOG_KEYS else th[k]) for k in keys}
+        return dense.nll(w, y, theta=th, X=X)["L"]
+
+    for i in range(len(vec)):
+        e = np.zeros_like(vec)
+        e[i] = h
+        fd = (L_of(vec + e) - L_of(vec - e)) / (2 * h)
+        assert abs(fd - gvec[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, gvec[i])
+
+
+@pytest.mark.parametrize("family", ["dseq", "lat"])
+def test_posterior_mean_interpolates(family):
+    w = tiny(family, 2, [5, 4], 2, seed=5, xi=1e-10)
+    X = pts.task_points(w)
+    y = dense.targets(w, np.random.default_rng(3), X)
+    for t in range(2):
+        mu = dense.posterior_mean(w, y, X[t], X=X)[:, t]
+        yt = y[:32] if t == 0 else y[32:]
+        np.testing.assert_allclose(mu, yt, rtol=0, atol=1e-6 * np.abs(y).max())
+
+
+@pytest.mark.parametrize("family", ["dseq", "lat"])
+def test_bayesian_cubature_identity(family):
+    w = tiny(family, 3, [5, 4, 3], 2, seed=6)
+    X = pts.task_points(w)
+    y = dense.targets(w, np.random.default_rng(4), X)
+    r = dense.nll(w, y, X=X)
+    Ea = dense.summing_matrix([32, 16, 8]) @ r["alpha"]
+    assert np.abs(Ea).max() < 1e-8 * np.abs(r["alpha"]).sum()
