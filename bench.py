@@ -1,0 +1,211 @@
+"""Benchmark: MLE loss + gradient evaluations per second of the fast MTGP
+hot path at T=8 tasks x n=2^24 digitally shifted digital-net points per task
+(d=10, order-2 DSI product kernel, low-rank + diagonal task covariance),
+on one MI355X.
+
+One step = one mtgp_nll_grad call: kernel columns, forward transforms,
+per-frequency 8x8 factorisations, loss, adjoint transforms and the
+derivative reduction (the data transform yhat is computed once per data set
+by mtgp_set_data, outside the timed region).  Inputs are seeded and
+synthetic; they are resident in HBM before timing starts.
+
+Prints one JSON line (see the README of the measurement contract in the
+design notes): evals/s of the primary path, the FP64 path beside it, the
+mixed-vs-FP64 differences, a roofline entry for the dominant kernel and the
+dense CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+import workloads  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def targets_on_device(plan, w):
+    """Seeded targets of the workload, built on the GPU from the plan's points."""
+    rng = np.random.default_rng(w.seed + 1000)
+    p = w.target_params
+    ys = []
+    for t in range(w.T):
+        n = 1 << w.m[t]
+        x = plan.gen_points(t, 0, n).view(torch.int32)
+        xf = (x.to(torch.int64) & 0xFFFFFFFF).to(torch.float64) * (2.0 ** -32)
+        del x
+
+        def g(k):
+            s = torch.zeros(n, dtype=torch.float64, device="cuda")
+            for j in range(w.d):
+                s += torch.sin(2 * math.pi * p["freq"][k][j] * xf[:, j] + p["phase"][k][j]) / (j + 1)
+            return s
+        rho = p["rho"][t]
+        y = rho * g(0) + math.sqrt(1 - rho * rho) * g(t + 1)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(int(rng.integers(0, 2 ** 31)))
+        y += math.sqrt(w.noise_var) * torch.randn(n, dtype=torch.float64, device="cuda", generator=gen)
+        ys.append(y)
+        del xf
+    return torch.cat(ys)
+
+
+def time_evals(plan, theta, steps, warmup):
+    out3 = torch.empty(3, dtype=torch.float64, device="cuda")
+    grad = torch.empty(plan.theta_size, dtype=torch.float64, device="cuda")
+    tau = torch.empty(plan.T, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        plan.nll_grad(theta, out3, grad, tau)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    plan.enable_timing(True)
+    e0.record(st)
+    phases = None
+    for i in range(steps):
+        plan.nll_grad(theta, out3, grad, tau)
+        ph = plan.phase_times()
+        phases = ph if phases is None else {k: phases[k] + ph[k] for k in ph}
+    e1.record(st)
+    torch.cuda.synchronize()
+    plan.enable_timing(False)
+    ms = e0.elapsed_time(e1) / steps
+    phases = {k: v / steps for k, v in phases.items()}
+    code, bad = plan.status()
+    if code != 0:
+        raise RuntimeError(f"status {code} at frequency {bad}")
+    return ms, out3.cpu().numpy(), grad.cpu().numpy(), tau.cpu().numpy(), phases
+
+
+def cpu_baseline(w, budget_s=20.0):
+    """Dense oracle (loss + gradient) on a scaled copy of the workload."""
+    from oracle import dense, points
+    import threadpoolctl
+    info = threadpoolctl.threadpool_info()
+    threads = max([i.get("num_threads", 1) for i in info] + [1])
+    m = 8
+    ws = workloads.scaled(w, [m] * w.T)
+    X = points.task_points(ws)
+    y = dense.targets(ws, np.random.default_rng(1), X)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        dense.grad(ws, y, X=X)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s / 4 or reps >= 3:
+            break
+    per = el / reps
+    N_s = ws.N
+    N_full = w.N
+    # dense Cholesky + dense gradient are O(N^3): extrapolate to the full size
+    per_full = per * (N_full / N_s) ** 3
+    return {"value": 1.0 / per_full, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"dense FP64 oracle loss+gradient at T={w.T}, d={w.d}, n=2^{m} per task "
+                      f"(N={N_s}): {per:.3f} s/eval measured over {reps} evals; value is that "
+                      f"rate extrapolated by (N_full/N_sample)^3 to N={N_full} (O(N^3) "
+                      f"extrapolation, not measured)",
+            "measured_sample_evals_per_s": 1.0 / per}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--m", type=int, default=24, help="log2 points per task")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precisions", default="fp64,mixed")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the fast MTGP path here runs on a single "
+              "MI355X (no multi-GPU sharding is built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    from paper_2603_16014_amd import mtgp
+
+    w = workloads.config5()
+    if args.m != 24:
+        w = workloads.scaled(w, [args.m] * w.T)
+    results = {}
+    y = None
+    for prec in args.precisions.split(","):
+        plan = mtgp.Plan.from_workload(w, prec)
+        if y is None:
+            y = targets_on_device(plan, w)
+        plan.set_data(y)
+        theta = plan.pack_theta(w.theta)
+        ms, out3, grad, tau, phases = time_evals(plan, theta, args.steps, args.warmup)
+        results[prec] = dict(ms=ms, out3=out3, grad=grad, phases=phases,
+                             ws_bytes=int(plan.ws.numel()))
+        del plan
+        torch.cuda.empty_cache()
+    primary = "mixed" if "mixed" in results else "fp64"
+    r = results[primary]
+    T, n, P = w.T, 1 << w.m[0], 1 + w.T * (w.T - 1) // 2
+    extra = {}
+    if "fp64" in results and "mixed" in results:
+        a, b = results["mixed"], results["fp64"]
+        den = abs(b["out3"][0]) + abs(b["out3"][1])
+        extra["mixed_vs_fp64"] = {
+            "L_rel": float(abs(a["out3"][2] - b["out3"][2]) / den),
+            "grad_rel_maxnorm": float(np.abs(a["grad"] - b["grad"]).max() / np.abs(b["grad"]).max()),
+        }
+        extra["fp64_evals_per_s"] = 1000.0 / b["ms"]
+        extra["fp64_ms_per_step"] = b["ms"]
+    # roofline of the dominant kernel phase
+    ph = r["phases"]
+    dom = max(ph, key=ph.get)
+    # algorithmic HBM bytes per launch of each phase (P columns of length n):
+    # working precision wb (forward), spectrum / adjoint precision sb
+    wb, sb = (8, 8) if primary == "fp64" else (8, 4)
+    algo_bytes = {
+        "gen_fwd_low": P * n * wb,               # write the low-bit transformed columns
+        "fwd_high": P * n * (wb + sb),           # read them, write the spectrum
+        "solve": P * n * 2 * sb + T * n * 8,     # read spectrum + yhat, write adjoint weights
+        "adj_high": P * n * 2 * sb,              # read + write adjoint weights
+        "adj_low_reduce": P * n * sb,            # read adjoint weights
+    }
+    roof = None
+    if dom in algo_bytes:
+        gbs = algo_bytes[dom] / (ph[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None}
+    line = {
+        "metric": "NLL+grad evals/sec at T=8,n=2^24",
+        "value": 1000.0 / r["ms"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if primary == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"fast MTGP loss+gradient, DSEQ digital nets, T={T}, d={w.d}, "
+                               f"n=2^{w.m[0]} per task (N={w.N}), order-2 DSI kernel, "
+                               f"{primary} path",
+                   "T": T, "d": w.d, "n_per_task": n, "N": w.N, "precision": primary},
+        "phases_ms": {k: round(v, 4) for k, v in ph.items()},
+        "roofline": roof,
+    }
+    line.update(extra)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,228 @@
+/*
+ * mtgp.h -- C ABI of the MI355X (gfx950) fast multitask Gaussian-process
+ * likelihood library.
+ *
+ * The library evaluates, exactly, the MLE loss of a multitask GP with the
+ * product kernel K((t,x),(t',x')) = R_tt' Q(x,x') (Eq. mtprod), its gradient
+ * and the posterior mean, on the design-kernel pairings of Condition
+ * "Fast MTGP":
+ *   MTGP_DSEQ: digitally shifted base-2 digital sequences in radical-inverse
+ *              order (Def. "Base-2 digitally-shifted digital sequences") with
+ *              digitally-shift-invariant kernels (Eq. DSI_kernel_1d_ex),
+ *              diagonalised by the Walsh-Hadamard transform;
+ *   MTGP_LAT:  shifted rank-1 lattices in radical-inverse order (Def.
+ *              "Shifted rank-1 lattice") with shift-invariant Bernoulli kernels
+ *              (Eq. SI_kernel_1d_ex), diagonalised by bit reversal + DFT.
+ * Task t has n_t = 2^m_t points, n_1 >= ... >= n_T, a common generator and
+ * its own shift; the Gram matrix factors as Ktilde = V Lambda V^dagger
+ * (Theorem "Fast MTGP computations") and Lambda is inverted per frequency
+ * (equal sizes) or by block Gaussian elimination in task order (Algorithm
+ * "Inverse and log-determinant of Lambda") for nested unequal sizes.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named `stream` are hipStream_t values passed as void*.
+ *   - Device pointers: theta, y, out3, grad, tau_hat, mean, xs, cols, ws, x, X,
+ *     out.  Host pointers: everything inside mtgp_design, and the arguments
+ *     of mtgp_plan_create / mtgp_status / the query functions.
+ *   - Calls that take a stream only enqueue work; none synchronises, none
+ *     allocates device memory, so they may be captured in a HIP graph.
+ *     Errors found on the device (a non-positive pivot, a NaN) are written to
+ *     a status word inside `ws` and read back with mtgp_status after the
+ *     caller synchronises.
+ *   - The caller owns every buffer.  `ws` is a device buffer of
+ *     mtgp_workspace_bytes(plan) bytes; it holds the transformed data written
+ *     by mtgp_set_data and scratch for the other calls, so calls that share a
+ *     `ws` must be ordered on one stream.  Plans are immutable after creation
+ *     and may be shared between threads.
+ *   - Return value: MTGP_OK or a negative MTGP_E* code (see mtgp_strerror).
+ *
+ * Hyperparameter vector theta (FP64, device), packed in this order:
+ *   tau[T] | log gamma | log eta[d] | log b[4] (adaptive DSI kernels only) |
+ *   log xi[T] | B[T][s] (row-major) | log zeta[T]
+ * with R = B B^T + diag(zeta) (Section "Multitask Setting"), Q(x,x') =
+ * gamma prod_j [1 + eta_j K(x_j,x'_j)] (Eq. prod_kernel), K = Khat_order or
+ * sum_alpha b_alpha Khat_alpha (adaptive), and per-task noise xi_t.
+ * The gradient is returned in the same packing, with respect to the packed
+ * coordinates (log-parameters where the packing says log).
+ * Data y (FP64, device, length N = sum n_t) is task-major, each task in the
+ * radical-inverse order of its points (i = 0 .. n_t - 1).
+ * Points and test inputs are 32-bit digits u standing for x = u 2^-32.
+ */
+#ifndef MTGP_H
+#define MTGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MTGP_OK = 0,
+  MTGP_EINVAL = -1,   /* invalid argument (sizes, ordering, null pointer, order) */
+  MTGP_ENOTPD = -2,   /* Lambda not positive definite at some frequency / NaN */
+  MTGP_EHIP = -3,     /* a HIP runtime call failed */
+  MTGP_ENOMEM = -4,   /* plan creation could not allocate its small tables */
+  MTGP_ENOTSUP = -5   /* combination not supported by this build */
+};
+
+enum { MTGP_DSEQ = 0, MTGP_LAT = 1 };
+/* Precision modes.  Per-frequency factorisations, log-det and quadratic-form
+ * reductions are FP64 in all of them.
+ *   MTGP_FP64:  everything FP64.
+ *   MTGP_MIXED: kernel columns and forward-transform arithmetic FP64, the
+ *               finished spectrum stored in FP32 (relative rounding only),
+ *               adjoint weights, adjoint transforms and the derivative
+ *               reduction in FP32 (FP64 block sums).
+ *   MTGP_F32:   kernel columns and all transform arithmetic in FP32.  The
+ *               transform's absolute rounding error (~eps32 ||c||_2 sqrt(m))
+ *               exceeds small noise variances xi at large n, which makes
+ *               Lambda indefinite (reported as MTGP_ENOTPD); kept to measure
+ *               exactly that. */
+enum { MTGP_FP64 = 0, MTGP_MIXED = 1, MTGP_F32 = 2 };
+enum { MTGP_DTYPE_F64 = 0, MTGP_DTYPE_F32 = 1 };
+
+typedef struct mtgp_plan mtgp_plan;
+
+typedef struct mtgp_design {
+  int32_t T;             /* number of tasks, 1 <= T <= 16 */
+  int32_t d;             /* input dimension, 1 <= d <= 32 */
+  int32_t family;        /* MTGP_DSEQ or MTGP_LAT */
+  const int32_t* m;      /* [T] log2 sizes, non-increasing (Condition "Fast MTGP"), 0 <= m_t <= 30 */
+  const uint32_t* gen;   /* DSEQ: [d][32] generating columns, column p = image of input digit p
+                            (bit 31 is the first output digit); LAT: [d] odd generating vector */
+  const uint32_t* shift; /* [T][d] digital shift (DSEQ) or lattice shift times 2^32 (LAT) */
+  int32_t kernel_order;  /* DSI: 1..4; SI: 1..3 (alpha of the Bernoulli polynomial B_{2 alpha}) */
+  int32_t adaptive;      /* DSI only: K = sum_{alpha=1..4} b_alpha Khat_alpha with weights in theta */
+  int32_t rank_s;        /* number of columns of B, 1 <= s <= 16 */
+  int32_t profile_tau;   /* 1: tau = tau_hat_MLE (Eq. MTGP_optimal_tau), theta's tau ignored and its
+                            gradient zero; 0: tau taken from theta */
+} mtgp_design;
+
+/* Validates the design, copies it, and uploads its small tables (generating
+ * matrices, shifts, column schedule) to the current HIP device.  Errors:
+ * MTGP_EINVAL (T, d, m ordering, m > 30, even lattice generator, unsupported
+ * order, adaptive with LAT), MTGP_ENOMEM, MTGP_EHIP. */
+int mtgp_plan_create(const mtgp_design* design, int32_t precision, mtgp_plan** out);
+int mtgp_plan_destroy(mtgp_plan* plan);
+
+/* Transform schedule (tuning only; results are the same up to rounding):
+ * each length-2^m transform runs as one LDS-resident pass over the low
+ * pass_a_bits index bits (1..13; fused with kernel-column generation) and
+ * passes over at most pass_b_bits (1..12) further bits each, with an LDS
+ * tile of about pass_b_tile_bytes (4096..147456).  Changes
+ * mtgp_workspace_bytes, so call it before sizing the workspace.  Defaults:
+ * 13, 11, 73728. */
+int mtgp_plan_set_schedule(mtgp_plan* plan, int32_t pass_a_bits, int32_t pass_b_bits,
+                           int64_t pass_b_tile_bytes);
+
+/* Profiling aid (not thread safe): when enabled, mtgp_nll / mtgp_nll_grad /
+ * mtgp_predict record HIP events on the caller's stream between their
+ * phases; mtgp_phase_times then waits for the last event and returns the
+ * duration in ms of each phase of the most recent call (ms[max_phases]);
+ * *nphases receives the number of phases, mtgp_phase_name(k) their names:
+ * prep, gen_fwd_low (column generation fused with the low-bit transform
+ * pass), fwd_high, solve, adj_high, adj_low_reduce (adjoint low-bit pass
+ * fused with the derivative reduction), finalize. */
+int mtgp_plan_enable_timing(mtgp_plan* plan, int32_t on);
+int mtgp_phase_times(const mtgp_plan* plan, double* ms, int32_t max_phases, int32_t* nphases);
+const char* mtgp_phase_name(int32_t k);
+
+/* Number of FP64 entries of theta (and of the gradient). */
+int64_t mtgp_theta_size(const mtgp_plan* plan);
+/* Bytes of the device workspace `ws` the other calls need. */
+size_t mtgp_workspace_bytes(const mtgp_plan* plan);
+/* Total number of data points N = sum_t n_t. */
+int64_t mtgp_num_points(const mtgp_plan* plan);
+/* Distinct kernel columns (Theorem "Fast MTGP computations", item 3: one
+ * zeroth column per task pair, tall case; pairs with equal length and equal
+ * pair shift share a column, e.g. all diagonal pairs of equal-size tasks).
+ * mtgp_column_info reports column c's log2 length, its offset (in elements)
+ * inside the buffer written by mtgp_kernel_cols, and one task pair (t <= u)
+ * that uses it. */
+int32_t mtgp_num_columns(const mtgp_plan* plan);
+int mtgp_column_info(const mtgp_plan* plan, int32_t c, int32_t* log2n, int64_t* offset,
+                     int32_t* t, int32_t* u);
+
+/* Points x_{t,i}, i = first .. first+count-1, of task t (0-based) as digits,
+ * out[count][d] (Def. "Base-2 digitally-shifted digital sequences":
+ * x_i = (XOR_{p: i_p = 1} g_p) XOR Delta_t; Def. "Shifted rank-1 lattice":
+ * x_i = (v(i) g + Delta_t) mod 1).  Bit-exact.  Indices may exceed n_t (the
+ * sequences are extensible) but must stay below 2^32. */
+int mtgp_gen_points(const mtgp_plan* plan, int32_t task, int64_t first, int64_t count,
+                    uint32_t* out, void* stream);
+
+/* Raw kernel columns c_p(i) = Q(z_i XOR s_p) (DSEQ, i in radical-inverse
+ * order) or Q((j g / n + s_p) mod 1) (LAT, natural lattice order j), one per
+ * distinct column, without the task factor R, in the plan's column precision
+ * (FP64 and MIXED plans: double, F32 plan: float).  `cols` holds
+ * sum_c 2^log2n(c) elements laid out at the offsets of mtgp_column_info.
+ * (Eq. prod_kernel; Theorem "Fast MTGP computations", item 3.) */
+int mtgp_kernel_cols(const mtgp_plan* plan, const double* theta, void* cols, void* ws,
+                     void* stream);
+
+/* In-place unnormalised Walsh-Hadamard transform of `batch` contiguous
+ * vectors of length 2^log2n, natural (Sylvester) order:
+ * X_f = sum_i (-1)^popcount(f & i) x_i  (the V^dagger of Theorem "Fast GP
+ * computations" for DSEQ, up to the factor 2^(-log2n/2)).  dtype is
+ * MTGP_DTYPE_F64 or MTGP_DTYPE_F32; 0 <= log2n <= 30. */
+int mtgp_fwht(void* x, int64_t batch, int32_t log2n, int32_t dtype, void* stream);
+
+/* Unnormalised forward DFT X_f = sum_j x_j e^{-2 pi i f j / n} of `batch`
+ * contiguous real vectors of length n = 2^log2n into complex outputs
+ * (interleaved re, im; X has batch * n complex entries).  If bitrev_input is
+ * nonzero the input is first read in bit-reversed order, i.e. the transform
+ * is the V^dagger of Theorem "Fast GP computations" for lattices times
+ * sqrt(n).  dtype as for mtgp_fwht; 0 <= log2n <= 30. */
+int mtgp_fft(const void* x, void* X, int64_t batch, int32_t log2n, int32_t dtype,
+             int32_t bitrev_input, void* stream);
+
+/* Transforms the data once per data set: yhat_t = V^dagger_{m_t} y_t
+ * (Theorem "Fast MTGP computations"), kept inside ws for later calls. */
+int mtgp_set_data(const mtgp_plan* plan, const double* y, void* ws, void* stream);
+
+/* MLE loss (Eq. MTGP_MLE_GCV_loss): out3[0] = (y - E^T tau)^T Ktilde^-1 (y - E^T tau),
+ * out3[1] = log det Ktilde, out3[2] = their sum L.  tau_hat (may be NULL)
+ * receives the means used (tau_hat_MLE when profiling, Eq. MTGP_optimal_tau;
+ * theta's tau otherwise).  Requires mtgp_set_data on the same ws. */
+int mtgp_nll(const mtgp_plan* plan, const double* theta, double* out3, double* tau_hat, void* ws,
+             void* stream);
+
+/* As mtgp_nll, plus grad = dL/dtheta in the packed coordinates.  The paper
+ * gives no gradient formula; this is the exact derivative of L (adjoint of
+ * Ktilde = V Lambda V^dagger with V independent of theta). */
+int mtgp_nll_grad(const mtgp_plan* plan, const double* theta, double* out3, double* grad,
+                  double* tau_hat, void* ws, void* stream);
+
+/* Posterior mean (Eq. MTGP_post_mean_cov) at M arbitrary inputs xs[M][d]
+ * (digits): mean[M][T], mean[m][t] = tau_t + sum_t' R_tt' sum_k
+ * Q(x*_m, x_t'k) alpha_t'k with alpha = Ktilde^-1 (y - E^T tau).  Direct
+ * sum, O(M N d).  Requires mtgp_set_data. */
+int mtgp_predict(const mtgp_plan* plan, const double* theta, const uint32_t* xs, int64_t M,
+                 double* mean, void* ws, void* stream);
+
+/* Posterior mean on a structured test net: the first 2^m_star points of the
+ * plan's sequence with shift shift_star[d] (host), in radical-inverse order:
+ * mean[2^m_star][T].  Uses the cross-block structure of Theorem "Fast MTGP
+ * computations" for each (test net, task) pair, O(N log N + T n* log n*)
+ * instead of O(M N d).  `scratch` is a device buffer of
+ * mtgp_predict_net_scratch_bytes(plan, m_star) bytes.  Requires
+ * mtgp_set_data; 0 <= m_star <= 30. */
+size_t mtgp_predict_net_scratch_bytes(const mtgp_plan* plan, int32_t m_star);
+int mtgp_predict_net(const mtgp_plan* plan, const double* theta, const uint32_t* shift_star,
+                     int32_t m_star, double* mean, void* ws, void* scratch, void* stream);
+
+/* Reads the device status word of ws (synchronously, after the caller has
+ * synchronised the stream).  Returns MTGP_OK or MTGP_ENOTPD; *bad_index (may
+ * be NULL) receives the first frequency (or residue class) whose pivot was
+ * not positive or not finite, else -1.  The status is cleared by each
+ * mtgp_nll / mtgp_nll_grad / mtgp_predict call. */
+int mtgp_status(const mtgp_plan* plan, const void* ws, int64_t* bad_index);
+
+const char* mtgp_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MTGP_H */

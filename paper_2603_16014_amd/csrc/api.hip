@@ -1,0 +1,545 @@
+// C ABI of the fast MTGP library: plan construction, workspace layout and
+// the orchestration of the device passes for each entry point.
+//
+// Evaluation order of one loss + gradient (equal sample sizes):
+//   prep      decode theta -> Params (R = B B^T + diag zeta, exp of logs)
+//   gen+A     kernel columns c_p regenerated from the design and transformed
+//             over the low index bits in LDS (Eq. prod_kernel; Theorem
+//             "Fast MTGP computations", item 3: lambda = transform of the
+//             zeroth column of each pair block)
+//   B         remaining high index bits
+//   solve     per-frequency T x T Cholesky, log det, quadratic form, W
+//   B^T, A^T  the adjoint transform of the weights, fused with the
+//             derivative reduction over the regenerated columns
+//   finalize  deterministic sums of block partials, chain rule
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mtgp.h"
+#include "kernels.h"
+
+using namespace mtgp;
+
+#define MTGP_NPHASE 7
+static const char* kPhaseNames[MTGP_NPHASE] = {"prep",  "gen_fwd_low",    "fwd_high", "solve",
+                                               "adj_high", "adj_low_reduce", "finalize"};
+
+struct mtgp_plan {
+  int T, d, family, order, adaptive, s, profile, precision;
+  int m[MTGP_MAXT];
+  int64_t n[MTGP_MAXT];
+  int64_t off[MTGP_MAXT + 1];
+  int64_t N;
+  bool equal;
+  std::vector<uint32_t> gen;    // [d][32] (DSEQ) or [d] (LAT)
+  std::vector<uint32_t> shift;  // [T][d]
+  // distinct kernel columns, ordered by non-increasing length
+  int ncol;
+  std::vector<int> col_m, col_t, col_u;
+  std::vector<int64_t> col_off;
+  std::vector<uint32_t> col_shift;  // [ncol][d]
+  PairMap pm;
+  struct Group {
+    int first, count, m;
+  };
+  std::vector<Group> groups;
+  // device tables
+  uint32_t* d_gen = nullptr;
+  uint32_t* d_colshift = nullptr;
+  uint32_t* d_taskshift = nullptr;
+  // workspace layout (byte offsets)
+  size_t o_params, o_status, o_cols, o_work, o_yhat, o_ahat, o_sp, o_ap, o_ap2, o_misc, ws_bytes;
+  int nadj_blocks;
+  int64_t cols_elems;
+  size_t real_bytes;  // bytes of a stored spectrum / adjoint value
+  size_t work_bytes;  // bytes of a forward working value (0: works in the spectrum buffer)
+  Sched sched;
+  // optional phase timing (profiling aid; not thread safe)
+  bool timing = false;
+  hipEvent_t ev[MTGP_NPHASE + 1] = {};
+  KDesc kd() const {
+    KDesc k;
+    k.T = T;
+    k.d = d;
+    k.family = family;
+    k.order = order;
+    k.adaptive = adaptive;
+    k.s = s;
+    k.profile = profile;
+    return k;
+  }
+};
+
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+#define HIP_OK(expr)                        \
+  do {                                      \
+    if ((expr) != hipSuccess) return MTGP_EHIP; \
+  } while (0)
+#define LAUNCH_OK(...)                        \
+  do {                                        \
+    if ((__VA_ARGS__) != 0) return MTGP_EHIP; \
+  } while (0)
+
+struct WsView {
+  Params* P;
+  int* status;
+  unsigned char* cols;
+  unsigned char* work;
+  double* yhat;
+  double* ahat;
+  double* sp;
+  double* ap;
+  double* ap2;
+  double* misc;
+};
+
+WsView view(const mtgp_plan* p, void* ws) {
+  unsigned char* b = static_cast<unsigned char*>(ws);
+  WsView v;
+  v.P = reinterpret_cast<Params*>(b + p->o_params);
+  v.status = reinterpret_cast<int*>(b + p->o_status);
+  v.cols = b + p->o_cols;
+  v.work = p->work_bytes ? b + p->o_work : b + p->o_cols;
+  v.yhat = reinterpret_cast<double*>(b + p->o_yhat);
+  v.ahat = reinterpret_cast<double*>(b + p->o_ahat);
+  v.sp = reinterpret_cast<double*>(b + p->o_sp);
+  v.ap = reinterpret_cast<double*>(b + p->o_ap);
+  v.ap2 = reinterpret_cast<double*>(b + p->o_ap2);
+  v.misc = reinterpret_cast<double*>(b + p->o_misc);
+  return v;
+}
+
+int64_t theta_size(const mtgp_plan* p) {
+  return (int64_t)p->T + 1 + p->d + (p->adaptive ? 4 : 0) + p->T + (int64_t)p->T * p->s + p->T;
+}
+
+inline void mark(const mtgp_plan* p, int phase, hipStream_t st) {
+  if (p->timing) (void)hipEventRecord(p->ev[phase], st);
+}
+
+// Kernel columns and their forward transforms: arithmetic in CR, spectrum
+// stored as SR.  When CR != SR the working buffer holds the partially
+// transformed columns and only the final pass rounds to SR.
+template <typename CR, typename SR>
+int run_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
+  SR* spec = reinterpret_cast<SR*>(w.cols);
+  CR* work = reinterpret_cast<CR*>(w.work);
+  const KDesc kd = p->kd();
+  mark(p, 1, st);
+  for (const auto& g : p->groups) {
+    const int64_t len = (int64_t)1 << g.m;
+    const uint32_t* sh = p->d_colshift + (size_t)g.first * p->d;
+    if (g.m > p->sched.lb(g.m))
+      LAUNCH_OK(launch_gen_cols<CR, CR>(work + p->col_off[g.first], len, g.count, g.m, p->d_gen, sh,
+                                        w.P, kd, true, p->sched, st));
+    else
+      LAUNCH_OK(launch_gen_cols<CR, SR>(spec + p->col_off[g.first], len, g.count, g.m, p->d_gen, sh,
+                                        w.P, kd, true, p->sched, st));
+  }
+  mark(p, 2, st);
+  for (const auto& g : p->groups) {
+    LAUNCH_OK(launch_fwht_high<CR, SR>(work + p->col_off[g.first], spec + p->col_off[g.first],
+                                       (int64_t)1 << g.m, g.count, g.m, p->sched, st));
+  }
+  return MTGP_OK;
+}
+
+template <typename CR, typename Real>
+int run_loss(const mtgp_plan* p, const double* theta, double* out3, double* grad, double* tau_hat,
+             void* ws, hipStream_t st, bool want_ahat) {
+  const WsView w = view(p, ws);
+  const KDesc kd = p->kd();
+  mark(p, 0, st);
+  LAUNCH_OK(launch_prep(theta, w.P, kd, w.status, st));
+  int rc = run_columns<CR, Real>(p, w, st);
+  if (rc) return rc;
+  Real* cols = reinterpret_cast<Real*>(w.cols);
+  const int64_t n = p->n[0];
+  mark(p, 3, st);
+  LAUNCH_OK(launch_solve_eq<Real>(cols, n, p->pm, p->ncol, w.yhat, w.P, kd, grad != nullptr, w.sp,
+                                  want_ahat ? w.ahat : nullptr, w.status, st));
+  int nadj = 0;
+  mark(p, 4, st);
+  if (grad) {
+    for (const auto& g : p->groups) {
+      Real* base = cols + p->col_off[g.first];
+      LAUNCH_OK(launch_fwht_high<Real, Real>(base, base, (int64_t)1 << g.m, g.count, g.m, p->sched,
+                                             st));
+    }
+  }
+  mark(p, 5, st);
+  if (grad) {
+    for (const auto& g : p->groups) {
+      Real* base = cols + p->col_off[g.first];
+      const int nb = 1 << (g.m - p->sched.lb(g.m));
+      LAUNCH_OK(launch_adj_reduce<Real>(base, (int64_t)1 << g.m, g.count, g.m, p->d_gen,
+                                        p->d_colshift + (size_t)g.first * p->d, w.P, kd,
+                                        w.ap + (size_t)nadj * adj_nq(p->d), p->sched, st));
+      nadj += nb * g.count;
+    }
+  }
+  if (grad) LAUNCH_OK(launch_colsum(w.ap, nadj, adj_nq(p->d), w.ap2, COLSUM_BLOCKS, st));
+  mark(p, 6, st);
+  LAUNCH_OK(launch_finalize(w.sp, SOLVE_BLOCKS, grad ? w.ap2 : nullptr, COLSUM_BLOCKS, w.yhat, n,
+                            w.P, kd, out3, grad, tau_hat, st));
+  mark(p, 7, st);
+  return MTGP_OK;
+}
+
+int dispatch_loss(const mtgp_plan* p, const double* theta, double* out3, double* grad,
+                  double* tau_hat, void* ws, hipStream_t st, bool want_ahat) {
+  switch (p->precision) {
+    case MTGP_FP64: return run_loss<double, double>(p, theta, out3, grad, tau_hat, ws, st, want_ahat);
+    case MTGP_MIXED: return run_loss<double, float>(p, theta, out3, grad, tau_hat, ws, st, want_ahat);
+    default: return run_loss<float, float>(p, theta, out3, grad, tau_hat, ws, st, want_ahat);
+  }
+}
+
+// Workspace layout; depends on the schedule through the number of blocks of
+// the adjoint reduction.
+void layout(mtgp_plan* p) {
+  const int T = p->T, d = p->d;
+  size_t o = 0;
+  p->o_params = o;
+  o = align_up(o + sizeof(Params));
+  p->o_status = o;
+  o = align_up(o + 64);
+  p->o_cols = o;
+  o = align_up(o + (size_t)p->cols_elems * p->real_bytes);
+  p->o_work = o;
+  o = align_up(o + (size_t)p->cols_elems * p->work_bytes);
+  p->o_yhat = o;
+  o = align_up(o + (size_t)p->N * sizeof(double));
+  p->o_ahat = o;
+  o = align_up(o + (size_t)p->N * sizeof(double));
+  p->o_sp = o;
+  o = align_up(o + (size_t)SOLVE_BLOCKS * solve_ns(T) * sizeof(double));
+  p->nadj_blocks = 0;
+  for (const auto& g : p->groups) p->nadj_blocks += (1 << (g.m - p->sched.lb(g.m))) * g.count;
+  p->o_ap = o;
+  o = align_up(o + (size_t)p->nadj_blocks * adj_nq(d) * sizeof(double));
+  p->o_ap2 = o;
+  o = align_up(o + (size_t)COLSUM_BLOCKS * adj_nq(d) * sizeof(double));
+  p->o_misc = o;
+  o = align_up(o + 4096);
+  p->ws_bytes = o;
+}
+
+bool valid_family_order(const mtgp_design* d) {
+  if (d->family == MTGP_DSEQ) return d->kernel_order >= 1 && d->kernel_order <= 4;
+  if (d->family == MTGP_LAT) return d->kernel_order >= 1 && d->kernel_order <= 3 && !d->adaptive;
+  return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mtgp_strerror(int code) {
+  switch (code) {
+    case MTGP_OK: return "ok";
+    case MTGP_EINVAL: return "invalid argument";
+    case MTGP_ENOTPD: return "Lambda is not positive definite (or not finite) at some frequency";
+    case MTGP_EHIP: return "HIP runtime error";
+    case MTGP_ENOMEM: return "out of memory";
+    case MTGP_ENOTSUP: return "not supported by this build";
+  }
+  return "unknown error";
+}
+
+int mtgp_plan_create(const mtgp_design* des, int32_t precision, mtgp_plan** out) {
+  if (!des || !out || !des->m || !des->gen || !des->shift) return MTGP_EINVAL;
+  *out = nullptr;
+  if (des->T < 1 || des->T > MTGP_MAXT || des->d < 1 || des->d > MTGP_MAXD) return MTGP_EINVAL;
+  if (des->rank_s < 1 || des->rank_s > MTGP_MAXS) return MTGP_EINVAL;
+  if (!valid_family_order(des)) return MTGP_EINVAL;
+  if (precision != MTGP_FP64 && precision != MTGP_MIXED && precision != MTGP_F32) return MTGP_EINVAL;
+  for (int t = 0; t < des->T; t++) {
+    if (des->m[t] < 0 || des->m[t] > 30) return MTGP_EINVAL;
+    if (t > 0 && des->m[t] > des->m[t - 1]) return MTGP_EINVAL;
+  }
+  if (des->family == MTGP_LAT)
+    for (int j = 0; j < des->d; j++)
+      if (!(des->gen[j] & 1u)) return MTGP_EINVAL;
+  mtgp_plan* p = new (std::nothrow) mtgp_plan();
+  if (!p) return MTGP_ENOMEM;
+  p->T = des->T;
+  p->d = des->d;
+  p->family = des->family;
+  p->order = des->kernel_order;
+  p->adaptive = des->adaptive ? 1 : 0;
+  p->s = des->rank_s;
+  p->profile = des->profile_tau ? 1 : 0;
+  p->precision = precision;
+  p->off[0] = 0;
+  p->equal = true;
+  for (int t = 0; t < p->T; t++) {
+    p->m[t] = des->m[t];
+    p->n[t] = (int64_t)1 << des->m[t];
+    p->off[t + 1] = p->off[t] + p->n[t];
+    if (des->m[t] != des->m[0]) p->equal = false;
+  }
+  p->N = p->off[p->T];
+  const int gl = des->family == MTGP_DSEQ ? 32 : 1;
+  p->gen.assign(des->gen, des->gen + (size_t)gl * des->d);
+  p->shift.assign(des->shift, des->shift + (size_t)des->T * des->d);
+  if (!p->equal) {  // nested unequal sizes are handled by a later stage of the build
+    delete p;
+    return MTGP_ENOTSUP;
+  }
+  // columns: the shared diagonal column, then one per task pair t < u
+  const int T = p->T, d = p->d;
+  auto pair_shift = [&](int t, int u, int j) -> uint32_t {
+    const uint32_t a = p->shift[(size_t)t * d + j], b = p->shift[(size_t)u * d + j];
+    return p->family == MTGP_DSEQ ? (a ^ b) : (uint32_t)(a - b);
+  };
+  std::memset(&p->pm, 0, sizeof(p->pm));
+  p->ncol = 0;
+  auto add_col = [&](int t, int u, int mlen) {
+    p->col_m.push_back(mlen);
+    p->col_t.push_back(t);
+    p->col_u.push_back(u);
+    for (int j = 0; j < d; j++) p->col_shift.push_back(t == u ? 0u : pair_shift(t, u, j));
+    return p->ncol++;
+  };
+  const int c0 = add_col(0, 0, p->m[0]);
+  for (int t = 0; t < T; t++) p->pm.col[t][t] = (int8_t)c0;
+  for (int t = 0; t < T; t++)
+    for (int u = t + 1; u < T; u++) {
+      const int c = add_col(t, u, p->m[t]);
+      p->pm.col[t][u] = p->pm.col[u][t] = (int8_t)c;
+    }
+  p->col_off.resize(p->ncol);
+  int64_t acc = 0;
+  for (int c = 0; c < p->ncol; c++) {
+    p->col_off[c] = acc;
+    acc += (int64_t)1 << p->col_m[c];
+  }
+  p->cols_elems = acc;
+  p->groups.push_back({0, p->ncol, p->m[0]});
+  p->real_bytes = precision == MTGP_FP64 ? sizeof(double) : sizeof(float);
+  p->work_bytes = precision == MTGP_MIXED ? sizeof(double) : 0;
+  layout(p);
+  // device tables
+  if (hipMalloc(&p->d_gen, p->gen.size() * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&p->d_colshift, p->col_shift.size() * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&p->d_taskshift, p->shift.size() * sizeof(uint32_t)) != hipSuccess) {
+    mtgp_plan_destroy(p);
+    return MTGP_ENOMEM;
+  }
+  if (hipMemcpy(p->d_gen, p->gen.data(), p->gen.size() * sizeof(uint32_t),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_colshift, p->col_shift.data(), p->col_shift.size() * sizeof(uint32_t),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_taskshift, p->shift.data(), p->shift.size() * sizeof(uint32_t),
+                hipMemcpyHostToDevice) != hipSuccess) {
+    mtgp_plan_destroy(p);
+    return MTGP_EHIP;
+  }
+  *out = p;
+  return MTGP_OK;
+}
+
+int mtgp_plan_set_schedule(mtgp_plan* p, int32_t pass_a_bits, int32_t pass_b_bits,
+                           int64_t pass_b_tile_bytes) {
+  if (!p || pass_a_bits < 1 || pass_a_bits > PASS_A_MAX_BITS || pass_b_bits < 1 ||
+      pass_b_bits > 12 || pass_b_tile_bytes < 4096 || pass_b_tile_bytes > 147456)
+    return MTGP_EINVAL;
+  p->sched.a_bits = pass_a_bits;
+  p->sched.b_bits = pass_b_bits;
+  p->sched.b_tile = (size_t)pass_b_tile_bytes;
+  layout(p);
+  return MTGP_OK;
+}
+
+int mtgp_plan_enable_timing(mtgp_plan* p, int32_t on) {
+  if (!p) return MTGP_EINVAL;
+  if (on && !p->ev[0]) {
+    for (int k = 0; k <= MTGP_NPHASE; k++)
+      if (hipEventCreate(&p->ev[k]) != hipSuccess) return MTGP_EHIP;
+  }
+  p->timing = on != 0;
+  return MTGP_OK;
+}
+
+int mtgp_phase_times(const mtgp_plan* p, double* ms, int32_t max_phases, int32_t* nphases) {
+  if (!p || !p->ev[0]) return MTGP_EINVAL;
+  if (nphases) *nphases = MTGP_NPHASE;
+  if (hipEventSynchronize(p->ev[MTGP_NPHASE]) != hipSuccess) return MTGP_EHIP;
+  for (int k = 0; k < MTGP_NPHASE && k < max_phases; k++) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, p->ev[k], p->ev[k + 1]) != hipSuccess) return MTGP_EHIP;
+    ms[k] = t;
+  }
+  return MTGP_OK;
+}
+
+const char* mtgp_phase_name(int32_t k) {
+  return (k >= 0 && k < MTGP_NPHASE) ? kPhaseNames[k] : "";
+}
+
+int mtgp_plan_destroy(mtgp_plan* p) {
+  if (!p) return MTGP_OK;
+  for (int k = 0; k <= MTGP_NPHASE; k++)
+    if (p->ev[k]) (void)hipEventDestroy(p->ev[k]);
+  if (p->d_gen) (void)hipFree(p->d_gen);
+  if (p->d_colshift) (void)hipFree(p->d_colshift);
+  if (p->d_taskshift) (void)hipFree(p->d_taskshift);
+  delete p;
+  return MTGP_OK;
+}
+
+int64_t mtgp_theta_size(const mtgp_plan* p) { return p ? theta_size(p) : MTGP_EINVAL; }
+size_t mtgp_workspace_bytes(const mtgp_plan* p) { return p ? p->ws_bytes : 0; }
+int64_t mtgp_num_points(const mtgp_plan* p) { return p ? p->N : MTGP_EINVAL; }
+int32_t mtgp_num_columns(const mtgp_plan* p) { return p ? p->ncol : MTGP_EINVAL; }
+
+int mtgp_column_info(const mtgp_plan* p, int32_t c, int32_t* log2n, int64_t* offset, int32_t* t,
+                     int32_t* u) {
+  if (!p || c < 0 || c >= p->ncol) return MTGP_EINVAL;
+  if (log2n) *log2n = p->col_m[c];
+  if (offset) *offset = p->col_off[c];
+  if (t) *t = p->col_t[c];
+  if (u) *u = p->col_u[c];
+  return MTGP_OK;
+}
+
+int mtgp_gen_points(const mtgp_plan* p, int32_t task, int64_t first, int64_t count, uint32_t* out,
+                    void* stream) {
+  if (!p || task < 0 || task >= p->T || first < 0 || count < 0 || (count > 0 && !out))
+    return MTGP_EINVAL;
+  if (first + count > ((int64_t)1 << 32)) return MTGP_EINVAL;
+  LAUNCH_OK(launch_gen_points(p->d_gen, p->d_taskshift + (size_t)task * p->d, p->family, p->d,
+                              p->m[task], first, count, out, (hipStream_t)stream));
+  return MTGP_OK;
+}
+
+int mtgp_kernel_cols(const mtgp_plan* p, const double* theta, void* cols, void* ws, void* stream) {
+  if (!p || !theta || !cols || !ws) return MTGP_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const WsView w = view(p, ws);
+  const KDesc kd = p->kd();
+  LAUNCH_OK(launch_prep(theta, w.P, kd, w.status, st));
+  for (const auto& g : p->groups) {
+    if (p->precision != MTGP_F32) {
+      double* c = static_cast<double*>(cols) + p->col_off[g.first];
+      LAUNCH_OK(launch_gen_cols<double, double>(c, (int64_t)1 << g.m, g.count, g.m, p->d_gen,
+                                        p->d_colshift + (size_t)g.first * p->d, w.P, kd, false,
+                                        p->sched, st));
+    } else {
+      float* c = static_cast<float*>(cols) + p->col_off[g.first];
+      LAUNCH_OK(launch_gen_cols<float, float>(c, (int64_t)1 << g.m, g.count, g.m, p->d_gen,
+                                       p->d_colshift + (size_t)g.first * p->d, w.P, kd, false,
+                                       p->sched, st));
+    }
+  }
+  return MTGP_OK;
+}
+
+int mtgp_fwht(void* x, int64_t batch, int32_t log2n, int32_t dtype, void* stream) {
+  if (!x || batch < 0 || log2n < 0 || log2n > 30) return MTGP_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = (int64_t)1 << log2n;
+  const Sched sc;
+  if (dtype == MTGP_DTYPE_F64)
+    LAUNCH_OK(launch_fwht<double>(static_cast<double*>(x), n, batch, log2n, sc, st));
+  else if (dtype == MTGP_DTYPE_F32)
+    LAUNCH_OK(launch_fwht<float>(static_cast<float*>(x), n, batch, log2n, sc, st));
+  else return MTGP_EINVAL;
+  return MTGP_OK;
+}
+
+int mtgp_fft(const void* x, void* X, int64_t batch, int32_t log2n, int32_t dtype,
+             int32_t bitrev_input, void* stream) {
+  (void)x; (void)X; (void)batch; (void)log2n; (void)dtype; (void)bitrev_input; (void)stream;
+  return MTGP_ENOTSUP;
+}
+
+int mtgp_set_data(const mtgp_plan* p, const double* y, void* ws, void* stream) {
+  if (!p || !y || !ws) return MTGP_EINVAL;
+  if (p->family != MTGP_DSEQ) return MTGP_ENOTSUP;
+  hipStream_t st = (hipStream_t)stream;
+  const WsView w = view(p, ws);
+  HIP_OK(hipMemcpyAsync(w.yhat, y, (size_t)p->N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  for (int t = 0; t < p->T; t++) {
+    LAUNCH_OK(launch_fwht<double>(w.yhat + p->off[t], p->n[t], 1, p->m[t], p->sched, st));
+    LAUNCH_OK(launch_scale<double>(w.yhat + p->off[t], p->n[t], 1.0 / std::sqrt((double)p->n[t]), st));
+  }
+  return MTGP_OK;
+}
+
+int mtgp_nll(const mtgp_plan* p, const double* theta, double* out3, double* tau_hat, void* ws,
+             void* stream) {
+  if (!p || !theta || !out3 || !ws) return MTGP_EINVAL;
+  if (p->family != MTGP_DSEQ) return MTGP_ENOTSUP;
+  hipStream_t st = (hipStream_t)stream;
+  return dispatch_loss(p, theta, out3, nullptr, tau_hat, ws, st, false);
+}
+
+int mtgp_nll_grad(const mtgp_plan* p, const double* theta, double* out3, double* grad,
+                  double* tau_hat, void* ws, void* stream) {
+  if (!p || !theta || !out3 || !grad || !ws) return MTGP_EINVAL;
+  if (p->family != MTGP_DSEQ) return MTGP_ENOTSUP;
+  hipStream_t st = (hipStream_t)stream;
+  return dispatch_loss(p, theta, out3, grad, tau_hat, ws, st, false);
+}
+
+int mtgp_predict(const mtgp_plan* p, const double* theta, const uint32_t* xs, int64_t M,
+                 double* mean, void* ws, void* stream) {
+  if (!p || !theta || !ws || M < 0 || (M > 0 && (!xs || !mean))) return MTGP_EINVAL;
+  if (p->family != MTGP_DSEQ) return MTGP_ENOTSUP;
+  hipStream_t st = (hipStream_t)stream;
+  const WsView w = view(p, ws);
+  int rc = dispatch_loss(p, theta, w.misc, nullptr, nullptr, ws, st, true);
+  if (rc) return rc;
+  // alpha_t = V_{m_t} ahat_t = H ahat_t / sqrt(n_t) (digital sequences: V real symmetric)
+  for (int t = 0; t < p->T; t++) {
+    LAUNCH_OK(launch_fwht<double>(w.ahat + p->off[t], p->n[t], 1, p->m[t], p->sched, st));
+    LAUNCH_OK(launch_scale<double>(w.ahat + p->off[t], p->n[t], 1.0 / std::sqrt((double)p->n[t]), st));
+  }
+  PredTasks pt;
+  for (int t = 0; t < p->T; t++) {
+    pt.m[t] = p->m[t];
+    pt.off[t] = p->off[t];
+  }
+  const KDesc kd = p->kd();
+  if (p->precision == MTGP_FP64)
+    LAUNCH_OK(launch_predict_direct<double>(p->d_gen, p->d_taskshift, pt, w.ahat, xs, M, w.P, kd,
+                                            mean, st));
+  else
+    LAUNCH_OK(launch_predict_direct<float>(p->d_gen, p->d_taskshift, pt, w.ahat, xs, M, w.P, kd,
+                                           mean, st));
+  return MTGP_OK;
+}
+
+size_t mtgp_predict_net_scratch_bytes(const mtgp_plan* p, int32_t m_star) {
+  (void)p; (void)m_star;
+  return 0;
+}
+
+int mtgp_predict_net(const mtgp_plan* p, const double* theta, const uint32_t* shift_star,
+                     int32_t m_star, double* mean, void* ws, void* scratch, void* stream) {
+  (void)p; (void)theta; (void)shift_star; (void)m_star; (void)mean; (void)ws; (void)scratch;
+  (void)stream;
+  return MTGP_ENOTSUP;
+}
+
+int mtgp_status(const mtgp_plan* p, const void* ws, int64_t* bad_index) {
+  if (!p || !ws) return MTGP_EINVAL;
+  int st[4];
+  const unsigned char* b = static_cast<const unsigned char*>(ws);
+  if (hipMemcpy(st, b + p->o_status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+    return MTGP_EHIP;
+  unsigned long long bad;
+  std::memcpy(&bad, st + 2, sizeof(bad));
+  if (bad_index) *bad_index = st[0] ? (int64_t)bad : -1;
+  return st[0] ? MTGP_ENOTPD : MTGP_OK;
+}
+
+}  // extern "C"

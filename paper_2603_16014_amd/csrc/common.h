@@ -1,0 +1,263 @@
+// Device-side building blocks shared by the HIP kernels of the fast MTGP
+// library (gfx950, wave64).
+//
+//  * Params: the decoded hyperparameters (written by the prep kernel from the
+//    packed theta vector), read by every other kernel.
+//  * Univariate kernels on 32-bit digits: adaptive-smoothness DSI kernels
+//    Khat_1..Khat_4 (Eq. DSI_kernel_1d_ex; Khat_1 read as 1 - 3 t_1, the
+//    zero-mean order-one Walsh kernel) and SI Bernoulli kernels (Eq.
+//    SI_kernel_1d_ex).
+//  * Point generation helpers: digital sequences (XOR of generating columns
+//    over the set bits of the index, Def. "Base-2 digitally-shifted digital
+//    sequences") and rank-1 lattices in natural order (j g / n mod 1).
+//  * LDS Walsh-Hadamard rounds: radix-2^r butterflies over a group of index
+//    bits, used by every transform pass.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MTGP_MAXT 16
+#define MTGP_MAXD 32
+#define MTGP_MAXS 16
+
+namespace mtgp {
+
+enum Family { FAM_DSEQ = 0, FAM_LAT = 1 };
+
+// Decoded hyperparameters; one copy lives at the start of the workspace.
+struct Params {
+  double gamma;
+  double eta[MTGP_MAXD];
+  double b[4];
+  double xi[MTGP_MAXT];
+  double zeta[MTGP_MAXT];
+  double tau[MTGP_MAXT];
+  double tau_used[MTGP_MAXT];  // means of the last loss evaluation (tau_hat or tau)
+  double R[MTGP_MAXT * MTGP_MAXT];
+  double B[MTGP_MAXT * MTGP_MAXS];
+  float gamma_f;
+  float eta_f[MTGP_MAXD];
+  float b_f[4];
+};
+
+// Static description of a plan that kernels need, passed by value.
+struct KDesc {
+  int T, d, family, order, adaptive, s, profile;
+};
+
+// ---------------------------------------------------------------------------
+// precision traits
+// ---------------------------------------------------------------------------
+template <typename Real> struct RT;
+template <> struct RT<double> {
+  __device__ static inline double unit(uint32_t u) { return (double)u * 0x1p-32; }
+  // 2^-e for 0 <= e < 1023, built from the exponent field
+  __device__ static inline double pow2neg(int e) { return __hiloint2double((1023 - e) << 20, 0); }
+  __device__ static inline double gamma(const Params* p) { return p->gamma; }
+  __device__ static inline double eta(const Params* p, int j) { return p->eta[j]; }
+  __device__ static inline double bw(const Params* p, int a) { return p->b[a]; }
+};
+template <> struct RT<float> {
+  // x = u 2^-32 rounded to float; a value that rounds to 1 is mapped to the
+  // largest float below 1 (the boundary convention for points equal to 1)
+  __device__ static inline float unit(uint32_t u) {
+    return fminf((float)u * 0x1p-32f, 0x1.fffffep-1f);
+  }
+  __device__ static inline float pow2neg(int e) { return __int_as_float((127 - e) << 23); }
+  __device__ static inline float gamma(const Params* p) { return p->gamma_f; }
+  __device__ static inline float eta(const Params* p, int j) { return p->eta_f[j]; }
+  __device__ static inline float bw(const Params* p, int a) { return p->b_f[a]; }
+};
+
+// ---------------------------------------------------------------------------
+// univariate kernels on digits
+// ---------------------------------------------------------------------------
+// sum_{a=1..32} x_a 8^-(a-1) for x = u 2^-32 with binary digits x_a
+__device__ inline uint64_t spread3_21(uint64_t x) {
+  x &= 0x1fffffull;
+  x = (x | (x << 32)) & 0x1f00000000ffffull;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+__device__ inline double octal_digit_sum(uint32_t u) {
+  // digits 1..21 (top 21 bits) then digits 22..32 (low 11 bits)
+  uint64_t hi = spread3_21(u >> 11);
+  uint64_t lo = spread3_21(u & 0x7ffu);
+  return (double)hi * 0x1p-60 + (double)lo * 0x1p-93;
+}
+
+// Khat_alpha(x), x = u 2^-32 (Eq. DSI_kernel_1d_ex), beta(0) = t_nu(0) = 0.
+template <typename Real>
+__device__ inline Real dsi_khat(int order, uint32_t u) {
+  const int beta = __clz(u) + 1;          // -floor(log2 x) for u != 0
+  const Real x = RT<Real>::unit(u);
+  const Real b = (Real)beta;
+  const Real t1 = RT<Real>::pow2neg(beta);
+  Real r, z;
+  switch (order) {
+    case 1:
+      r = (Real)1 - (Real)3 * t1;
+      z = (Real)1;
+      break;
+    case 2:
+      r = fma(-b, x, fma((Real)-2.5, t1, (Real)1.5));
+      z = (Real)1.5;
+      break;
+    case 3: {
+      const Real t2 = t1 * t1;
+      r = (Real)-1 + b * x * x - (Real)5 * ((Real)1 - t1) * x + (Real)(43.0 / 18.0) * ((Real)1 - t2);
+      z = (Real)(25.0 / 18.0);
+      break;
+    }
+    default: {
+      const Real t2 = t1 * t1, t3 = t2 * t1;
+      const Real s = (Real)(8.0 / 7.0) - (Real)2 * (Real)octal_digit_sum(u);
+      r = (Real)-1 - (Real)(2.0 / 3.0) * b * x * x * x + (Real)5 * ((Real)1 - t1) * x * x -
+          (Real)(43.0 / 9.0) * ((Real)1 - t2) * x + (Real)(701.0 / 294.0) * ((Real)1 - t3) +
+          b * (s * (Real)(1.0 / 48.0) - (Real)(1.0 / 42.0));
+      z = (Real)(407.0 / 294.0);
+      break;
+    }
+  }
+  return u == 0u ? z : r;
+}
+
+// all four Khat_alpha at once (adaptive kernel), sharing beta, x, t_nu
+template <typename Real>
+__device__ inline void dsi_khat_all(uint32_t u, Real k[4]) {
+  const int beta = __clz(u) + 1;
+  const Real x = RT<Real>::unit(u);
+  const Real b = (Real)beta;
+  const Real t1 = RT<Real>::pow2neg(beta), t2 = t1 * t1, t3 = t2 * t1;
+  const Real s = (Real)(8.0 / 7.0) - (Real)2 * (Real)octal_digit_sum(u);
+  const bool zero = (u == 0u);
+  k[0] = zero ? (Real)1 : (Real)1 - (Real)3 * t1;
+  k[1] = zero ? (Real)1.5 : fma(-b, x, fma((Real)-2.5, t1, (Real)1.5));
+  k[2] = zero ? (Real)(25.0 / 18.0)
+              : (Real)-1 + b * x * x - (Real)5 * ((Real)1 - t1) * x +
+                    (Real)(43.0 / 18.0) * ((Real)1 - t2);
+  k[3] = zero ? (Real)(407.0 / 294.0)
+              : (Real)-1 - (Real)(2.0 / 3.0) * b * x * x * x + (Real)5 * ((Real)1 - t1) * x * x -
+                    (Real)(43.0 / 9.0) * ((Real)1 - t2) * x + (Real)(701.0 / 294.0) * ((Real)1 - t3) +
+                    b * (s * (Real)(1.0 / 48.0) - (Real)(1.0 / 42.0));
+}
+
+// (-1)^(alpha+1) (2 pi)^(2 alpha) / (2 alpha)! B_{2 alpha}(x) (Eq. SI_kernel_1d_ex)
+template <typename Real>
+__device__ inline Real si_kern(int order, uint32_t u) {
+  const Real x = RT<Real>::unit(u);
+  const Real x2 = x * x;
+  switch (order) {
+    case 1:  // 2 pi^2 (x^2 - x + 1/6)
+      return (Real)19.739208802178716 * (x2 - x + (Real)(1.0 / 6.0));
+    case 2:  // -(2/3) pi^4 (x^4 - 2x^3 + x^2 - 1/30)
+      return (Real)-64.939394022668291 * (x2 * (x2 - (Real)2 * x + (Real)1) - (Real)(1.0 / 30.0));
+    default:  // (4/45) pi^6 (x^6 - 3x^5 + 5/2 x^4 - 1/2 x^2 + 1/42)
+      return (Real)85.456817206693727 *
+             (x2 * (x2 * (x2 - (Real)3 * x + (Real)2.5) - (Real)0.5) + (Real)(1.0 / 42.0));
+  }
+}
+
+// univariate kernel value for a (non-adaptive) family/order
+template <typename Real, int FAM>
+__device__ inline Real univ(int order, uint32_t u) {
+  if (FAM == FAM_DSEQ) return dsi_khat<Real>(order, u);
+  return si_kern<Real>(order, u);
+}
+
+// ---------------------------------------------------------------------------
+// points
+// ---------------------------------------------------------------------------
+// z(i) of dimension j for a digital sequence: XOR of generating columns over
+// the set bits of i (gen laid out [d][32]).
+__device__ inline uint32_t dseq_z(const uint32_t* gen_j, uint32_t i) {
+  uint32_t z = 0;
+  while (i) {
+    const int p = __ffs(i) - 1;
+    z ^= gen_j[p];
+    i &= i - 1;
+  }
+  return z;
+}
+
+// ---------------------------------------------------------------------------
+// LDS Walsh-Hadamard rounds
+// ---------------------------------------------------------------------------
+// Sequences of length 2^L live in LDS at seq * stride + i + (i >> 4); the
+// extra element per 16 (and a stride that is not a multiple of 32) keeps
+// strided accesses off a single bank.
+__host__ __device__ inline int lds_stride(int L) { return (1 << L) + ((1 << L) >> 4) + 1; }
+__device__ inline int lds_at(int seq, int stride, int i) { return seq * stride + i + (i >> 4); }
+
+// Butterflies over bits [lo, lo + R) of every one of nseq sequences.
+template <typename Real, int R>
+__device__ inline void lds_round(Real* lds, int nseq, int L, int lo, int stride) {
+  const int per_seq = 1 << (L - R);
+  const int total = nseq * per_seq;
+  const int lo_mask = (1 << lo) - 1;
+  for (int g = threadIdx.x; g < total; g += blockDim.x) {
+    const int seq = g / per_seq;
+    const int q = g - seq * per_seq;
+    const int base = (q & lo_mask) | ((q >> lo) << (lo + R));
+    Real v[1 << R];
+#pragma unroll
+    for (int k = 0; k < (1 << R); k++) v[k] = lds[lds_at(seq, stride, base + (k << lo))];
+#pragma unroll
+    for (int h = 1; h < (1 << R); h <<= 1) {
+#pragma unroll
+      for (int k = 0; k < (1 << R); k++) {
+        if (!(k & h)) {
+          const Real a = v[k], c = v[k + h];
+          v[k] = a + c;
+          v[k + h] = a - c;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < (1 << R); k++) lds[lds_at(seq, stride, base + (k << lo))] = v[k];
+  }
+}
+
+// Full transform over bits [0, L) of nseq LDS sequences, in rounds of <= 4 bits.
+template <typename Real>
+__device__ inline void lds_fwht(Real* lds, int nseq, int L, int stride) {
+  int lo = 0;
+  while (lo < L) {
+    const int r = min(4, L - lo);
+    __syncthreads();
+    switch (r) {
+      case 4: lds_round<Real, 4>(lds, nseq, L, lo, stride); break;
+      case 3: lds_round<Real, 3>(lds, nseq, L, lo, stride); break;
+      case 2: lds_round<Real, 2>(lds, nseq, L, lo, stride); break;
+      default: lds_round<Real, 1>(lds, nseq, L, lo, stride); break;
+    }
+    lo += r;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// block reductions (FP64)
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sums v over the block; every thread gets the result.  `red` holds >= 16 doubles.
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; i++) s += red[i];
+  return s;
+}
+
+}  // namespace mtgp

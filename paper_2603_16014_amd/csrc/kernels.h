@@ -1,0 +1,98 @@
+// Internal declarations shared by the HIP translation units of the library.
+#pragma once
+#include "common.h"
+
+namespace mtgp {
+
+// Pass A covers index bits [0, PASS_A_MAX_BITS); 256 threads hold up to
+// MAXE = 2^13 / 256 elements each.  Pass B covers <= PASS_B_MAX_BITS more bits
+// per launch with a tile of about PASS_B_TILE_BYTES of LDS.
+constexpr int PASS_A_MAX_BITS = 13;
+constexpr int MAXE = (1 << PASS_A_MAX_BITS) / 256;
+constexpr int PASS_B_MAX_BITS = 11;
+constexpr size_t PASS_B_TILE_BYTES = 73728;
+
+// Lattice digit of natural-order index j: (j g mod 2^m) 2^(32-m), i.e. the
+// point j g / n mod 1 of the unshifted rank-1 lattice with n = 2^m.
+__device__ inline uint32_t lat_z(uint32_t g, uint32_t j, int m) {
+  return (uint32_t)((uint64_t)(j * g) << (32 - m));
+}
+
+// Univariate kernel value; the adaptive DSI kernel weights Khat_1..4 by b.
+template <typename Real, int FAM, int ADAPT>
+__device__ inline Real univ_value(int order, uint32_t u, const Params* __restrict__ P) {
+  if (ADAPT) {
+    Real k[4];
+    dsi_khat_all<Real>(u, k);
+    return RT<Real>::bw(P, 0) * k[0] + RT<Real>::bw(P, 1) * k[1] + RT<Real>::bw(P, 2) * k[2] +
+           RT<Real>::bw(P, 3) * k[3];
+  }
+  return univ<Real, FAM>(order, u);
+}
+
+// Task-pair -> column index map, and per-column scale / multiplicity.
+struct PairMap {
+  int8_t col[MTGP_MAXT][MTGP_MAXT];
+};
+
+// Transform schedule: pass A covers a_bits low index bits, each pass B at
+// most b_bits more, with an LDS tile of about b_tile bytes.
+struct Sched {
+  int a_bits = PASS_A_MAX_BITS;
+  int b_bits = PASS_B_MAX_BITS;
+  size_t b_tile = PASS_B_TILE_BYTES;
+  int lb(int m) const { return m < a_bits ? m : a_bits; }
+};
+
+// ---- transform.hip
+size_t gen_cols_lds_bytes(int LB, int real_bytes);
+template <typename Real>
+int launch_fwht(Real* base, int64_t vec_stride, int64_t nvec, int m, const Sched& sc,
+                hipStream_t st);
+template <typename TIn, typename TOut>
+int launch_fwht_high(TIn* work, TOut* out, int64_t vec_stride, int64_t nvec, int m,
+                     const Sched& sc, hipStream_t st);
+template <typename Real, typename TOut>
+int launch_gen_cols(TOut* base, int64_t col_stride, int ncols, int m, const uint32_t* gen,
+                    const uint32_t* colshift, const Params* P, const KDesc& kd, bool do_fwht,
+                    const Sched& sc, hipStream_t st);
+template <typename Real>
+int launch_scale(Real* x, int64_t n, Real s, hipStream_t st);
+
+// ---- adjoint.hip
+// Number of FP64 partial sums written per block by the derivative reduction.
+__host__ __device__ inline int adj_nq(int d) { return d + 5; }
+template <typename Real>
+int launch_adj_reduce(const Real* base, int64_t col_stride, int ncols, int m, const uint32_t* gen,
+                      const uint32_t* colshift, const Params* P, const KDesc& kd, double* partials,
+                      const Sched& sc, hipStream_t st);
+
+// ---- solve.hip
+int launch_prep(const double* theta, Params* P, const KDesc& kd, int* status, hipStream_t st);
+// number of FP64 partial sums per block of the equal-size solve
+__host__ __device__ inline int solve_ns(int T) { return 2 + T * (T + 1) / 2 + T + T; }
+constexpr int SOLVE_BLOCKS = 1024;
+template <typename Real>
+int launch_solve_eq(Real* cols, int64_t n, const PairMap& pm, int ncol, const double* yhat,
+                    const Params* P, const KDesc& kd, bool grad, double* partials, double* ahat,
+                    int* status, hipStream_t st);
+constexpr int COLSUM_BLOCKS = 256;
+int launch_colsum(const double* in, int64_t nrows, int ncols, double* out, int nblk,
+                  hipStream_t st);
+int launch_finalize(const double* solve_partials, int nsolve, const double* adj_partials, int nadj,
+                    const double* yhat0, int64_t n, Params* P, const KDesc& kd, double* out3,
+                    double* grad, double* tau_hat, hipStream_t st);
+
+// ---- points.hip
+int launch_gen_points(const uint32_t* gen, const uint32_t* shift, int family, int d, int m,
+                      int64_t first, int64_t count, uint32_t* out, hipStream_t st);
+struct PredTasks {
+  int m[MTGP_MAXT];
+  int64_t off[MTGP_MAXT];
+};
+template <typename Real>
+int launch_predict_direct(const uint32_t* gen, const uint32_t* shifts, const PredTasks& pt,
+                          const double* alpha, const uint32_t* xs, int64_t M, const Params* P,
+                          const KDesc& kd, double* mean, hipStream_t st);
+
+}  // namespace mtgp

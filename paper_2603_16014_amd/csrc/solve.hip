@@ -1,0 +1,371 @@
+// Per-frequency factorisation for equal sample sizes, parameter decoding and
+// the final reductions / chain rule.
+//
+// Equal sizes (Corollary on equal sample sizes): Lambda is block diagonal
+// over frequencies f, each block the T x T matrix
+//   Lambda(f)_tu = R_tu lambda_{p(t,u)}(f) + delta_tu xi_t
+// with lambda_p the transform of kernel column p.  One thread per frequency
+// factors it (Cholesky, FP64), accumulates log det and the quadratic form of
+// rhat(f) = yhat(f) - delta_{f0} sqrt(n) tau, and for the gradient forms
+// W(f) = Lambda(f)^-1 - ahat ahat^T and the adjoint weights
+//   omega_diag(f) = sum_t R_tt W_tt(f),  omega_tu(f) = 2 R_tu W_tu(f)
+// written over the column buffer, plus G_tu = sum_f W_tu(f) lambda_tu(f)
+// (dL/dR_tu) and sum_f W_tt(f) (dL/dxi_t).
+// With profiled means and equal sizes, tau_hat_t = yhat_t(0) / sqrt(n), the
+// per-task sample mean (Theorem "Fast MTGP computations", item 4 with
+// Pi = n Lambda(0)^-1), so rhat(0) = 0.
+#include "kernels.h"
+
+namespace mtgp {
+
+__global__ void prep_kernel(const double* __restrict__ theta, Params* __restrict__ P, KDesc kd,
+                            int* __restrict__ status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int T = kd.T, d = kd.d, s = kd.s;
+  const int nb = kd.adaptive ? 4 : 0;
+  int o = 0;
+  for (int t = 0; t < T; t++) P->tau[t] = theta[o + t];
+  o += T;
+  P->gamma = exp(theta[o]);
+  o += 1;
+  for (int j = 0; j < MTGP_MAXD; j++) P->eta[j] = j < d ? exp(theta[o + j]) : 0.0;
+  o += d;
+  for (int a = 0; a < 4; a++) P->b[a] = a < nb ? exp(theta[o + a]) : 0.0;
+  o += nb;
+  for (int t = 0; t < T; t++) P->xi[t] = exp(theta[o + t]);
+  o += T;
+  for (int i = 0; i < T * s; i++) P->B[i] = theta[o + i];
+  o += T * s;
+  for (int t = 0; t < T; t++) P->zeta[t] = exp(theta[o + t]);
+  for (int t = 0; t < T; t++)
+    for (int u = 0; u < T; u++) {
+      double acc = (t == u) ? P->zeta[t] : 0.0;
+      for (int k = 0; k < s; k++) acc += P->B[t * s + k] * P->B[u * s + k];
+      P->R[t * MTGP_MAXT + u] = acc;
+    }
+  P->gamma_f = (float)P->gamma;
+  for (int j = 0; j < MTGP_MAXD; j++) P->eta_f[j] = (float)P->eta[j];
+  for (int a = 0; a < 4; a++) P->b_f[a] = (float)P->b[a];
+  status[0] = 0;
+  status[1] = 0;
+  *reinterpret_cast<unsigned long long*>(status + 2) = ~0ull;
+}
+
+int launch_prep(const double* theta, Params* P, const KDesc& kd, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(64), 0, st, theta, P, kd, status);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+__device__ inline void flag_bad(int* status, int64_t idx) {
+  atomicOr(status, 1);
+  atomicMin(reinterpret_cast<unsigned long long*>(status + 2), (unsigned long long)idx);
+}
+
+template <int TM>
+__device__ constexpr int pk(int i, int j) {
+  return i * (i + 1) / 2 + j;
+}
+
+template <typename Real, int TM, bool GRAD>
+__global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, int64_t n,
+                                                       PairMap pm, const double* __restrict__ yhat,
+                                                       const Params* __restrict__ P, KDesc kd,
+                                                       double* __restrict__ partials,
+                                                       double* __restrict__ ahat,
+                                                       int* __restrict__ status) {
+  __shared__ double red[16];
+  constexpr int NP = TM * (TM + 1) / 2;
+  const int T = kd.T;
+  const double sqn = sqrt((double)n);
+  double acc_quad = 0.0, acc_ld = 0.0;
+  double accG[GRAD ? NP : 1];
+  double accX[GRAD ? TM : 1];
+  double acc_a0[TM];
+#pragma unroll
+  for (int q = 0; q < (GRAD ? NP : 1); q++) accG[q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < (GRAD ? TM : 1); q++) accX[q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < TM; q++) acc_a0[q] = 0.0;
+
+  for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < n;
+       f += (int64_t)gridDim.x * blockDim.x) {
+    double lam[NP], A[NP], r[TM];
+#pragma unroll
+    for (int i = 0; i < TM; i++) {
+#pragma unroll
+      for (int j = 0; j <= i; j++) {
+        if (i < T) {
+          const double l = (double)cols[(int64_t)pm.col[j][i] * n + f];
+          lam[pk<TM>(i, j)] = l;
+          A[pk<TM>(i, j)] = P->R[j * MTGP_MAXT + i] * l + (i == j ? P->xi[i] : 0.0);
+        } else {
+          lam[pk<TM>(i, j)] = 0.0;
+          A[pk<TM>(i, j)] = (i == j) ? 1.0 : 0.0;
+        }
+      }
+      if (i < T) {
+        double y = yhat[(int64_t)i * n + f];
+        if (f == 0) y = kd.profile ? 0.0 : y - sqn * P->tau[i];
+        r[i] = y;
+      } else {
+        r[i] = 0.0;
+      }
+    }
+    // Cholesky A = L L^T in place (lower, packed)
+    bool ok = true;
+    double prod = 1.0;
+#pragma unroll
+    for (int j = 0; j < TM; j++) {
+      double s = A[pk<TM>(j, j)];
+#pragma unroll
+      for (int k = 0; k < j; k++) s -= A[pk<TM>(j, k)] * A[pk<TM>(j, k)];
+      ok = ok && (s > 0.0);
+      const double l = sqrt(s);
+      const double il = 1.0 / l;
+      A[pk<TM>(j, j)] = l;
+      prod *= l;
+#pragma unroll
+      for (int i = j + 1; i < TM; i++) {
+        double v = A[pk<TM>(i, j)];
+#pragma unroll
+        for (int k = 0; k < j; k++) v -= A[pk<TM>(i, k)] * A[pk<TM>(j, k)];
+        A[pk<TM>(i, j)] = v * il;
+      }
+    }
+    if (!ok || !isfinite(prod)) flag_bad(status, f);
+    acc_ld += 2.0 * log(prod);
+    // L z = r, quad = z^T z, L^T a = z
+    double a[TM];
+#pragma unroll
+    for (int i = 0; i < TM; i++) {
+      double v = r[i];
+#pragma unroll
+      for (int k = 0; k < i; k++) v -= A[pk<TM>(i, k)] * a[k];
+      a[i] = v / A[pk<TM>(i, i)];
+      acc_quad += a[i] * a[i];
+    }
+#pragma unroll
+    for (int i = TM - 1; i >= 0; i--) {
+      double v = a[i];
+#pragma unroll
+      for (int k = i + 1; k < TM; k++) v -= A[pk<TM>(k, i)] * a[k];
+      a[i] = v / A[pk<TM>(i, i)];
+    }
+    if (f == 0) {
+#pragma unroll
+      for (int i = 0; i < TM; i++) acc_a0[i] = a[i];
+    }
+    if (ahat) {
+#pragma unroll
+      for (int i = 0; i < TM; i++)
+        if (i < T) ahat[(int64_t)i * n + f] = a[i];
+    }
+    if (GRAD) {
+      // X = L^-1 in place
+#pragma unroll
+      for (int i = 0; i < TM; i++) {
+#pragma unroll
+        for (int j = 0; j < i; j++) {
+          double s = 0.0;
+#pragma unroll
+          for (int k = j; k < i; k++) s += A[pk<TM>(i, k)] * A[pk<TM>(k, j)];
+          A[pk<TM>(i, j)] = -s / A[pk<TM>(i, i)];
+        }
+        A[pk<TM>(i, i)] = 1.0 / A[pk<TM>(i, i)];
+      }
+      double wdiag = 0.0;
+#pragma unroll
+      for (int u = 0; u < TM; u++) {
+#pragma unroll
+        for (int t = 0; t <= u; t++) {
+          double s = 0.0;
+#pragma unroll
+          for (int k = u; k < TM; k++) s += A[pk<TM>(k, t)] * A[pk<TM>(k, u)];
+          const double w = s - a[t] * a[u];
+          if (u < T) {
+            accG[pk<TM>(u, t)] += w * lam[pk<TM>(u, t)];
+            if (t == u) {
+              accX[t] += w;
+              wdiag += P->R[t * MTGP_MAXT + t] * w;
+            } else {
+              cols[(int64_t)pm.col[t][u] * n + f] = (Real)(2.0 * P->R[t * MTGP_MAXT + u] * w);
+            }
+          }
+        }
+      }
+      cols[(int64_t)pm.col[0][0] * n + f] = (Real)wdiag;
+    }
+  }
+  // block reductions -> partials[block][ns]
+  const int ns = solve_ns(T);
+  double* out = partials + (size_t)blockIdx.x * ns;
+  double v = block_sum(acc_quad, red);
+  if (threadIdx.x == 0) out[0] = v;
+  v = block_sum(acc_ld, red);
+  if (threadIdx.x == 0) out[1] = v;
+  int q = 2;
+  if (GRAD) {
+#pragma unroll
+    for (int u = 0; u < TM; u++) {
+#pragma unroll
+      for (int t = 0; t <= u; t++) {
+        if (u < T) {
+          v = block_sum(accG[pk<TM>(u, t)], red);
+          if (threadIdx.x == 0) out[2 + pk<TM>(u, t)] = v;
+        }
+      }
+    }
+  }
+  q = 2 + T * (T + 1) / 2;
+#pragma unroll
+  for (int t = 0; t < TM; t++) {
+    if (t < T) {
+      v = GRAD ? block_sum(accX[GRAD ? t : 0], red) : 0.0;
+      if (threadIdx.x == 0) out[q + t] = v;
+    }
+  }
+  q += T;
+#pragma unroll
+  for (int t = 0; t < TM; t++) {
+    if (t < T) {
+      v = block_sum(acc_a0[t], red);
+      if (threadIdx.x == 0) out[q + t] = v;
+    }
+  }
+  if (!GRAD && threadIdx.x == 0)
+    for (int i = 2; i < 2 + T * (T + 1) / 2; i++) out[i] = 0.0;
+}
+
+template <typename Real>
+int launch_solve_eq(Real* cols, int64_t n, const PairMap& pm, int ncol, const double* yhat,
+                    const Params* P, const KDesc& kd, bool grad, double* partials, double* ahat,
+                    int* status, hipStream_t st) {
+  (void)ncol;
+  dim3 grid(SOLVE_BLOCKS), block(256);
+#define MTGP_SOLVE(TMV)                                                                          \
+  do {                                                                                           \
+    if (grad)                                                                                    \
+      hipLaunchKernelGGL((solve_eq_kernel<Real, TMV, true>), grid, block, 0, st, cols, n, pm,    \
+                         yhat, P, kd, partials, ahat, status);                                   \
+    else                                                                                         \
+      hipLaunchKernelGGL((solve_eq_kernel<Real, TMV, false>), grid, block, 0, st, cols, n, pm,   \
+                         yhat, P, kd, partials, ahat, status);                                   \
+  } while (0)
+  if (kd.T <= 1) MTGP_SOLVE(1);
+  else if (kd.T <= 2) MTGP_SOLVE(2);
+  else if (kd.T <= 4) MTGP_SOLVE(4);
+  else if (kd.T <= 8) MTGP_SOLVE(8);
+  else MTGP_SOLVE(16);
+#undef MTGP_SOLVE
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template int launch_solve_eq<double>(double*, int64_t, const PairMap&, int, const double*,
+                                     const Params*, const KDesc&, bool, double*, double*, int*,
+                                     hipStream_t);
+template int launch_solve_eq<float>(float*, int64_t, const PairMap&, int, const double*,
+                                    const Params*, const KDesc&, bool, double*, double*, int*,
+                                    hipStream_t);
+
+// ---------------------------------------------------------------------------
+// finalize: deterministic sums of the block partials and the chain rule
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ sp, int nsolve,
+                                                       const double* __restrict__ ap, int nadj,
+                                                       const double* __restrict__ yhat, int64_t n,
+                                                       Params* __restrict__ P, KDesc kd,
+                                                       double* __restrict__ out3,
+                                                       double* __restrict__ grad,
+                                                       double* __restrict__ tau_hat) {
+  __shared__ double red[16];
+  __shared__ double sums[256];
+  const int T = kd.T, d = kd.d, s = kd.s;
+  const int ns = solve_ns(T);
+  const int nq = adj_nq(d);
+  for (int q = 0; q < ns; q++) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nsolve; b += blockDim.x) v += sp[(size_t)b * ns + q];
+    v = block_sum(v, red);
+    if (threadIdx.x == 0) sums[q] = v;
+  }
+  for (int q = 0; q < nq; q++) {
+    double v = 0.0;
+    if (ap)
+      for (int b = threadIdx.x; b < nadj; b += blockDim.x) v += ap[(size_t)b * nq + q];
+    v = block_sum(v, red);
+    if (threadIdx.x == 0) sums[ns + q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double quad = sums[0], logdet = sums[1];
+  out3[0] = quad;
+  out3[1] = logdet;
+  out3[2] = quad + logdet;
+  const double sqn = sqrt((double)n);
+  const int qX = 2 + T * (T + 1) / 2, qA = qX + T;
+  for (int t = 0; t < T; t++) {
+    const double tu = kd.profile ? yhat[(int64_t)t * n] / sqn : P->tau[t];
+    P->tau_used[t] = tu;
+    if (tau_hat) tau_hat[t] = tu;
+  }
+  if (!grad) return;
+  auto G = [&](int t, int u) {
+    const int a = t > u ? t : u, b = t > u ? u : t;
+    return sums[2 + a * (a + 1) / 2 + b];
+  };
+  int o = 0;
+  for (int t = 0; t < T; t++) grad[o + t] = kd.profile ? 0.0 : -2.0 * sqn * sums[qA + t];
+  o += T;
+  double gg = 0.0;
+  for (int t = 0; t < T; t++)
+    for (int u = 0; u < T; u++) gg += P->R[t * MTGP_MAXT + u] * G(t, u);
+  grad[o++] = gg;
+  for (int j = 0; j < d; j++) grad[o + j] = sums[ns + 1 + j];
+  o += d;
+  if (kd.adaptive) {
+    for (int a = 0; a < 4; a++) grad[o + a] = P->b[a] * sums[ns + 1 + d + a];
+    o += 4;
+  }
+  for (int t = 0; t < T; t++) grad[o + t] = P->xi[t] * sums[qX + t];
+  o += T;
+  for (int t = 0; t < T; t++)
+    for (int k = 0; k < s; k++) {
+      double acc = 0.0;
+      for (int u = 0; u < T; u++) acc += 2.0 * G(t, u) * P->B[u * s + k];
+      grad[o + t * s + k] = acc;
+    }
+  o += T * s;
+  for (int t = 0; t < T; t++) grad[o + t] = P->zeta[t] * G(t, t);
+}
+
+// First stage of the deterministic reduction of a [nrows][ncols] table of
+// block partials: block b sums rows b, b + nblk, ... into out[b][ncols].
+__global__ __launch_bounds__(256) void colsum_kernel(const double* __restrict__ in, int64_t nrows,
+                                                     int ncols, double* __restrict__ out) {
+  __shared__ double red[16];
+  for (int q = 0; q < ncols; q++) {
+    double v = 0.0;
+    for (int64_t r = blockIdx.x + (int64_t)gridDim.x * threadIdx.x; r < nrows;
+         r += (int64_t)gridDim.x * blockDim.x)
+      v += in[r * ncols + q];
+    v = block_sum(v, red);
+    if (threadIdx.x == 0) out[(size_t)blockIdx.x * ncols + q] = v;
+  }
+}
+
+int launch_colsum(const double* in, int64_t nrows, int ncols, double* out, int nblk,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(colsum_kernel, dim3(nblk), dim3(256), 0, st, in, nrows, ncols, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_finalize(const double* solve_partials, int nsolve, const double* adj_partials, int nadj,
+                    const double* yhat0, int64_t n, Params* P, const KDesc& kd, double* out3,
+                    double* grad, double* tau_hat, hipStream_t st) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, st, solve_partials, nsolve,
+                     adj_partials, nadj, yhat0, n, P, kd, out3, grad, tau_hat);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace mtgp

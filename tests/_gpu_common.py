@@ -1,0 +1,52 @@
+"""Helpers of the GPU parity tests: run a workload through the C ABI and
+through the dense oracle on the same seeded inputs."""
+import functools
+import sys
+
+import numpy as np
+
+import workloads
+from oracle import dense, hp, points
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@functools.lru_cache(maxsize=64)
+def _oracle_cached(key):
+    w, want_grad, want_hp, xs_seed, M = _PENDING[key]
+    X = points.task_points(w)
+    y = dense.targets(w, np.random.default_rng(w.seed + 1000), X)
+    out = dict(X=X, y=y)
+    if want_grad:
+        g, res = dense.grad(w, y, X=X)
+        out["grad"] = g
+    else:
+        res = dense.nll(w, y, X=X)
+    out["res"] = res
+    if M:
+        xs = workloads.uniform_digits(np.random.default_rng(xs_seed), M, w.d)
+        out["xs"] = xs
+        out["mean"] = dense.posterior_mean(w, y, xs, X=X, res=res)
+    if want_hp:
+        out["hp"] = hp.mtgp(w, y, X=X, Xs=out.get("xs"))
+    return out
+
+
+_PENDING = {}
+
+
+def oracle_for(w, want_grad=True, want_hp=False, xs_seed=99, M=0):
+    key = (w.name, tuple(w.m), w.profile_tau, want_grad, want_hp, xs_seed, M,
+           tuple(np.atleast_1d(w.theta["xi"]).tolist()))
+    _PENDING[key] = (w, want_grad, want_hp, xs_seed, M)
+    return _oracle_cached(key)
+
+
+def rel_err(a, b, scale=None):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    s = np.abs(b).max() if scale is None else scale
+    return float(np.abs(a - b).max() / max(s, 1e-300))
