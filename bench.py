@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--m", type=int, default=24, help="log2 points per task")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="fp64,mixed")
+    ap.add_argument("--sched", default=None,
+                    help="transform schedule a_bits,b_bits,b_tile_bytes (default: library default)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the fast MTGP path here runs on a single "
@@ -140,7 +142,8 @@ def main():
     results = {}
     y = None
     for prec in args.precisions.split(","):
-        plan = mtgp.Plan.from_workload(w, prec)
+        sched = tuple(int(v) for v in args.sched.split(",")) if args.sched else None
+        plan = mtgp.Plan.from_workload(w, prec, schedule=sched)
         if y is None:
             y = targets_on_device(plan, w)
         plan.set_data(y)
@@ -202,6 +205,8 @@ def main():
         "roofline": roof,
     }
     line.update(extra)
+    if args.sched:
+        line["schedule"] = args.sched
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line))

@@ -51,7 +51,8 @@ struct mtgp_plan {
   uint32_t* d_colshift = nullptr;
   uint32_t* d_taskshift = nullptr;
   // workspace layout (byte offsets)
-  size_t o_params, o_status, o_cols, o_work, o_yhat, o_ahat, o_sp, o_ap, o_ap2, o_misc, ws_bytes;
+  size_t o_params, o_status, o_cols, o_work, o_yhat, o_ahat, o_sp, o_sp2, o_ap, o_ap2, o_misc,
+      ws_bytes;
   int nadj_blocks;
   int64_t cols_elems;
   size_t real_bytes;  // bytes of a stored spectrum / adjoint value
@@ -94,6 +95,7 @@ struct WsView {
   double* yhat;
   double* ahat;
   double* sp;
+  double* sp2;
   double* ap;
   double* ap2;
   double* misc;
@@ -109,6 +111,7 @@ WsView view(const mtgp_plan* p, void* ws) {
   v.yhat = reinterpret_cast<double*>(b + p->o_yhat);
   v.ahat = reinterpret_cast<double*>(b + p->o_ahat);
   v.sp = reinterpret_cast<double*>(b + p->o_sp);
+  v.sp2 = reinterpret_cast<double*>(b + p->o_sp2);
   v.ap = reinterpret_cast<double*>(b + p->o_ap);
   v.ap2 = reinterpret_cast<double*>(b + p->o_ap2);
   v.misc = reinterpret_cast<double*>(b + p->o_misc);
@@ -136,57 +139,67 @@ int run_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
     const int64_t len = (int64_t)1 << g.m;
     const uint32_t* sh = p->d_colshift + (size_t)g.first * p->d;
     if (g.m > p->sched.lb(g.m))
-      LAUNCH_OK(launch_gen_cols<CR, CR>(work + p->col_off[g.first], len, g.count, g.m, p->d_gen, sh,
-                                        w.P, kd, true, p->sched, st));
+      LAUNCH_OK(launch_gen_fwd<CR, CR>(work + p->col_off[g.first], len, g.count, g.m, p->d_gen, sh,
+                                       w.P, kd, p->sched, st));
     else
-      LAUNCH_OK(launch_gen_cols<CR, SR>(spec + p->col_off[g.first], len, g.count, g.m, p->d_gen, sh,
-                                        w.P, kd, true, p->sched, st));
+      LAUNCH_OK(launch_gen_fwd<CR, SR>(spec + p->col_off[g.first], len, g.count, g.m, p->d_gen, sh,
+                                       w.P, kd, p->sched, st));
   }
   mark(p, 2, st);
   for (const auto& g : p->groups) {
-    LAUNCH_OK(launch_fwht_high<CR, SR>(work + p->col_off[g.first], spec + p->col_off[g.first],
-                                       (int64_t)1 << g.m, g.count, g.m, p->sched, st));
+    const int64_t o = p->col_off[g.first];
+    LAUNCH_OK(launch_strided<CR, CR, SR>(work + o, work + o, spec + o, (int64_t)1 << g.m, g.count,
+                                         g.m, p->sched, st));
   }
   return MTGP_OK;
 }
 
-template <typename CR, typename Real>
+// Loss (and gradient): columns and transforms in CR arithmetic, spectrum and
+// adjoint weights stored as SR, adjoint transform arithmetic in CR.
+template <typename CR, typename SR>
 int run_loss(const mtgp_plan* p, const double* theta, double* out3, double* grad, double* tau_hat,
              void* ws, hipStream_t st, bool want_ahat) {
   const WsView w = view(p, ws);
   const KDesc kd = p->kd();
   mark(p, 0, st);
   LAUNCH_OK(launch_prep(theta, w.P, kd, w.status, st));
-  int rc = run_columns<CR, Real>(p, w, st);
+  int rc = run_columns<CR, SR>(p, w, st);
   if (rc) return rc;
-  Real* cols = reinterpret_cast<Real*>(w.cols);
+  SR* spec = reinterpret_cast<SR*>(w.cols);
+  CR* work = reinterpret_cast<CR*>(w.work);
   const int64_t n = p->n[0];
   mark(p, 3, st);
-  LAUNCH_OK(launch_solve_eq<Real>(cols, n, p->pm, p->ncol, w.yhat, w.P, kd, grad != nullptr, w.sp,
-                                  want_ahat ? w.ahat : nullptr, w.status, st));
+  LAUNCH_OK(launch_solve_eq<SR>(spec, n, p->pm, p->ncol, w.yhat, w.P, kd, grad != nullptr, w.sp,
+                                want_ahat ? w.ahat : nullptr, w.status, st));
   int nadj = 0;
   mark(p, 4, st);
   if (grad) {
     for (const auto& g : p->groups) {
-      Real* base = cols + p->col_off[g.first];
-      LAUNCH_OK(launch_fwht_high<Real, Real>(base, base, (int64_t)1 << g.m, g.count, g.m, p->sched,
-                                             st));
+      const int64_t o = p->col_off[g.first];
+      LAUNCH_OK(launch_strided<CR, SR, CR>(spec + o, work + o, work + o, (int64_t)1 << g.m,
+                                           g.count, g.m, p->sched, st));
     }
   }
   mark(p, 5, st);
   if (grad) {
     for (const auto& g : p->groups) {
-      Real* base = cols + p->col_off[g.first];
+      const int64_t o = p->col_off[g.first];
       const int nb = 1 << (g.m - p->sched.lb(g.m));
-      LAUNCH_OK(launch_adj_reduce<Real>(base, (int64_t)1 << g.m, g.count, g.m, p->d_gen,
-                                        p->d_colshift + (size_t)g.first * p->d, w.P, kd,
-                                        w.ap + (size_t)nadj * adj_nq(p->d), p->sched, st));
+      const uint32_t* sh = p->d_colshift + (size_t)g.first * p->d;
+      double* part = w.ap + (size_t)nadj * adj_nq(p->d);
+      if (g.m > p->sched.lb(g.m))
+        LAUNCH_OK(launch_adj_reduce<CR, CR>(work + o, (int64_t)1 << g.m, g.count, g.m, p->d_gen,
+                                            sh, w.P, kd, part, p->sched, st));
+      else
+        LAUNCH_OK(launch_adj_reduce<CR, SR>(spec + o, (int64_t)1 << g.m, g.count, g.m, p->d_gen,
+                                            sh, w.P, kd, part, p->sched, st));
       nadj += nb * g.count;
     }
+    LAUNCH_OK(launch_colsum(w.ap, nadj, adj_nq(p->d), w.ap2, COLSUM_BLOCKS, st));
   }
-  if (grad) LAUNCH_OK(launch_colsum(w.ap, nadj, adj_nq(p->d), w.ap2, COLSUM_BLOCKS, st));
+  LAUNCH_OK(launch_colsum(w.sp, solve_blocks(n), solve_ns(p->T), w.sp2, COLSUM_BLOCKS, st));
   mark(p, 6, st);
-  LAUNCH_OK(launch_finalize(w.sp, SOLVE_BLOCKS, grad ? w.ap2 : nullptr, COLSUM_BLOCKS, w.yhat, n,
+  LAUNCH_OK(launch_finalize(w.sp2, COLSUM_BLOCKS, grad ? w.ap2 : nullptr, COLSUM_BLOCKS, w.yhat, n,
                             w.P, kd, out3, grad, tau_hat, st));
   mark(p, 7, st);
   return MTGP_OK;
@@ -219,7 +232,9 @@ void layout(mtgp_plan* p) {
   p->o_ahat = o;
   o = align_up(o + (size_t)p->N * sizeof(double));
   p->o_sp = o;
-  o = align_up(o + (size_t)SOLVE_BLOCKS * solve_ns(T) * sizeof(double));
+  o = align_up(o + (size_t)solve_blocks(p->n[p->T - 1]) * solve_ns(T) * sizeof(double));
+  p->o_sp2 = o;
+  o = align_up(o + (size_t)COLSUM_BLOCKS * solve_ns(T) * sizeof(double));
   p->nadj_blocks = 0;
   for (const auto& g : p->groups) p->nadj_blocks += (1 << (g.m - p->sched.lb(g.m))) * g.count;
   p->o_ap = o;
@@ -427,17 +442,13 @@ int mtgp_kernel_cols(const mtgp_plan* p, const double* theta, void* cols, void* 
   const KDesc kd = p->kd();
   LAUNCH_OK(launch_prep(theta, w.P, kd, w.status, st));
   for (const auto& g : p->groups) {
-    if (p->precision != MTGP_F32) {
-      double* c = static_cast<double*>(cols) + p->col_off[g.first];
-      LAUNCH_OK(launch_gen_cols<double, double>(c, (int64_t)1 << g.m, g.count, g.m, p->d_gen,
-                                        p->d_colshift + (size_t)g.first * p->d, w.P, kd, false,
-                                        p->sched, st));
-    } else {
-      float* c = static_cast<float*>(cols) + p->col_off[g.first];
-      LAUNCH_OK(launch_gen_cols<float, float>(c, (int64_t)1 << g.m, g.count, g.m, p->d_gen,
-                                       p->d_colshift + (size_t)g.first * p->d, w.P, kd, false,
-                                       p->sched, st));
-    }
+    const uint32_t* sh = p->d_colshift + (size_t)g.first * p->d;
+    if (p->precision != MTGP_F32)
+      LAUNCH_OK(launch_raw_cols<double>(static_cast<double*>(cols) + p->col_off[g.first], g.count,
+                                        g.m, p->d_gen, sh, w.P, kd, st));
+    else
+      LAUNCH_OK(launch_raw_cols<float>(static_cast<float*>(cols) + p->col_off[g.first], g.count,
+                                       g.m, p->d_gen, sh, w.P, kd, st));
   }
   return MTGP_OK;
 }

@@ -1,0 +1,87 @@
+// Per-thread generation of kernel-column arguments inside a transform block.
+//
+// A block covers indices i0 + e, e < 2^LB; thread t owns e = t + 256 kk for
+// kk = 0 .. E-1.  The digit of index i0 + t + 256 kk in dimension j splits
+// into a per-thread part a_j (index t) and a part s_j that is the same for
+// the whole block (indices i0 + 256 kk, plus the pair shift):
+//   digital sequences: z(i) is XOR-linear in the bits of i, so
+//     u_j = z_j(t) XOR z_j(i0 + 256 kk) XOR shift_j, and visiting kk in
+//     Gray-code order changes s_j by one generating column per element
+//     (the recursive identity x_{2^p + i} = x_{2^p} XOR x_i of Section
+//     "Algorithm for Gram Matrix Calculations");
+//   lattices (natural order j g / n): u_j = t g 2^(32-m) + (i0 + 256 kk) g
+//     2^(32-m) + shift_j mod 2^32, advanced by one constant per element.
+#pragma once
+#include "kernels.h"
+
+namespace mtgp {
+
+template <int FAM, int D>
+struct Digits {
+  uint32_t a[D];     // per-thread part
+  uint32_t s[D];     // block part of the current element (uniform)
+  uint32_t step[D];  // lattice increment per element (uniform)
+
+  __device__ inline void init(const uint32_t* __restrict__ gen, const uint32_t* __restrict__ sh,
+                              int d, uint32_t t, uint32_t i0, int m) {
+    // every slot is computed from a valid dimension (padding slots reuse
+    // dimension 0) and masked afterwards, so no slot is indexed at run time
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+      const int jj = j < d ? j : 0;
+      const uint32_t keep = j < d ? 0xffffffffu : 0u;
+      if (FAM == FAM_DSEQ) {
+        a[j] = dseq_z(gen + 32 * jj, t) & keep;
+        s[j] = (dseq_z(gen + 32 * jj, i0) ^ sh[jj]) & keep;
+        step[j] = 0;
+      } else {
+        a[j] = lat_z(gen[jj], t, m) & keep;
+        s[j] = (lat_z(gen[jj], i0, m) + sh[jj]) & keep;
+        step[j] = lat_z(gen[jj], 256u, m) & keep;
+      }
+    }
+  }
+  __device__ inline uint32_t u(int j) const { return FAM == FAM_DSEQ ? (a[j] ^ s[j]) : (a[j] + s[j]); }
+  // element offset (in units of 256) visited at step k
+  __device__ static inline int elem(int k) { return FAM == FAM_DSEQ ? (k ^ (k >> 1)) : k; }
+  // move from step k to step k + 1
+  __device__ inline void advance(const uint32_t* __restrict__ gen, int d, int k) {
+    if (FAM == FAM_DSEQ) {
+      const int p = 8 + __ffs(k + 1) - 1;
+#pragma unroll
+      for (int j = 0; j < D; j++)
+        if (j < d) s[j] ^= gen[32 * j + p];
+    } else {
+#pragma unroll
+      for (int j = 0; j < D; j++)
+        if (j < d) s[j] += step[j];
+    }
+  }
+};
+
+// univariate kernel value of a compile-time kernel type
+template <typename Real, int KT>
+__device__ inline Real kval(uint32_t u, const Params* __restrict__ P) {
+  if constexpr (KT == KT_DSIA) {
+    Real k[4];
+    dsi_khat_all<Real>(u, k);
+    return RT<Real>::bw(P, 0) * k[0] + RT<Real>::bw(P, 1) * k[1] + RT<Real>::bw(P, 2) * k[2] +
+           RT<Real>::bw(P, 3) * k[3];
+  } else if constexpr (KT >= KT_SI1) {
+    return si_kern<Real>(KT - 10, u);
+  } else {
+    return dsi_khat_o<Real, KT>(u);
+  }
+}
+
+// dispatch helpers: D in {4, 8, 12, 16, 32}
+#define MTGP_DISPATCH_D(d, MACRO, ...)          \
+  do {                                          \
+    if ((d) <= 4) MACRO(4, __VA_ARGS__);        \
+    else if ((d) <= 8) MACRO(8, __VA_ARGS__);   \
+    else if ((d) <= 12) MACRO(12, __VA_ARGS__); \
+    else if ((d) <= 16) MACRO(16, __VA_ARGS__); \
+    else MACRO(32, __VA_ARGS__);                \
+  } while (0)
+
+}  // namespace mtgp

@@ -89,60 +89,64 @@ __device__ inline double octal_digit_sum(uint32_t u) {
   return (double)hi * 0x1p-60 + (double)lo * 0x1p-93;
 }
 
+// beta(x) = -floor(log2 x) with beta(0) = 0, and t_1(x) = 2^-beta(x) with
+// t_1(0) = 0.  t_1 is the leading power of two of x: x with its mantissa bits
+// cleared (x = 0 stays 0).  In FP32 the digit is converted by truncation so
+// that x never rounds up across a power of two (consistent with beta).
+template <typename Real> __device__ inline Real lead_pow2(Real x);
+template <> __device__ inline double lead_pow2<double>(double x) {
+  return __hiloint2double(__double2hiint(x) & 0x7ff00000, 0);
+}
+template <> __device__ inline float lead_pow2<float>(float x) {
+  return __int_as_float(__float_as_int(x) & 0x7f800000);
+}
+template <typename Real> __device__ inline Real unit_trunc(uint32_t u);
+template <> __device__ inline double unit_trunc<double>(uint32_t u) { return (double)u * 0x1p-32; }
+template <> __device__ inline float unit_trunc<float>(uint32_t u) { return __uint2float_rz(u) * 0x1p-32f; }
+
+__device__ inline int beta_of(uint32_t u) { return u ? __clz(u) + 1 : 0; }
+
 // Khat_alpha(x), x = u 2^-32 (Eq. DSI_kernel_1d_ex), beta(0) = t_nu(0) = 0.
+template <typename Real, int ORDER>
+__device__ inline Real dsi_khat_o(uint32_t u) {
+  const Real x = unit_trunc<Real>(u);
+  const Real t1 = lead_pow2<Real>(x);
+  if (ORDER == 1) return fma((Real)-3, t1, (Real)1);
+  const Real b = (Real)beta_of(u);
+  if (ORDER == 2) return fma(-b, x, fma((Real)-2.5, t1, (Real)1.5));
+  const Real t2 = t1 * t1;
+  if (ORDER == 3)
+    return (Real)-1 + b * x * x - (Real)5 * ((Real)1 - t1) * x + (Real)(43.0 / 18.0) * ((Real)1 - t2);
+  const Real t3 = t2 * t1;
+  const Real s = (Real)(8.0 / 7.0) - (Real)2 * (Real)octal_digit_sum(u);
+  return (Real)-1 - (Real)(2.0 / 3.0) * b * x * x * x + (Real)5 * ((Real)1 - t1) * x * x -
+         (Real)(43.0 / 9.0) * ((Real)1 - t2) * x + (Real)(701.0 / 294.0) * ((Real)1 - t3) +
+         b * (s * (Real)(1.0 / 48.0) - (Real)(1.0 / 42.0));
+}
+
 template <typename Real>
 __device__ inline Real dsi_khat(int order, uint32_t u) {
-  const int beta = __clz(u) + 1;          // -floor(log2 x) for u != 0
-  const Real x = RT<Real>::unit(u);
-  const Real b = (Real)beta;
-  const Real t1 = RT<Real>::pow2neg(beta);
-  Real r, z;
   switch (order) {
-    case 1:
-      r = (Real)1 - (Real)3 * t1;
-      z = (Real)1;
-      break;
-    case 2:
-      r = fma(-b, x, fma((Real)-2.5, t1, (Real)1.5));
-      z = (Real)1.5;
-      break;
-    case 3: {
-      const Real t2 = t1 * t1;
-      r = (Real)-1 + b * x * x - (Real)5 * ((Real)1 - t1) * x + (Real)(43.0 / 18.0) * ((Real)1 - t2);
-      z = (Real)(25.0 / 18.0);
-      break;
-    }
-    default: {
-      const Real t2 = t1 * t1, t3 = t2 * t1;
-      const Real s = (Real)(8.0 / 7.0) - (Real)2 * (Real)octal_digit_sum(u);
-      r = (Real)-1 - (Real)(2.0 / 3.0) * b * x * x * x + (Real)5 * ((Real)1 - t1) * x * x -
-          (Real)(43.0 / 9.0) * ((Real)1 - t2) * x + (Real)(701.0 / 294.0) * ((Real)1 - t3) +
-          b * (s * (Real)(1.0 / 48.0) - (Real)(1.0 / 42.0));
-      z = (Real)(407.0 / 294.0);
-      break;
-    }
+    case 1: return dsi_khat_o<Real, 1>(u);
+    case 2: return dsi_khat_o<Real, 2>(u);
+    case 3: return dsi_khat_o<Real, 3>(u);
+    default: return dsi_khat_o<Real, 4>(u);
   }
-  return u == 0u ? z : r;
 }
 
 // all four Khat_alpha at once (adaptive kernel), sharing beta, x, t_nu
 template <typename Real>
 __device__ inline void dsi_khat_all(uint32_t u, Real k[4]) {
-  const int beta = __clz(u) + 1;
-  const Real x = RT<Real>::unit(u);
-  const Real b = (Real)beta;
-  const Real t1 = RT<Real>::pow2neg(beta), t2 = t1 * t1, t3 = t2 * t1;
+  const Real x = unit_trunc<Real>(u);
+  const Real b = (Real)beta_of(u);
+  const Real t1 = lead_pow2<Real>(x), t2 = t1 * t1, t3 = t2 * t1;
   const Real s = (Real)(8.0 / 7.0) - (Real)2 * (Real)octal_digit_sum(u);
-  const bool zero = (u == 0u);
-  k[0] = zero ? (Real)1 : (Real)1 - (Real)3 * t1;
-  k[1] = zero ? (Real)1.5 : fma(-b, x, fma((Real)-2.5, t1, (Real)1.5));
-  k[2] = zero ? (Real)(25.0 / 18.0)
-              : (Real)-1 + b * x * x - (Real)5 * ((Real)1 - t1) * x +
-                    (Real)(43.0 / 18.0) * ((Real)1 - t2);
-  k[3] = zero ? (Real)(407.0 / 294.0)
-              : (Real)-1 - (Real)(2.0 / 3.0) * b * x * x * x + (Real)5 * ((Real)1 - t1) * x * x -
-                    (Real)(43.0 / 9.0) * ((Real)1 - t2) * x + (Real)(701.0 / 294.0) * ((Real)1 - t3) +
-                    b * (s * (Real)(1.0 / 48.0) - (Real)(1.0 / 42.0));
+  k[0] = fma((Real)-3, t1, (Real)1);
+  k[1] = fma(-b, x, fma((Real)-2.5, t1, (Real)1.5));
+  k[2] = (Real)-1 + b * x * x - (Real)5 * ((Real)1 - t1) * x + (Real)(43.0 / 18.0) * ((Real)1 - t2);
+  k[3] = (Real)-1 - (Real)(2.0 / 3.0) * b * x * x * x + (Real)5 * ((Real)1 - t1) * x * x -
+         (Real)(43.0 / 9.0) * ((Real)1 - t2) * x + (Real)(701.0 / 294.0) * ((Real)1 - t3) +
+         b * (s * (Real)(1.0 / 48.0) - (Real)(1.0 / 42.0));
 }
 
 // (-1)^(alpha+1) (2 pi)^(2 alpha) / (2 alpha)! B_{2 alpha}(x) (Eq. SI_kernel_1d_ex)
@@ -166,6 +170,16 @@ template <typename Real, int FAM>
 __device__ inline Real univ(int order, uint32_t u) {
   if (FAM == FAM_DSEQ) return dsi_khat<Real>(order, u);
   return si_kern<Real>(order, u);
+}
+
+// Kernel types known at compile time: DSI orders 1..4, the adaptive DSI
+// kernel, SI orders 1..3.
+enum KType { KT_DSI1 = 1, KT_DSI2 = 2, KT_DSI3 = 3, KT_DSI4 = 4, KT_DSIA = 5,
+             KT_SI1 = 11, KT_SI2 = 12, KT_SI3 = 13 };
+__host__ __device__ constexpr int kt_family(int kt) { return kt >= 11 ? FAM_LAT : FAM_DSEQ; }
+__host__ inline int kt_of(int family, int order, int adaptive) {
+  if (family == FAM_LAT) return 10 + order;
+  return adaptive ? KT_DSIA : order;
 }
 
 // ---------------------------------------------------------------------------
@@ -195,12 +209,13 @@ __device__ inline int lds_at(int seq, int stride, int i) { return seq * stride +
 // Butterflies over bits [lo, lo + R) of every one of nseq sequences.
 template <typename Real, int R>
 __device__ inline void lds_round(Real* lds, int nseq, int L, int lo, int stride) {
-  const int per_seq = 1 << (L - R);
-  const int total = nseq * per_seq;
+  const int ps_bits = L - R;  // groups per sequence = 2^ps_bits
+  const int total = nseq << ps_bits;
   const int lo_mask = (1 << lo) - 1;
+  const int q_mask = (1 << ps_bits) - 1;
   for (int g = threadIdx.x; g < total; g += blockDim.x) {
-    const int seq = g / per_seq;
-    const int q = g - seq * per_seq;
+    const int seq = g >> ps_bits;
+    const int q = g & q_mask;
     const int base = (q & lo_mask) | ((q >> lo) << (lo + R));
     Real v[1 << R];
 #pragma unroll
@@ -258,6 +273,28 @@ __device__ inline double block_sum(double v, double* red) {
   double s = 0.0;
   for (int i = 0; i < nw; i++) s += red[i];
   return s;
+}
+
+// Block reduction of NQ values per thread (q < nq used).  One barrier:
+// each wave reduces in registers, lane 0 stores to red[wave][NQ], and the
+// first nq threads add the per-wave rows in a fixed order (deterministic).
+// `red` holds (blockDim.x / 64) * NQ doubles.
+template <int NQ>
+__device__ inline void block_sum_store(const double* vals, int nq, double* red, double* out) {
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    if (q < nq) {
+      const double v = wave_sum(vals[q]);
+      if ((threadIdx.x & 63) == 0) red[w * NQ + q] = v;
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < nw; i++) s += red[i * NQ + q];
+    out[q] = s;
+  }
 }
 
 }  // namespace mtgp

@@ -49,29 +49,40 @@ size_t gen_cols_lds_bytes(int LB, int real_bytes);
 template <typename Real>
 int launch_fwht(Real* base, int64_t vec_stride, int64_t nvec, int m, const Sched& sc,
                 hipStream_t st);
-template <typename TIn, typename TOut>
-int launch_fwht_high(TIn* work, TOut* out, int64_t vec_stride, int64_t nvec, int m,
-                     const Sched& sc, hipStream_t st);
+// passes over bits [lb(m), m): first pass reads `first`, last writes `last`,
+// intermediates in `work` (arithmetic in TC)
+template <typename TC, typename TIn, typename TOut>
+int launch_strided(const TIn* first, TC* work, TOut* last, int64_t vec_stride, int64_t nvec,
+                   int m, const Sched& sc, hipStream_t st);
+// kernel columns generated and transformed over the low index bits
 template <typename Real, typename TOut>
-int launch_gen_cols(TOut* base, int64_t col_stride, int ncols, int m, const uint32_t* gen,
-                    const uint32_t* colshift, const Params* P, const KDesc& kd, bool do_fwht,
-                    const Sched& sc, hipStream_t st);
+int launch_gen_fwd(TOut* base, int64_t col_stride, int ncols, int m, const uint32_t* gen,
+                   const uint32_t* colshift, const Params* P, const KDesc& kd, const Sched& sc,
+                   hipStream_t st);
+template <typename Real>
+int launch_raw_cols(Real* base, int ncols, int m, const uint32_t* gen, const uint32_t* colshift,
+                    const Params* P, const KDesc& kd, hipStream_t st);
 template <typename Real>
 int launch_scale(Real* x, int64_t n, Real s, hipStream_t st);
 
 // ---- adjoint.hip
 // Number of FP64 partial sums written per block by the derivative reduction.
 __host__ __device__ inline int adj_nq(int d) { return d + 5; }
-template <typename Real>
-int launch_adj_reduce(const Real* base, int64_t col_stride, int ncols, int m, const uint32_t* gen,
+template <typename Real, typename TIn>
+int launch_adj_reduce(const TIn* base, int64_t col_stride, int ncols, int m, const uint32_t* gen,
                       const uint32_t* colshift, const Params* P, const KDesc& kd, double* partials,
                       const Sched& sc, hipStream_t st);
 
 // ---- solve.hip
 int launch_prep(const double* theta, Params* P, const KDesc& kd, int* status, hipStream_t st);
 // number of FP64 partial sums per block of the equal-size solve
-__host__ __device__ inline int solve_ns(int T) { return 2 + T * (T + 1) / 2 + T + T; }
-constexpr int SOLVE_BLOCKS = 1024;
+// T padded to the factorisation template size, and the partial-sum layout size
+__host__ __device__ inline int solve_tm(int T) { return T <= 1 ? 1 : T <= 2 ? 2 : T <= 4 ? 4 : T <= 8 ? 8 : 16; }
+__host__ __device__ inline int solve_ns(int T) {
+  const int tm = solve_tm(T);
+  return 2 + tm * (tm + 1) / 2 + 2 * tm;
+}
+inline int64_t solve_blocks(int64_t n) { return (n + 255) / 256; }
 template <typename Real>
 int launch_solve_eq(Real* cols, int64_t n, const PairMap& pm, int ncol, const double* yhat,
                     const Params* P, const KDesc& kd, bool grad, double* partials, double* ahat,

@@ -66,6 +66,14 @@ __device__ constexpr int pk(int i, int j) {
   return i * (i + 1) / 2 + j;
 }
 
+// One thread per frequency f (grid ceil(n/256) x 256).  Lambda(f) = L D L^T
+// (unit lower L, FP64): log det = sum log D_j, quad = sum z_j^2 / D_j with
+// L z = rhat, ahat = L^-T (z / D), Lambda^-1 = L^-T D^-1 L^-1; eight
+// reciprocals and no square roots per frequency.  Per-block sums go to
+// partials[block][solve_ns(T)] with TM = solve_tm(T) (T padded to 1/2/4/8/16):
+//   [0] quad, [1] log det, [2 + pk(u,t)] G_tu = sum W_tu lambda_tu (t <= u),
+//   [2 + TM(TM+1)/2 + t] sum W_tt, [2 + TM(TM+1)/2 + TM + t] ahat_t(0)
+//   (nonzero in block 0 only).
 template <typename Real, int TM, bool GRAD>
 __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, int64_t n,
                                                        PairMap pm, const double* __restrict__ yhat,
@@ -73,88 +81,87 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
                                                        double* __restrict__ partials,
                                                        double* __restrict__ ahat,
                                                        int* __restrict__ status) {
-  __shared__ double red[16];
   constexpr int NP = TM * (TM + 1) / 2;
+  constexpr int NQ = 2 + NP + 2 * TM;
+  __shared__ double red[4 * NQ];
   const int T = kd.T;
-  const double sqn = sqrt((double)n);
-  double acc_quad = 0.0, acc_ld = 0.0;
-  double accG[GRAD ? NP : 1];
-  double accX[GRAD ? TM : 1];
-  double acc_a0[TM];
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool active = f < n;
+  double vals[NQ];
 #pragma unroll
-  for (int q = 0; q < (GRAD ? NP : 1); q++) accG[q] = 0.0;
-#pragma unroll
-  for (int q = 0; q < (GRAD ? TM : 1); q++) accX[q] = 0.0;
-#pragma unroll
-  for (int q = 0; q < TM; q++) acc_a0[q] = 0.0;
-
-  for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < n;
-       f += (int64_t)gridDim.x * blockDim.x) {
-    double lam[NP], A[NP], r[TM];
+  for (int q = 0; q < NQ; q++) vals[q] = 0.0;
+  if (active) {
+    Real lam[NP];
+    double A[NP], r[TM];
 #pragma unroll
     for (int i = 0; i < TM; i++) {
 #pragma unroll
       for (int j = 0; j <= i; j++) {
         if (i < T) {
-          const double l = (double)cols[(int64_t)pm.col[j][i] * n + f];
+          const Real l = cols[(int64_t)pm.col[j][i] * n + f];
           lam[pk<TM>(i, j)] = l;
-          A[pk<TM>(i, j)] = P->R[j * MTGP_MAXT + i] * l + (i == j ? P->xi[i] : 0.0);
+          A[pk<TM>(i, j)] = P->R[j * MTGP_MAXT + i] * (double)l + (i == j ? P->xi[i] : 0.0);
         } else {
-          lam[pk<TM>(i, j)] = 0.0;
+          lam[pk<TM>(i, j)] = 0;
           A[pk<TM>(i, j)] = (i == j) ? 1.0 : 0.0;
         }
       }
       if (i < T) {
         double y = yhat[(int64_t)i * n + f];
-        if (f == 0) y = kd.profile ? 0.0 : y - sqn * P->tau[i];
+        if (f == 0) y = kd.profile ? 0.0 : y - sqrt((double)n) * P->tau[i];
         r[i] = y;
       } else {
         r[i] = 0.0;
       }
     }
-    // Cholesky A = L L^T in place (lower, packed)
-    bool ok = true;
+    // L D L^T in place: strictly lower part of A becomes L
+    double invD[TM];
     double prod = 1.0;
+    bool ok = true;
 #pragma unroll
     for (int j = 0; j < TM; j++) {
-      double s = A[pk<TM>(j, j)];
+      double u[TM];
+      double dj = A[pk<TM>(j, j)];
 #pragma unroll
-      for (int k = 0; k < j; k++) s -= A[pk<TM>(j, k)] * A[pk<TM>(j, k)];
-      ok = ok && (s > 0.0);
-      const double l = sqrt(s);
-      const double il = 1.0 / l;
-      A[pk<TM>(j, j)] = l;
-      prod *= l;
+      for (int k = 0; k < j; k++) {
+        u[k] = A[pk<TM>(j, k)] / invD[k];  // L_jk D_k
+        dj -= A[pk<TM>(j, k)] * u[k];
+      }
+      ok = ok && (dj > 0.0);
+      prod *= dj;
+      invD[j] = 1.0 / dj;
 #pragma unroll
       for (int i = j + 1; i < TM; i++) {
         double v = A[pk<TM>(i, j)];
 #pragma unroll
-        for (int k = 0; k < j; k++) v -= A[pk<TM>(i, k)] * A[pk<TM>(j, k)];
-        A[pk<TM>(i, j)] = v * il;
+        for (int k = 0; k < j; k++) v -= A[pk<TM>(i, k)] * u[k];
+        A[pk<TM>(i, j)] = v * invD[j];
       }
     }
     if (!ok || !isfinite(prod)) flag_bad(status, f);
-    acc_ld += 2.0 * log(prod);
-    // L z = r, quad = z^T z, L^T a = z
+    vals[1] = log(prod);
+    // L z = r; quad = sum z^2 / D; L^T a = z / D
     double a[TM];
+    double quad = 0.0;
 #pragma unroll
     for (int i = 0; i < TM; i++) {
       double v = r[i];
 #pragma unroll
       for (int k = 0; k < i; k++) v -= A[pk<TM>(i, k)] * a[k];
-      a[i] = v / A[pk<TM>(i, i)];
-      acc_quad += a[i] * a[i];
+      a[i] = v;
+      quad += v * v * invD[i];
     }
+    vals[0] = quad;
 #pragma unroll
     for (int i = TM - 1; i >= 0; i--) {
-      double v = a[i];
+      double v = a[i] * invD[i];
 #pragma unroll
       for (int k = i + 1; k < TM; k++) v -= A[pk<TM>(k, i)] * a[k];
-      a[i] = v / A[pk<TM>(i, i)];
+      a[i] = v;
     }
     if (f == 0) {
 #pragma unroll
-      for (int i = 0; i < TM; i++) acc_a0[i] = a[i];
+      for (int i = 0; i < TM; i++) vals[2 + NP + TM + i] = a[i];
     }
     if (ahat) {
 #pragma unroll
@@ -162,31 +169,31 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
         if (i < T) ahat[(int64_t)i * n + f] = a[i];
     }
     if (GRAD) {
-      // X = L^-1 in place
+      // X = L^-1 (unit lower) in place, row by row
 #pragma unroll
-      for (int i = 0; i < TM; i++) {
+      for (int i = 1; i < TM; i++) {
 #pragma unroll
         for (int j = 0; j < i; j++) {
-          double s = 0.0;
+          double v = A[pk<TM>(i, j)];
 #pragma unroll
-          for (int k = j; k < i; k++) s += A[pk<TM>(i, k)] * A[pk<TM>(k, j)];
-          A[pk<TM>(i, j)] = -s / A[pk<TM>(i, i)];
+          for (int k = j + 1; k < i; k++) v += A[pk<TM>(i, k)] * A[pk<TM>(k, j)];
+          A[pk<TM>(i, j)] = -v;
         }
-        A[pk<TM>(i, i)] = 1.0 / A[pk<TM>(i, i)];
       }
       double wdiag = 0.0;
 #pragma unroll
       for (int u = 0; u < TM; u++) {
 #pragma unroll
         for (int t = 0; t <= u; t++) {
-          double s = 0.0;
+          // (Lambda^-1)_tu = sum_{k >= u} X_kt X_ku / D_k, with X_kk = 1
+          double v = (t == u ? 1.0 : A[pk<TM>(u, t)]) * invD[u];
 #pragma unroll
-          for (int k = u; k < TM; k++) s += A[pk<TM>(k, t)] * A[pk<TM>(k, u)];
-          const double w = s - a[t] * a[u];
+          for (int k = u + 1; k < TM; k++) v += A[pk<TM>(k, t)] * A[pk<TM>(k, u)] * invD[k];
+          const double w = v - a[t] * a[u];
           if (u < T) {
-            accG[pk<TM>(u, t)] += w * lam[pk<TM>(u, t)];
+            vals[2 + pk<TM>(u, t)] = w * (double)lam[pk<TM>(u, t)];
             if (t == u) {
-              accX[t] += w;
+              vals[2 + NP + t] = w;
               wdiag += P->R[t * MTGP_MAXT + t] * w;
             } else {
               cols[(int64_t)pm.col[t][u] * n + f] = (Real)(2.0 * P->R[t * MTGP_MAXT + u] * w);
@@ -197,44 +204,7 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
       cols[(int64_t)pm.col[0][0] * n + f] = (Real)wdiag;
     }
   }
-  // block reductions -> partials[block][ns]
-  const int ns = solve_ns(T);
-  double* out = partials + (size_t)blockIdx.x * ns;
-  double v = block_sum(acc_quad, red);
-  if (threadIdx.x == 0) out[0] = v;
-  v = block_sum(acc_ld, red);
-  if (threadIdx.x == 0) out[1] = v;
-  int q = 2;
-  if (GRAD) {
-#pragma unroll
-    for (int u = 0; u < TM; u++) {
-#pragma unroll
-      for (int t = 0; t <= u; t++) {
-        if (u < T) {
-          v = block_sum(accG[pk<TM>(u, t)], red);
-          if (threadIdx.x == 0) out[2 + pk<TM>(u, t)] = v;
-        }
-      }
-    }
-  }
-  q = 2 + T * (T + 1) / 2;
-#pragma unroll
-  for (int t = 0; t < TM; t++) {
-    if (t < T) {
-      v = GRAD ? block_sum(accX[GRAD ? t : 0], red) : 0.0;
-      if (threadIdx.x == 0) out[q + t] = v;
-    }
-  }
-  q += T;
-#pragma unroll
-  for (int t = 0; t < TM; t++) {
-    if (t < T) {
-      v = block_sum(acc_a0[t], red);
-      if (threadIdx.x == 0) out[q + t] = v;
-    }
-  }
-  if (!GRAD && threadIdx.x == 0)
-    for (int i = 2; i < 2 + T * (T + 1) / 2; i++) out[i] = 0.0;
+  block_sum_store<NQ>(vals, NQ, red, partials + (size_t)blockIdx.x * NQ);
 }
 
 template <typename Real>
@@ -242,7 +212,7 @@ int launch_solve_eq(Real* cols, int64_t n, const PairMap& pm, int ncol, const do
                     const Params* P, const KDesc& kd, bool grad, double* partials, double* ahat,
                     int* status, hipStream_t st) {
   (void)ncol;
-  dim3 grid(SOLVE_BLOCKS), block(256);
+  const dim3 grid((unsigned)solve_blocks(n)), block(256);
 #define MTGP_SOLVE(TMV)                                                                          \
   do {                                                                                           \
     if (grad)                                                                                    \
@@ -303,7 +273,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   out3[1] = logdet;
   out3[2] = quad + logdet;
   const double sqn = sqrt((double)n);
-  const int qX = 2 + T * (T + 1) / 2, qA = qX + T;
+  const int TMp = solve_tm(T);
+  const int qX = 2 + TMp * (TMp + 1) / 2, qA = qX + TMp;
   for (int t = 0; t < T; t++) {
     const double tu = kd.profile ? yhat[(int64_t)t * n] / sqn : P->tau[t];
     P->tau_used[t] = tu;
