@@ -113,7 +113,7 @@ int mtgp_plan_destroy(mtgp_plan* plan);
  * passes over at most pass_b_bits (1..12) further bits each, with an LDS
  * tile of about pass_b_tile_bytes (4096..147456).  Changes
  * mtgp_workspace_bytes, so call it before sizing the workspace.  Defaults:
- * 13, 11, 73728. */
+ * 12, 6, 36864 (measured best on MI355X for 2^24-point columns). */
 int mtgp_plan_set_schedule(mtgp_plan* plan, int32_t pass_a_bits, int32_t pass_b_bits,
                            int64_t pass_b_tile_bytes);
 
@@ -170,12 +170,15 @@ int mtgp_kernel_cols(const mtgp_plan* plan, const double* theta, void* cols, voi
 int mtgp_fwht(void* x, int64_t batch, int32_t log2n, int32_t dtype, void* stream);
 
 /* Unnormalised forward DFT X_f = sum_j x_j e^{-2 pi i f j / n} of `batch`
- * contiguous real vectors of length n = 2^log2n into complex outputs
- * (interleaved re, im; X has batch * n complex entries).  If bitrev_input is
- * nonzero the input is first read in bit-reversed order, i.e. the transform
- * is the V^dagger of Theorem "Fast GP computations" for lattices times
- * sqrt(n).  dtype as for mtgp_fwht; 0 <= log2n <= 30. */
-int mtgp_fft(const void* x, void* X, int64_t batch, int32_t log2n, int32_t dtype,
+ * contiguous real vectors of length n = 2^log2n into complex outputs in
+ * natural frequency order (interleaved re, im; X has batch * n complex
+ * entries).  If bitrev_input is nonzero the input is first read in
+ * bit-reversed order, i.e. the transform is the V^dagger of Theorem "Fast GP
+ * computations" for lattices times sqrt(n).  dtype as for mtgp_fwht;
+ * 0 <= log2n <= 21, batch <= 65535.  For log2n > 12 the two-pass transform
+ * needs `scratch` with room for batch * n complex values of dtype (else it
+ * may be NULL). */
+int mtgp_fft(const void* x, void* X, void* scratch, int64_t batch, int32_t log2n, int32_t dtype,
              int32_t bitrev_input, void* stream);
 
 /* Transforms the data once per data set: yhat_t = V^dagger_{m_t} y_t

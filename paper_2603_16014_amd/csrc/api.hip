@@ -51,8 +51,8 @@ struct mtgp_plan {
   uint32_t* d_colshift = nullptr;
   uint32_t* d_taskshift = nullptr;
   // workspace layout (byte offsets)
-  size_t o_params, o_status, o_cols, o_work, o_yhat, o_ahat, o_sp, o_sp2, o_ap, o_ap2, o_misc,
-      ws_bytes;
+  size_t o_params, o_status, o_cols, o_work, o_yhat, o_ahat, o_sp, o_sp2, o_ap, o_ap2, o_alpha,
+      o_pwork, o_misc, ws_bytes;
   int nadj_blocks;
   int64_t cols_elems;
   size_t real_bytes;  // bytes of a stored spectrum / adjoint value
@@ -98,6 +98,8 @@ struct WsView {
   double* sp2;
   double* ap;
   double* ap2;
+  double* alpha;
+  double* pwork;
   double* misc;
 };
 
@@ -114,6 +116,8 @@ WsView view(const mtgp_plan* p, void* ws) {
   v.sp2 = reinterpret_cast<double*>(b + p->o_sp2);
   v.ap = reinterpret_cast<double*>(b + p->o_ap);
   v.ap2 = reinterpret_cast<double*>(b + p->o_ap2);
+  v.alpha = reinterpret_cast<double*>(b + p->o_alpha);
+  v.pwork = reinterpret_cast<double*>(b + p->o_pwork);
   v.misc = reinterpret_cast<double*>(b + p->o_misc);
   return v;
 }
@@ -154,6 +158,41 @@ int run_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
   return MTGP_OK;
 }
 
+// Lattice family (equal sizes): DFT transforms in the four-step layout, the
+// Hermitian per-frequency solve, the DFT adjoint fused with the reduction.
+template <typename CR, typename SR>
+int run_loss_lat(const mtgp_plan* p, const WsView& w, double* out3, double* grad, double* tau_hat,
+                 hipStream_t st, bool want_ahat) {
+  const KDesc kd = p->kd();
+  const int m = p->m[0];
+  const int64_t n = p->n[0];
+  cx<SR>* spec = reinterpret_cast<cx<SR>*>(w.cols);
+  cx<CR>* work = reinterpret_cast<cx<CR>*>(w.work);
+  mark(p, 1, st);
+  LAUNCH_OK(launch_lat_forward<CR, SR>(LAT_SRC_GEN, work, spec, n, p->ncol, m, nullptr, 0, 1.0,
+                                       p->d_gen, p->d_colshift, w.P, kd, st));
+  mark(p, 2, st);
+  mark(p, 3, st);
+  LAUNCH_OK(launch_solve_eq_c<SR>(reinterpret_cast<SR*>(w.cols), n, p->pm, w.yhat, w.P, kd,
+                                  grad != nullptr, w.sp, want_ahat ? w.ahat : nullptr, w.status,
+                                  st));
+  mark(p, 4, st);
+  mark(p, 5, st);
+  int nadj = 0;
+  if (grad) {
+    LAUNCH_OK(launch_lat_adjoint<CR, SR>(LAT_SINK_REDUCE, spec, work, nullptr, n, p->ncol, m, 0, 1.0,
+                                         p->d_gen, p->d_colshift, w.P, kd, w.ap, st));
+    nadj = lat_adj_blocks(m, sizeof(cx<CR>)) * p->ncol;
+    LAUNCH_OK(launch_colsum(w.ap, nadj, adj_nq(p->d), w.ap2, COLSUM_BLOCKS, st));
+  }
+  LAUNCH_OK(launch_colsum(w.sp, solve_blocks(n), solve_ns(p->T), w.sp2, COLSUM_BLOCKS, st));
+  mark(p, 6, st);
+  LAUNCH_OK(launch_finalize(w.sp2, COLSUM_BLOCKS, grad ? w.ap2 : nullptr, COLSUM_BLOCKS, w.yhat, n,
+                            w.P, kd, out3, grad, tau_hat, st));
+  mark(p, 7, st);
+  return MTGP_OK;
+}
+
 // Loss (and gradient): columns and transforms in CR arithmetic, spectrum and
 // adjoint weights stored as SR, adjoint transform arithmetic in CR.
 template <typename CR, typename SR>
@@ -163,6 +202,7 @@ int run_loss(const mtgp_plan* p, const double* theta, double* out3, double* grad
   const KDesc kd = p->kd();
   mark(p, 0, st);
   LAUNCH_OK(launch_prep(theta, w.P, kd, w.status, st));
+  if (p->family == MTGP_LAT) return run_loss_lat<CR, SR>(p, w, out3, grad, tau_hat, st, want_ahat);
   int rc = run_columns<CR, SR>(p, w, st);
   if (rc) return rc;
   SR* spec = reinterpret_cast<SR*>(w.cols);
@@ -218,25 +258,37 @@ int dispatch_loss(const mtgp_plan* p, const double* theta, double* out3, double*
 // the adjoint reduction.
 void layout(mtgp_plan* p) {
   const int T = p->T, d = p->d;
+  const size_t cplx = p->family == MTGP_LAT ? 2 : 1;
   size_t o = 0;
   p->o_params = o;
   o = align_up(o + sizeof(Params));
   p->o_status = o;
   o = align_up(o + 64);
   p->o_cols = o;
-  o = align_up(o + (size_t)p->cols_elems * p->real_bytes);
+  o = align_up(o + (size_t)p->cols_elems * p->real_bytes * cplx);
   p->o_work = o;
-  o = align_up(o + (size_t)p->cols_elems * p->work_bytes);
+  o = align_up(o + (size_t)p->cols_elems * p->work_bytes * cplx);
   p->o_yhat = o;
-  o = align_up(o + (size_t)p->N * sizeof(double));
+  o = align_up(o + (size_t)p->N * sizeof(double) * cplx);
   p->o_ahat = o;
-  o = align_up(o + (size_t)p->N * sizeof(double));
+  o = align_up(o + (size_t)p->N * sizeof(double) * cplx);
+  p->o_alpha = o;
+  o = align_up(o + (cplx == 2 ? (size_t)p->N * sizeof(double) : 0));
+  p->o_pwork = o;
+  o = align_up(o + (cplx == 2 ? (size_t)p->N * 2 * sizeof(double) : 0));
   p->o_sp = o;
   o = align_up(o + (size_t)solve_blocks(p->n[p->T - 1]) * solve_ns(T) * sizeof(double));
   p->o_sp2 = o;
   o = align_up(o + (size_t)COLSUM_BLOCKS * solve_ns(T) * sizeof(double));
   p->nadj_blocks = 0;
-  for (const auto& g : p->groups) p->nadj_blocks += (1 << (g.m - p->sched.lb(g.m))) * g.count;
+  for (const auto& g : p->groups) {
+    if (p->family == MTGP_LAT)
+      p->nadj_blocks += lat_adj_blocks(g.m, p->precision == MTGP_F32 ? sizeof(cx<float>)
+                                                                      : sizeof(cx<double>)) *
+                        g.count;
+    else
+      p->nadj_blocks += (1 << (g.m - p->sched.lb(g.m))) * g.count;
+  }
   p->o_ap = o;
   o = align_up(o + (size_t)p->nadj_blocks * adj_nq(d) * sizeof(double));
   p->o_ap2 = o;
@@ -304,6 +356,10 @@ int mtgp_plan_create(const mtgp_design* des, int32_t precision, mtgp_plan** out)
   const int gl = des->family == MTGP_DSEQ ? 32 : 1;
   p->gen.assign(des->gen, des->gen + (size_t)gl * des->d);
   p->shift.assign(des->shift, des->shift + (size_t)des->T * des->d);
+  if (p->family == MTGP_LAT && p->m[0] > 21) {  // two DFT passes of <= 2^12 and <= 2^9
+    delete p;
+    return MTGP_ENOTSUP;
+  }
   if (!p->equal) {  // nested unequal sizes are handled by a later stage of the build
     delete p;
     return MTGP_ENOTSUP;
@@ -466,17 +522,46 @@ int mtgp_fwht(void* x, int64_t batch, int32_t log2n, int32_t dtype, void* stream
   return MTGP_OK;
 }
 
-int mtgp_fft(const void* x, void* X, int64_t batch, int32_t log2n, int32_t dtype,
+int mtgp_fft(const void* x, void* X, void* scratch, int64_t batch, int32_t log2n, int32_t dtype,
              int32_t bitrev_input, void* stream) {
-  (void)x; (void)X; (void)batch; (void)log2n; (void)dtype; (void)bitrev_input; (void)stream;
-  return MTGP_ENOTSUP;
+  if (!x || !X || batch < 0 || batch > 65535 || log2n < 0 || log2n > 21) return MTGP_EINVAL;
+  if (log2n > 12 && !scratch) return MTGP_EINVAL;
+  if (dtype != MTGP_DTYPE_F64 && dtype != MTGP_DTYPE_F32) return MTGP_EINVAL;
+  if (batch == 0) return MTGP_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const int src = bitrev_input ? LAT_SRC_Y : LAT_SRC_X;
+  const int64_t n = (int64_t)1 << log2n;
+  KDesc kd{};
+  kd.family = FAM_LAT;
+  kd.order = 1;
+  const int f32 = dtype == MTGP_DTYPE_F32;
+  // single pass: natural order directly into X; two passes: layout in scratch, then X
+  void* spec = log2n > 12 ? scratch : X;
+  if (f32)
+    LAUNCH_OK(launch_lat_forward<float, float>(src, static_cast<cx<float>*>(spec),
+                                               static_cast<cx<float>*>(spec), n, (int)batch, log2n,
+                                               x, 1, 1.0, nullptr, nullptr, nullptr, kd, st));
+  else
+    LAUNCH_OK(launch_lat_forward<double, double>(src, static_cast<cx<double>*>(spec),
+                                                 static_cast<cx<double>*>(spec), n, (int)batch,
+                                                 log2n, x, 0, 1.0, nullptr, nullptr, nullptr, kd, st));
+  if (log2n > 12) LAUNCH_OK(launch_lat_natural(scratch, f32, X, batch, log2n, st));
+  return MTGP_OK;
 }
 
 int mtgp_set_data(const mtgp_plan* p, const double* y, void* ws, void* stream) {
   if (!p || !y || !ws) return MTGP_EINVAL;
-  if (p->family != MTGP_DSEQ) return MTGP_ENOTSUP;
   hipStream_t st = (hipStream_t)stream;
   const WsView w = view(p, ws);
+  if (p->family == MTGP_LAT) {
+    // yhat_t = n^-1/2 F (bit reversal of y_t), in the spectrum layout
+    const KDesc kd = p->kd();
+    LAUNCH_OK(launch_lat_forward<double, double>(
+        LAT_SRC_Y, reinterpret_cast<cx<double>*>(w.pwork), reinterpret_cast<cx<double>*>(w.yhat),
+        p->n[0], p->T, p->m[0], y, 0, 1.0 / std::sqrt((double)p->n[0]), nullptr, nullptr, nullptr,
+        kd, st));
+    return MTGP_OK;
+  }
   HIP_OK(hipMemcpyAsync(w.yhat, y, (size_t)p->N * sizeof(double), hipMemcpyDeviceToDevice, st));
   for (int t = 0; t < p->T; t++) {
     LAUNCH_OK(launch_fwht<double>(w.yhat + p->off[t], p->n[t], 1, p->m[t], p->sched, st));
@@ -488,31 +573,39 @@ int mtgp_set_data(const mtgp_plan* p, const double* y, void* ws, void* stream) {
 int mtgp_nll(const mtgp_plan* p, const double* theta, double* out3, double* tau_hat, void* ws,
              void* stream) {
   if (!p || !theta || !out3 || !ws) return MTGP_EINVAL;
-  if (p->family != MTGP_DSEQ) return MTGP_ENOTSUP;
-  hipStream_t st = (hipStream_t)stream;
+    hipStream_t st = (hipStream_t)stream;
   return dispatch_loss(p, theta, out3, nullptr, tau_hat, ws, st, false);
 }
 
 int mtgp_nll_grad(const mtgp_plan* p, const double* theta, double* out3, double* grad,
                   double* tau_hat, void* ws, void* stream) {
   if (!p || !theta || !out3 || !grad || !ws) return MTGP_EINVAL;
-  if (p->family != MTGP_DSEQ) return MTGP_ENOTSUP;
-  hipStream_t st = (hipStream_t)stream;
+    hipStream_t st = (hipStream_t)stream;
   return dispatch_loss(p, theta, out3, grad, tau_hat, ws, st, false);
 }
 
 int mtgp_predict(const mtgp_plan* p, const double* theta, const uint32_t* xs, int64_t M,
                  double* mean, void* ws, void* stream) {
   if (!p || !theta || !ws || M < 0 || (M > 0 && (!xs || !mean))) return MTGP_EINVAL;
-  if (p->family != MTGP_DSEQ) return MTGP_ENOTSUP;
-  hipStream_t st = (hipStream_t)stream;
+    hipStream_t st = (hipStream_t)stream;
   const WsView w = view(p, ws);
   int rc = dispatch_loss(p, theta, w.misc, nullptr, nullptr, ws, st, true);
   if (rc) return rc;
-  // alpha_t = V_{m_t} ahat_t = H ahat_t / sqrt(n_t) (digital sequences: V real symmetric)
-  for (int t = 0; t < p->T; t++) {
-    LAUNCH_OK(launch_fwht<double>(w.ahat + p->off[t], p->n[t], 1, p->m[t], p->sched, st));
-    LAUNCH_OK(launch_scale<double>(w.ahat + p->off[t], p->n[t], 1.0 / std::sqrt((double)p->n[t]), st));
+  double* alpha = w.ahat;
+  if (p->family == MTGP_LAT) {
+    // alpha (natural lattice order) = n^-1/2 F^H ahat = n^-1/2 Re F conj(ahat)
+    const KDesc kd0 = p->kd();
+    LAUNCH_OK(launch_lat_adjoint<double, double>(
+        LAT_SINK_REAL, reinterpret_cast<const cx<double>*>(w.ahat),
+        reinterpret_cast<cx<double>*>(w.pwork), w.alpha, p->n[0], p->T, p->m[0], 1,
+        1.0 / std::sqrt((double)p->n[0]), p->d_gen, p->d_colshift, w.P, kd0, nullptr, st));
+    alpha = w.alpha;
+  } else {
+    // alpha_t = V_{m_t} ahat_t = H ahat_t / sqrt(n_t) (digital sequences: V real symmetric)
+    for (int t = 0; t < p->T; t++) {
+      LAUNCH_OK(launch_fwht<double>(w.ahat + p->off[t], p->n[t], 1, p->m[t], p->sched, st));
+      LAUNCH_OK(launch_scale<double>(w.ahat + p->off[t], p->n[t], 1.0 / std::sqrt((double)p->n[t]), st));
+    }
   }
   PredTasks pt;
   for (int t = 0; t < p->T; t++) {
@@ -520,11 +613,13 @@ int mtgp_predict(const mtgp_plan* p, const double* theta, const uint32_t* xs, in
     pt.off[t] = p->off[t];
   }
   const KDesc kd = p->kd();
-  if (p->precision == MTGP_FP64)
-    LAUNCH_OK(launch_predict_direct<double>(p->d_gen, p->d_taskshift, pt, w.ahat, xs, M, w.P, kd,
+  // the direct sum cancels heavily (alpha = Ktilde^-1 r is large where Ktilde
+  // is ill conditioned), so it stays FP64 unless every column op is FP32
+  if (p->precision != MTGP_F32)
+    LAUNCH_OK(launch_predict_direct<double>(p->d_gen, p->d_taskshift, pt, alpha, xs, M, w.P, kd,
                                             mean, st));
   else
-    LAUNCH_OK(launch_predict_direct<float>(p->d_gen, p->d_taskshift, pt, w.ahat, xs, M, w.P, kd,
+    LAUNCH_OK(launch_predict_direct<float>(p->d_gen, p->d_taskshift, pt, alpha, xs, M, w.P, kd,
                                            mean, st));
   return MTGP_OK;
 }

@@ -38,9 +38,9 @@ struct PairMap {
 // Transform schedule: pass A covers a_bits low index bits, each pass B at
 // most b_bits more, with an LDS tile of about b_tile bytes.
 struct Sched {
-  int a_bits = PASS_A_MAX_BITS;
-  int b_bits = PASS_B_MAX_BITS;
-  size_t b_tile = PASS_B_TILE_BYTES;
+  int a_bits = 12;
+  int b_bits = 6;
+  size_t b_tile = 36864;
   int lb(int m) const { return m < a_bits ? m : a_bits; }
 };
 
@@ -90,6 +90,10 @@ int launch_solve_eq(Real* cols, int64_t n, const PairMap& pm, int ncol, const do
 constexpr int COLSUM_BLOCKS = 256;
 int launch_colsum(const double* in, int64_t nrows, int ncols, double* out, int nblk,
                   hipStream_t st);
+template <typename SR>
+int launch_solve_eq_c(SR* cols, int64_t n, const PairMap& pm, const double* yhat, const Params* P,
+                      const KDesc& kd, bool grad, double* partials, double* ahat, int* status,
+                      hipStream_t st);
 int launch_finalize(const double* solve_partials, int nsolve, const double* adj_partials, int nadj,
                     const double* yhat0, int64_t n, Params* P, const KDesc& kd, double* out3,
                     double* grad, double* tau_hat, hipStream_t st);
@@ -105,5 +109,25 @@ template <typename Real>
 int launch_predict_direct(const uint32_t* gen, const uint32_t* shifts, const PredTasks& pt,
                           const double* alpha, const uint32_t* xs, int64_t M, const Params* P,
                           const KDesc& kd, double* mean, hipStream_t st);
+
+// ---- lattice.hip (complex values interleaved re, im)
+template <typename R>
+struct alignas(2 * sizeof(R)) cx {
+  R x, y;
+};
+enum { LAT_SRC_GEN = 0, LAT_SRC_Y = 1, LAT_SRC_X = 2 };  // columns, bit-reversed data, plain data
+int launch_lat_natural(const void* spec, int spec_f32, void* X, int64_t nvec, int m,
+                       hipStream_t st);
+enum { LAT_SINK_Z = 0, LAT_SINK_REDUCE = 1, LAT_SINK_REAL = 2 };
+int lat_adj_blocks(int m, size_t cbytes);
+template <typename CR, typename SR>
+int launch_lat_forward(int src, cx<CR>* work, cx<SR>* spec, int64_t vstride, int nvec, int m,
+                       const void* y, int y_f32, double scale, const uint32_t* gen, const uint32_t* colshift,
+                       const Params* P, const KDesc& kd, hipStream_t st);
+template <typename CR, typename SR>
+int launch_lat_adjoint(int sink, const cx<SR>* spec, cx<CR>* work, double* real_out,
+                       int64_t vstride, int nvec, int m, int conj_in, double scale,
+                       const uint32_t* gen, const uint32_t* colshift, const Params* P,
+                       const KDesc& kd, double* partials, hipStream_t st);
 
 }  // namespace mtgp

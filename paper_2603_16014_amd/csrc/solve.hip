@@ -239,6 +239,207 @@ template int launch_solve_eq<float>(float*, int64_t, const PairMap&, int, const 
                                     hipStream_t);
 
 // ---------------------------------------------------------------------------
+// Lattices: Lambda(f) is Hermitian, Lambda_tu = R_tu lambda_tu(f) for t < u
+// (column of the pair, shift Delta_t - Delta_u), Lambda_ut = conj(Lambda_tu),
+// diagonal R_tt Re(lambda_0(f)) + xi_t.  Lambda = L D L^H (complex unit lower
+// L, real D).  dL = sum_f sum_tu Re(W_ut dLambda_tu) gives
+//   omega_tu = 2 R_tu conj(W_tu) (t < u), omega_diag = sum_t R_tt W_tt,
+//   G_tu = sum_f Re(conj(W_tu) lambda_tu), same partial layout as the real case.
+// ---------------------------------------------------------------------------
+struct zc {
+  double x, y;
+};
+__device__ inline zc zmul(zc a, zc b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ inline zc zmulc(zc a, zc b) { return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }  // a conj(b)
+__device__ inline zc zsub(zc a, zc b) { return {a.x - b.x, a.y - b.y}; }
+__device__ inline zc zscale(zc a, double s) { return {a.x * s, a.y * s}; }
+
+template <typename SR, int TM, bool GRAD>
+__global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, int64_t n,
+                                                         PairMap pm,
+                                                         const double* __restrict__ yhat,
+                                                         const Params* __restrict__ P, KDesc kd,
+                                                         double* __restrict__ partials,
+                                                         double* __restrict__ ahat,
+                                                         int* __restrict__ status) {
+  constexpr int NP = TM * (TM + 1) / 2;
+  constexpr int NQ = 2 + NP + 2 * TM;
+  __shared__ double red[4 * NQ];
+  const int T = kd.T;
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool active = f < n;
+  double vals[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; q++) vals[q] = 0.0;
+  if (active) {
+    zc lam[NP], A[NP], r[TM];
+#pragma unroll
+    for (int i = 0; i < TM; i++) {
+#pragma unroll
+      for (int j = 0; j <= i; j++) {
+        if (i < T) {
+          const size_t at = ((size_t)pm.col[j][i] * n + f) * 2;
+          zc l = {(double)cols[at], (double)cols[at + 1]};
+          if (i == j) l.y = 0.0;
+          lam[pk<TM>(i, j)] = l;
+          // lower entry (i, j), i > j: conj(Lambda_ji) = R_ji conj(lambda_ji)
+          const double R = P->R[j * MTGP_MAXT + i];
+          A[pk<TM>(i, j)] = {R * l.x + (i == j ? P->xi[i] : 0.0), -R * l.y};
+        } else {
+          lam[pk<TM>(i, j)] = {0.0, 0.0};
+          A[pk<TM>(i, j)] = {i == j ? 1.0 : 0.0, 0.0};
+        }
+      }
+      if (i < T) {
+        zc yv = {yhat[((size_t)i * n + f) * 2], yhat[((size_t)i * n + f) * 2 + 1]};
+        if (f == 0) yv = kd.profile ? zc{0.0, 0.0} : zc{yv.x - sqrt((double)n) * P->tau[i], yv.y};
+        r[i] = yv;
+      } else {
+        r[i] = {0.0, 0.0};
+      }
+    }
+    double invD[TM];
+    double prod = 1.0;
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < TM; j++) {
+      zc u[TM];
+      double dj = A[pk<TM>(j, j)].x;
+#pragma unroll
+      for (int k = 0; k < j; k++) {
+        const zc l = A[pk<TM>(j, k)];
+        const double Dk = 1.0 / invD[k];
+        u[k] = zscale(l, Dk);  // L_jk D_k
+        dj -= (l.x * l.x + l.y * l.y) * Dk;
+      }
+      ok = ok && (dj > 0.0);
+      prod *= dj;
+      invD[j] = 1.0 / dj;
+#pragma unroll
+      for (int i = j + 1; i < TM; i++) {
+        zc v = A[pk<TM>(i, j)];
+#pragma unroll
+        for (int k = 0; k < j; k++) v = zsub(v, zmulc(A[pk<TM>(i, k)], u[k]));  // L_ik conj(L_jk) D_k
+        A[pk<TM>(i, j)] = zscale(v, invD[j]);
+      }
+    }
+    if (!ok || !isfinite(prod)) flag_bad(status, f);
+    vals[1] = log(prod);
+    zc a[TM];
+    double quad = 0.0;
+#pragma unroll
+    for (int i = 0; i < TM; i++) {
+      zc v = r[i];
+#pragma unroll
+      for (int k = 0; k < i; k++) v = zsub(v, zmul(A[pk<TM>(i, k)], a[k]));
+      a[i] = v;
+      quad += (v.x * v.x + v.y * v.y) * invD[i];
+    }
+    vals[0] = quad;
+#pragma unroll
+    for (int i = TM - 1; i >= 0; i--) {
+      zc v = zscale(a[i], invD[i]);
+#pragma unroll
+      for (int k = i + 1; k < TM; k++) {
+        const zc l = A[pk<TM>(k, i)];
+        v = zsub(v, zmul({l.x, -l.y}, a[k]));  // conj(L_ki) a_k
+      }
+      a[i] = v;
+    }
+    if (f == 0) {
+#pragma unroll
+      for (int i = 0; i < TM; i++) vals[2 + NP + TM + i] = a[i].x;
+    }
+    if (ahat) {
+#pragma unroll
+      for (int i = 0; i < TM; i++)
+        if (i < T) {
+          ahat[((size_t)i * n + f) * 2] = a[i].x;
+          ahat[((size_t)i * n + f) * 2 + 1] = a[i].y;
+        }
+    }
+    if (GRAD) {
+#pragma unroll
+      for (int i = 1; i < TM; i++) {
+#pragma unroll
+        for (int j = 0; j < i; j++) {
+          zc v = A[pk<TM>(i, j)];
+#pragma unroll
+          for (int k = j + 1; k < i; k++) {
+            const zc p2 = zmul(A[pk<TM>(i, k)], A[pk<TM>(k, j)]);
+            v = {v.x + p2.x, v.y + p2.y};
+          }
+          A[pk<TM>(i, j)] = {-v.x, -v.y};
+        }
+      }
+      double wdiag = 0.0;
+#pragma unroll
+      for (int u = 0; u < TM; u++) {
+#pragma unroll
+        for (int t = 0; t <= u; t++) {
+          // (Lambda^-1)_tu = sum_{k >= u} conj(X_kt) X_ku / D_k
+          zc v = (t == u) ? zc{invD[u], 0.0} : zscale({A[pk<TM>(u, t)].x, -A[pk<TM>(u, t)].y}, invD[u]);
+#pragma unroll
+          for (int k = u + 1; k < TM; k++) {
+            const zc xt = A[pk<TM>(k, t)], xu = A[pk<TM>(k, u)];
+            const zc p2 = zmulc(xu, xt);  // X_ku conj(X_kt)
+            v = {v.x + p2.x * invD[k], v.y + p2.y * invD[k]};
+          }
+          const zc w = zsub(v, zmulc(a[t], a[u]));  // W_tu = Ainv_tu - a_t conj(a_u)
+          if (u < T) {
+            const zc l = lam[pk<TM>(u, t)];
+            if (t == u) {
+              vals[2 + pk<TM>(u, t)] = w.x * l.x;
+              vals[2 + NP + t] = w.x;
+              wdiag += P->R[t * MTGP_MAXT + t] * w.x;
+            } else {
+              vals[2 + pk<TM>(u, t)] = w.x * l.x + w.y * l.y;  // Re(conj(W_tu) lambda_tu)
+              const double R2 = 2.0 * P->R[t * MTGP_MAXT + u];
+              const size_t at = ((size_t)pm.col[t][u] * n + f) * 2;
+              cols[at] = (SR)(R2 * w.x);
+              cols[at + 1] = (SR)(-R2 * w.y);
+            }
+          }
+        }
+      }
+      const size_t at0 = ((size_t)pm.col[0][0] * n + f) * 2;
+      cols[at0] = (SR)wdiag;
+      cols[at0 + 1] = (SR)0;
+    }
+  }
+  block_sum_store<NQ>(vals, NQ, red, partials + (size_t)blockIdx.x * NQ);
+}
+
+template <typename SR>
+int launch_solve_eq_c(SR* cols, int64_t n, const PairMap& pm, const double* yhat, const Params* P,
+                      const KDesc& kd, bool grad, double* partials, double* ahat, int* status,
+                      hipStream_t st) {
+  const dim3 grid((unsigned)solve_blocks(n)), block(256);
+#define MTGP_SOLVEC(TMV)                                                                         \
+  do {                                                                                           \
+    if (grad)                                                                                    \
+      hipLaunchKernelGGL((solve_eq_c_kernel<SR, TMV, true>), grid, block, 0, st, cols, n, pm,    \
+                         yhat, P, kd, partials, ahat, status);                                   \
+    else                                                                                         \
+      hipLaunchKernelGGL((solve_eq_c_kernel<SR, TMV, false>), grid, block, 0, st, cols, n, pm,   \
+                         yhat, P, kd, partials, ahat, status);                                   \
+  } while (0)
+  if (kd.T <= 1) MTGP_SOLVEC(1);
+  else if (kd.T <= 2) MTGP_SOLVEC(2);
+  else if (kd.T <= 4) MTGP_SOLVEC(4);
+  else if (kd.T <= 8) MTGP_SOLVEC(8);
+  else MTGP_SOLVEC(16);
+#undef MTGP_SOLVEC
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+template int launch_solve_eq_c<double>(double*, int64_t, const PairMap&, const double*,
+                                       const Params*, const KDesc&, bool, double*, double*, int*,
+                                       hipStream_t);
+template int launch_solve_eq_c<float>(float*, int64_t, const PairMap&, const double*,
+                                      const Params*, const KDesc&, bool, double*, double*, int*,
+                                      hipStream_t);
+
+// ---------------------------------------------------------------------------
 // finalize: deterministic sums of the block partials and the chain rule
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ sp, int nsolve,
@@ -276,7 +477,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   const int TMp = solve_tm(T);
   const int qX = 2 + TMp * (TMp + 1) / 2, qA = qX + TMp;
   for (int t = 0; t < T; t++) {
-    const double tu = kd.profile ? yhat[(int64_t)t * n] / sqn : P->tau[t];
+    const int64_t y0 = (int64_t)t * n * (kd.family == FAM_LAT ? 2 : 1);
+    const double tu = kd.profile ? yhat[y0] / sqn : P->tau[t];
     P->tau_used[t] = tu;
     if (tau_hat) tau_hat[t] = tu;
   }

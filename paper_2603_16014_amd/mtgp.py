@@ -229,9 +229,10 @@ def fft(x: torch.Tensor, log2n: int, bitrev_input=False) -> torch.Tensor:
     _need_cuda(x, x.dtype, "x")
     batch = x.numel() >> log2n
     X = torch.empty(2 * x.numel(), dtype=x.dtype, device="cuda")
+    scratch = torch.empty(2 * x.numel() if log2n > 12 else 1, dtype=x.dtype, device="cuda")
     dt = 0 if x.dtype == torch.float64 else 1
-    _lib.check(_lib.load().mtgp_fft(_ptr(x), _ptr(X), batch, log2n, dt, int(bool(bitrev_input)),
-                                    _stream()), "mtgp_fft")
+    _lib.check(_lib.load().mtgp_fft(_ptr(x), _ptr(X), _ptr(scratch), batch, log2n, dt,
+                                    int(bool(bitrev_input)), _stream()), "mtgp_fft")
     return torch.view_as_complex(X.view(-1, 2)).view(batch, 1 << log2n)
 
 

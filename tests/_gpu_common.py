@@ -46,7 +46,8 @@ def oracle_for(w, want_grad=True, want_hp=False, xs_seed=99, M=0):
 
 
 def rel_err(a, b, scale=None):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
+    """max |a - b| / max |b| (complex values compared as complex numbers)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
     s = np.abs(b).max() if scale is None else scale
     return float(np.abs(a - b).max() / max(s, 1e-300))

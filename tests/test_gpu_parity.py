@@ -112,6 +112,30 @@ def test_fwht_large_sampled(dtype, log2n):
     assert rel_err(back, x) < (1e-13 if dtype == torch.float64 else 1e-5) * log2n
 
 
+# ---------------------------------------------------------------------- fft
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("log2n,batch", [(0, 2), (3, 3), (9, 2), (12, 2), (13, 2), (16, 3), (20, 1)])
+@pytest.mark.parametrize("bitrev", [False, True])
+def test_fft_vs_numpy(dtype, log2n, batch, bitrev):
+    say("fft", dtype, log2n, batch, bitrev)
+    rng = np.random.default_rng(7 + log2n)
+    n = 1 << log2n
+    x = rng.normal(size=(batch, n))
+    X = mt.fft(torch.from_numpy(x).to(dtype).cuda(), log2n, bitrev_input=bitrev).cpu().numpy()
+    xin = x
+    if bitrev:
+        perm = np.array([_bitrev(j, log2n) for j in range(n)]) if log2n <= 16 else None
+        if perm is None:
+            idx = np.arange(n, dtype=np.uint64)
+            perm = np.zeros(n, dtype=np.int64)
+            for b in range(log2n):
+                perm |= (((idx >> np.uint64(b)) & np.uint64(1)) << np.uint64(log2n - 1 - b)).astype(np.int64)
+        xin = x[:, perm]
+    ref = np.fft.fft(xin, axis=1)
+    tol = (1e-13 if dtype == torch.float64 else 3e-6) * max(1, log2n)
+    assert rel_err(X, ref) < tol, rel_err(X, ref)
+
+
 # -------------------------------------------------------------------- loss
 CASES = [
     # (family, T, m, d, order, adaptive, profile, schedule)
@@ -123,6 +147,10 @@ CASES = [
     ("dseq", 4, [7, 7, 7, 7], 3, 2, True, True, (4, 2, 4096)),
     ("dseq", 5, [6, 6, 6, 6, 6], 2, 2, False, True, None),
     ("dseq", 8, [6] * 8, 10, 2, False, True, (3, 3, 4096)),
+    ("lat", 1, [8], 2, 2, False, True, None),
+    ("lat", 3, [7, 7, 7], 3, 1, False, False, None),
+    ("lat", 4, [8, 8, 8, 8], 6, 2, False, True, None),
+    ("lat", 2, [9, 9], 4, 3, False, False, None),
 ]
 
 
@@ -164,6 +192,47 @@ def test_loss_grad_parity(case, precision):
         assert e < tolg, (k, g[k], v, e)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_lattice_two_pass_against_oracle(precision):
+    # m = 13 > 12 runs the two-pass DFT (pass 1 over the high index bits fused
+    # with generation, pass 2 contiguous) and the two-pass adjoint
+    w = tiny("lat", 1, [13], 2, seed=51, xi=1e-3)
+    say("lattice two-pass", precision)
+    ref = oracle_for(w, want_grad=False, M=64, xs_seed=5)
+    plan = mt.Plan.from_workload(w, precision)
+    theta = plan.pack_theta(w.theta)
+    plan.set_data(torch.from_numpy(ref["y"]).cuda())
+    out3, tau = plan.nll(theta)
+    r = ref["res"]
+    den = abs(r["quad"]) + abs(r["logdet"])
+    assert abs(float(out3[2]) - r["L"]) < (1e-10 if precision == "fp64" else 1e-5) * den
+    mean = plan.predict(theta, mt.digits_to_device(ref["xs"])).cpu().numpy()
+    assert rel_err(mean, ref["mean"]) < (1e-9 if precision == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("family,m", [("dseq", 14), ("lat", 14)])
+def test_gradient_matches_fd_of_gpu_loss_beyond_oracle_sizes(family, m):
+    # a property at any size: the adjoint gradient equals central finite
+    # differences of the same (FP64) loss, here at N = 3 * 2^14
+    w = tiny(family, 3, [m, m, m], 3, seed=61, xi=1e-2, rank=2)
+    say("gradient vs FD of GPU loss", family, m)
+    rng = np.random.default_rng(3)
+    y = rng.normal(size=w.N)
+    plan = mt.Plan.from_workload(w, "fp64")
+    plan.set_data(torch.from_numpy(y).cuda())
+    theta = plan.pack_theta(w.theta)
+    out3, grad, _ = plan.nll_grad(theta)
+    g = grad.cpu().numpy()
+    th = theta.clone()
+    h = 1e-5
+    for i in range(plan.theta_size):
+        tp, tm_ = th.clone(), th.clone()
+        tp[i] += h
+        tm_[i] -= h
+        fd = (float(plan.nll(tp)[0][2]) - float(plan.nll(tm_)[0][2])) / (2 * h)
+        assert abs(fd - g[i]) <= 2e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
 def test_config1_fp64_against_extended_precision():
     w = workloads.config1()
     say("config1 fp64 vs long double")
@@ -185,7 +254,8 @@ def test_config1_fp64_against_extended_precision():
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("family,T,m,d,adaptive", [("dseq", 3, [7, 7, 7], 3, False),
-                                                   ("dseq", 2, [8, 8], 5, True)])
+                                                   ("dseq", 2, [8, 8], 5, True),
+                                                   ("lat", 3, [7, 7, 7], 3, False)])
 def test_predict_parity(precision, family, T, m, d, adaptive):
     w = tiny(family, T, m, d, adaptive=adaptive, seed=41)
     say("predict", family, T, m, d, adaptive, precision)
