@@ -12,6 +12,7 @@
 //   B^T, A^T  the adjoint transform of the weights, fused with the
 //             derivative reduction over the regenerated columns
 //   finalize  deterministic sums of block partials, chain rule
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -52,12 +53,14 @@ struct mtgp_plan {
   uint32_t* d_taskshift = nullptr;
   // workspace layout (byte offsets)
   size_t o_params, o_status, o_cols, o_work, o_yhat, o_ahat, o_sp, o_sp2, o_ap, o_ap2, o_alpha,
-      o_pwork, o_misc, ws_bytes;
+      o_pwork, o_a1a, o_a1b, o_logs, o_lp2, o_misc, ws_bytes;
   int nadj_blocks;
   int64_t cols_elems;
   size_t real_bytes;  // bytes of a stored spectrum / adjoint value
   size_t work_bytes;  // bytes of a forward working value (0: works in the spectrum buffer)
   Sched sched;
+  Alg1Desc a1;      // stage descriptors of the unequal-size elimination
+  int64_t a1_ms;    // final block size N / n_T
   // optional phase timing (profiling aid; not thread safe)
   bool timing = false;
   hipEvent_t ev[MTGP_NPHASE + 1] = {};
@@ -70,6 +73,8 @@ struct mtgp_plan {
     k.adaptive = adaptive;
     k.s = s;
     k.profile = profile;
+    k.unequal = equal ? 0 : 1;
+    for (int t = 0; t < MTGP_MAXT; t++) k.m[t] = t < T ? m[t] : 0;
     return k;
   }
 };
@@ -100,6 +105,10 @@ struct WsView {
   double* ap2;
   double* alpha;
   double* pwork;
+  z2* a1a;
+  z2* a1b;
+  double* logs;
+  double* lp2;
   double* misc;
 };
 
@@ -118,6 +127,10 @@ WsView view(const mtgp_plan* p, void* ws) {
   v.ap2 = reinterpret_cast<double*>(b + p->o_ap2);
   v.alpha = reinterpret_cast<double*>(b + p->o_alpha);
   v.pwork = reinterpret_cast<double*>(b + p->o_pwork);
+  v.a1a = reinterpret_cast<z2*>(b + p->o_a1a);
+  v.a1b = reinterpret_cast<z2*>(b + p->o_a1b);
+  v.logs = reinterpret_cast<double*>(b + p->o_logs);
+  v.lp2 = reinterpret_cast<double*>(b + p->o_lp2);
   v.misc = reinterpret_cast<double*>(b + p->o_misc);
   return v;
 }
@@ -158,70 +171,39 @@ int run_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
   return MTGP_OK;
 }
 
-// Lattice family (equal sizes): DFT transforms in the four-step layout, the
-// Hermitian per-frequency solve, the DFT adjoint fused with the reduction.
+// Forward transforms of all kernel columns (CR arithmetic, spectrum as SR).
 template <typename CR, typename SR>
-int run_loss_lat(const mtgp_plan* p, const WsView& w, double* out3, double* grad, double* tau_hat,
-                 hipStream_t st, bool want_ahat) {
+int forward_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
+  if (p->family == MTGP_DSEQ) return run_columns<CR, SR>(p, w, st);
   const KDesc kd = p->kd();
-  const int m = p->m[0];
-  const int64_t n = p->n[0];
   cx<SR>* spec = reinterpret_cast<cx<SR>*>(w.cols);
   cx<CR>* work = reinterpret_cast<cx<CR>*>(w.work);
   mark(p, 1, st);
-  LAUNCH_OK(launch_lat_forward<CR, SR>(LAT_SRC_GEN, work, spec, n, p->ncol, m, nullptr, 0, 1.0,
-                                       p->d_gen, p->d_colshift, w.P, kd, st));
-  mark(p, 2, st);
-  mark(p, 3, st);
-  LAUNCH_OK(launch_solve_eq_c<SR>(reinterpret_cast<SR*>(w.cols), n, p->pm, w.yhat, w.P, kd,
-                                  grad != nullptr, w.sp, want_ahat ? w.ahat : nullptr, w.status,
-                                  st));
-  mark(p, 4, st);
-  mark(p, 5, st);
-  int nadj = 0;
-  if (grad) {
-    LAUNCH_OK(launch_lat_adjoint<CR, SR>(LAT_SINK_REDUCE, spec, work, nullptr, n, p->ncol, m, 0, 1.0,
-                                         p->d_gen, p->d_colshift, w.P, kd, w.ap, st));
-    nadj = lat_adj_blocks(m, sizeof(cx<CR>)) * p->ncol;
-    LAUNCH_OK(launch_colsum(w.ap, nadj, adj_nq(p->d), w.ap2, COLSUM_BLOCKS, st));
+  for (const auto& g : p->groups) {
+    const int64_t o = p->col_off[g.first];
+    LAUNCH_OK(launch_lat_forward<CR, SR>(LAT_SRC_GEN, work + o, spec + o, (int64_t)1 << g.m,
+                                         g.count, g.m, nullptr, 0, 1.0, p->d_gen,
+                                         p->d_colshift + (size_t)g.first * p->d, w.P, kd, st));
   }
-  LAUNCH_OK(launch_colsum(w.sp, solve_blocks(n), solve_ns(p->T), w.sp2, COLSUM_BLOCKS, st));
-  mark(p, 6, st);
-  LAUNCH_OK(launch_finalize(w.sp2, COLSUM_BLOCKS, grad ? w.ap2 : nullptr, COLSUM_BLOCKS, w.yhat, n,
-                            w.P, kd, out3, grad, tau_hat, st));
-  mark(p, 7, st);
+  mark(p, 2, st);
   return MTGP_OK;
 }
 
-// Loss (and gradient): columns and transforms in CR arithmetic, spectrum and
-// adjoint weights stored as SR, adjoint transform arithmetic in CR.
+// Adjoint transforms of the weights fused with the derivative reduction;
+// returns the number of partial rows written to w.ap (or a negative error).
 template <typename CR, typename SR>
-int run_loss(const mtgp_plan* p, const double* theta, double* out3, double* grad, double* tau_hat,
-             void* ws, hipStream_t st, bool want_ahat) {
-  const WsView w = view(p, ws);
+int adjoint_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
   const KDesc kd = p->kd();
-  mark(p, 0, st);
-  LAUNCH_OK(launch_prep(theta, w.P, kd, w.status, st));
-  if (p->family == MTGP_LAT) return run_loss_lat<CR, SR>(p, w, out3, grad, tau_hat, st, want_ahat);
-  int rc = run_columns<CR, SR>(p, w, st);
-  if (rc) return rc;
-  SR* spec = reinterpret_cast<SR*>(w.cols);
-  CR* work = reinterpret_cast<CR*>(w.work);
-  const int64_t n = p->n[0];
-  mark(p, 3, st);
-  LAUNCH_OK(launch_solve_eq<SR>(spec, n, p->pm, p->ncol, w.yhat, w.P, kd, grad != nullptr, w.sp,
-                                want_ahat ? w.ahat : nullptr, w.status, st));
   int nadj = 0;
-  mark(p, 4, st);
-  if (grad) {
+  if (p->family == MTGP_DSEQ) {
+    SR* spec = reinterpret_cast<SR*>(w.cols);
+    CR* work = reinterpret_cast<CR*>(w.work);
     for (const auto& g : p->groups) {
       const int64_t o = p->col_off[g.first];
       LAUNCH_OK(launch_strided<CR, SR, CR>(spec + o, work + o, work + o, (int64_t)1 << g.m,
                                            g.count, g.m, p->sched, st));
     }
-  }
-  mark(p, 5, st);
-  if (grad) {
+    mark(p, 5, st);
     for (const auto& g : p->groups) {
       const int64_t o = p->col_off[g.first];
       const int nb = 1 << (g.m - p->sched.lb(g.m));
@@ -235,12 +217,67 @@ int run_loss(const mtgp_plan* p, const double* theta, double* out3, double* grad
                                             sh, w.P, kd, part, p->sched, st));
       nadj += nb * g.count;
     }
-    LAUNCH_OK(launch_colsum(w.ap, nadj, adj_nq(p->d), w.ap2, COLSUM_BLOCKS, st));
+    return nadj;
   }
-  LAUNCH_OK(launch_colsum(w.sp, solve_blocks(n), solve_ns(p->T), w.sp2, COLSUM_BLOCKS, st));
+  cx<SR>* spec = reinterpret_cast<cx<SR>*>(w.cols);
+  cx<CR>* work = reinterpret_cast<cx<CR>*>(w.work);
+  mark(p, 5, st);
+  for (const auto& g : p->groups) {
+    const int64_t o = p->col_off[g.first];
+    LAUNCH_OK(launch_lat_adjoint<CR, SR>(LAT_SINK_REDUCE, spec + o, work + o, nullptr,
+                                         (int64_t)1 << g.m, g.count, g.m, 0, 1.0, p->d_gen,
+                                         p->d_colshift + (size_t)g.first * p->d, w.P, kd,
+                                         w.ap + (size_t)nadj * adj_nq(p->d), st));
+    nadj += lat_adj_blocks(g.m, sizeof(cx<CR>)) * g.count;
+  }
+  return nadj;
+}
+
+// Loss (and gradient): columns and transforms in CR arithmetic, spectrum and
+// adjoint weights stored as SR, adjoint transform arithmetic in CR.  Equal
+// sizes: per-frequency T x T factorisations; nested unequal sizes: the
+// elimination in task order.
+template <typename CR, typename SR>
+int run_loss(const mtgp_plan* p, const double* theta, double* out3, double* grad, double* tau_hat,
+             void* ws, hipStream_t st, bool want_ahat) {
+  const WsView w = view(p, ws);
+  const KDesc kd = p->kd();
+  mark(p, 0, st);
+  LAUNCH_OK(launch_prep(theta, w.P, kd, w.status, st));
+  int rc = forward_columns<CR, SR>(p, w, st);
+  if (rc) return rc;
+  SR* spec = reinterpret_cast<SR*>(w.cols);
+  const int64_t n = p->n[0];
+  int64_t nsolve;
+  mark(p, 3, st);
+  if (!p->equal) {
+    LAUNCH_OK(launch_alg1<SR>(spec, p->a1, w.P, kd.family, grad != nullptr, w.yhat, w.a1a, w.a1b,
+                              w.logs, want_ahat ? w.ahat : nullptr, w.sp, w.status, st));
+    nsolve = p->n[p->T - 1];
+  } else if (p->family == MTGP_LAT) {
+    LAUNCH_OK(launch_solve_eq_c<SR>(spec, n, p->pm, w.yhat, w.P, kd, grad != nullptr, w.sp,
+                                    want_ahat ? w.ahat : nullptr, w.status, st));
+    nsolve = solve_blocks(n);
+  } else {
+    LAUNCH_OK(launch_solve_eq<SR>(spec, n, p->pm, p->ncol, w.yhat, w.P, kd, grad != nullptr, w.sp,
+                                  want_ahat ? w.ahat : nullptr, w.status, st));
+    nsolve = solve_blocks(n);
+  }
+  mark(p, 4, st);
+  int nadj = 0;
+  if (grad) {
+    nadj = adjoint_columns<CR, SR>(p, w, st);
+    if (nadj < 0) return nadj;
+    LAUNCH_OK(launch_colsum(w.ap, nadj, adj_nq(p->d), w.ap2, COLSUM_BLOCKS, st));
+  } else {
+    mark(p, 5, st);
+  }
+  LAUNCH_OK(launch_colsum(w.sp, nsolve, solve_ns(p->T), w.sp2, COLSUM_BLOCKS, st));
+  if (!p->equal) LAUNCH_OK(launch_colsum(w.logs, p->N, 1, w.lp2, COLSUM_BLOCKS, st));
   mark(p, 6, st);
-  LAUNCH_OK(launch_finalize(w.sp2, COLSUM_BLOCKS, grad ? w.ap2 : nullptr, COLSUM_BLOCKS, w.yhat, n,
-                            w.P, kd, out3, grad, tau_hat, st));
+  LAUNCH_OK(launch_finalize(w.sp2, COLSUM_BLOCKS, grad ? w.ap2 : nullptr, COLSUM_BLOCKS,
+                            p->equal ? nullptr : w.lp2, COLSUM_BLOCKS, w.yhat, n, w.P, kd, out3,
+                            grad, tau_hat, st));
   mark(p, 7, st);
   return MTGP_OK;
 }
@@ -276,8 +313,20 @@ void layout(mtgp_plan* p) {
   o = align_up(o + (cplx == 2 ? (size_t)p->N * sizeof(double) : 0));
   p->o_pwork = o;
   o = align_up(o + (cplx == 2 ? (size_t)p->N * 2 * sizeof(double) : 0));
+  const size_t a1 = p->equal ? 0 : (size_t)p->N * (size_t)p->a1_ms * sizeof(z2);
+  p->o_a1a = o;
+  o = align_up(o + a1);
+  p->o_a1b = o;
+  o = align_up(o + a1);
+  p->o_logs = o;
+  o = align_up(o + (p->equal ? 0 : (size_t)p->N * sizeof(double)));
+  p->o_lp2 = o;
+  o = align_up(o + (size_t)COLSUM_BLOCKS * sizeof(double));
   p->o_sp = o;
-  o = align_up(o + (size_t)solve_blocks(p->n[p->T - 1]) * solve_ns(T) * sizeof(double));
+  {
+    const int64_t rows = p->equal ? solve_blocks(p->n[0]) : p->n[p->T - 1];
+    o = align_up(o + (size_t)rows * solve_ns(T) * sizeof(double));
+  }
   p->o_sp2 = o;
   o = align_up(o + (size_t)COLSUM_BLOCKS * solve_ns(T) * sizeof(double));
   p->nadj_blocks = 0;
@@ -360,32 +409,60 @@ int mtgp_plan_create(const mtgp_design* des, int32_t precision, mtgp_plan** out)
     delete p;
     return MTGP_ENOTSUP;
   }
-  if (!p->equal) {  // nested unequal sizes are handled by a later stage of the build
-    delete p;
-    return MTGP_ENOTSUP;
-  }
-  // columns: the shared diagonal column, then one per task pair t < u
   const int T = p->T, d = p->d;
-  auto pair_shift = [&](int t, int u, int j) -> uint32_t {
-    const uint32_t a = p->shift[(size_t)t * d + j], b = p->shift[(size_t)u * d + j];
-    return p->family == MTGP_DSEQ ? (a ^ b) : (uint32_t)(a - b);
-  };
-  std::memset(&p->pm, 0, sizeof(p->pm));
-  p->ncol = 0;
-  auto add_col = [&](int t, int u, int mlen) {
-    p->col_m.push_back(mlen);
-    p->col_t.push_back(t);
-    p->col_u.push_back(u);
-    for (int j = 0; j < d; j++) p->col_shift.push_back(t == u ? 0u : pair_shift(t, u, j));
-    return p->ncol++;
-  };
-  const int c0 = add_col(0, 0, p->m[0]);
-  for (int t = 0; t < T; t++) p->pm.col[t][t] = (int8_t)c0;
-  for (int t = 0; t < T; t++)
-    for (int u = t + 1; u < T; u++) {
-      const int c = add_col(t, u, p->m[t]);
-      p->pm.col[t][u] = p->pm.col[u][t] = (int8_t)c;
+  if (!p->equal) {
+    int64_t ms = 0;
+    for (int t = 0; t < T; t++) ms += p->n[t] >> p->m[T - 1];
+    if (ms > ALG1_MAX_BLOCK) {  // the elimination keeps N / n_T x N / n_T blocks
+      delete p;
+      return MTGP_ENOTSUP;
     }
+    p->a1_ms = ms;
+  } else {
+    p->a1_ms = 0;
+  }
+  // columns: one diagonal column per distinct length (shift 0; every diagonal
+  // pair of tasks with that length uses it), one per task pair t < u (length
+  // n_t, the larger task: the tall case); then ordered by non-increasing
+  // length so equal-length columns form contiguous groups
+  auto pair_shift = [&](int t, int u, int j) -> uint32_t {
+    const uint32_t a0 = p->shift[(size_t)t * d + j], b0 = p->shift[(size_t)u * d + j];
+    return p->family == MTGP_DSEQ ? (a0 ^ b0) : (uint32_t)(a0 - b0);
+  };
+  struct ColSpec {
+    int m, t, u;
+  };
+  std::vector<ColSpec> specs;
+  int diag_of_m[31];
+  for (int q = 0; q < 31; q++) diag_of_m[q] = -1;
+  for (int t = 0; t < T; t++)
+    if (diag_of_m[p->m[t]] < 0) {
+      diag_of_m[p->m[t]] = (int)specs.size();
+      specs.push_back({p->m[t], t, t});
+    }
+  for (int t = 0; t < T; t++)
+    for (int u = t + 1; u < T; u++) specs.push_back({p->m[t], t, u});
+  std::vector<int> order(specs.size());
+  for (size_t q = 0; q < order.size(); q++) order[q] = (int)q;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return specs[x].m > specs[y].m; });
+  std::vector<int> newidx(specs.size());
+  std::memset(&p->pm, 0, sizeof(p->pm));
+  p->ncol = (int)specs.size();
+  for (int c = 0; c < p->ncol; c++) {
+    const ColSpec& cs = specs[order[c]];
+    newidx[order[c]] = c;
+    p->col_m.push_back(cs.m);
+    p->col_t.push_back(cs.t);
+    p->col_u.push_back(cs.u);
+    for (int j = 0; j < d; j++) p->col_shift.push_back(cs.t == cs.u ? 0u : pair_shift(cs.t, cs.u, j));
+  }
+  for (int t = 0; t < T; t++) p->pm.col[t][t] = (int8_t)newidx[diag_of_m[p->m[t]]];
+  {
+    int q = (int)std::count_if(specs.begin(), specs.end(), [](const ColSpec& c) { return c.t == c.u; });
+    for (int t = 0; t < T; t++)
+      for (int u = t + 1; u < T; u++, q++) p->pm.col[t][u] = p->pm.col[u][t] = (int8_t)newidx[q];
+  }
   p->col_off.resize(p->ncol);
   int64_t acc = 0;
   for (int c = 0; c < p->ncol; c++) {
@@ -393,7 +470,39 @@ int mtgp_plan_create(const mtgp_design* des, int32_t precision, mtgp_plan** out)
     acc += (int64_t)1 << p->col_m[c];
   }
   p->cols_elems = acc;
-  p->groups.push_back({0, p->ncol, p->m[0]});
+  for (int c = 0; c < p->ncol;) {
+    int e2 = c;
+    while (e2 < p->ncol && p->col_m[e2] == p->col_m[c]) e2++;
+    p->groups.push_back({c, e2 - c, p->col_m[c]});
+    c = e2;
+  }
+  // elimination descriptors
+  std::memset(&p->a1, 0, sizeof(p->a1));
+  p->a1.T = T;
+  p->a1.profile = p->profile;
+  int64_t so = 0;
+  for (int s = 0; s < T; s++) {
+    p->a1.m[s] = p->m[s];
+    int64_t msz = 0;
+    for (int t = 0; t <= s; t++) msz += p->n[t] >> p->m[s];
+    p->a1.msz[s] = msz;
+    p->a1.stage_off[s] = so;
+    so += p->n[s];
+    p->a1.task_off[s] = p->off[s];
+    int first = s;
+    for (int t = 0; t < s; t++)
+      if (p->m[t] == p->m[s]) {
+        first = t;
+        break;
+      }
+    p->a1.diag_first[s] = (int8_t)first;
+  }
+  for (int t = 0; t < T; t++)
+    for (int u = 0; u < T; u++) p->a1.pair_col[t][u] = p->pm.col[t][u];
+  for (int c = 0; c < p->ncol; c++) {
+    p->a1.col_m[c] = p->col_m[c];
+    p->a1.col_off[c] = p->col_off[c];
+  }
   p->real_bytes = precision == MTGP_FP64 ? sizeof(double) : sizeof(float);
   p->work_bytes = precision == MTGP_MIXED ? sizeof(double) : 0;
   layout(p);
@@ -554,12 +663,15 @@ int mtgp_set_data(const mtgp_plan* p, const double* y, void* ws, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const WsView w = view(p, ws);
   if (p->family == MTGP_LAT) {
-    // yhat_t = n^-1/2 F (bit reversal of y_t), in the spectrum layout
+    // yhat_t = n_t^-1/2 F (bit reversal of y_t), in the spectrum layout of length n_t
     const KDesc kd = p->kd();
-    LAUNCH_OK(launch_lat_forward<double, double>(
-        LAT_SRC_Y, reinterpret_cast<cx<double>*>(w.pwork), reinterpret_cast<cx<double>*>(w.yhat),
-        p->n[0], p->T, p->m[0], y, 0, 1.0 / std::sqrt((double)p->n[0]), nullptr, nullptr, nullptr,
-        kd, st));
+    const int nv = p->equal ? p->T : 1;
+    for (int t = 0; t < p->T; t += nv) {
+      LAUNCH_OK(launch_lat_forward<double, double>(
+          LAT_SRC_Y, reinterpret_cast<cx<double>*>(w.pwork) + p->off[t],
+          reinterpret_cast<cx<double>*>(w.yhat) + p->off[t], p->n[t], nv, p->m[t], y + p->off[t], 0,
+          1.0 / std::sqrt((double)p->n[t]), nullptr, nullptr, nullptr, kd, st));
+    }
     return MTGP_OK;
   }
   HIP_OK(hipMemcpyAsync(w.yhat, y, (size_t)p->N * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -595,10 +707,14 @@ int mtgp_predict(const mtgp_plan* p, const double* theta, const uint32_t* xs, in
   if (p->family == MTGP_LAT) {
     // alpha (natural lattice order) = n^-1/2 F^H ahat = n^-1/2 Re F conj(ahat)
     const KDesc kd0 = p->kd();
-    LAUNCH_OK(launch_lat_adjoint<double, double>(
-        LAT_SINK_REAL, reinterpret_cast<const cx<double>*>(w.ahat),
-        reinterpret_cast<cx<double>*>(w.pwork), w.alpha, p->n[0], p->T, p->m[0], 1,
-        1.0 / std::sqrt((double)p->n[0]), p->d_gen, p->d_colshift, w.P, kd0, nullptr, st));
+    const int nv = p->equal ? p->T : 1;
+    for (int t = 0; t < p->T; t += nv) {
+      LAUNCH_OK(launch_lat_adjoint<double, double>(
+          LAT_SINK_REAL, reinterpret_cast<const cx<double>*>(w.ahat) + p->off[t],
+          reinterpret_cast<cx<double>*>(w.pwork) + p->off[t], w.alpha + p->off[t], p->n[t], nv,
+          p->m[t], 1, 1.0 / std::sqrt((double)p->n[t]), p->d_gen, p->d_colshift, w.P, kd0, nullptr,
+          st));
+    }
     alpha = w.alpha;
   } else {
     // alpha_t = V_{m_t} ahat_t = H ahat_t / sqrt(n_t) (digital sequences: V real symmetric)

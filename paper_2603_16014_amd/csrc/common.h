@@ -43,6 +43,8 @@ struct Params {
 // Static description of a plan that kernels need, passed by value.
 struct KDesc {
   int T, d, family, order, adaptive, s, profile;
+  int unequal;        // nested unequal sizes (Algorithm 1 path)
+  int m[MTGP_MAXT];   // per-task log2 sizes
 };
 
 // ---------------------------------------------------------------------------
@@ -252,6 +254,13 @@ __device__ inline void lds_fwht(Real* lds, int nseq, int L, int stride) {
     lo += r;
   }
   __syncthreads();
+}
+
+// Records a non-positive or non-finite pivot: status[0] |= 1 and the smallest
+// offending index in the 64-bit word at status + 2.
+__device__ inline void flag_bad(int* status, int64_t idx) {
+  atomicOr(status, 1);
+  atomicMin(reinterpret_cast<unsigned long long*>(status + 2), (unsigned long long)idx);
 }
 
 // ---------------------------------------------------------------------------

@@ -95,8 +95,8 @@ int launch_solve_eq_c(SR* cols, int64_t n, const PairMap& pm, const double* yhat
                       const KDesc& kd, bool grad, double* partials, double* ahat, int* status,
                       hipStream_t st);
 int launch_finalize(const double* solve_partials, int nsolve, const double* adj_partials, int nadj,
-                    const double* yhat0, int64_t n, Params* P, const KDesc& kd, double* out3,
-                    double* grad, double* tau_hat, hipStream_t st);
+                    const double* ld_partials, int nld, const double* yhat0, int64_t n, Params* P,
+                    const KDesc& kd, double* out3, double* grad, double* tau_hat, hipStream_t st);
 
 // ---- points.hip
 int launch_gen_points(const uint32_t* gen, const uint32_t* shift, int family, int d, int m,
@@ -129,5 +129,27 @@ int launch_lat_adjoint(int sink, const cx<SR>* spec, cx<CR>* work, double* real_
                        int64_t vstride, int nvec, int m, int conj_in, double scale,
                        const uint32_t* gen, const uint32_t* colshift, const Params* P,
                        const KDesc& kd, double* partials, hipStream_t st);
+
+// ---- alg1.hip
+constexpr int MTGP_MAXCOL = MTGP_MAXT + MTGP_MAXT * (MTGP_MAXT - 1) / 2;
+struct z2 {
+  double x, y;
+};
+struct Alg1Desc {
+  int T, profile;
+  int m[MTGP_MAXT];
+  int64_t msz[MTGP_MAXT];        // block size after stage s: sum_{t<=s} n_t / n_s
+  int64_t stage_off[MTGP_MAXT];  // offset of stage s in the log-pivot buffer
+  int64_t task_off[MTGP_MAXT];   // offset of task t in yhat / ahat (elements)
+  int8_t pair_col[MTGP_MAXT][MTGP_MAXT];
+  int8_t diag_first[MTGP_MAXT];  // first task with the same length
+  int col_m[MTGP_MAXCOL];
+  int64_t col_off[MTGP_MAXCOL];
+};
+constexpr int64_t ALG1_MAX_BLOCK = 2048;  // largest final block N / n_T handled
+template <typename SR>
+int launch_alg1(SR* cols, const Alg1Desc& A1, Params* P, int family, bool grad,
+                const double* yhat, z2* bufA, z2* bufB, double* logs, double* ahat,
+                double* partials, int* status, hipStream_t st);
 
 }  // namespace mtgp

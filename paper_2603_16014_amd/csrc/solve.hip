@@ -56,10 +56,6 @@ int launch_prep(const double* theta, Params* P, const KDesc& kd, int* status, hi
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-__device__ inline void flag_bad(int* status, int64_t idx) {
-  atomicOr(status, 1);
-  atomicMin(reinterpret_cast<unsigned long long*>(status + 2), (unsigned long long)idx);
-}
 
 template <int TM>
 __device__ constexpr int pk(int i, int j) {
@@ -444,6 +440,7 @@ template int launch_solve_eq_c<float>(float*, int64_t, const PairMap&, const dou
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ sp, int nsolve,
                                                        const double* __restrict__ ap, int nadj,
+                                                       const double* __restrict__ lp, int nld,
                                                        const double* __restrict__ yhat, int64_t n,
                                                        Params* __restrict__ P, KDesc kd,
                                                        double* __restrict__ out3,
@@ -467,9 +464,13 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
     v = block_sum(v, red);
     if (threadIdx.x == 0) sums[ns + q] = v;
   }
+  double ldx = 0.0;  // log pivots of the elimination stages (unequal sizes)
+  if (lp)
+    for (int b = threadIdx.x; b < nld; b += blockDim.x) ldx += lp[b];
+  ldx = block_sum(ldx, red);
   __syncthreads();
   if (threadIdx.x != 0) return;
-  const double quad = sums[0], logdet = sums[1];
+  const double quad = sums[0], logdet = sums[1] + ldx;
   out3[0] = quad;
   out3[1] = logdet;
   out3[2] = quad + logdet;
@@ -478,7 +479,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   const int qX = 2 + TMp * (TMp + 1) / 2, qA = qX + TMp;
   for (int t = 0; t < T; t++) {
     const int64_t y0 = (int64_t)t * n * (kd.family == FAM_LAT ? 2 : 1);
-    const double tu = kd.profile ? yhat[y0] / sqn : P->tau[t];
+    const double tu = kd.unequal ? P->tau_used[t] : (kd.profile ? yhat[y0] / sqn : P->tau[t]);
     P->tau_used[t] = tu;
     if (tau_hat) tau_hat[t] = tu;
   }
@@ -488,7 +489,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
     return sums[2 + a * (a + 1) / 2 + b];
   };
   int o = 0;
-  for (int t = 0; t < T; t++) grad[o + t] = kd.profile ? 0.0 : -2.0 * sqn * sums[qA + t];
+  for (int t = 0; t < T; t++)
+    grad[o + t] = kd.profile ? 0.0 : -2.0 * sqrt(ldexp(1.0, kd.m[t])) * sums[qA + t];
   o += T;
   double gg = 0.0;
   for (int t = 0; t < T; t++)
@@ -534,10 +536,10 @@ int launch_colsum(const double* in, int64_t nrows, int ncols, double* out, int n
 }
 
 int launch_finalize(const double* solve_partials, int nsolve, const double* adj_partials, int nadj,
-                    const double* yhat0, int64_t n, Params* P, const KDesc& kd, double* out3,
-                    double* grad, double* tau_hat, hipStream_t st) {
+                    const double* ld_partials, int nld, const double* yhat0, int64_t n, Params* P,
+                    const KDesc& kd, double* out3, double* grad, double* tau_hat, hipStream_t st) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, st, solve_partials, nsolve,
-                     adj_partials, nadj, yhat0, n, P, kd, out3, grad, tau_hat);
+                     adj_partials, nadj, ld_partials, nld, yhat0, n, P, kd, out3, grad, tau_hat);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -151,6 +151,14 @@ CASES = [
     ("lat", 3, [7, 7, 7], 3, 1, False, False, None),
     ("lat", 4, [8, 8, 8, 8], 6, 2, False, True, None),
     ("lat", 2, [9, 9], 4, 3, False, False, None),
+    # nested unequal sizes (elimination in task order)
+    ("dseq", 3, [3, 2, 1], 2, 2, False, True, None),
+    ("dseq", 3, [8, 6, 5], 2, 2, False, False, None),
+    ("dseq", 5, [9, 7, 5, 3, 1], 8, 4, False, True, None),
+    ("dseq", 4, [9, 8, 8, 6], 3, 2, True, True, (4, 2, 4096)),
+    ("dseq", 2, [10, 6], 3, 1, False, False, None),
+    ("lat", 3, [7, 5, 4], 3, 2, False, True, None),
+    ("lat", 4, [8, 7, 7, 5], 2, 1, False, False, None),
 ]
 
 
@@ -255,7 +263,9 @@ def test_config1_fp64_against_extended_precision():
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("family,T,m,d,adaptive", [("dseq", 3, [7, 7, 7], 3, False),
                                                    ("dseq", 2, [8, 8], 5, True),
-                                                   ("lat", 3, [7, 7, 7], 3, False)])
+                                                   ("lat", 3, [7, 7, 7], 3, False),
+                                                   ("dseq", 3, [8, 6, 4], 3, False),
+                                                   ("lat", 3, [8, 6, 5], 2, False)])
 def test_predict_parity(precision, family, T, m, d, adaptive):
     w = tiny(family, T, m, d, adaptive=adaptive, seed=41)
     say("predict", family, T, m, d, adaptive, precision)
