@@ -216,6 +216,23 @@ size_t mtgp_predict_net_scratch_bytes(const mtgp_plan* plan, int32_t m_star);
 int mtgp_predict_net(const mtgp_plan* plan, const double* theta, const uint32_t* shift_star,
                      int32_t m_star, double* mean, void* ws, void* scratch, void* stream);
 
+/* Many independent fits: mtgp_nll_grad for fit i = 0 .. nfits-1 with its own
+ * plan, theta, outputs and workspace, all enqueued on one stream (host
+ * arrays of device pointers).  Calls into it may be captured once in a HIP
+ * graph and replayed (the library never synchronises or allocates), which
+ * removes the per-launch host cost of many small fits. */
+int mtgp_nll_grad_batched(int32_t nfits, mtgp_plan* const* plans, const double* const* thetas,
+                          double* const* out3, double* const* grads, void* const* ws,
+                          void* stream);
+
+/* One Adam step on the packed theta (device, length n <= 4096) with moments
+ * m1, m2 (device, zero before the first step) and a device step counter
+ * (int64, incremented by the call); entries with frozen[i] != 0 (device, may
+ * be NULL) are left unchanged.  Graph-capturable. */
+int mtgp_adam_step(double* theta, const double* grad, double* m1, double* m2, int64_t n, double lr,
+                   double beta1, double beta2, double eps, int64_t* step, const uint8_t* frozen,
+                   void* stream);
+
 /* Reads the device status word of ws (synchronously, after the caller has
  * synchronised the stream).  Returns MTGP_OK or MTGP_ENOTPD; *bad_index (may
  * be NULL) receives the first frequency (or residue class) whose pivot was

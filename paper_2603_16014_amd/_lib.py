@@ -47,6 +47,11 @@ SIGNATURES = {
     "mtgp_predict_net_scratch_bytes": (c_sz, [vp, c_i32]),
     "mtgp_predict_net": (ctypes.c_int, [vp, vp, ctypes.POINTER(c_u32), c_i32, vp, vp, vp, vp]),
     "mtgp_status": (ctypes.c_int, [vp, vp, ctypes.POINTER(c_i64)]),
+    "mtgp_nll_grad_batched": (ctypes.c_int, [c_i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                             ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                             ctypes.POINTER(vp), vp]),
+    "mtgp_adam_step": (ctypes.c_int, [vp, vp, vp, vp, c_i64, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, vp, vp, vp]),
     "mtgp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
 

@@ -740,16 +740,89 @@ int mtgp_predict(const mtgp_plan* p, const double* theta, const uint32_t* xs, in
   return MTGP_OK;
 }
 
+// scratch: T test-net columns of length max(n*, n_u) (FP64), T x n* folded
+// spectra, the pair-shift table
+static size_t prednet_layout(const mtgp_plan* p, int m_star, PredNet& pn, size_t& o_w,
+                             size_t& o_sh) {
+  pn.T = p->T;
+  pn.m_star = m_star;
+  size_t o = 0;
+  for (int u = 0; u < p->T; u++) {
+    pn.m[u] = p->m[u];
+    pn.col_off[u] = (int64_t)(o / sizeof(double));
+    pn.task_off[u] = p->off[u];
+    const int L = m_star > p->m[u] ? m_star : p->m[u];
+    o += ((size_t)1 << L) * sizeof(double);
+  }
+  o = align_up(o);
+  o_w = o;
+  o = align_up(o + ((size_t)1 << m_star) * p->T * sizeof(double));
+  o_sh = o;
+  o = align_up(o + (size_t)p->T * p->d * sizeof(uint32_t));
+  return o;
+}
+
 size_t mtgp_predict_net_scratch_bytes(const mtgp_plan* p, int32_t m_star) {
-  (void)p; (void)m_star;
-  return 0;
+  if (!p || m_star < 0 || m_star > 30) return 0;
+  PredNet pn;
+  size_t ow, osh;
+  return prednet_layout(p, m_star, pn, ow, osh);
 }
 
 int mtgp_predict_net(const mtgp_plan* p, const double* theta, const uint32_t* shift_star,
                      int32_t m_star, double* mean, void* ws, void* scratch, void* stream) {
-  (void)p; (void)theta; (void)shift_star; (void)m_star; (void)mean; (void)ws; (void)scratch;
-  (void)stream;
-  return MTGP_ENOTSUP;
+  if (!p || !theta || !shift_star || !mean || !ws || !scratch || m_star < 0 || m_star > 30)
+    return MTGP_EINVAL;
+  if (p->family != MTGP_DSEQ) return MTGP_ENOTSUP;
+  hipStream_t st = (hipStream_t)stream;
+  const WsView w = view(p, ws);
+  // loss pass with ahat (and tau_used) at theta
+  int rc = dispatch_loss(p, theta, w.misc, nullptr, nullptr, ws, st, true);
+  if (rc) return rc;
+  PredNet pn;
+  size_t o_w, o_sh;
+  prednet_layout(p, m_star, pn, o_w, o_sh);
+  unsigned char* sb = static_cast<unsigned char*>(scratch);
+  double* lam = reinterpret_cast<double*>(sb);
+  double* wbuf = reinterpret_cast<double*>(sb + o_w);
+  uint32_t* shd = reinterpret_cast<uint32_t*>(sb + o_sh);
+  std::vector<uint32_t> sh((size_t)p->T * p->d);
+  for (int u = 0; u < p->T; u++)
+    for (int j = 0; j < p->d; j++) sh[(size_t)u * p->d + j] = shift_star[j] ^ p->shift[(size_t)u * p->d + j];
+  LAUNCH_OK(launch_prednet_shifts(sh.data(), (int)sh.size(), shd, st));
+  const KDesc kd = p->kd();
+  for (int u = 0; u < p->T; u++) {
+    const int L = m_star > p->m[u] ? m_star : p->m[u];
+    double* col = lam + pn.col_off[u];
+    LAUNCH_OK(launch_gen_fwd<double, double>(col, (int64_t)1 << L, 1, L, p->d_gen,
+                                             shd + (size_t)u * p->d, w.P, kd, p->sched, st));
+    LAUNCH_OK(launch_strided<double, double, double>(col, col, col, (int64_t)1 << L, 1, L,
+                                                     p->sched, st));
+  }
+  LAUNCH_OK(launch_prednet_fold(lam, pn, w.ahat, w.P, wbuf, st));
+  LAUNCH_OK(launch_fwht<double>(wbuf, (int64_t)1 << m_star, p->T, m_star, p->sched, st));
+  LAUNCH_OK(launch_prednet_out(wbuf, pn, w.P, mean, st));
+  return MTGP_OK;
+}
+
+int mtgp_nll_grad_batched(int32_t nfits, mtgp_plan* const* plans, const double* const* thetas,
+                          double* const* out3, double* const* grads, void* const* ws,
+                          void* stream) {
+  if (nfits < 0 || (nfits > 0 && (!plans || !thetas || !out3 || !grads || !ws))) return MTGP_EINVAL;
+  for (int i = 0; i < nfits; i++) {
+    const int rc = mtgp_nll_grad(plans[i], thetas[i], out3[i], grads[i], nullptr, ws[i], stream);
+    if (rc) return rc;
+  }
+  return MTGP_OK;
+}
+
+int mtgp_adam_step(double* theta, const double* grad, double* m1, double* m2, int64_t n, double lr,
+                   double beta1, double beta2, double eps, int64_t* step, const uint8_t* frozen,
+                   void* stream) {
+  if (!theta || !grad || !m1 || !m2 || !step || n < 0 || n > 4096) return MTGP_EINVAL;
+  LAUNCH_OK(launch_adam(theta, grad, m1, m2, n, lr, beta1, beta2, eps, step, frozen,
+                        (hipStream_t)stream));
+  return MTGP_OK;
 }
 
 int mtgp_status(const mtgp_plan* p, const void* ws, int64_t* bad_index) {

@@ -152,4 +152,22 @@ int launch_alg1(SR* cols, const Alg1Desc& A1, Params* P, int family, bool grad,
                 const double* yhat, z2* bufA, z2* bufB, double* logs, double* ahat,
                 double* partials, int* status, hipStream_t st);
 
+// ---- optim.hip
+int launch_adam(double* theta, const double* grad, double* m1, double* m2, int64_t n, double lr,
+                double b1, double b2, double eps, int64_t* step, const uint8_t* frozen,
+                hipStream_t st);
+
+// ---- prednet.hip
+struct PredNet {
+  int T, m_star;
+  int m[MTGP_MAXT];
+  int64_t col_off[MTGP_MAXT];   // test-net column of task u in the scratch buffer
+  int64_t task_off[MTGP_MAXT];  // ahat of task u
+};
+int launch_prednet_shifts(const uint32_t* host_shifts, int count, uint32_t* dev, hipStream_t st);
+int launch_prednet_fold(const double* lam, const PredNet& pn, const double* ahat, const Params* P,
+                        double* w, hipStream_t st);
+int launch_prednet_out(const double* w, const PredNet& pn, const Params* P, double* mean,
+                       hipStream_t st);
+
 }  // namespace mtgp

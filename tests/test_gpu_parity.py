@@ -311,3 +311,27 @@ def test_not_pd_reported():
     # a valid call afterwards clears the status
     plan.nll(plan.pack_theta(w.theta))
     assert plan.status() == (0, -1)
+
+
+# -------------------------------------------------------- structured test net
+@pytest.mark.parametrize("m,m_star,precision", [
+    ([8, 8], 6, "fp64"), ([8, 8], 10, "fp64"), ([8, 8], 8, "fp64"),
+    ([8, 6, 4], 5, "fp64"), ([8, 6, 4], 9, "mixed"), ([7, 7, 7], 4, "mixed")])
+def test_predict_net_against_oracle(m, m_star, precision):
+    w = tiny("dseq", len(m), m, 3, seed=71, xi=1e-3)
+    say("predict_net", m, m_star, precision)
+    rng = np.random.default_rng(9)
+    shift_star = workloads.random_shifts(rng, 1, w.d)[0]
+    Xs = points.dseq_points(w.gen, 1 << m_star, shift_star)
+    ref = oracle_for(w, want_grad=False)
+    from oracle import dense
+    mu_ref = dense.posterior_mean(w, ref["y"], Xs, X=ref["X"], res=ref["res"])
+    plan = mt.Plan.from_workload(w, precision)
+    theta = plan.pack_theta(w.theta)
+    plan.set_data(torch.from_numpy(ref["y"]).cuda())
+    mean = plan.predict_net(theta, shift_star, m_star).cpu().numpy()
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    assert rel_err(mean, mu_ref) < tol, rel_err(mean, mu_ref)
+    # the direct sum at the same points agrees as well
+    direct = plan.predict(theta, mt.digits_to_device(Xs)).cpu().numpy()
+    assert rel_err(direct, mean) < tol
