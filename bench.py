@@ -3,18 +3,28 @@ hot path at T=8 tasks x n=2^24 digitally shifted digital-net points per task
 (d=10, order-2 DSI product kernel, low-rank + diagonal task covariance),
 on one MI355X.
 
-One step = one mtgp_nll_grad call: kernel columns, forward transforms,
-per-frequency 8x8 factorisations, loss, adjoint transforms and the
-derivative reduction (the data transform yhat is computed once per data set
-by mtgp_set_data, outside the timed region).  Inputs are seeded and
-synthetic; they are resident in HBM before timing starts.
+One step = one mtgp_nll_grad call: kernel columns fused with the low-bit
+forward transform pass, the high-bit pass, the per-frequency 8x8
+factorisations, loss, the adjoint transform passes fused with the derivative
+reduction, and the final reductions (the data transform yhat is computed once
+per data set by mtgp_set_data, outside the timed region).  Inputs are seeded
+and synthetic and resident in HBM before timing starts.
 
-Prints one JSON line (see the README of the measurement contract in the
-design notes): evals/s of the primary path, the FP64 path beside it, the
-mixed-vs-FP64 differences, a roofline entry for the dominant kernel and the
-dense CPU oracle timed on a bounded sample.
+Prints one JSON line: evals/s of the primary (mixed) path, the FP64 path
+beside it, the mixed-vs-FP64 differences, per-kernel durations from HIP
+events recorded on the launch stream inside the timed region, a roofline
+entry for the dominant kernel, and the dense CPU oracle timed on a bounded
+sample.
+
+``python bench.py --pmc-summary FETCH_DIR WRITE_DIR TRACE_DIR`` turns the CSV
+output of three rocprofv3 runs of this script (``--pmc FETCH_SIZE``,
+``--pmc WRITE_SIZE``, ``--kernel-trace --stats``) into the markdown summary
+kept under profiles/, whose JSON block is read back for ``traffic``.
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import math
 import os
@@ -26,16 +36,37 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
-import torch  # noqa: E402
 
-import workloads  # noqa: E402
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
+COPY_PROBE_BYTES = 1 << 30     # plain streaming kernel used to scale the HBM counters
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_loss_grad_T8_d10_n2e24_mixed.md")
 
-HBM_PEAK_GBS = 8000.0
-FP64_VALU_PEAK_TFLOPS = 78.6
+# phase -> (kernel-name pattern in rocprofv3 output, bound)
+PHASE_KERNELS = {
+    "gen_fwd_low": ("gen_fwd_kernel", "alu"),
+    "fwd_high": ("fwht_strided_kernel<double, double, float>", "hbm"),
+    "solve": ("solve_eq_kernel", "hbm"),
+    "adj_high": ("fwht_strided_kernel<double, float, double>", "hbm"),
+    "adj_low_reduce": ("adj_reduce_kernel", "alu"),
+}
+
+
+def kernel_sources_digest():
+    """Digest of the HIP sources; a counter summary is stale once it changes."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2603_16014_amd", "csrc", "*")))
+    for f in files:
+        if f.endswith((".hip", ".h")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def targets_on_device(plan, w):
     """Seeded targets of the workload, built on the GPU from the plan's points."""
+    import torch
     rng = np.random.default_rng(w.seed + 1000)
     p = w.target_params
     ys = []
@@ -60,7 +91,25 @@ def targets_on_device(plan, w):
     return torch.cat(ys)
 
 
+def copy_probe():
+    """One plain streaming kernel (read B bytes, write B bytes) of known size,
+    so that HBM byte counters of the other kernels can be scaled by what the
+    same counters read for it."""
+    import torch
+    src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+
+
 def time_evals(plan, theta, steps, warmup):
+    """K timed evaluations bracketed by device synchronisation; per-phase
+    durations come from the library's HIP events recorded on the same stream
+    in the same timed region (no host wait between steps)."""
+    import torch
     out3 = torch.empty(3, dtype=torch.float64, device="cuda")
     grad = torch.empty(plan.theta_size, dtype=torch.float64, device="cuda")
     tau = torch.empty(plan.T, dtype=torch.float64, device="cuda")
@@ -72,29 +121,65 @@ def time_evals(plan, theta, steps, warmup):
     e1 = torch.cuda.Event(enable_timing=True)
     plan.enable_timing(True)
     e0.record(st)
-    phases = None
     for i in range(steps):
         plan.nll_grad(theta, out3, grad, tau)
-        ph = plan.phase_times()
-        phases = ph if phases is None else {k: phases[k] + ph[k] for k in ph}
     e1.record(st)
     torch.cuda.synchronize()
+    # the event ring holds the 64 most recent steps
+    phases = plan.phase_times()
+    done = min(steps, 64)
     plan.enable_timing(False)
     ms = e0.elapsed_time(e1) / steps
-    phases = {k: v / steps for k, v in phases.items()}
     code, bad = plan.status()
     if code != 0:
         raise RuntimeError(f"status {code} at frequency {bad}")
-    return ms, out3.cpu().numpy(), grad.cpu().numpy(), tau.cpu().numpy(), phases
+    return ms, out3.cpu().numpy(), grad.cpu().numpy(), tau.cpu().numpy(), phases, done
 
 
-def cpu_baseline(w, budget_s=20.0):
-    """Dense oracle (loss + gradient) on a scaled copy of the workload."""
+def algo_units(w, precision, a_bits=12):
+    """Algorithmic HBM bytes (and FP64 flops for the fused evaluation kernels)
+    per launch of each phase at this workload: P distinct kernel columns of
+    length n, forward working values of wb bytes, spectrum / adjoint weights
+    of sb bytes."""
+    T, d, n, P = w.T, w.d, 1 << w.m[0], 1 + w.T * (w.T - 1) // 2
+    wb, sb = {"fp64": (8, 8), "mixed": (8, 4), "f32": (4, 4)}[precision]
+    lb = min(a_bits, w.m[0])  # width of the low-bit (LDS) transform pass
+    return {
+        # write the low-bit transformed columns; flops: kernel factor 2 FMA +
+        # 1 FMA + product 1 mul per (element, dimension), lb butterfly adds
+        "gen_fwd_low": {"bytes": P * n * wb, "flops": P * n * (7 * d + lb)},
+        "fwd_high": {"bytes": P * n * (wb + sb)},        # read work, write spectrum
+        "solve": {"bytes": P * n * 2 * sb + T * n * 8},  # read spectrum + yhat, write weights
+        "adj_high": {"bytes": P * n * (sb + wb)},        # read weights, write work
+        # read the partly transformed weights; flops: lb butterflies, kernel factor 6, prefix and
+        # suffix products 2, product with the weight 2, accumulation 2 per dim
+        "adj_low_reduce": {"bytes": P * n * (wb if w.m[0] > lb else sb),
+                           "flops": P * n * (12 * d + lb)},
+    }
+
+
+def load_traffic(precision):
+    """HBM bytes per launch of each kernel from the committed counter summary,
+    or None when it is missing, for another precision, or stale."""
+    if precision != "mixed" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    if "```json" not in txt:
+        return None
+    blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+    if blob.get("sources_digest") != kernel_sources_digest():
+        return None
+    return {k: v["hbm_bytes"] for k, v in blob.get("phases", {}).items()}
+
+
+def cpu_baseline(w, budget_s=25.0):
+    """Dense FP64 oracle (loss + gradient) on a scaled copy of the workload."""
+    import workloads
     from oracle import dense, points
     import threadpoolctl
     info = threadpoolctl.threadpool_info()
     threads = max([i.get("num_threads", 1) for i in info] + [1])
-    m = 8
+    m = 9
     ws = workloads.scaled(w, [m] * w.T)
     X = points.task_points(ws)
     y = dense.targets(ws, np.random.default_rng(1), X)
@@ -104,19 +189,224 @@ def cpu_baseline(w, budget_s=20.0):
         dense.grad(ws, y, X=X)
         reps += 1
         el = time.perf_counter() - t0
-        if el > budget_s / 4 or reps >= 3:
+        if el > budget_s / 2 or reps >= 3:
             break
     per = el / reps
-    N_s = ws.N
-    N_full = w.N
-    # dense Cholesky + dense gradient are O(N^3): extrapolate to the full size
+    N_s, N_full = ws.N, w.N
     per_full = per * (N_full / N_s) ** 3
     return {"value": 1.0 / per_full, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"dense FP64 oracle loss+gradient at T={w.T}, d={w.d}, n=2^{m} per task "
-                      f"(N={N_s}): {per:.3f} s/eval measured over {reps} evals; value is that "
-                      f"rate extrapolated by (N_full/N_sample)^3 to N={N_full} (O(N^3) "
-                      f"extrapolation, not measured)",
-            "measured_sample_evals_per_s": 1.0 / per}
+                      f"(N={N_s}), {reps} evals in {el:.1f} s = {per:.2f} s/eval; value = that "
+                      f"rate scaled by the dense O(N^3) cost to N={N_full} (extrapolated, the "
+                      f"dense Gram matrix at full N would need {8 * N_full ** 2 / 2 ** 50:.0f} PiB)",
+            "sample_evals_per_s": 1.0 / per}
+
+
+def run(args):
+    import torch
+    import workloads
+    from paper_2603_16014_amd import mtgp
+
+    w = workloads.config5()
+    if args.m != 24:
+        w = workloads.scaled(w, [args.m] * w.T)
+    copy_probe()
+    results = {}
+    y = None
+    for prec in args.precisions.split(","):
+        sched = tuple(int(v) for v in args.sched.split(",")) if args.sched else None
+        plan = mtgp.Plan.from_workload(w, prec, schedule=sched)
+        if y is None:
+            y = targets_on_device(plan, w)
+        plan.set_data(y)
+        theta = plan.pack_theta(w.theta)
+        ms, out3, grad, tau, phases, nph = time_evals(plan, theta, args.steps, args.warmup)
+        results[prec] = dict(ms=ms, out3=out3, grad=grad, phases=phases, nph=nph)
+        del plan
+        torch.cuda.empty_cache()
+    primary = "mixed" if "mixed" in results else args.precisions.split(",")[0]
+    r = results[primary]
+    T, n = w.T, 1 << w.m[0]
+    extra = {}
+    if "fp64" in results and "mixed" in results:
+        a, b = results["mixed"], results["fp64"]
+        den = abs(b["out3"][0]) + abs(b["out3"][1])
+        extra["mixed_vs_fp64"] = {
+            "L_rel": float(abs(a["out3"][2] - b["out3"][2]) / den),
+            "grad_rel_maxnorm": float(np.abs(a["grad"] - b["grad"]).max() / np.abs(b["grad"]).max()),
+        }
+        extra["fp64_evals_per_s"] = 1000.0 / b["ms"]
+        extra["fp64_ms_per_step"] = b["ms"]
+        extra["fp64_phases_ms"] = {k: round(v, 4) for k, v in b["phases"].items()}
+    ph = r["phases"]
+    units = algo_units(w, primary, int(args.sched.split(",")[0]) if args.sched else 12)
+    traffic = load_traffic(primary) if args.m == 24 and not args.sched else None
+    kernels = {}
+    for k, (pat, bound) in PHASE_KERNELS.items():
+        if k not in ph or ph[k] <= 0:
+            continue
+        u = units[k]
+        e = {"kernel": pat, "ms": round(ph[k], 4), "bound": bound,
+             "GB_s": u["bytes"] / (ph[k] * 1e-3) / 1e9}
+        e["hbm_frac"] = e["GB_s"] / HBM_PEAK_GBS
+        if "flops" in u:
+            e["TFLOP_s"] = u["flops"] / (ph[k] * 1e-3) / 1e12
+            e["fp64_frac"] = e["TFLOP_s"] / FP64_VALU_PEAK_TFLOPS
+        if traffic and k in traffic:
+            e["traffic"] = traffic[k]
+        kernels[k] = e
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    kd = kernels[dom]
+    if kd["bound"] == "hbm":
+        roof = {"bound": "hbm", "kernel": kd["kernel"], "achieved": kd["GB_s"],
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kd["hbm_frac"]}
+    else:
+        roof = {"bound": "alu", "kernel": kd["kernel"], "achieved": kd["TFLOP_s"],
+                "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": kd["fp64_frac"]}
+    roof["traffic"] = kd.get("traffic")
+    line = {
+        "metric": "NLL+grad evals/sec at T=8,n=2^24",
+        "value": 1000.0 / r["ms"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"mixed": "f64 arithmetic, f32 spectrum storage", "fp64": "f64",
+                  "f32": "f32"}[primary],
+        "data": "synthetic",
+        "config": {"workload": f"fast MTGP loss+gradient, digitally shifted digital nets, T={T}, "
+                               f"d={w.d}, n=2^{w.m[0]} per task (N={w.N}), order-2 DSI kernel, "
+                               f"rank-2 + diagonal task covariance, {primary} path",
+                   "T": T, "d": w.d, "n_per_task": n, "N": w.N, "precision": primary},
+        "phases_ms": {k: round(v, 4) for k, v in ph.items()},
+        "phase_steps_timed": r["nph"],
+        "kernels": kernels,
+        "roofline": roof,
+    }
+    line.update(extra)
+    if args.sched:
+        line["schedule"] = args.sched
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+# --------------------------------------------------------------------------
+# rocprofv3 CSV -> markdown summary
+# --------------------------------------------------------------------------
+def _csv_rows(d, suffix):
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _phase_of(name, cur):
+    """Phase of a library kernel given the phase of the previous dispatch of
+    the same evaluation (the order is fixed: prep, generation + low pass,
+    high passes, solve, adjoint high passes, adjoint low pass + reduction,
+    partial-sum reductions and chain rule)."""
+    if "mtgp::prep_kernel" in name:
+        return "prep"
+    if "gen_fwd_kernel" in name or "lat_pass" in name and cur == "prep":
+        return "gen_fwd_low"
+    if "fwht_strided_kernel" in name:
+        return "fwd_high" if cur in ("gen_fwd_low", "fwd_high") else "adj_high"
+    if "solve_eq" in name or "alg1_" in name:
+        return "solve"
+    if "adj_reduce_kernel" in name:
+        return "adj_low_reduce"
+    if "colsum_kernel" in name or "finalize_kernel" in name:
+        return "finalize"
+    return None
+
+
+def _per_eval(rows, value):
+    """Mean over complete evaluations of the per-phase sum of value(row)."""
+    evals, cur, acc = [], None, None
+    for row in sorted(rows, key=lambda r: int(r["Dispatch_Id"])):
+        name = row["Kernel_Name"]
+        ph = _phase_of(name, cur)
+        if ph == "prep":
+            if acc is not None and "finalize" in acc:
+                evals.append(acc)
+            acc = {}
+        if ph is None or acc is None:
+            continue
+        cur = ph
+        v, k = value(row)
+        a = acc.setdefault(ph, [0.0, 0, set()])
+        a[0] += v
+        a[1] += 1
+        a[2].add(name.split("(")[0].replace("void ", ""))
+    if acc is not None and "finalize" in acc:
+        evals.append(acc)
+    if not evals:
+        return {}, 0
+    out = {}
+    for ph in evals[-1]:
+        vals = [e[ph][0] for e in evals if ph in e]
+        out[ph] = (sum(vals) / len(vals), evals[-1][ph][1], sorted(evals[-1][ph][2]))
+    return out, len(evals)
+
+
+def pmc_summary(fetch_dir, write_dir, trace_dir, cmdline):
+    fetch_rows = [r for r in _csv_rows(fetch_dir, "counter_collection.csv")
+                  if r.get("Counter_Name") == "FETCH_SIZE"]
+    write_rows = [r for r in _csv_rows(write_dir, "counter_collection.csv")
+                  if r.get("Counter_Name") == "WRITE_SIZE"]
+    trace_rows = _csv_rows(trace_dir, "kernel_trace.csv")
+    stats = _csv_rows(trace_dir, "kernel_stats.csv")
+
+    def probe(rows):
+        v = [float(r["Counter_Value"]) for r in rows if "neg_kernel" in r["Kernel_Name"]]
+        if not v:
+            raise SystemExit("copy probe kernel not found in the counter output")
+        return v[0]
+    kib = COPY_PROBE_BYTES / 1024.0
+    pf, pw = probe(fetch_rows), probe(write_rows)
+    sf, sw = kib / pf, kib / pw
+    fetch, nf = _per_eval(fetch_rows, lambda r: (float(r["Counter_Value"]), 1))
+    write, nw = _per_eval(write_rows, lambda r: (float(r["Counter_Value"]), 1))
+    dur, nt = _per_eval(trace_rows, lambda r: ((int(r["End_Timestamp"]) -
+                                                int(r["Start_Timestamp"])) * 1e-3, 1))
+    out = ["# HBM traffic and kernel durations: loss + gradient, T=8, d=10, n=2^24, mixed path",
+           "", "Commands (run from the repository root on one MI355X):", "", "```"]
+    out += cmdline
+    out += ["```", "",
+            f"Copy probe (torch.neg over {COPY_PROBE_BYTES} B of float32: reads and writes "
+            f"{COPY_PROBE_BYTES} B): FETCH_SIZE {pf:.0f} KiB, WRITE_SIZE {pw:.0f} KiB per "
+            f"dispatch, so bytes = FETCH_SIZE x 1024 x {sf:.4f} and WRITE_SIZE x 1024 x {sw:.4f}.",
+            "", f"Per evaluation (means over {nf} / {nw} / {nt} complete evaluations of the "
+            "FETCH, WRITE and trace runs); a phase may hold several kernel launches:", "",
+            "| phase | kernels | launches | us (trace) | FETCH KiB | WRITE KiB | HBM bytes (scaled) |",
+            "|---|---|---|---|---|---|---|"]
+    blob = {"sources_digest": kernel_sources_digest(), "scale_fetch": sf, "scale_write": sw,
+            "phases": {}}
+    for ph in ("prep", "gen_fwd_low", "fwd_high", "solve", "adj_high", "adj_low_reduce",
+               "finalize"):
+        if ph not in fetch or ph not in write:
+            continue
+        b = (fetch[ph][0] * sf + write[ph][0] * sw) * 1024.0
+        us = dur[ph][0] if ph in dur else float("nan")
+        names = ", ".join(f"`{n[:60]}`" for n in fetch[ph][2])
+        out.append(f"| {ph} | {names} | {fetch[ph][1]} | {us:.1f} | {fetch[ph][0]:.0f} | "
+                   f"{write[ph][0]:.0f} | {b:.4g} |")
+        blob["phases"][ph] = {"hbm_bytes": b, "us": us, "launches": fetch[ph][1]}
+    out += ["", "Library kernels in the trace run (rocprofv3 --stats):", "",
+            "| kernel | calls | avg us | total ms |", "|---|---|---|---|"]
+    for row in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        if "mtgp::" not in row["Name"]:
+            continue
+        out.append(f"| `{row['Name'].split('(')[0][:90]}` | {row['Calls']} | "
+                   f"{float(row['AverageNs']) / 1e3:.1f} | {float(row['TotalDurationNs']) / 1e6:.2f} |")
+    out += ["", "```json", json.dumps(blob, indent=1), "```", ""]
+    return "\n".join(out)
 
 
 def main():
@@ -129,87 +419,18 @@ def main():
     ap.add_argument("--precisions", default="fp64,mixed")
     ap.add_argument("--sched", default=None,
                     help="transform schedule a_bits,b_bits,b_tile_bytes (default: library default)")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "TRACE_DIR"))
+    ap.add_argument("--pmc-command", action="append", default=[],
+                    help="command line recorded in the summary (repeatable)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        print(pmc_summary(*args.pmc_summary, args.pmc_command))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the fast MTGP path here runs on a single "
               "MI355X (no multi-GPU sharding is built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
-    from paper_2603_16014_amd import mtgp
-
-    w = workloads.config5()
-    if args.m != 24:
-        w = workloads.scaled(w, [args.m] * w.T)
-    results = {}
-    y = None
-    for prec in args.precisions.split(","):
-        sched = tuple(int(v) for v in args.sched.split(",")) if args.sched else None
-        plan = mtgp.Plan.from_workload(w, prec, schedule=sched)
-        if y is None:
-            y = targets_on_device(plan, w)
-        plan.set_data(y)
-        theta = plan.pack_theta(w.theta)
-        ms, out3, grad, tau, phases = time_evals(plan, theta, args.steps, args.warmup)
-        results[prec] = dict(ms=ms, out3=out3, grad=grad, phases=phases,
-                             ws_bytes=int(plan.ws.numel()))
-        del plan
-        torch.cuda.empty_cache()
-    primary = "mixed" if "mixed" in results else "fp64"
-    r = results[primary]
-    T, n, P = w.T, 1 << w.m[0], 1 + w.T * (w.T - 1) // 2
-    extra = {}
-    if "fp64" in results and "mixed" in results:
-        a, b = results["mixed"], results["fp64"]
-        den = abs(b["out3"][0]) + abs(b["out3"][1])
-        extra["mixed_vs_fp64"] = {
-            "L_rel": float(abs(a["out3"][2] - b["out3"][2]) / den),
-            "grad_rel_maxnorm": float(np.abs(a["grad"] - b["grad"]).max() / np.abs(b["grad"]).max()),
-        }
-        extra["fp64_evals_per_s"] = 1000.0 / b["ms"]
-        extra["fp64_ms_per_step"] = b["ms"]
-    # roofline of the dominant kernel phase
-    ph = r["phases"]
-    dom = max(ph, key=ph.get)
-    # algorithmic HBM bytes per launch of each phase (P columns of length n):
-    # working precision wb (forward), spectrum / adjoint precision sb
-    wb, sb = (8, 8) if primary == "fp64" else (8, 4)
-    algo_bytes = {
-        "gen_fwd_low": P * n * wb,               # write the low-bit transformed columns
-        "fwd_high": P * n * (wb + sb),           # read them, write the spectrum
-        "solve": P * n * 2 * sb + T * n * 8,     # read spectrum + yhat, write adjoint weights
-        "adj_high": P * n * 2 * sb,              # read + write adjoint weights
-        "adj_low_reduce": P * n * sb,            # read adjoint weights
-    }
-    roof = None
-    if dom in algo_bytes:
-        gbs = algo_bytes[dom] / (ph[dom] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None}
-    line = {
-        "metric": "NLL+grad evals/sec at T=8,n=2^24",
-        "value": 1000.0 / r["ms"],
-        "unit": "evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": r["ms"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64" if primary == "mixed" else "f64",
-        "data": "synthetic",
-        "config": {"workload": f"fast MTGP loss+gradient, DSEQ digital nets, T={T}, d={w.d}, "
-                               f"n=2^{w.m[0]} per task (N={w.N}), order-2 DSI kernel, "
-                               f"{primary} path",
-                   "T": T, "d": w.d, "n_per_task": n, "N": w.N, "precision": primary},
-        "phases_ms": {k: round(v, 4) for k, v in ph.items()},
-        "roofline": roof,
-    }
-    line.update(extra)
-    if args.sched:
-        line["schedule"] = args.sched
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w)
-    print(json.dumps(line))
+    run(args)
 
 
 if __name__ == "__main__":

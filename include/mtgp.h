@@ -117,14 +117,19 @@ int mtgp_plan_destroy(mtgp_plan* plan);
 int mtgp_plan_set_schedule(mtgp_plan* plan, int32_t pass_a_bits, int32_t pass_b_bits,
                            int64_t pass_b_tile_bytes);
 
-/* Profiling aid (not thread safe): when enabled, mtgp_nll / mtgp_nll_grad /
- * mtgp_predict record HIP events on the caller's stream between their
- * phases; mtgp_phase_times then waits for the last event and returns the
- * duration in ms of each phase of the most recent call (ms[max_phases]);
+/* Profiling aid (not thread safe): when enabled, every loss evaluation of the
+ * plan (mtgp_nll, mtgp_nll_grad and the loss inside mtgp_predict*) records
+ * HIP events on the caller's stream between its phases, into a ring of 64
+ * event sets, so consecutive calls are timed without any host wait.
+ * mtgp_phase_times waits for the last recorded event and writes to
+ * ms[0 .. max_phases-1] the mean duration in ms of each phase over the calls
+ * recorded since the previous mtgp_phase_times (or since enabling; the 64 most
+ * recent if more), then starts a new count; all zero if none was recorded.
  * *nphases receives the number of phases, mtgp_phase_name(k) their names:
  * prep, gen_fwd_low (column generation fused with the low-bit transform
  * pass), fwd_high, solve, adj_high, adj_low_reduce (adjoint low-bit pass
- * fused with the derivative reduction), finalize. */
+ * fused with the derivative reduction), finalize (partial-sum reductions and
+ * the chain rule).  Enabling or disabling resets the count. */
 int mtgp_plan_enable_timing(mtgp_plan* plan, int32_t on);
 int mtgp_phase_times(const mtgp_plan* plan, double* ms, int32_t max_phases, int32_t* nphases);
 const char* mtgp_phase_name(int32_t k);

@@ -62,8 +62,12 @@ struct mtgp_plan {
   Alg1Desc a1;      // stage descriptors of the unequal-size elimination
   int64_t a1_ms;    // final block size N / n_T
   // optional phase timing (profiling aid; not thread safe)
+  // a ring of event sets lets many calls be timed without a host wait
+  static constexpr int kRing = 64;
   bool timing = false;
-  hipEvent_t ev[MTGP_NPHASE + 1] = {};
+  int ev_slot = 0;     // set the next call records into
+  int ev_pending = 0;  // calls recorded since the last mtgp_phase_times
+  hipEvent_t ev[kRing][MTGP_NPHASE + 1] = {};
   KDesc kd() const {
     KDesc k;
     k.T = T;
@@ -140,7 +144,16 @@ int64_t theta_size(const mtgp_plan* p) {
 }
 
 inline void mark(const mtgp_plan* p, int phase, hipStream_t st) {
-  if (p->timing) (void)hipEventRecord(p->ev[phase], st);
+  if (p->timing) (void)hipEventRecord(p->ev[p->ev_slot][phase], st);
+}
+
+// closes the event set of one timed call
+inline void mark_done(const mtgp_plan* p, hipStream_t st) {
+  if (!p->timing) return;
+  mtgp_plan* q = const_cast<mtgp_plan*>(p);
+  (void)hipEventRecord(q->ev[q->ev_slot][MTGP_NPHASE], st);
+  q->ev_slot = (q->ev_slot + 1) % mtgp_plan::kRing;
+  q->ev_pending = std::min(q->ev_pending + 1, mtgp_plan::kRing);
 }
 
 // Kernel columns and their forward transforms: arithmetic in CR, spectrum
@@ -268,17 +281,17 @@ int run_loss(const mtgp_plan* p, const double* theta, double* out3, double* grad
   if (grad) {
     nadj = adjoint_columns<CR, SR>(p, w, st);
     if (nadj < 0) return nadj;
-    LAUNCH_OK(launch_colsum(w.ap, nadj, adj_nq(p->d), w.ap2, COLSUM_BLOCKS, st));
   } else {
     mark(p, 5, st);
   }
+  mark(p, 6, st);
+  if (grad) LAUNCH_OK(launch_colsum(w.ap, nadj, adj_nq(p->d), w.ap2, COLSUM_BLOCKS, st));
   LAUNCH_OK(launch_colsum(w.sp, nsolve, solve_ns(p->T), w.sp2, COLSUM_BLOCKS, st));
   if (!p->equal) LAUNCH_OK(launch_colsum(w.logs, p->N, 1, w.lp2, COLSUM_BLOCKS, st));
-  mark(p, 6, st);
   LAUNCH_OK(launch_finalize(w.sp2, COLSUM_BLOCKS, grad ? w.ap2 : nullptr, COLSUM_BLOCKS,
                             p->equal ? nullptr : w.lp2, COLSUM_BLOCKS, w.yhat, n, w.P, kd, out3,
                             grad, tau_hat, st));
-  mark(p, 7, st);
+  mark_done(p, st);
   return MTGP_OK;
 }
 
@@ -540,23 +553,33 @@ int mtgp_plan_set_schedule(mtgp_plan* p, int32_t pass_a_bits, int32_t pass_b_bit
 
 int mtgp_plan_enable_timing(mtgp_plan* p, int32_t on) {
   if (!p) return MTGP_EINVAL;
-  if (on && !p->ev[0]) {
-    for (int k = 0; k <= MTGP_NPHASE; k++)
-      if (hipEventCreate(&p->ev[k]) != hipSuccess) return MTGP_EHIP;
+  if (on && !p->ev[0][0]) {
+    for (int s = 0; s < mtgp_plan::kRing; s++)
+      for (int k = 0; k <= MTGP_NPHASE; k++)
+        if (hipEventCreate(&p->ev[s][k]) != hipSuccess) return MTGP_EHIP;
   }
   p->timing = on != 0;
+  p->ev_pending = 0;
   return MTGP_OK;
 }
 
 int mtgp_phase_times(const mtgp_plan* p, double* ms, int32_t max_phases, int32_t* nphases) {
-  if (!p || !p->ev[0]) return MTGP_EINVAL;
+  if (!p || !p->ev[0][0] || (max_phases > 0 && !ms)) return MTGP_EINVAL;
   if (nphases) *nphases = MTGP_NPHASE;
-  if (hipEventSynchronize(p->ev[MTGP_NPHASE]) != hipSuccess) return MTGP_EHIP;
-  for (int k = 0; k < MTGP_NPHASE && k < max_phases; k++) {
-    float t = 0.f;
-    if (hipEventElapsedTime(&t, p->ev[k], p->ev[k + 1]) != hipSuccess) return MTGP_EHIP;
-    ms[k] = t;
+  const int cnt = p->ev_pending;
+  for (int k = 0; k < max_phases; k++) ms[k] = 0.0;
+  if (cnt == 0) return MTGP_OK;
+  const int last = (p->ev_slot + mtgp_plan::kRing - 1) % mtgp_plan::kRing;
+  if (hipEventSynchronize(p->ev[last][MTGP_NPHASE]) != hipSuccess) return MTGP_EHIP;
+  for (int c = 0; c < cnt; c++) {
+    const int s = (p->ev_slot + mtgp_plan::kRing - 1 - c) % mtgp_plan::kRing;
+    for (int k = 0; k < MTGP_NPHASE && k < max_phases; k++) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, p->ev[s][k], p->ev[s][k + 1]) != hipSuccess) return MTGP_EHIP;
+      ms[k] += t / cnt;
+    }
   }
+  const_cast<mtgp_plan*>(p)->ev_pending = 0;
   return MTGP_OK;
 }
 
@@ -566,8 +589,9 @@ const char* mtgp_phase_name(int32_t k) {
 
 int mtgp_plan_destroy(mtgp_plan* p) {
   if (!p) return MTGP_OK;
-  for (int k = 0; k <= MTGP_NPHASE; k++)
-    if (p->ev[k]) (void)hipEventDestroy(p->ev[k]);
+  for (int s = 0; s < mtgp_plan::kRing; s++)
+    for (int k = 0; k <= MTGP_NPHASE; k++)
+      if (p->ev[s][k]) (void)hipEventDestroy(p->ev[s][k]);
   if (p->d_gen) (void)hipFree(p->d_gen);
   if (p->d_colshift) (void)hipFree(p->d_colshift);
   if (p->d_taskshift) (void)hipFree(p->d_taskshift);

@@ -197,7 +197,8 @@ class Plan:
         _lib.check(self.lib.mtgp_plan_enable_timing(self.h, int(bool(on))), "mtgp_plan_enable_timing")
 
     def phase_times(self) -> dict:
-        """Per-phase milliseconds of the most recent evaluation (waits for it)."""
+        """Mean per-phase milliseconds over the evaluations recorded since the
+        previous call (at most the 64 most recent; waits for the last one)."""
         buf = (ctypes.c_double * 16)()
         k = ctypes.c_int32()
         _lib.check(self.lib.mtgp_phase_times(self.h, buf, 16, ctypes.byref(k)), "mtgp_phase_times")
