@@ -231,9 +231,10 @@ __global__ void alg1_tau_kernel(Alg1Desc A1, Params* P, const double* __restrict
 
 // Final residue classes r mod n_T: ahat = Lambda^-1 rhat, quad, and for the
 // gradient W = Lambda^-1 - ahat ahat^H on Lambda's pattern:
-//   omega_tu(f) = 2 sqrt(n_u/n_t) R_tu conj(W_{(t,f),(u,f mod n_u)}),
-//   omega_diag col(f) += R_tt W_{(t,f),(t,f)},  G_tu, sum_f W_tt, ahat(0).
-// Partials per block use the solve layout with TM = solve_tm(T).
+//   omega_tu(f) = 2 sqrt(n_u/n_t) conj(W_{(t,f),(u,f mod n_u)})  (t < u; R_tu
+//   is applied to the pair column's sums in the chain rule),
+//   omega_diag col(f) += R_tt W_{(t,f),(t,f)},  G_tt, sum_f W_tt, ahat(0).
+// Partials per block use the solve layout (solve_ns) with TM = solve_tm(T).
 template <typename SR, int TM>
 __global__ __launch_bounds__(256) void alg1_final_kernel(SR* __restrict__ cols, Alg1Desc A1,
                                                          const Params* P, int family, int grad,
@@ -241,8 +242,7 @@ __global__ __launch_bounds__(256) void alg1_final_kernel(SR* __restrict__ cols, 
                                                          const z2* __restrict__ Afin,
                                                          double* __restrict__ ahat,
                                                          double* __restrict__ partials) {
-  constexpr int NP = TM * (TM + 1) / 2;
-  constexpr int NQ = 2 + NP + 2 * TM;
+  constexpr int NQ = 2 + 3 * TM;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[4 * NQ];
   const int T = A1.T, s = T - 1;
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256) void alg1_final_kernel(SR* __restrict__ cols, 
     if (f == 0) {
 #pragma unroll
       for (int i = 0; i < TM; i++)
-        if (i == t) vals[2 + NP + TM + i] = ah[q].x;
+        if (i == t) vals[2 + 2 * TM + i] = ah[q].x;
     }
   }
   if (grad) {
@@ -311,8 +311,8 @@ __global__ __launch_bounds__(256) void alg1_final_kernel(SR* __restrict__ cols, 
 #pragma unroll
       for (int i = 0; i < TM; i++) {
         if (i == t) {
-          vals[2 + (i * (i + 1)) / 2 + i] += w * lam;
-          vals[2 + NP + i] += w;
+          vals[2 + i] += w * lam;
+          vals[2 + TM + i] += w;
         }
       }
       if (A1.diag_first[t] == t) {
@@ -349,13 +349,8 @@ __global__ __launch_bounds__(256) void alg1_final_kernel(SR* __restrict__ cols, 
         const z2 Atu = A[q * ms + qu];
         const z2 aa = zmc(aq, au);  // a_t conj(a_u)
         const z2 wtu = {Atu.x - aa.x, Atu.y - aa.y};
-        const z2 l = lam_at<SR>(cols, A1, family, A1.pair_col[t][u], f);
         const double sc = sqrt(ldexp(1.0, A1.m[u] - A1.m[t]));
-        const int pi = (u * (u + 1)) / 2 + t;
-#pragma unroll
-        for (int i = 0; i < NP; i++)
-          if (i == pi) vals[2 + i] += sc * (wtu.x * l.x + wtu.y * l.y);  // Re(conj(W_tu) lambda)
-        const double R2 = 2.0 * sc * P->R[t * MTGP_MAXT + u];
+        const double R2 = 2.0 * sc;
         const int c = A1.pair_col[t][u];
         const int64_t pos = A1.col_off[c] + spec_pos(family, f, A1.m[t]);
         if (family == FAM_DSEQ) {

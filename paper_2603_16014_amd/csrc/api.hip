@@ -50,6 +50,7 @@ struct mtgp_plan {
   // device tables
   uint32_t* d_gen = nullptr;
   uint32_t* d_colshift = nullptr;
+  ColInfo* d_colinfo = nullptr;  // per column: task pair, rows of the adjoint partial table
   uint32_t* d_taskshift = nullptr;
   // workspace layout (byte offsets)
   size_t o_params, o_status, o_cols, o_work, o_yhat, o_ahat, o_sp, o_sp2, o_ap, o_ap2, o_alpha,
@@ -285,10 +286,13 @@ int run_loss(const mtgp_plan* p, const double* theta, double* out3, double* grad
     mark(p, 5, st);
   }
   mark(p, 6, st);
-  if (grad) LAUNCH_OK(launch_colsum(w.ap, nadj, adj_nq(p->d), w.ap2, COLSUM_BLOCKS, st));
+  if (grad) {
+    if (nadj != p->nadj_blocks) return MTGP_EINVAL;  // table rows must match the column map
+    LAUNCH_OK(launch_colseg(w.ap, p->d_colinfo, p->ncol, adj_nq(p->d), w.ap2, st));
+  }
   LAUNCH_OK(launch_colsum(w.sp, nsolve, solve_ns(p->T), w.sp2, COLSUM_BLOCKS, st));
   if (!p->equal) LAUNCH_OK(launch_colsum(w.logs, p->N, 1, w.lp2, COLSUM_BLOCKS, st));
-  LAUNCH_OK(launch_finalize(w.sp2, COLSUM_BLOCKS, grad ? w.ap2 : nullptr, COLSUM_BLOCKS,
+  LAUNCH_OK(launch_finalize(w.sp2, COLSUM_BLOCKS, grad ? w.ap2 : nullptr, p->d_colinfo, p->ncol,
                             p->equal ? nullptr : w.lp2, COLSUM_BLOCKS, w.yhat, n, w.P, kd, out3,
                             grad, tau_hat, st));
   mark_done(p, st);
@@ -354,10 +358,37 @@ void layout(mtgp_plan* p) {
   p->o_ap = o;
   o = align_up(o + (size_t)p->nadj_blocks * adj_nq(d) * sizeof(double));
   p->o_ap2 = o;
-  o = align_up(o + (size_t)COLSUM_BLOCKS * adj_nq(d) * sizeof(double));
+  o = align_up(o + (size_t)std::max(COLSUM_BLOCKS, p->ncol) * adj_nq(d) * sizeof(double));
   p->o_misc = o;
   o = align_up(o + 4096);
   p->ws_bytes = o;
+}
+
+// Column map of the adjoint partial table (rows in the order adjoint_columns
+// writes them: groups in order, within a group column-major blocks).
+int upload_colinfo(mtgp_plan* p) {
+  std::vector<ColInfo> ci(p->ncol);
+  int64_t row = 0;
+  for (const auto& g : p->groups) {
+    const int64_t nb =
+        p->family == MTGP_LAT
+            ? lat_adj_blocks(g.m, p->precision == MTGP_F32 ? sizeof(cx<float>) : sizeof(cx<double>))
+            : ((int64_t)1 << (g.m - p->sched.lb(g.m)));
+    for (int c = g.first; c < g.first + g.count; c++) {
+      ci[c].t = p->col_t[c];
+      ci[c].u = p->col_u[c];
+      ci[c].row_off = row;
+      ci[c].row_cnt = nb;
+      row += nb;
+    }
+  }
+  if (row != p->nadj_blocks) return MTGP_EINVAL;
+  if (!p->d_colinfo && hipMalloc(&p->d_colinfo, ci.size() * sizeof(ColInfo)) != hipSuccess)
+    return MTGP_ENOMEM;
+  if (hipMemcpy(p->d_colinfo, ci.data(), ci.size() * sizeof(ColInfo), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return MTGP_EHIP;
+  return MTGP_OK;
 }
 
 bool valid_family_order(const mtgp_design* d) {
@@ -535,6 +566,11 @@ int mtgp_plan_create(const mtgp_design* des, int32_t precision, mtgp_plan** out)
     mtgp_plan_destroy(p);
     return MTGP_EHIP;
   }
+  const int rc = upload_colinfo(p);
+  if (rc != MTGP_OK) {
+    mtgp_plan_destroy(p);
+    return rc;
+  }
   *out = p;
   return MTGP_OK;
 }
@@ -548,7 +584,7 @@ int mtgp_plan_set_schedule(mtgp_plan* p, int32_t pass_a_bits, int32_t pass_b_bit
   p->sched.b_bits = pass_b_bits;
   p->sched.b_tile = (size_t)pass_b_tile_bytes;
   layout(p);
-  return MTGP_OK;
+  return upload_colinfo(p);
 }
 
 int mtgp_plan_enable_timing(mtgp_plan* p, int32_t on) {
@@ -594,6 +630,7 @@ int mtgp_plan_destroy(mtgp_plan* p) {
       if (p->ev[s][k]) (void)hipEventDestroy(p->ev[s][k]);
   if (p->d_gen) (void)hipFree(p->d_gen);
   if (p->d_colshift) (void)hipFree(p->d_colshift);
+  if (p->d_colinfo) (void)hipFree(p->d_colinfo);
   if (p->d_taskshift) (void)hipFree(p->d_taskshift);
   delete p;
   return MTGP_OK;

@@ -44,17 +44,20 @@ struct Digits {
   __device__ inline uint32_t u(int j) const { return FAM == FAM_DSEQ ? (a[j] ^ s[j]) : (a[j] + s[j]); }
   // element offset (in units of 256) visited at step k
   __device__ static inline int elem(int k) { return FAM == FAM_DSEQ ? (k ^ (k >> 1)) : k; }
-  // move from step k to step k + 1
+  // move from step k to step k + 1 (padding slots XOR a masked column of
+  // dimension 0, so the update is branch-free and stays in bounds)
   __device__ inline void advance(const uint32_t* __restrict__ gen, int d, int k) {
     if (FAM == FAM_DSEQ) {
       const int p = 8 + __ffs(k + 1) - 1;
 #pragma unroll
-      for (int j = 0; j < D; j++)
-        if (j < d) s[j] ^= gen[32 * j + p];
+      for (int j = 0; j < D; j++) {
+        const int jj = j < d ? j : 0;
+        const uint32_t keep = j < d ? 0xffffffffu : 0u;
+        s[j] ^= gen[32 * jj + p] & keep;
+      }
     } else {
 #pragma unroll
-      for (int j = 0; j < D; j++)
-        if (j < d) s[j] += step[j];
+      for (int j = 0; j < D; j++) s[j] += step[j];
     }
   }
 };
@@ -74,11 +77,32 @@ __device__ inline Real kval(uint32_t u, const Params* __restrict__ P) {
   }
 }
 
-// dispatch helpers: D in {4, 8, 12, 16, 32}
+// Walsh-Hadamard butterflies over the E register slots of a thread (slot e
+// holds in-block index t + 256 e, so these are the index bits 8 ..).
+template <typename Real, int E>
+__device__ inline void reg_fwht(Real (&v)[E]) {
+#pragma unroll
+  for (int h = 1; h < E; h <<= 1) {
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+      if (!(k & h)) {
+        const Real a = v[k], b = v[k + h];
+        v[k] = a + b;
+        v[k + h] = a - b;
+      }
+    }
+  }
+}
+
+// Dimension slots are padded to D (padding slots carry eta = 0, so their
+// kernel factor is exactly 1): D in {2, 4, 6, 8, 10, 12, 16, 32}.
 #define MTGP_DISPATCH_D(d, MACRO, ...)          \
   do {                                          \
-    if ((d) <= 4) MACRO(4, __VA_ARGS__);        \
+    if ((d) <= 2) MACRO(2, __VA_ARGS__);        \
+    else if ((d) <= 4) MACRO(4, __VA_ARGS__);   \
+    else if ((d) <= 6) MACRO(6, __VA_ARGS__);   \
     else if ((d) <= 8) MACRO(8, __VA_ARGS__);   \
+    else if ((d) <= 10) MACRO(10, __VA_ARGS__); \
     else if ((d) <= 12) MACRO(12, __VA_ARGS__); \
     else if ((d) <= 16) MACRO(16, __VA_ARGS__); \
     else MACRO(32, __VA_ARGS__);                \

@@ -1,0 +1,12 @@
+// Instantiations of the fused low-bit adjoint pass + derivative reduction for one
+// kernel type (KT_DSIA); split per type so the kernels compile in parallel.
+#include "fused_eval.h"
+
+namespace mtgp {
+template int launch_adj_reduce_kt<double, double, KT_DSIA>(const double*, int64_t, int, int,
+    const uint32_t*, const uint32_t*, const Params*, int, double*, const Sched&, hipStream_t);
+template int launch_adj_reduce_kt<double, float, KT_DSIA>(const float*, int64_t, int, int,
+    const uint32_t*, const uint32_t*, const Params*, int, double*, const Sched&, hipStream_t);
+template int launch_adj_reduce_kt<float, float, KT_DSIA>(const float*, int64_t, int, int,
+    const uint32_t*, const uint32_t*, const Params*, int, double*, const Sched&, hipStream_t);
+}  // namespace mtgp

@@ -59,6 +59,15 @@ template <typename Real, typename TOut>
 int launch_gen_fwd(TOut* base, int64_t col_stride, int ncols, int m, const uint32_t* gen,
                    const uint32_t* colshift, const Params* P, const KDesc& kd, const Sched& sc,
                    hipStream_t st);
+// per kernel type (fused_eval.h; instantiated in fused_*.hip)
+template <typename Real, typename TOut, int KT>
+int launch_gen_fwd_kt(TOut* base, int64_t col_stride, int ncols, int m, const uint32_t* gen,
+                      const uint32_t* colshift, const Params* P, int d, const Sched& sc,
+                      hipStream_t st);
+template <typename Real, typename TIn, int KT>
+int launch_adj_reduce_kt(const TIn* base, int64_t col_stride, int ncols, int m,
+                         const uint32_t* gen, const uint32_t* colshift, const Params* P, int d,
+                         double* partials, const Sched& sc, hipStream_t st);
 template <typename Real>
 int launch_raw_cols(Real* base, int ncols, int m, const uint32_t* gen, const uint32_t* colshift,
                     const Params* P, const KDesc& kd, hipStream_t st);
@@ -75,13 +84,17 @@ int launch_adj_reduce(const TIn* base, int64_t col_stride, int ncols, int m, con
 
 // ---- solve.hip
 int launch_prep(const double* theta, Params* P, const KDesc& kd, int* status, hipStream_t st);
-// number of FP64 partial sums per block of the equal-size solve
-// T padded to the factorisation template size, and the partial-sum layout size
+// T padded to the factorisation template size, and the number of FP64
+// partial sums per block of the solves (equal sizes and the elimination):
+//   [0] quad, [1] log det, [2 + t] G_tt = sum_f W_tt lambda_tt,
+//   [2 + TM + t] sum_f W_tt, [2 + 2 TM + t] ahat_t(0).
+// The cross-task sums G_tu (t != u) are not formed here: the adjoint weights
+// of a pair column are written without their R_tu factor, so the adjoint
+// reduction's sum of w c over that column is 2 G_tu, and R_tu is applied to
+// the column's derivative sums in the chain rule.
 __host__ __device__ inline int solve_tm(int T) { return T <= 1 ? 1 : T <= 2 ? 2 : T <= 4 ? 4 : T <= 8 ? 8 : 16; }
-__host__ __device__ inline int solve_ns(int T) {
-  const int tm = solve_tm(T);
-  return 2 + tm * (tm + 1) / 2 + 2 * tm;
-}
+__host__ __device__ inline int solve_ns(int T) { return 2 + 3 * solve_tm(T); }
+// blocks of the equal-size solves (grid-stride over frequencies beyond)
 inline int64_t solve_blocks(int64_t n) { return (n + 255) / 256; }
 template <typename Real>
 int launch_solve_eq(Real* cols, int64_t n, const PairMap& pm, int ncol, const double* yhat,
@@ -94,9 +107,19 @@ template <typename SR>
 int launch_solve_eq_c(SR* cols, int64_t n, const PairMap& pm, const double* yhat, const Params* P,
                       const KDesc& kd, bool grad, double* partials, double* ahat, int* status,
                       hipStream_t st);
-int launch_finalize(const double* solve_partials, int nsolve, const double* adj_partials, int nadj,
-                    const double* ld_partials, int nld, const double* yhat0, int64_t n, Params* P,
-                    const KDesc& kd, double* out3, double* grad, double* tau_hat, hipStream_t st);
+// Kernel column c: the task pair (t, u) it serves (t == u: a diagonal column,
+// whose weights already carry R) and its rows in the adjoint partial table.
+struct ColInfo {
+  int32_t t, u;
+  int64_t row_off, row_cnt;
+};
+// per-column sums of the adjoint partial table: out[c][nq]
+int launch_colseg(const double* in, const ColInfo* ci, int ncol, int nq, double* out,
+                  hipStream_t st);
+int launch_finalize(const double* solve_partials, int nsolve, const double* col_sums,
+                    const ColInfo* ci, int ncol, const double* ld_partials, int nld,
+                    const double* yhat0, int64_t n, Params* P, const KDesc& kd, double* out3,
+                    double* grad, double* tau_hat, hipStream_t st);
 
 // ---- points.hip
 int launch_gen_points(const uint32_t* gen, const uint32_t* shift, int family, int d, int m,

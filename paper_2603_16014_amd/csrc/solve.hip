@@ -8,9 +8,10 @@
 // factors it (Cholesky, FP64), accumulates log det and the quadratic form of
 // rhat(f) = yhat(f) - delta_{f0} sqrt(n) tau, and for the gradient forms
 // W(f) = Lambda(f)^-1 - ahat ahat^T and the adjoint weights
-//   omega_diag(f) = sum_t R_tt W_tt(f),  omega_tu(f) = 2 R_tu W_tu(f)
-// written over the column buffer, plus G_tu = sum_f W_tu(f) lambda_tu(f)
-// (dL/dR_tu) and sum_f W_tt(f) (dL/dxi_t).
+//   omega_diag(f) = sum_t R_tt W_tt(f),  omega_tu(f) = 2 W_tu(f)  (t < u)
+// written over the column buffer (R_tu is applied to the pair column's
+// derivative sums in the chain rule), plus G_tt = sum_f W_tt(f) lambda_tt(f)
+// (dL/dR_tt) and sum_f W_tt(f) (dL/dxi_t).
 // With profiled means and equal sizes, tau_hat_t = yhat_t(0) / sqrt(n), the
 // per-task sample mean (Theorem "Fast MTGP computations", item 4 with
 // Pi = n Lambda(0)^-1), so rhat(0) = 0.
@@ -62,14 +63,12 @@ __device__ constexpr int pk(int i, int j) {
   return i * (i + 1) / 2 + j;
 }
 
-// One thread per frequency f (grid ceil(n/256) x 256).  Lambda(f) = L D L^T
+// One thread per frequency f (grid solve_blocks(n) x 256).  Lambda(f) = L D L^T
 // (unit lower L, FP64): log det = sum log D_j, quad = sum z_j^2 / D_j with
 // L z = rhat, ahat = L^-T (z / D), Lambda^-1 = L^-T D^-1 L^-1; eight
 // reciprocals and no square roots per frequency.  Per-block sums go to
-// partials[block][solve_ns(T)] with TM = solve_tm(T) (T padded to 1/2/4/8/16):
-//   [0] quad, [1] log det, [2 + pk(u,t)] G_tu = sum W_tu lambda_tu (t <= u),
-//   [2 + TM(TM+1)/2 + t] sum W_tt, [2 + TM(TM+1)/2 + TM + t] ahat_t(0)
-//   (nonzero in block 0 only).
+// partials[block][solve_ns(T)] in the layout of solve_ns, TM = solve_tm(T)
+// (T padded to 1/2/4/8/16); ahat_t(0) is nonzero in block 0 only.
 template <typename Real, int TM, bool GRAD>
 __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, int64_t n,
                                                        PairMap pm, const double* __restrict__ yhat,
@@ -77,17 +76,16 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
                                                        double* __restrict__ partials,
                                                        double* __restrict__ ahat,
                                                        int* __restrict__ status) {
-  constexpr int NP = TM * (TM + 1) / 2;
-  constexpr int NQ = 2 + NP + 2 * TM;
+  constexpr int NQ = 2 + 3 * TM;
   __shared__ double red[4 * NQ];
   const int T = kd.T;
-  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const bool active = f < n;
   double vals[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; q++) vals[q] = 0.0;
-  if (active) {
-    Real lam[NP];
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f < n) {
+    constexpr int NP = TM * (TM + 1) / 2;
+    Real lamd[TM];  // diagonal-column values lambda_tt(f)
     double A[NP], r[TM];
 #pragma unroll
     for (int i = 0; i < TM; i++) {
@@ -95,10 +93,10 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
       for (int j = 0; j <= i; j++) {
         if (i < T) {
           const Real l = cols[(int64_t)pm.col[j][i] * n + f];
-          lam[pk<TM>(i, j)] = l;
+          if (i == j) lamd[i] = l;
           A[pk<TM>(i, j)] = P->R[j * MTGP_MAXT + i] * (double)l + (i == j ? P->xi[i] : 0.0);
         } else {
-          lam[pk<TM>(i, j)] = 0;
+          if (i == j) lamd[i] = 0;
           A[pk<TM>(i, j)] = (i == j) ? 1.0 : 0.0;
         }
       }
@@ -111,7 +109,7 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
       }
     }
     // L D L^T in place: strictly lower part of A becomes L
-    double invD[TM];
+    double invD[TM], Dv[TM];
     double prod = 1.0;
     bool ok = true;
 #pragma unroll
@@ -120,11 +118,12 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
       double dj = A[pk<TM>(j, j)];
 #pragma unroll
       for (int k = 0; k < j; k++) {
-        u[k] = A[pk<TM>(j, k)] / invD[k];  // L_jk D_k
+        u[k] = A[pk<TM>(j, k)] * Dv[k];  // L_jk D_k
         dj -= A[pk<TM>(j, k)] * u[k];
       }
       ok = ok && (dj > 0.0);
       prod *= dj;
+      Dv[j] = dj;
       invD[j] = 1.0 / dj;
 #pragma unroll
       for (int i = j + 1; i < TM; i++) {
@@ -135,7 +134,7 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
       }
     }
     if (!ok || !isfinite(prod)) flag_bad(status, f);
-    vals[1] = log(prod);
+    vals[1] += log(prod);
     // L z = r; quad = sum z^2 / D; L^T a = z / D
     double a[TM];
     double quad = 0.0;
@@ -147,7 +146,7 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
       a[i] = v;
       quad += v * v * invD[i];
     }
-    vals[0] = quad;
+    vals[0] += quad;
 #pragma unroll
     for (int i = TM - 1; i >= 0; i--) {
       double v = a[i] * invD[i];
@@ -157,7 +156,7 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
     }
     if (f == 0) {
 #pragma unroll
-      for (int i = 0; i < TM; i++) vals[2 + NP + TM + i] = a[i];
+      for (int i = 0; i < TM; i++) vals[2 + 2 * TM + i] += a[i];
     }
     if (ahat) {
 #pragma unroll
@@ -187,12 +186,12 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
           for (int k = u + 1; k < TM; k++) v += A[pk<TM>(k, t)] * A[pk<TM>(k, u)] * invD[k];
           const double w = v - a[t] * a[u];
           if (u < T) {
-            vals[2 + pk<TM>(u, t)] = w * (double)lam[pk<TM>(u, t)];
             if (t == u) {
-              vals[2 + NP + t] = w;
+              vals[2 + t] += w * (double)lamd[t];
+              vals[2 + TM + t] += w;
               wdiag += P->R[t * MTGP_MAXT + t] * w;
             } else {
-              cols[(int64_t)pm.col[t][u] * n + f] = (Real)(2.0 * P->R[t * MTGP_MAXT + u] * w);
+              cols[(int64_t)pm.col[t][u] * n + f] = (Real)(2.0 * w);
             }
           }
         }
@@ -259,16 +258,16 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
                                                          double* __restrict__ ahat,
                                                          int* __restrict__ status) {
   constexpr int NP = TM * (TM + 1) / 2;
-  constexpr int NQ = 2 + NP + 2 * TM;
+  constexpr int NQ = 2 + 3 * TM;
   __shared__ double red[4 * NQ];
   const int T = kd.T;
-  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const bool active = f < n;
   double vals[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; q++) vals[q] = 0.0;
-  if (active) {
-    zc lam[NP], A[NP], r[TM];
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f < n) {
+    zc A[NP], r[TM];
+    double lamd[TM];  // diagonal-column values (real)
 #pragma unroll
     for (int i = 0; i < TM; i++) {
 #pragma unroll
@@ -276,13 +275,15 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
         if (i < T) {
           const size_t at = ((size_t)pm.col[j][i] * n + f) * 2;
           zc l = {(double)cols[at], (double)cols[at + 1]};
-          if (i == j) l.y = 0.0;
-          lam[pk<TM>(i, j)] = l;
+          if (i == j) {
+            l.y = 0.0;
+            lamd[i] = l.x;
+          }
           // lower entry (i, j), i > j: conj(Lambda_ji) = R_ji conj(lambda_ji)
           const double R = P->R[j * MTGP_MAXT + i];
           A[pk<TM>(i, j)] = {R * l.x + (i == j ? P->xi[i] : 0.0), -R * l.y};
         } else {
-          lam[pk<TM>(i, j)] = {0.0, 0.0};
+          if (i == j) lamd[i] = 0.0;
           A[pk<TM>(i, j)] = {i == j ? 1.0 : 0.0, 0.0};
         }
       }
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
         r[i] = {0.0, 0.0};
       }
     }
-    double invD[TM];
+    double invD[TM], Dv[TM];
     double prod = 1.0;
     bool ok = true;
 #pragma unroll
@@ -304,12 +305,12 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
 #pragma unroll
       for (int k = 0; k < j; k++) {
         const zc l = A[pk<TM>(j, k)];
-        const double Dk = 1.0 / invD[k];
-        u[k] = zscale(l, Dk);  // L_jk D_k
-        dj -= (l.x * l.x + l.y * l.y) * Dk;
+        u[k] = zscale(l, Dv[k]);  // L_jk D_k
+        dj -= (l.x * l.x + l.y * l.y) * Dv[k];
       }
       ok = ok && (dj > 0.0);
       prod *= dj;
+      Dv[j] = dj;
       invD[j] = 1.0 / dj;
 #pragma unroll
       for (int i = j + 1; i < TM; i++) {
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
       }
     }
     if (!ok || !isfinite(prod)) flag_bad(status, f);
-    vals[1] = log(prod);
+    vals[1] += log(prod);
     zc a[TM];
     double quad = 0.0;
 #pragma unroll
@@ -331,7 +332,7 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
       a[i] = v;
       quad += (v.x * v.x + v.y * v.y) * invD[i];
     }
-    vals[0] = quad;
+    vals[0] += quad;
 #pragma unroll
     for (int i = TM - 1; i >= 0; i--) {
       zc v = zscale(a[i], invD[i]);
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
     }
     if (f == 0) {
 #pragma unroll
-      for (int i = 0; i < TM; i++) vals[2 + NP + TM + i] = a[i].x;
+      for (int i = 0; i < TM; i++) vals[2 + 2 * TM + i] += a[i].x;
     }
     if (ahat) {
 #pragma unroll
@@ -383,17 +384,14 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
           }
           const zc w = zsub(v, zmulc(a[t], a[u]));  // W_tu = Ainv_tu - a_t conj(a_u)
           if (u < T) {
-            const zc l = lam[pk<TM>(u, t)];
             if (t == u) {
-              vals[2 + pk<TM>(u, t)] = w.x * l.x;
-              vals[2 + NP + t] = w.x;
+              vals[2 + t] += w.x * lamd[t];
+              vals[2 + TM + t] += w.x;
               wdiag += P->R[t * MTGP_MAXT + t] * w.x;
             } else {
-              vals[2 + pk<TM>(u, t)] = w.x * l.x + w.y * l.y;  // Re(conj(W_tu) lambda_tu)
-              const double R2 = 2.0 * P->R[t * MTGP_MAXT + u];
               const size_t at = ((size_t)pm.col[t][u] * n + f) * 2;
-              cols[at] = (SR)(R2 * w.x);
-              cols[at + 1] = (SR)(-R2 * w.y);
+              cols[at] = (SR)(2.0 * w.x);
+              cols[at + 1] = (SR)(-2.0 * w.y);
             }
           }
         }
@@ -439,7 +437,8 @@ template int launch_solve_eq_c<float>(float*, int64_t, const PairMap&, const dou
 // finalize: deterministic sums of the block partials and the chain rule
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ sp, int nsolve,
-                                                       const double* __restrict__ ap, int nadj,
+                                                       const double* __restrict__ cs,
+                                                       const ColInfo* __restrict__ ci, int ncol,
                                                        const double* __restrict__ lp, int nld,
                                                        const double* __restrict__ yhat, int64_t n,
                                                        Params* __restrict__ P, KDesc kd,
@@ -447,7 +446,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
                                                        double* __restrict__ grad,
                                                        double* __restrict__ tau_hat) {
   __shared__ double red[16];
-  __shared__ double sums[256];
+  __shared__ double sums[64];
+  __shared__ double Gm[MTGP_MAXT * MTGP_MAXT];
   const int T = kd.T, d = kd.d, s = kd.s;
   const int ns = solve_ns(T);
   const int nq = adj_nq(d);
@@ -456,13 +456,6 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
     for (int b = threadIdx.x; b < nsolve; b += blockDim.x) v += sp[(size_t)b * ns + q];
     v = block_sum(v, red);
     if (threadIdx.x == 0) sums[q] = v;
-  }
-  for (int q = 0; q < nq; q++) {
-    double v = 0.0;
-    if (ap)
-      for (int b = threadIdx.x; b < nadj; b += blockDim.x) v += ap[(size_t)b * nq + q];
-    v = block_sum(v, red);
-    if (threadIdx.x == 0) sums[ns + q] = v;
   }
   double ldx = 0.0;  // log pivots of the elimination stages (unequal sizes)
   if (lp)
@@ -476,7 +469,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   out3[2] = quad + logdet;
   const double sqn = sqrt((double)n);
   const int TMp = solve_tm(T);
-  const int qX = 2 + TMp * (TMp + 1) / 2, qA = qX + TMp;
+  const int qG = 2, qX = 2 + TMp, qA = 2 + 2 * TMp;
   for (int t = 0; t < T; t++) {
     const int64_t y0 = (int64_t)t * n * (kd.family == FAM_LAT ? 2 : 1);
     const double tu = kd.unequal ? P->tau_used[t] : (kd.profile ? yhat[y0] / sqn : P->tau[t]);
@@ -484,10 +477,20 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
     if (tau_hat) tau_hat[t] = tu;
   }
   if (!grad) return;
-  auto G = [&](int t, int u) {
-    const int a = t > u ? t : u, b = t > u ? u : t;
-    return sums[2 + a * (a + 1) / 2 + b];
-  };
+  // G_tu = sum_f Re(W_ut lambda_tu): diagonal from the solve, cross-task from
+  // the pair columns (their w c sums are 2 G_tu); kernel-hyperparameter sums
+  // of a pair column carry R_tu, diagonal columns carry it in their weights
+  for (int t = 0; t < T; t++) Gm[t * MTGP_MAXT + t] = sums[qG + t];
+  double geta[MTGP_MAXD + 4];
+  for (int q = 0; q < d + 4; q++) geta[q] = 0.0;
+  for (int c = 0; c < ncol; c++) {
+    const int t = ci[c].t, u = ci[c].u;
+    const double* row = cs + (size_t)c * nq;
+    const double Rc = t == u ? 1.0 : P->R[t * MTGP_MAXT + u];
+    if (t != u) Gm[t * MTGP_MAXT + u] = Gm[u * MTGP_MAXT + t] = 0.5 * row[0];
+    for (int q = 0; q < d + 4; q++) geta[q] += Rc * row[1 + q];
+  }
+  auto G = [&](int t, int u) { return Gm[t * MTGP_MAXT + u]; };
   int o = 0;
   for (int t = 0; t < T; t++)
     grad[o + t] = kd.profile ? 0.0 : -2.0 * sqrt(ldexp(1.0, kd.m[t])) * sums[qA + t];
@@ -496,10 +499,10 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   for (int t = 0; t < T; t++)
     for (int u = 0; u < T; u++) gg += P->R[t * MTGP_MAXT + u] * G(t, u);
   grad[o++] = gg;
-  for (int j = 0; j < d; j++) grad[o + j] = sums[ns + 1 + j];
+  for (int j = 0; j < d; j++) grad[o + j] = geta[j];
   o += d;
   if (kd.adaptive) {
-    for (int a = 0; a < 4; a++) grad[o + a] = P->b[a] * sums[ns + 1 + d + a];
+    for (int a = 0; a < 4; a++) grad[o + a] = P->b[a] * geta[d + a];
     o += 4;
   }
   for (int t = 0; t < T; t++) grad[o + t] = P->xi[t] * sums[qX + t];
@@ -512,6 +515,28 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
     }
   o += T * s;
   for (int t = 0; t < T; t++) grad[o + t] = P->zeta[t] * G(t, t);
+}
+
+// Per-column sums of the adjoint partial table: block c adds the rows
+// [row_off, row_off + row_cnt) of column c (fixed order, deterministic).
+__global__ __launch_bounds__(256) void colseg_kernel(const double* __restrict__ in,
+                                                     const ColInfo* __restrict__ ci, int nq,
+                                                     double* __restrict__ out) {
+  __shared__ double red[16];
+  const int64_t off = ci[blockIdx.x].row_off, cnt = ci[blockIdx.x].row_cnt;
+  for (int q = 0; q < nq; q++) {
+    double v = 0.0;
+    for (int64_t r = threadIdx.x; r < cnt; r += blockDim.x) v += in[(off + r) * nq + q];
+    v = block_sum(v, red);
+    if (threadIdx.x == 0) out[(size_t)blockIdx.x * nq + q] = v;
+  }
+}
+
+int launch_colseg(const double* in, const ColInfo* ci, int ncol, int nq, double* out,
+                  hipStream_t st) {
+  if (ncol <= 0) return 0;
+  hipLaunchKernelGGL(colseg_kernel, dim3(ncol), dim3(256), 0, st, in, ci, nq, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // First stage of the deterministic reduction of a [nrows][ncols] table of
@@ -535,11 +560,12 @@ int launch_colsum(const double* in, int64_t nrows, int ncols, double* out, int n
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_finalize(const double* solve_partials, int nsolve, const double* adj_partials, int nadj,
-                    const double* ld_partials, int nld, const double* yhat0, int64_t n, Params* P,
-                    const KDesc& kd, double* out3, double* grad, double* tau_hat, hipStream_t st) {
+int launch_finalize(const double* solve_partials, int nsolve, const double* col_sums,
+                    const ColInfo* ci, int ncol, const double* ld_partials, int nld,
+                    const double* yhat0, int64_t n, Params* P, const KDesc& kd, double* out3,
+                    double* grad, double* tau_hat, hipStream_t st) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, st, solve_partials, nsolve,
-                     adj_partials, nadj, ld_partials, nld, yhat0, n, P, kd, out3, grad, tau_hat);
+                     col_sums, ci, ncol, ld_partials, nld, yhat0, n, P, kd, out3, grad, tau_hat);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

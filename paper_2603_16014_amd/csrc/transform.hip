@@ -38,45 +38,6 @@ __global__ __launch_bounds__(256) void raw_cols_kernel(Real* __restrict__ base, 
   }
 }
 
-// ---------------------------------------------------------------------------
-// pass A fused with column generation (digital sequences): grid (2^(m-LB), ncols)
-// arithmetic in Real, block stored as TOut
-// ---------------------------------------------------------------------------
-template <typename Real, typename TOut, int KT, int D>
-__global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, int64_t col_stride,
-                                                      int m, int LB,
-                                                      const uint32_t* __restrict__ gen,
-                                                      const uint32_t* __restrict__ colshift,
-                                                      const Params* __restrict__ P, int d) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  Real* lds = reinterpret_cast<Real*>(smem);
-  const int nb = 1 << LB;
-  const int E = nb > 256 ? nb >> 8 : 1;
-  const int col = blockIdx.y;
-  const uint32_t i0 = (uint32_t)blockIdx.x << LB;
-  const uint32_t t = threadIdx.x;
-  const int stride = lds_stride(LB);
-  if ((int)t < nb) {
-    Digits<FAM_DSEQ, D> dg;
-    dg.init(gen, colshift + (size_t)col * d, d, t, i0, m);
-    Real eta[D];
-#pragma unroll
-    for (int j = 0; j < D; j++) eta[j] = j < d ? RT<Real>::eta(P, j) : (Real)0;
-    const Real gam = RT<Real>::gamma(P);
-    for (int k = 0; k < E; k++) {
-      Real c = gam;
-#pragma unroll
-      for (int j = 0; j < D; j++)
-        if (j < d) c = fma(c * eta[j], kval<Real, KT>(dg.u(j), P), c);
-      lds[lds_at(0, stride, (int)t + 256 * dg.elem(k))] = c;
-      if (k + 1 < E) dg.advance(gen, d, k);
-    }
-  }
-  lds_fwht<Real>(lds, 1, LB, stride);
-  TOut* out = base + (size_t)col * col_stride + i0;
-  for (int e = t; e < nb; e += 256) out[e] = (TOut)lds[lds_at(0, stride, e)];
-}
-
 // Pass A on data already in memory: grid (2^(m-LB), nvec); in place.
 template <typename Real>
 __global__ __launch_bounds__(256) void fwht_lo_kernel(Real* __restrict__ base, int64_t vec_stride,
@@ -199,23 +160,24 @@ int launch_gen_fwd(TOut* base, int64_t col_stride, int ncols, int m, const uint3
                    const uint32_t* colshift, const Params* P, const KDesc& kd, const Sched& sc,
                    hipStream_t st) {
   if (ncols <= 0) return 0;
-  const int LB = sc.lb(m);
-  const size_t lds = gen_cols_lds_bytes(LB, sizeof(Real));
-  const dim3 grid(1u << (m - LB), (unsigned)ncols);
-  const int kt = kt_of(kd.family, kd.order, kd.adaptive);
-#define MTGP_GEN(DD, KTV)                                                                         \
-  hipLaunchKernelGGL((gen_fwd_kernel<Real, TOut, KTV, DD>), grid, dim3(256), lds, st, base,       \
-                     col_stride, m, LB, gen, colshift, P, kd.d)
-  switch (kt) {
-    case KT_DSI1: MTGP_DISPATCH_D(kd.d, MTGP_GEN, KT_DSI1); break;
-    case KT_DSI2: MTGP_DISPATCH_D(kd.d, MTGP_GEN, KT_DSI2); break;
-    case KT_DSI3: MTGP_DISPATCH_D(kd.d, MTGP_GEN, KT_DSI3); break;
-    case KT_DSI4: MTGP_DISPATCH_D(kd.d, MTGP_GEN, KT_DSI4); break;
-    case KT_DSIA: MTGP_DISPATCH_D(kd.d, MTGP_GEN, KT_DSIA); break;
+  switch (kt_of(kd.family, kd.order, kd.adaptive)) {
+    case KT_DSI1:
+      return launch_gen_fwd_kt<Real, TOut, KT_DSI1>(base, col_stride, ncols, m, gen, colshift, P,
+                                                    kd.d, sc, st);
+    case KT_DSI2:
+      return launch_gen_fwd_kt<Real, TOut, KT_DSI2>(base, col_stride, ncols, m, gen, colshift, P,
+                                                    kd.d, sc, st);
+    case KT_DSI3:
+      return launch_gen_fwd_kt<Real, TOut, KT_DSI3>(base, col_stride, ncols, m, gen, colshift, P,
+                                                    kd.d, sc, st);
+    case KT_DSI4:
+      return launch_gen_fwd_kt<Real, TOut, KT_DSI4>(base, col_stride, ncols, m, gen, colshift, P,
+                                                    kd.d, sc, st);
+    case KT_DSIA:
+      return launch_gen_fwd_kt<Real, TOut, KT_DSIA>(base, col_stride, ncols, m, gen, colshift, P,
+                                                    kd.d, sc, st);
     default: return -1;
   }
-#undef MTGP_GEN
-  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename Real>
