@@ -245,3 +245,33 @@ def digits_as_uint32(t: torch.Tensor) -> np.ndarray:
 def digits_to_device(u: np.ndarray) -> torch.Tensor:
     """Host uint32 digits -> device int32 tensor holding the same bits."""
     return torch.from_numpy(np.ascontiguousarray(u, dtype=np.uint32).view(np.int32)).cuda()
+
+
+def adam_step(theta: torch.Tensor, grad: torch.Tensor, m1: torch.Tensor, m2: torch.Tensor,
+              step: torch.Tensor, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, frozen=None):
+    """One on-device Adam update of theta in place (mtgp_adam_step)."""
+    lib = _lib.load()
+    for name, t in (("theta", theta), ("grad", grad), ("m1", m1), ("m2", m2)):
+        _need_cuda(t, torch.float64, name)
+    _need_cuda(step, torch.int64, "step")
+    if frozen is not None:
+        _need_cuda(frozen, torch.uint8, "frozen")
+    _lib.check(lib.mtgp_adam_step(_ptr(theta), _ptr(grad), _ptr(m1), _ptr(m2), theta.numel(),
+                                  float(lr), float(beta1), float(beta2), float(eps), _ptr(step),
+                                  _ptr(frozen) if frozen is not None else None, _stream()),
+               "mtgp_adam_step")
+
+
+def nll_grad_batched(plans, thetas, out3s, grads):
+    """mtgp_nll_grad for every fit, enqueued on the current stream in one call."""
+    lib = _lib.load()
+    k = len(plans)
+    if not (len(thetas) == len(out3s) == len(grads) == k):
+        raise ValueError("plans, thetas, out3s and grads must have the same length")
+    arr = ctypes.c_void_p * max(k, 1)
+    P = arr(*[p.h.value for p in plans])
+    Th = arr(*[t.data_ptr() for t in thetas])
+    O = arr(*[o.data_ptr() for o in out3s])
+    G = arr(*[g.data_ptr() for g in grads])
+    W = arr(*[p.ws.data_ptr() for p in plans])
+    _lib.check(lib.mtgp_nll_grad_batched(k, P, Th, O, G, W, _stream()), "mtgp_nll_grad_batched")
