@@ -52,6 +52,14 @@ PHASE_KERNELS = {
 }
 
 
+_T0 = time.perf_counter()
+
+
+def progress(*a):
+    """Progress of the run on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f}s]", *a, file=sys.stderr, flush=True)
+
+
 def kernel_sources_digest():
     """Digest of the HIP sources; a counter summary is stale once it changes."""
     h = hashlib.sha256()
@@ -188,6 +196,7 @@ def cpu_baseline(w, budget_s=25.0):
     while True:
         dense.grad(ws, y, X=X)
         reps += 1
+        progress(f"cpu baseline: {reps} evals")
         el = time.perf_counter() - t0
         if el > budget_s / 2 or reps >= 3:
             break
@@ -200,6 +209,101 @@ def cpu_baseline(w, budget_s=25.0):
                       f"rate scaled by the dense O(N^3) cost to N={N_full} (extrapolated, the "
                       f"dense Gram matrix at full N would need {8 * N_full ** 2 / 2 ** 50:.0f} PiB)",
             "sample_evals_per_s": 1.0 / per}
+
+
+def train_leg(plan, theta, steps, lr=0.05):
+    """`steps` Adam steps of loss+gradient captured as one HIP graph step and
+    replayed; timed with events around the replays (capture excluded)."""
+    import torch
+    from paper_2603_16014_amd import training
+    f = training.Fit(plan, theta, lr=lr)
+    f.step()
+    torch.cuda.synchronize()
+    f.theta.copy_(theta)
+    f.opt.reset()
+    g = training._capture(lambda ss: f.step(), [])
+    hist = torch.zeros(steps, dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for k in range(steps):
+        g.replay()
+        hist[k].copy_(f.out3[2])
+    e1.record(st)
+    torch.cuda.synchronize()
+    h = hist.cpu().numpy()
+    code, bad = plan.status()
+    return {"adam_steps": steps, "lr": lr, "ms_per_step": e0.elapsed_time(e1) / steps,
+            "L_first": float(h[0]), "L_last": float(h[-1]), "status": code,
+            "theta_last": f.theta}
+
+
+def predict_leg(plan, w, theta, m_star=20, M_direct=1 << 10):
+    """Posterior mean at a fresh shifted test net of 2^m_star points
+    (structured cross-block path) and at M_direct uniform points (direct sum)."""
+    import torch
+    import workloads
+    rng = np.random.default_rng(w.seed + 2000)
+    shift_star = workloads.random_shifts(rng, 1, w.d)[0]
+    xs = workloads.uniform_digits(rng, M_direct, w.d)
+    from paper_2603_16014_amd import mtgp
+    xs_dev = mtgp.digits_to_device(xs)
+    out = {}
+    for name, fn in (("net", lambda: plan.predict_net(theta, shift_star, m_star)),
+                     ("direct", lambda: plan.predict(theta, xs_dev))):
+        progress("posterior mean", name)
+        fn()
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        reps = 3
+        for _ in range(reps):
+            mean = fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        npts = (1 << m_star) if name == "net" else M_direct
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"points": npts, "ms": ms, "points_per_s": npts / (ms * 1e-3),
+                     "finite": bool(torch.isfinite(mean).all().item())}
+    return out
+
+
+def batched_leg(nfits, steps, nstreams=16, eager_steps=3):
+    """Config of many small fits: each an independent MTGP (T 2..8, d 2..10,
+    mixed families, nested sizes 2^8..2^14), `steps` Adam steps of every fit
+    per replay of one captured graph, against a Python loop of single fits."""
+    import torch
+    import workloads
+    from paper_2603_16014_amd import mtgp, training
+    fits = workloads.config4_fits(nfits)
+    plans, thetas = [], []
+    for i, w in enumerate(fits):
+        p = mtgp.Plan.from_workload(w, "mixed")
+        p.set_data(targets_on_device(p, w))
+        plans.append(p)
+        thetas.append(p.pack_theta(w.theta))
+        if (i + 1) % 32 == 0:
+            progress(f"batched leg: {i + 1} plans")
+    torch.cuda.synchronize()
+    progress("batched leg: capture")
+    bf = training.BatchedFits(plans, thetas, lr=0.05, nstreams=nstreams)
+    t0 = time.perf_counter()
+    bf.capture()
+    cap_s = time.perf_counter() - t0
+    ms = np.array(bf.run(steps))
+    progress("batched leg: graph replays done")
+    bad = sum(1 for p in plans if p.status()[0] != 0)
+    bf.reset()
+    eager = np.array(bf.run_eager(eager_steps))
+    progress("batched leg: eager loop done")
+    return {"fits": nfits, "adam_steps": steps, "streams": nstreams,
+            "fits_steps_per_s": nfits * steps / (ms.sum() * 1e-3),
+            "step_ms_p50": float(np.percentile(ms, 50)), "step_ms_p99": float(np.percentile(ms, 99)),
+            "graph_capture_s": cap_s, "fits_not_pd": bad,
+            "eager_loop_fits_steps_per_s": nfits * eager_steps / (eager.sum() * 1e-3),
+            "eager_step_ms_p50": float(np.percentile(eager, 50)),
+            "total_points": int(sum(w.N for w in fits))}
 
 
 def run(args):
@@ -215,13 +319,25 @@ def run(args):
     y = None
     for prec in args.precisions.split(","):
         sched = tuple(int(v) for v in args.sched.split(",")) if args.sched else None
+        progress("plan", prec)
         plan = mtgp.Plan.from_workload(w, prec, schedule=sched)
         if y is None:
             y = targets_on_device(plan, w)
         plan.set_data(y)
         theta = plan.pack_theta(w.theta)
+        progress("timing", prec)
         ms, out3, grad, tau, phases, nph = time_evals(plan, theta, args.steps, args.warmup)
+        progress(f"{prec}: {ms:.3f} ms per loss+gradient")
         results[prec] = dict(ms=ms, out3=out3, grad=grad, phases=phases, nph=nph)
+        if prec == "mixed" and args.train_steps > 0:
+            progress("training leg")
+            tr = train_leg(plan, theta, args.train_steps)
+            th_last = tr.pop("theta_last")
+            tr["evals_per_s_at_last_theta"] = 1000.0 / time_evals(plan, th_last, 5, 1)[0]
+            results["train"] = tr
+            if args.predict:
+                progress("posterior-mean leg")
+                results["predict"] = predict_leg(plan, w, th_last)
         del plan
         torch.cuda.empty_cache()
     primary = "mixed" if "mixed" in results else args.precisions.split(",")[0]
@@ -290,7 +406,15 @@ def run(args):
     line.update(extra)
     if args.sched:
         line["schedule"] = args.sched
+    if "train" in results:
+        line["training"] = results["train"]
+    if "predict" in results:
+        line["posterior_mean"] = results["predict"]
+    if args.fits > 0:
+        progress("batched leg")
+        line["batched_fits"] = batched_leg(args.fits, args.fit_steps)
     if not args.no_cpu_baseline:
+        progress("cpu baseline (dense oracle)")
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)
 
@@ -419,6 +543,11 @@ def main():
     ap.add_argument("--precisions", default="fp64,mixed")
     ap.add_argument("--sched", default=None,
                     help="transform schedule a_bits,b_bits,b_tile_bytes (default: library default)")
+    ap.add_argument("--train-steps", type=int, default=100,
+                    help="Adam steps of the captured training leg (0: skip)")
+    ap.add_argument("--no-predict", dest="predict", action="store_false")
+    ap.add_argument("--fits", type=int, default=256, help="fits of the batched leg (0: skip)")
+    ap.add_argument("--fit-steps", type=int, default=50)
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "TRACE_DIR"))
     ap.add_argument("--pmc-command", action="append", default=[],
                     help="command line recorded in the summary (repeatable)")

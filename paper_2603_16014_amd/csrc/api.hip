@@ -790,14 +790,34 @@ int mtgp_predict(const mtgp_plan* p, const double* theta, const uint32_t* xs, in
     pt.off[t] = p->off[t];
   }
   const KDesc kd = p->kd();
-  // the direct sum cancels heavily (alpha = Ktilde^-1 r is large where Ktilde
-  // is ill conditioned), so it stays FP64 unless every column op is FP32
-  if (p->precision != MTGP_F32)
-    LAUNCH_OK(launch_predict_direct<double>(p->d_gen, p->d_taskshift, pt, alpha, xs, M, w.P, kd,
-                                            mean, st));
-  else
-    LAUNCH_OK(launch_predict_direct<float>(p->d_gen, p->d_taskshift, pt, alpha, xs, M, w.P, kd,
-                                           mean, st));
+  // chunking of the training points: about 2048 blocks in all, chunks of at
+  // least 256 points; the spectrum buffer (free once alpha is formed) holds
+  // the partial sums, test points are taken in batches that fit it
+  const int64_t gx = (M + 255) / 256;
+  const int64_t want = std::max<int64_t>(1, (2048 + gx - 1) / gx);
+  PredChunks pc;
+  pc.chunk = std::max<int64_t>(256, ((p->N + want - 1) / want + 255) / 256 * 256);
+  pc.cstart[0] = 0;
+  for (int t = 0; t < p->T; t++)
+    pc.cstart[t + 1] = pc.cstart[t] + (int)((p->n[t] + pc.chunk - 1) / pc.chunk);
+  // spectrum and working buffers (contiguous) are both free at this point
+  const int64_t cap = (int64_t)((p->o_yhat - p->o_cols) / sizeof(double));
+  const int64_t Mb = std::min<int64_t>(M, cap / pc.cstart[p->T]);
+  if (Mb < 1) return MTGP_ENOMEM;
+  double* part = reinterpret_cast<double*>(w.cols);
+  for (int64_t m0 = 0; m0 < M; m0 += Mb) {
+    const int64_t mb = std::min<int64_t>(Mb, M - m0);
+    // the direct sum cancels heavily (alpha = Ktilde^-1 r is large where
+    // Ktilde is ill conditioned), so it stays FP64 unless every column op is FP32
+    if (p->precision != MTGP_F32)
+      LAUNCH_OK(launch_predict_direct<double>(p->d_gen, p->d_taskshift, pt, pc, alpha,
+                                              xs + (size_t)m0 * p->d, mb, w.P, kd, part,
+                                              mean + (size_t)m0 * p->T, st));
+    else
+      LAUNCH_OK(launch_predict_direct<float>(p->d_gen, p->d_taskshift, pt, pc, alpha,
+                                             xs + (size_t)m0 * p->d, mb, w.P, kd, part,
+                                             mean + (size_t)m0 * p->T, st));
+  }
   return MTGP_OK;
 }
 

@@ -128,10 +128,18 @@ struct PredTasks {
   int m[MTGP_MAXT];
   int64_t off[MTGP_MAXT];
 };
+// training points of the direct sum split into chunks of `chunk` indices;
+// chunks [cstart[u], cstart[u+1]) belong to task u
+struct PredChunks {
+  int64_t chunk;
+  int cstart[MTGP_MAXT + 1];
+};
+// part holds cstart[T] * M doubles of partial sums
 template <typename Real>
 int launch_predict_direct(const uint32_t* gen, const uint32_t* shifts, const PredTasks& pt,
-                          const double* alpha, const uint32_t* xs, int64_t M, const Params* P,
-                          const KDesc& kd, double* mean, hipStream_t st);
+                          const PredChunks& pc, const double* alpha, const uint32_t* xs,
+                          int64_t M, const Params* P, const KDesc& kd, double* part, double* mean,
+                          hipStream_t st);
 
 // ---- lattice.hip (complex values interleaved re, im)
 template <typename R>

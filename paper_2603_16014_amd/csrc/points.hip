@@ -9,7 +9,10 @@
 // Posterior mean (Eq. MTGP_post_mean_cov):
 //   mu(t, x*) = tau_t + sum_u R_tu sum_k Q(x*, x_uk) alpha_uk,
 // summed directly over training points regenerated on the fly and staged in
-// LDS 256 at a time; alpha is given per task in the order of the transform
+// LDS 256 at a time.  The training points are split into chunks (grid y) so
+// that a few thousand test points still fill the GPU; per-chunk partial sums
+// are added in a fixed order afterwards.  alpha is given per task in the
+// order of the transform
 // (radical-inverse order for digital sequences, natural lattice order j with
 // point j g / n + Delta for lattices).
 #include "kernels.h"
@@ -45,13 +48,20 @@ int launch_gen_points(const uint32_t* gen, const uint32_t* shift, int family, in
 template <typename Real, int FAM, int ADAPT, int D>
 __global__ __launch_bounds__(256) void predict_direct_kernel(
     const uint32_t* __restrict__ gen, const uint32_t* __restrict__ shifts, PredTasks pt,
-    const double* __restrict__ alpha, const uint32_t* __restrict__ xs, int64_t M,
-    const Params* __restrict__ P, KDesc kd, double* __restrict__ mean) {
+    PredChunks pc, const double* __restrict__ alpha, const uint32_t* __restrict__ xs, int64_t M,
+    const Params* __restrict__ P, KDesc kd, double* __restrict__ part) {
   __shared__ uint32_t xk[256 * D];
   __shared__ double ak[256];
-  const int d = kd.d, T = kd.T;
+  const int d = kd.d;
   const int64_t mi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const bool active = mi < M;
+  // chunk blockIdx.y: task u, training indices [k_lo, k_hi)
+  const int c = blockIdx.y;
+  int u = 0;
+  while (u + 1 < kd.T && pc.cstart[u + 1] <= c) u++;
+  const int64_t nu = (int64_t)1 << pt.m[u];
+  const int64_t k_lo = (int64_t)(c - pc.cstart[u]) * pc.chunk;
+  const int64_t k_hi = k_lo + pc.chunk < nu ? k_lo + pc.chunk : nu;
   uint32_t xm[D];
   Real eta[D];
 #pragma unroll
@@ -60,61 +70,73 @@ __global__ __launch_bounds__(256) void predict_direct_kernel(
     eta[j] = j < d ? RT<Real>::eta(P, j) : (Real)0;
   }
   const Real gam = RT<Real>::gamma(P);
-  double mu[MTGP_MAXT];
-#pragma unroll
-  for (int t = 0; t < MTGP_MAXT; t++) mu[t] = 0.0;
-  for (int u = 0; u < T; u++) {
-    const int64_t nu = (int64_t)1 << pt.m[u];
-    const uint32_t* sh = shifts + (size_t)u * d;
-    double acc = 0.0;
-    for (int64_t k0 = 0; k0 < nu; k0 += 256) {
-      __syncthreads();
-      const int64_t k = k0 + threadIdx.x;
-      if (k < nu) {
-        for (int j = 0; j < d; j++) {
-          xk[threadIdx.x * D + j] = (FAM == FAM_DSEQ) ? (dseq_z(gen + 32 * j, (uint32_t)k) ^ sh[j])
-                                                      : (lat_z(gen[j], (uint32_t)k, pt.m[u]) + sh[j]);
-        }
-        ak[threadIdx.x] = alpha[pt.off[u] + k];
+  const uint32_t* sh = shifts + (size_t)u * d;
+  double acc = 0.0;
+  for (int64_t k0 = k_lo; k0 < k_hi; k0 += 256) {
+    __syncthreads();
+    const int64_t k = k0 + threadIdx.x;
+    if (k < k_hi) {
+      for (int j = 0; j < d; j++) {
+        xk[threadIdx.x * D + j] = (FAM == FAM_DSEQ) ? (dseq_z(gen + 32 * j, (uint32_t)k) ^ sh[j])
+                                                    : (lat_z(gen[j], (uint32_t)k, pt.m[u]) + sh[j]);
       }
-      __syncthreads();
-      const int cnt = (nu - k0) < 256 ? (int)(nu - k0) : 256;
-      for (int q = 0; q < cnt; q++) {
-        Real qv = gam;
-#pragma unroll
-        for (int j = 0; j < D; j++) {
-          if (j < d) {
-            const uint32_t x2 = xk[q * D + j];
-            const uint32_t uu = (FAM == FAM_DSEQ) ? (xm[j] ^ x2) : (xm[j] - x2);
-            qv *= (Real)1 + eta[j] * univ_value<Real, FAM, ADAPT>(kd.order, uu, P);
-          }
-        }
-        acc += (double)qv * ak[q];
-      }
+      ak[threadIdx.x] = alpha[pt.off[u] + k];
     }
+    __syncthreads();
+    const int cnt = (k_hi - k0) < 256 ? (int)(k_hi - k0) : 256;
+    for (int q = 0; q < cnt; q++) {
+      Real qv = gam;
 #pragma unroll
-    for (int t = 0; t < MTGP_MAXT; t++)
-      if (t < T) mu[t] += P->R[t * MTGP_MAXT + u] * acc;
+      for (int j = 0; j < D; j++) {
+        // padding slots: eta = 0, so the factor is exactly 1
+        const uint32_t x2 = xk[q * D + (j < d ? j : 0)];
+        const uint32_t uu = (FAM == FAM_DSEQ) ? (xm[j] ^ x2) : (xm[j] - x2);
+        qv = fma(qv * eta[j], univ_value<Real, FAM, ADAPT>(kd.order, uu, P), qv);
+      }
+      acc += (double)qv * ak[q];
+    }
   }
-  if (!active) return;
-  for (int t = 0; t < T; t++) mean[mi * T + t] = P->tau_used[t] + mu[t];
+  if (active) part[(size_t)c * M + mi] = acc;
+}
+
+// mean[i][t] = tau_t + sum_c R_{t, u(c)} part[c][i], chunks in a fixed order
+__global__ __launch_bounds__(256) void predict_reduce_kernel(const double* __restrict__ part,
+                                                             PredChunks pc, int64_t M,
+                                                             const Params* __restrict__ P,
+                                                             KDesc kd, double* __restrict__ mean) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const int T = kd.T;
+  double su[MTGP_MAXT];
+  for (int u = 0; u < T; u++) {
+    double s = 0.0;
+    for (int c = pc.cstart[u]; c < pc.cstart[u + 1]; c++) s += part[(size_t)c * M + i];
+    su[u] = s;
+  }
+  for (int t = 0; t < T; t++) {
+    double v = 0.0;
+    for (int u = 0; u < T; u++) v += P->R[t * MTGP_MAXT + u] * su[u];
+    mean[i * T + t] = P->tau_used[t] + v;
+  }
 }
 
 template <typename Real>
 int launch_predict_direct(const uint32_t* gen, const uint32_t* shifts, const PredTasks& pt,
-                          const double* alpha, const uint32_t* xs, int64_t M, const Params* P,
-                          const KDesc& kd, double* mean, hipStream_t st) {
+                          const PredChunks& pc, const double* alpha, const uint32_t* xs,
+                          int64_t M, const Params* P, const KDesc& kd, double* part, double* mean,
+                          hipStream_t st) {
   if (M <= 0) return 0;
-  dim3 grid((unsigned)((M + 255) / 256)), block(256);
+  const dim3 grid((unsigned)((M + 255) / 256), (unsigned)pc.cstart[kd.T]), block(256);
 #define MTGP_PRED(F, A, DD)                                                                      \
   hipLaunchKernelGGL((predict_direct_kernel<Real, F, A, DD>), grid, block, 0, st, gen, shifts,   \
-                     pt, alpha, xs, M, P, kd, mean)
-#define MTGP_PRED_D(F, A)                    \
-  do {                                       \
-    if (kd.d <= 4) MTGP_PRED(F, A, 4);       \
-    else if (kd.d <= 8) MTGP_PRED(F, A, 8);  \
+                     pt, pc, alpha, xs, M, P, kd, part)
+#define MTGP_PRED_D(F, A)                     \
+  do {                                        \
+    if (kd.d <= 4) MTGP_PRED(F, A, 4);        \
+    else if (kd.d <= 8) MTGP_PRED(F, A, 8);   \
+    else if (kd.d <= 12) MTGP_PRED(F, A, 12); \
     else if (kd.d <= 16) MTGP_PRED(F, A, 16); \
-    else MTGP_PRED(F, A, 32);                \
+    else MTGP_PRED(F, A, 32);                 \
   } while (0)
   if (kd.family == FAM_DSEQ) {
     if (kd.adaptive) MTGP_PRED_D(FAM_DSEQ, 1); else MTGP_PRED_D(FAM_DSEQ, 0);
@@ -123,14 +145,19 @@ int launch_predict_direct(const uint32_t* gen, const uint32_t* shifts, const Pre
   }
 #undef MTGP_PRED_D
 #undef MTGP_PRED
+  if (hipGetLastError() != hipSuccess) return -1;
+  hipLaunchKernelGGL(predict_reduce_kernel, dim3((unsigned)((M + 255) / 256)), block, 0, st, part,
+                     pc, M, P, kd, mean);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template int launch_predict_direct<double>(const uint32_t*, const uint32_t*, const PredTasks&,
-                                           const double*, const uint32_t*, int64_t, const Params*,
-                                           const KDesc&, double*, hipStream_t);
+                                           const PredChunks&, const double*, const uint32_t*,
+                                           int64_t, const Params*, const KDesc&, double*, double*,
+                                           hipStream_t);
 template int launch_predict_direct<float>(const uint32_t*, const uint32_t*, const PredTasks&,
-                                          const double*, const uint32_t*, int64_t, const Params*,
-                                          const KDesc&, double*, hipStream_t);
+                                          const PredChunks&, const double*, const uint32_t*,
+                                          int64_t, const Params*, const KDesc&, double*, double*,
+                                          hipStream_t);
 
 }  // namespace mtgp
