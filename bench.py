@@ -306,6 +306,46 @@ def batched_leg(nfits, steps, nstreams=16, eager_steps=3):
             "total_points": int(sum(w.N for w in fits))}
 
 
+def transforms_leg(ncols=29, m=24, reps=5):
+    """Standalone transforms on the kernel-column shape of the workload:
+    mtgp_fwht on [ncols][2^m] in FP32 and FP64, and mtgp_fft on the same
+    number of real elements as rows of 2^21 (its largest size).  Algorithmic
+    bytes: read + write once (FWHT), real read + complex write (FFT)."""
+    import torch
+    from paper_2603_16014_amd import mtgp
+    out = {}
+    st = torch.cuda.current_stream()
+    for name, dt, b in (("fwht_f32", torch.float32, 4), ("fwht_f64", torch.float64, 8),
+                        ("fft_f32", torch.float32, 4), ("fft_f64", torch.float64, 8)):
+        progress("transform", name)
+        if name.startswith("fwht"):
+            x = torch.randn(ncols << m, dtype=dt, device="cuda")
+            fn = lambda: mtgp.fwht(x, m)  # noqa: E731
+            nbytes = 2 * x.numel() * b
+            shape = f"[{ncols}][2^{m}]"
+        else:
+            lm = min(m, 21)
+            x = torch.randn(ncols << m, dtype=dt, device="cuda")
+            fn = lambda: mtgp.fft(x, lm)  # noqa: E731
+            nbytes = 3 * x.numel() * b
+            shape = f"[{(ncols << m) >> lm}][2^{lm}]"
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"shape": shape, "ms": ms, "algorithmic_bytes": nbytes,
+                     "GB_s": nbytes / (ms * 1e-3) / 1e9,
+                     "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del x
+        torch.cuda.empty_cache()
+    return out
+
+
 def run(args):
     import torch
     import workloads
@@ -410,6 +450,8 @@ def run(args):
         line["training"] = results["train"]
     if "predict" in results:
         line["posterior_mean"] = results["predict"]
+    if args.transforms:
+        line["transforms"] = transforms_leg()
     if args.fits > 0:
         progress("batched leg")
         line["batched_fits"] = batched_leg(args.fits, args.fit_steps)
@@ -546,6 +588,7 @@ def main():
     ap.add_argument("--train-steps", type=int, default=100,
                     help="Adam steps of the captured training leg (0: skip)")
     ap.add_argument("--no-predict", dest="predict", action="store_false")
+    ap.add_argument("--no-transforms", dest="transforms", action="store_false")
     ap.add_argument("--fits", type=int, default=256, help="fits of the batched leg (0: skip)")
     ap.add_argument("--fit-steps", type=int, default=50)
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "TRACE_DIR"))
