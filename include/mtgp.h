@@ -110,10 +110,12 @@ int mtgp_plan_destroy(mtgp_plan* plan);
 /* Transform schedule (tuning only; results are the same up to rounding):
  * each length-2^m transform runs as one LDS-resident pass over the low
  * pass_a_bits index bits (1..13; fused with kernel-column generation) and
- * passes over at most pass_b_bits (1..12) further bits each, with an LDS
- * tile of about pass_b_tile_bytes (4096..147456).  Changes
- * mtgp_workspace_bytes, so call it before sizing the workspace.  Defaults:
- * 12, 6, 36864 (measured best on MI355X for 2^24-point columns). */
+ * passes over at most pass_b_bits (1..12) further bits each.  Passes of at
+ * most 6 bits above bit 8 keep each thread's 2^bits strided values in
+ * registers; wider passes use an LDS tile of about pass_b_tile_bytes
+ * (4096..147456).  Changes mtgp_workspace_bytes, so call it before sizing
+ * the workspace.  Defaults: 12, 6, 36864 (measured best on MI355X for
+ * 2^24-point columns). */
 int mtgp_plan_set_schedule(mtgp_plan* plan, int32_t pass_a_bits, int32_t pass_b_bits,
                            int64_t pass_b_tile_bytes);
 

@@ -5,8 +5,10 @@
 //   pass A: bits [0, LB) of contiguous 2^LB blocks, LDS resident.  For kernel
 //           columns the block is generated in registers first (fused column
 //           evaluation, Eq. prod_kernel), so raw columns never reach HBM.
-//   pass B: bits [lo, lo + hb), tiles of KC consecutive low indices times
-//           2^hb strided rows, LDS resident.
+//   pass B: bits [lo, lo + hb); for hb <= 6 each thread holds the 2^hb
+//           strided rows of one low index in registers (no LDS), wider
+//           passes use tiles of KC consecutive low indices times 2^hb
+//           strided rows, LDS resident.
 // The stages of a Walsh-Hadamard transform commute, so the split needs no
 // twiddles and the output stays in natural (Sylvester) order.
 #include "colgen.h"
@@ -89,6 +91,59 @@ __global__ __launch_bounds__(256) void fwht_strided_kernel(const TIn* in, TOut* 
   }
 }
 
+// Pass B in registers (hb <= 6 bits, lo >= 8): thread = one low index of a
+// group of 256 consecutive ones, holding its 2^HB strided rows.  Every row
+// access of a wave is 64 consecutive elements, there is no LDS and no
+// barrier, and each thread keeps 2^HB loads in flight.
+template <typename TC, typename TIn, typename TOut, int HB>
+__global__ __launch_bounds__(256) void fwht_reg_kernel(const TIn* in, TOut* out,
+                                                       int64_t vec_stride, int lo) {
+  constexpr int R = 1 << HB;
+  const int64_t tile = blockIdx.x;
+  const int gb = lo - 8;  // 256-index groups in the low part: 2^gb
+  const int64_t grp = tile & (((int64_t)1 << gb) - 1);
+  const int64_t hi = tile >> gb;
+  const int64_t base = (int64_t)blockIdx.y * vec_stride + (hi << (lo + HB)) + (grp << 8) +
+                       threadIdx.x;
+  TC v[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) v[r] = (TC)in[base + ((int64_t)r << lo)];
+#pragma unroll
+  for (int h = 1; h < R; h <<= 1) {
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+      if (!(k & h)) {
+        const TC a = v[k], b = v[k + h];
+        v[k] = a + b;
+        v[k + h] = a - b;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; r++) out[base + ((int64_t)r << lo)] = (TOut)v[r];
+}
+
+template <typename TC, typename TIn, typename TOut>
+void launch_reg_pass(const TIn* in, TOut* out, int64_t vec_stride, int nv, int m, int lo, int hb,
+                     hipStream_t st) {
+  const dim3 grid((unsigned)((int64_t)1 << (m - hb - 8)), (unsigned)nv);
+  switch (hb) {
+#define MTGP_REGP(H)                                                                          \
+  case H:                                                                                     \
+    hipLaunchKernelGGL((fwht_reg_kernel<TC, TIn, TOut, H>), grid, dim3(256), 0, st, in, out, \
+                       vec_stride, lo);                                                       \
+    break;
+    MTGP_REGP(1)
+    MTGP_REGP(2)
+    MTGP_REGP(3)
+    MTGP_REGP(4)
+    MTGP_REGP(5)
+    MTGP_REGP(6)
+#undef MTGP_REGP
+    default: break;
+  }
+}
+
 template <typename Real>
 __global__ void scale_kernel(Real* __restrict__ x, int64_t n, Real s) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -112,6 +167,23 @@ int launch_strided(const TIn* first, TC* work, TOut* last, int64_t vec_stride, i
   while (lo < m) {
     const int hb = (m - lo) < sc.b_bits ? (m - lo) : sc.b_bits;
     const bool is_last = lo + hb >= m;
+    if (hb <= 6 && lo >= 8) {
+      for (int64_t v0 = 0; v0 < nvec; v0 += 65535) {
+        const int nv = (int)((nvec - v0) < 65535 ? (nvec - v0) : 65535);
+        const int64_t o = v0 * vec_stride;
+        if (is_first && is_last)
+          launch_reg_pass<TC, TIn, TOut>(first + o, last + o, vec_stride, nv, m, lo, hb, st);
+        else if (is_first)
+          launch_reg_pass<TC, TIn, TC>(first + o, work + o, vec_stride, nv, m, lo, hb, st);
+        else if (is_last)
+          launch_reg_pass<TC, TC, TOut>(work + o, last + o, vec_stride, nv, m, lo, hb, st);
+        else
+          launch_reg_pass<TC, TC, TC>(work + o, work + o, vec_stride, nv, m, lo, hb, st);
+      }
+      is_first = false;
+      lo += hb;
+      continue;
+    }
     int KC = 1;  // largest power of two with KC padded sequences inside the tile budget
     while ((size_t)(2 * KC) * lds_stride(hb) * sizeof(TC) <= sc.b_tile && 2 * KC <= (1 << lo))
       KC *= 2;

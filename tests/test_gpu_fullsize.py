@@ -1,0 +1,169 @@
+"""Parity at the full benchmark sizes, in the launch configuration the
+benchmark times (default schedule), where the dense oracle cannot run:
+
+* kernel columns at sampled indices against the oracle's Gram entries
+  K[(t, i), (u, 0)] / R_tu, on points the oracle generates by definition;
+* the spectrum of a full-length column at sampled frequencies against the
+  defining Walsh sum (numpy, FP64) of that same column;
+* equal sizes: tau_hat against the per-task sample means (the closed form of
+  the profiled means when all sizes are equal);
+* the FP64 gradient against central differences of the FP64 loss;
+* the mixed path against the FP64 path at the stated tolerances
+  (L 1e-5 of |quad| + |log det|, gradient 1e-4).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from _gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(w, precision):
+    import bench
+    from paper_2603_16014_amd import mtgp
+    plan = mtgp.Plan.from_workload(w, precision)
+    y = bench.targets_on_device(plan, w)
+    plan.set_data(y)
+    return plan, y
+
+
+def _bitrev(j, m):
+    return int(format(j, f"0{m}b")[::-1], 2) if m else 0
+
+
+def _loss_grad(plan, theta):
+    out3, grad, tau = plan.nll_grad(theta)
+    torch.cuda.synchronize()
+    code, bad = plan.status()
+    assert code == 0, (code, bad)
+    return out3.cpu().numpy(), grad.cpu().numpy(), tau.cpu().numpy()
+
+
+def _sampled_columns(w, plan, theta, rng, nsample=64):
+    """Sampled entries of every kernel column against oracle Gram entries."""
+    from oracle import dense, points
+    cols = plan.kernel_cols(theta)
+    torch.cuda.synchronize()
+    Xfull = {}
+    for c in range(plan.ncol):
+        m, off, t, u = plan.column_info(c)
+        n = 1 << m
+        idx = np.unique(np.concatenate([[0, 1, n - 1], rng.integers(0, n, size=nsample)]))
+        got = cols[off + torch.as_tensor(idx, device="cuda")].double().cpu().numpy()
+        if m not in Xfull:
+            Xfull[m] = (points.dseq_unshifted(w.gen, n) if w.family == "dseq"
+                        else points.lattice_unshifted(w.gen, n))
+        z = Xfull[m]
+        xt = z ^ w.shift[t][None, :] if w.family == "dseq" else z + w.shift[t][None, :]
+        xu0 = (np.zeros((1, w.d), np.uint32) ^ w.shift[u][None, :]) if w.family == "dseq" \
+            else (np.zeros((1, w.d), np.uint32) + w.shift[u][None, :])
+        rows = idx if w.family == "dseq" else np.array([_bitrev(int(j), m) for j in idx])
+        ref = dense.cross_q(w, w.theta, xt[rows].astype(np.uint32), xu0.astype(np.uint32))[:, 0]
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        assert err < 1e-13, (c, err)
+    return cols
+
+
+def _fd_check(plan, theta, grad, ks, h=1e-3, tol=1e-4):
+    scale = np.abs(grad).max()
+    for k in ks:
+        tp = theta.clone()
+        tm = theta.clone()
+        tp[k] += h
+        tm[k] -= h
+        Lp = _loss_grad(plan, tp)[0][2]
+        Lm = _loss_grad(plan, tm)[0][2]
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - grad[k]) < tol * scale, (k, fd, grad[k], scale)
+
+
+def _mixed_vs_fp64(w, out64, g64, tau64):
+    from paper_2603_16014_amd import mtgp
+    plan, _ = _setup(w, "mixed")
+    theta = plan.pack_theta(w.theta)
+    o, g, tau = _loss_grad(plan, theta)
+    den = abs(out64[0]) + abs(out64[1])
+    assert abs(o[2] - out64[2]) < 1e-5 * den, (o, out64)
+    assert np.abs(g - g64).max() < 1e-4 * np.abs(g64).max()
+    np.testing.assert_allclose(tau, tau64, rtol=1e-5, atol=1e-9)
+    del plan
+    torch.cuda.empty_cache()
+    return mtgp
+
+
+def test_config5_full_size():
+    """T=8, d=10, n=2^24 digital nets (N = 2^27), order-2 DSI kernel."""
+    from paper_2603_16014_amd import mtgp
+    w = workloads.config5()
+    say("config5 full size fp64")
+    plan, y = _setup(w, "fp64")
+    theta = plan.pack_theta(w.theta)
+    rng = np.random.default_rng(55)
+    cols = _sampled_columns(w, plan, theta, rng)
+    # spectrum of two full-length columns at sampled frequencies
+    n = 1 << w.m[0]
+    i = np.arange(n, dtype=np.uint64)
+    for c in (0, plan.ncol - 1):
+        m, off, t, u = plan.column_info(c)
+        col = cols[off:off + n].clone()
+        host = col.cpu().numpy()
+        mtgp.fwht(col, m)
+        spec = col.cpu().numpy()
+        for f in (0, 1, 12345, n - 1):
+            v = i & np.uint64(f)
+            for s in (16, 8, 4, 2, 1):  # parity of popcount(f & i)
+                v ^= v >> np.uint64(s)
+            ref = np.sum(np.where((v & np.uint64(1)) == 1, -host, host))
+            assert abs(spec[f] - ref) < 1e-12 * np.abs(host).sum(), (c, f, spec[f], ref)
+    del cols, col
+    torch.cuda.empty_cache()
+    out64, g64, tau64 = _loss_grad(plan, theta)
+    # equal sizes: profiled means are the per-task sample means
+    means = y.view(w.T, -1).mean(dim=1).cpu().numpy()
+    np.testing.assert_allclose(tau64, means, rtol=1e-12, atol=1e-14)
+    T, d = w.T, w.d
+    k_eta0, k_xi0 = T + 1, T + 1 + d
+    k_B00, k_zeta0 = T + 1 + d + T, T + 1 + d + T + 2 * T
+    _fd_check(plan, theta, g64, [k_eta0, k_xi0, k_B00, k_zeta0])
+    del plan, y
+    torch.cuda.empty_cache()
+    say("config5 full size mixed")
+    _mixed_vs_fp64(w, out64, g64, tau64)
+
+
+def test_config3_full_size():
+    """T=5, d=8, nested n = 2^20 .. 2^12, order-4 DSI: Algorithm 1."""
+    w = workloads.config3()
+    say("config3 full size fp64")
+    plan, y = _setup(w, "fp64")
+    theta = plan.pack_theta(w.theta)
+    _sampled_columns(w, plan, theta, np.random.default_rng(33), nsample=32)
+    torch.cuda.empty_cache()
+    out64, g64, tau64 = _loss_grad(plan, theta)
+    T, d = w.T, w.d
+    _fd_check(plan, theta, g64, [T + 1, T + 1 + d + T - 1, T + 1 + d + T + 1])
+    del plan, y
+    torch.cuda.empty_cache()
+    say("config3 full size mixed")
+    _mixed_vs_fp64(w, out64, g64, tau64)
+
+
+def test_config2_full_size():
+    """T=4, d=6, n=2^16 rank-1 lattices, order-2 SI kernel: FFT path."""
+    w = workloads.config2()
+    say("config2 full size fp64")
+    plan, y = _setup(w, "fp64")
+    theta = plan.pack_theta(w.theta)
+    _sampled_columns(w, plan, theta, np.random.default_rng(22))
+    out64, g64, tau64 = _loss_grad(plan, theta)
+    means = y.view(w.T, -1).mean(dim=1).cpu().numpy()
+    np.testing.assert_allclose(tau64, means, rtol=1e-12, atol=1e-14)
+    T, d = w.T, w.d
+    _fd_check(plan, theta, g64, [T + 1, T + 3, T + 1 + d, T + 1 + d + T])
+    del plan, y
+    torch.cuda.empty_cache()
+    say("config2 full size mixed")
+    _mixed_vs_fp64(w, out64, g64, tau64)
