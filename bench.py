@@ -113,7 +113,7 @@ def copy_probe():
     torch.cuda.empty_cache()
 
 
-def time_evals(plan, theta, steps, warmup):
+def time_evals(plan, theta, steps, warmup, timing=True):
     """K timed evaluations bracketed by device synchronisation; per-phase
     durations come from the library's HIP events recorded on the same stream
     in the same timed region (no host wait between steps)."""
@@ -127,15 +127,15 @@ def time_evals(plan, theta, steps, warmup):
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    plan.enable_timing(True)
+    plan.enable_timing(timing)
     e0.record(st)
     for i in range(steps):
         plan.nll_grad(theta, out3, grad, tau)
     e1.record(st)
     torch.cuda.synchronize()
     # the event ring holds the 64 most recent steps
-    phases = plan.phase_times()
-    done = min(steps, 64)
+    phases = plan.phase_times() if timing else {}
+    done = min(steps, 64) if timing else 0
     plan.enable_timing(False)
     ms = e0.elapsed_time(e1) / steps
     code, bad = plan.status()
@@ -366,9 +366,15 @@ def run(args):
         plan.set_data(y)
         theta = plan.pack_theta(w.theta)
         progress("timing", prec)
-        ms, out3, grad, tau, phases, nph = time_evals(plan, theta, args.steps, args.warmup)
+        # the measured configuration: overlapped passes (library default)
+        ms, out3, grad, tau, _, _ = time_evals(plan, theta, args.steps, args.warmup, timing=False)
         progress(f"{prec}: {ms:.3f} ms per loss+gradient")
-        results[prec] = dict(ms=ms, out3=out3, grad=grad, phases=phases, nph=nph)
+        # per-kernel durations need the passes in sequence on one stream
+        plan.set_overlap(1)
+        ms_seq, _, _, _, phases, nph = time_evals(plan, theta, args.steps, 1, timing=True)
+        plan.set_overlap(4)
+        progress(f"{prec}: {ms_seq:.3f} ms per loss+gradient without overlap")
+        results[prec] = dict(ms=ms, out3=out3, grad=grad, phases=phases, nph=nph, ms_seq=ms_seq)
         if prec == "mixed" and args.train_steps > 0:
             progress("training leg")
             tr = train_leg(plan, theta, args.train_steps)
@@ -393,6 +399,7 @@ def run(args):
         }
         extra["fp64_evals_per_s"] = 1000.0 / b["ms"]
         extra["fp64_ms_per_step"] = b["ms"]
+        extra["fp64_sequential_ms_per_step"] = b["ms_seq"]
         extra["fp64_phases_ms"] = {k: round(v, 4) for k, v in b["phases"].items()}
     ph = r["phases"]
     units = algo_units(w, primary, int(args.sched.split(",")[0]) if args.sched else 12)
@@ -438,6 +445,7 @@ def run(args):
                                f"d={w.d}, n=2^{w.m[0]} per task (N={w.N}), order-2 DSI kernel, "
                                f"rank-2 + diagonal task covariance, {primary} path",
                    "T": T, "d": w.d, "n_per_task": n, "N": w.N, "precision": primary},
+        "sequential_ms_per_step": r["ms_seq"],
         "phases_ms": {k: round(v, 4) for k, v in ph.items()},
         "phase_steps_timed": r["nph"],
         "kernels": kernels,

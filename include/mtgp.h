@@ -119,6 +119,17 @@ int mtgp_plan_destroy(mtgp_plan* plan);
 int mtgp_plan_set_schedule(mtgp_plan* plan, int32_t pass_a_bits, int32_t pass_b_bits,
                            int64_t pass_b_tile_bytes);
 
+/* Overlap of the digital-net passes (tuning only; results are bitwise the
+ * same): the columns of each length group are processed in `chunks` chunks
+ * (1..8; default 4).  The VALU-bound fused passes (generation + low
+ * transform bits, adjoint low bits + derivative reduction) run on the
+ * caller's stream and the HBM-bound high transform passes on a stream owned
+ * by the plan, forked from and joined back into the caller's stream through
+ * events.  chunks = 1 runs every pass on the caller's stream in order, and
+ * so does every call made while the caller's stream is being captured into
+ * a HIP graph.  Lattice plans ignore it. */
+int mtgp_plan_set_overlap(mtgp_plan* plan, int32_t chunks);
+
 /* Profiling aid (not thread safe): when enabled, every loss evaluation of the
  * plan (mtgp_nll, mtgp_nll_grad and the loss inside mtgp_predict*) records
  * HIP events on the caller's stream between its phases, into a ring of 64

@@ -63,6 +63,18 @@ struct mtgp_plan {
   Alg1Desc a1;      // stage descriptors of the unequal-size elimination
   int64_t a1_ms;    // final block size N / n_T
   // optional phase timing (profiling aid; not thread safe)
+  // Overlap of the VALU-bound fused passes (caller's stream) with the
+  // HBM-bound strided passes (aux stream) over chunks of columns; fork and
+  // join through events, so the sequence can be captured in a HIP graph.
+  // Events are re-recorded round-robin: a wait takes the event's state at the
+  // time it is enqueued, so reuse after the matching wait is safe.
+  static constexpr int kMaxChunks = 8;
+  static constexpr int kEvents = 32;
+  int nchunks = 4;
+  hipStream_t aux = nullptr;
+  hipEvent_t xev[kEvents] = {};
+  mutable int xev_next = 0;
+  hipEvent_t next_ev() const { return xev[xev_next++ % kEvents]; }
   // a ring of event sets lets many calls be timed without a host wait
   static constexpr int kRing = 64;
   bool timing = false;
@@ -157,6 +169,22 @@ inline void mark_done(const mtgp_plan* p, hipStream_t st) {
   q->ev_pending = std::min(q->ev_pending + 1, mtgp_plan::kRing);
 }
 
+// Whether the caller's stream is being captured into a HIP graph.  The
+// overlapped passes fork onto the plan's own stream; under capture they are
+// switched off and the passes run in order on the caller's stream (a capture
+// of many fits forked from side streams ended in a host-side fault inside
+// the runtime's capture end with the fork enabled; its cause is not known).
+inline bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus s = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &s) == hipSuccess && s != hipStreamCaptureStatusNone;
+}
+
+// Column chunks of a group for the overlapped passes: [lo, hi) of chunk k.
+inline void chunk_range(int first, int count, int nch, int k, int& lo, int& hi) {
+  lo = first + (int)((int64_t)count * k / nch);
+  hi = first + (int)((int64_t)count * (k + 1) / nch);
+}
+
 // Kernel columns and their forward transforms: arithmetic in CR, spectrum
 // stored as SR.  When CR != SR the working buffer holds the partially
 // transformed columns and only the final pass rounds to SR.
@@ -166,22 +194,58 @@ int run_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
   CR* work = reinterpret_cast<CR*>(w.work);
   const KDesc kd = p->kd();
   mark(p, 1, st);
+  const bool ovl = p->aux && p->nchunks > 1 && !capturing(st);
+  if (!ovl) {
+    for (const auto& g : p->groups) {
+      const int64_t len = (int64_t)1 << g.m;
+      const uint32_t* sh = p->d_colshift + (size_t)g.first * p->d;
+      if (g.m > p->sched.lb(g.m))
+        LAUNCH_OK(launch_gen_fwd<CR, CR>(work + p->col_off[g.first], len, g.count, g.m, p->d_gen,
+                                         sh, w.P, kd, p->sched, st));
+      else
+        LAUNCH_OK(launch_gen_fwd<CR, SR>(spec + p->col_off[g.first], len, g.count, g.m, p->d_gen,
+                                         sh, w.P, kd, p->sched, st));
+    }
+    mark(p, 2, st);
+    for (const auto& g : p->groups) {
+      const int64_t o = p->col_off[g.first];
+      LAUNCH_OK(launch_strided<CR, CR, SR>(work + o, work + o, spec + o, (int64_t)1 << g.m,
+                                           g.count, g.m, p->sched, st));
+    }
+    return MTGP_OK;
+  }
+  // generation + low pass of chunk k on st, its high passes on aux once the
+  // chunk is written; aux joins st before the solve
+  hipEvent_t e = p->next_ev();
+  HIP_OK(hipEventRecord(e, st));
+  HIP_OK(hipStreamWaitEvent(p->aux, e, 0));
   for (const auto& g : p->groups) {
     const int64_t len = (int64_t)1 << g.m;
-    const uint32_t* sh = p->d_colshift + (size_t)g.first * p->d;
-    if (g.m > p->sched.lb(g.m))
-      LAUNCH_OK(launch_gen_fwd<CR, CR>(work + p->col_off[g.first], len, g.count, g.m, p->d_gen, sh,
-                                       w.P, kd, p->sched, st));
-    else
-      LAUNCH_OK(launch_gen_fwd<CR, SR>(spec + p->col_off[g.first], len, g.count, g.m, p->d_gen, sh,
-                                       w.P, kd, p->sched, st));
+    const bool high = g.m > p->sched.lb(g.m);
+    const int nch = high ? std::min(p->nchunks, g.count) : 1;
+    for (int k = 0; k < nch; k++) {
+      int c0, c1;
+      chunk_range(g.first, g.count, nch, k, c0, c1);
+      const uint32_t* sh = p->d_colshift + (size_t)c0 * p->d;
+      const int64_t o = p->col_off[c0];
+      if (!high) {
+        LAUNCH_OK(launch_gen_fwd<CR, SR>(spec + o, len, c1 - c0, g.m, p->d_gen, sh, w.P, kd,
+                                         p->sched, st));
+        continue;
+      }
+      LAUNCH_OK(launch_gen_fwd<CR, CR>(work + o, len, c1 - c0, g.m, p->d_gen, sh, w.P, kd,
+                                       p->sched, st));
+      e = p->next_ev();
+      HIP_OK(hipEventRecord(e, st));
+      HIP_OK(hipStreamWaitEvent(p->aux, e, 0));
+      LAUNCH_OK(launch_strided<CR, CR, SR>(work + o, work + o, spec + o, len, c1 - c0, g.m,
+                                           p->sched, p->aux));
+    }
   }
+  e = p->next_ev();
+  HIP_OK(hipEventRecord(e, p->aux));
+  HIP_OK(hipStreamWaitEvent(st, e, 0));
   mark(p, 2, st);
-  for (const auto& g : p->groups) {
-    const int64_t o = p->col_off[g.first];
-    LAUNCH_OK(launch_strided<CR, CR, SR>(work + o, work + o, spec + o, (int64_t)1 << g.m, g.count,
-                                         g.m, p->sched, st));
-  }
   return MTGP_OK;
 }
 
@@ -212,25 +276,66 @@ int adjoint_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
   if (p->family == MTGP_DSEQ) {
     SR* spec = reinterpret_cast<SR*>(w.cols);
     CR* work = reinterpret_cast<CR*>(w.work);
-    for (const auto& g : p->groups) {
-      const int64_t o = p->col_off[g.first];
-      LAUNCH_OK(launch_strided<CR, SR, CR>(spec + o, work + o, work + o, (int64_t)1 << g.m,
-                                           g.count, g.m, p->sched, st));
+    const bool ovl = p->aux && p->nchunks > 1 && !capturing(st);
+    if (!ovl) {
+      for (const auto& g : p->groups) {
+        const int64_t o = p->col_off[g.first];
+        LAUNCH_OK(launch_strided<CR, SR, CR>(spec + o, work + o, work + o, (int64_t)1 << g.m,
+                                             g.count, g.m, p->sched, st));
+      }
+      mark(p, 5, st);
+      for (const auto& g : p->groups) {
+        const int64_t o = p->col_off[g.first];
+        const int nb = 1 << (g.m - p->sched.lb(g.m));
+        const uint32_t* sh = p->d_colshift + (size_t)g.first * p->d;
+        double* part = w.ap + (size_t)nadj * adj_nq(p->d);
+        if (g.m > p->sched.lb(g.m))
+          LAUNCH_OK(launch_adj_reduce<CR, CR>(work + o, (int64_t)1 << g.m, g.count, g.m,
+                                              p->d_gen, sh, w.P, kd, part, p->sched, st));
+        else
+          LAUNCH_OK(launch_adj_reduce<CR, SR>(spec + o, (int64_t)1 << g.m, g.count, g.m,
+                                              p->d_gen, sh, w.P, kd, part, p->sched, st));
+        nadj += nb * g.count;
+      }
+      return nadj;
     }
+    // high passes of chunk k on aux, then its fused low pass + reduction on
+    // st; partial rows keep the column order of the non-overlapped sequence
+    hipEvent_t e = p->next_ev();
+    HIP_OK(hipEventRecord(e, st));
+    HIP_OK(hipStreamWaitEvent(p->aux, e, 0));
     mark(p, 5, st);
     for (const auto& g : p->groups) {
-      const int64_t o = p->col_off[g.first];
+      const int64_t len = (int64_t)1 << g.m;
       const int nb = 1 << (g.m - p->sched.lb(g.m));
-      const uint32_t* sh = p->d_colshift + (size_t)g.first * p->d;
-      double* part = w.ap + (size_t)nadj * adj_nq(p->d);
-      if (g.m > p->sched.lb(g.m))
-        LAUNCH_OK(launch_adj_reduce<CR, CR>(work + o, (int64_t)1 << g.m, g.count, g.m, p->d_gen,
-                                            sh, w.P, kd, part, p->sched, st));
-      else
-        LAUNCH_OK(launch_adj_reduce<CR, SR>(spec + o, (int64_t)1 << g.m, g.count, g.m, p->d_gen,
-                                            sh, w.P, kd, part, p->sched, st));
+      const bool high = g.m > p->sched.lb(g.m);
+      const int nch = high ? std::min(p->nchunks, g.count) : 1;
+      for (int k = 0; k < nch; k++) {
+        int c0, c1;
+        chunk_range(g.first, g.count, nch, k, c0, c1);
+        const int64_t o = p->col_off[c0];
+        const uint32_t* sh = p->d_colshift + (size_t)c0 * p->d;
+        double* part = w.ap + (size_t)(nadj + (c0 - g.first) * nb) * adj_nq(p->d);
+        if (!high) {
+          LAUNCH_OK(launch_adj_reduce<CR, SR>(spec + o, len, c1 - c0, g.m, p->d_gen, sh, w.P, kd,
+                                              part, p->sched, st));
+          continue;
+        }
+        LAUNCH_OK(launch_strided<CR, SR, CR>(spec + o, work + o, work + o, len, c1 - c0, g.m,
+                                             p->sched, p->aux));
+        e = p->next_ev();
+        HIP_OK(hipEventRecord(e, p->aux));
+        HIP_OK(hipStreamWaitEvent(st, e, 0));
+        LAUNCH_OK(launch_adj_reduce<CR, CR>(work + o, len, c1 - c0, g.m, p->d_gen, sh, w.P, kd,
+                                            part, p->sched, st));
+      }
       nadj += nb * g.count;
     }
+    // join aux back (its last chunk was already waited for; this covers
+    // groups without high passes)
+    e = p->next_ev();
+    HIP_OK(hipEventRecord(e, p->aux));
+    HIP_OK(hipStreamWaitEvent(st, e, 0));
     return nadj;
   }
   cx<SR>* spec = reinterpret_cast<cx<SR>*>(w.cols);
@@ -566,7 +671,13 @@ int mtgp_plan_create(const mtgp_design* des, int32_t precision, mtgp_plan** out)
     mtgp_plan_destroy(p);
     return MTGP_EHIP;
   }
-  const int rc = upload_colinfo(p);
+  int rc = upload_colinfo(p);
+  if (rc == MTGP_OK && p->family == MTGP_DSEQ) {
+    // default priority, non-blocking with respect to the null stream
+    if (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess) rc = MTGP_EHIP;
+    for (int k = 0; rc == MTGP_OK && k < mtgp_plan::kEvents; k++)
+      if (hipEventCreateWithFlags(&p->xev[k], hipEventDisableTiming) != hipSuccess) rc = MTGP_EHIP;
+  }
   if (rc != MTGP_OK) {
     mtgp_plan_destroy(p);
     return rc;
@@ -585,6 +696,12 @@ int mtgp_plan_set_schedule(mtgp_plan* p, int32_t pass_a_bits, int32_t pass_b_bit
   p->sched.b_tile = (size_t)pass_b_tile_bytes;
   layout(p);
   return upload_colinfo(p);
+}
+
+int mtgp_plan_set_overlap(mtgp_plan* p, int32_t chunks) {
+  if (!p || chunks < 1 || chunks > mtgp_plan::kMaxChunks) return MTGP_EINVAL;
+  p->nchunks = chunks;
+  return MTGP_OK;
 }
 
 int mtgp_plan_enable_timing(mtgp_plan* p, int32_t on) {
@@ -631,6 +748,9 @@ int mtgp_plan_destroy(mtgp_plan* p) {
   if (p->d_gen) (void)hipFree(p->d_gen);
   if (p->d_colshift) (void)hipFree(p->d_colshift);
   if (p->d_colinfo) (void)hipFree(p->d_colinfo);
+  for (int k = 0; k < mtgp_plan::kEvents; k++)
+    if (p->xev[k]) (void)hipEventDestroy(p->xev[k]);
+  if (p->aux) (void)hipStreamDestroy(p->aux);
   if (p->d_taskshift) (void)hipFree(p->d_taskshift);
   delete p;
   return MTGP_OK;

@@ -193,6 +193,10 @@ class Plan:
             _ptr(mean), _ptr(self.ws), _ptr(scratch), _stream()), "mtgp_predict_net")
         return mean
 
+    def set_overlap(self, chunks: int):
+        """Chunks of the overlapped digital-net passes (1 = no overlap)."""
+        _lib.check(self.lib.mtgp_plan_set_overlap(self.h, int(chunks)), "mtgp_plan_set_overlap")
+
     def enable_timing(self, on=True):
         _lib.check(self.lib.mtgp_plan_enable_timing(self.h, int(bool(on))), "mtgp_plan_enable_timing")
 
