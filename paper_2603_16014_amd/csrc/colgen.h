@@ -62,7 +62,48 @@ struct Digits {
   }
 };
 
+// Order-2 DSI kernel in integer-scaled form.  With X = u (the digit as an
+// integer, exact in FP64) and K2(x) = 3/2 - (5/2) t1(x) - beta(x) x,
+//   kappa = 2^32 K2 = (3/2) 2^32 - beta X - (5/2) lead(X),
+// where lead(X) = 2^32 t1(x) keeps X's exponent and drops its mantissa, and
+// beta X = (r + 1) X with r = find-first-bit-high(u) (-1 for u = 0).  kappa
+// is exact in FP64 (dyadic, < 2^53); for u = 0, lead is taken as the
+// smallest normal number times 5/4, which vanishes in the subtraction.
+template <typename Real> __device__ inline Real dsi2_kappa(uint32_t u);
+template <> __device__ inline double dsi2_kappa<double>(uint32_t u) {
+  const double X = (double)u;
+  int r;
+  asm("v_ffbh_u32 %0, %1" : "=v"(r) : "v"(u));
+  const double L = __hiloint2double((__double2hiint(X) & 0x7ff00000) + 0x00140000, 0);
+  return fma(-(double)r, X, (6442450944.0 - L) - X);
+}
+template <> __device__ inline float dsi2_kappa<float>(uint32_t u) {
+  const float X = __uint2float_rz(u);  // truncation keeps lead(X) = lead(u)
+  int r;
+  asm("v_ffbh_u32 %0, %1" : "=v"(r) : "v"(u));
+  const float L = __int_as_float((__float_as_int(X) & 0x7f800000) + 0x00a00000);
+  return fmaf(-(float)r, X, (6442450944.0f - L) - X);
+}
+
 // univariate kernel value of a compile-time kernel type
+template <typename Real, int KT>
+__device__ inline Real kval(uint32_t u, const Params* __restrict__ P);
+
+// The kernel factor of one dimension in scaled form: eta K(u) = s kappa(u),
+// so f = 1 + eta K = fma(s, kappa, 1) and derivative sums can accumulate
+// kappa and be scaled by s once at the end.  Order 2 uses the integer form
+// above (s = eta 2^-32); the other kernels use kappa = K, s = eta.
+template <typename Real, int KT>
+__device__ inline Real kscale(Real eta) {
+  if constexpr (KT == KT_DSI2) return eta * (Real)0x1p-32;
+  else return eta;
+}
+template <typename Real, int KT>
+__device__ inline Real kappa(uint32_t u, const Params* __restrict__ P) {
+  if constexpr (KT == KT_DSI2) return dsi2_kappa<Real>(u);
+  else return kval<Real, KT>(u, P);
+}
+
 template <typename Real, int KT>
 __device__ inline Real kval(uint32_t u, const Params* __restrict__ P) {
   if constexpr (KT == KT_DSIA) {

@@ -106,7 +106,14 @@ template <typename Real> __device__ inline Real unit_trunc(uint32_t u);
 template <> __device__ inline double unit_trunc<double>(uint32_t u) { return (double)u * 0x1p-32; }
 template <> __device__ inline float unit_trunc<float>(uint32_t u) { return __uint2float_rz(u) * 0x1p-32f; }
 
-__device__ inline int beta_of(uint32_t u) { return u ? __clz(u) + 1 : 0; }
+// beta(u) = (index of the leading 1 digit) = clz(u) + 1, beta(0) = 0.  The
+// find-first-bit-high instruction returns -1 for u = 0, so adding 1 gives
+// both cases without a compare and select.
+__device__ inline int beta_of(uint32_t u) {
+  int r;
+  asm("v_ffbh_u32 %0, %1" : "=v"(r) : "v"(u));
+  return r + 1;
+}
 
 // Khat_alpha(x), x = u 2^-32 (Eq. DSI_kernel_1d_ex), beta(0) = t_nu(0) = 0.
 template <typename Real, int ORDER>

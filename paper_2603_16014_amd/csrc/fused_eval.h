@@ -33,9 +33,9 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
   const uint32_t t = threadIdx.x;
   const int stride = lds_stride(LB);
   Digits<FAM_DSEQ, D> dg;
-  Real eta[D];
+  Real sc[D];  // eta K = sc kappa; padding slots: sc = 0, factor exactly 1
 #pragma unroll
-  for (int j = 0; j < D; j++) eta[j] = j < d ? RT<Real>::eta(P, j) : (Real)0;
+  for (int j = 0; j < D; j++) sc[j] = kscale<Real, KT>(j < d ? RT<Real>::eta(P, j) : (Real)0);
   const Real gam = RT<Real>::gamma(P);
   if constexpr (E > 0) {
     // nb == 256 E: thread t owns indices t + 256 e.  Index bits 8 .. 8+log2(E)
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
     for (int k = 0; k < E; k++) {
       Real c = gam;
 #pragma unroll
-      for (int j = 0; j < D; j++) c = fma(c * eta[j], kval<Real, KT>(dg.u(j), P), c);
+      for (int j = 0; j < D; j++) c *= fma(sc[j], kappa<Real, KT>(dg.u(j), P), (Real)1);
       v[Digits<FAM_DSEQ, D>::elem(k)] = c;
       if (k + 1 < E) dg.advance(gen, d, k);
     }
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
       for (int k = 0; k < En; k++) {
         Real c = gam;
 #pragma unroll
-        for (int j = 0; j < D; j++) c = fma(c * eta[j], kval<Real, KT>(dg.u(j), P), c);
+        for (int j = 0; j < D; j++) c *= fma(sc[j], kappa<Real, KT>(dg.u(j), P), (Real)1);
         lds[lds_at(0, stride, (int)t + 256 * dg.elem(k))] = c;
         if (k + 1 < En) dg.advance(gen, d, k);
       }
@@ -93,27 +93,26 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
 // plus dc/dlog b_alpha for the adaptive kernel and c itself (dc/dlog gamma).
 // ---------------------------------------------------------------------------
 
-// Accumulates the derivative sums of one element with weight wv into acc
-// (slot j: eta_j, slot D: c itself) and acc_b (adaptive weights).
+// Accumulates the derivative sums of one element with weight wv: slot j
+// gets w gamma kappa_j prod_{k != j} f_k (times sc_j at the end this is
+// w dc/dlog eta_j), slot D gets w c, acc_b the adaptive-weight sums.
 template <typename Real, int KT, int D>
 __device__ inline void adj_element(const Digits<kt_family(KT), D>& dg, Real wv, Real gam,
-                                   const Real (&eta)[D], const Params* __restrict__ P,
+                                   const Real (&sc)[D], const Params* __restrict__ P,
                                    Real (&acc)[D + 1], Real (&acc_b)[4]) {
   constexpr bool ADAPT = KT == KT_DSIA;
-  Real g[D], f[D];
+  Real kap[D], f[D];
   Real Ka[ADAPT ? D : 1][4];
 #pragma unroll
   for (int j = 0; j < D; j++) {
-    Real K;
     if constexpr (ADAPT) {
       dsi_khat_all<Real>(dg.u(j), Ka[j]);
-      K = RT<Real>::bw(P, 0) * Ka[j][0] + RT<Real>::bw(P, 1) * Ka[j][1] +
-          RT<Real>::bw(P, 2) * Ka[j][2] + RT<Real>::bw(P, 3) * Ka[j][3];
+      kap[j] = RT<Real>::bw(P, 0) * Ka[j][0] + RT<Real>::bw(P, 1) * Ka[j][1] +
+               RT<Real>::bw(P, 2) * Ka[j][2] + RT<Real>::bw(P, 3) * Ka[j][3];
     } else {
-      K = kval<Real, KT>(dg.u(j), P);
+      kap[j] = kappa<Real, KT>(dg.u(j), P);
     }
-    g[j] = eta[j] * K;  // padding slots: eta = 0, so g = 0 and f = 1
-    f[j] = g[j] + (Real)1;
+    f[j] = fma(sc[j], kap[j], (Real)1);
   }
   // pre[j] = w gamma prod_{k<j} f_k; the suffix product runs backwards
   Real pre[D];
@@ -128,9 +127,9 @@ __device__ inline void adj_element(const Digits<kt_family(KT), D>& dg, Real wv, 
 #pragma unroll
   for (int j = D - 1; j >= 0; j--) {
     const Real ps = pre[j] * suf;  // w gamma prod_{k != j} f_k
-    acc[j] = fma(ps, g[j], acc[j]);
+    acc[j] = fma(ps, kap[j], acc[j]);
     if constexpr (ADAPT) {
-      const Real pe = ps * eta[j];
+      const Real pe = ps * sc[j];
 #pragma unroll
       for (int q = 0; q < 4; q++) acc_b[q] = fma(pe, Ka[j][q], acc_b[q]);
     }
@@ -168,17 +167,19 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
   // exceed the register file
   const int En = nb > 256 ? nb >> 8 : 1;
   if ((int)t < nb) {
-    Real eta[D];
+    Real sc[D];  // eta K = sc kappa; padding slots: sc = 0
 #pragma unroll
-    for (int j = 0; j < D; j++) eta[j] = j < d ? RT<Real>::eta(P, j) : (Real)0;
+    for (int j = 0; j < D; j++) sc[j] = kscale<Real, KT>(j < d ? RT<Real>::eta(P, j) : (Real)0);
     const Real gam = RT<Real>::gamma(P);
     Digits<FAM, D> dg;
     dg.init(gen, colshift + (size_t)col * d, d, t, i0, m);
     for (int k = 0; k < En; k++) {
       const Real wv = lds[lds_at(0, stride, (int)t + 256 * dg.elem(k))];
-      adj_element<Real, KT, D>(dg, wv, gam, eta, P, acc, acc_b);
+      adj_element<Real, KT, D>(dg, wv, gam, sc, P, acc, acc_b);
       if (k + 1 < En) dg.advance(gen, d, k);
     }
+#pragma unroll
+    for (int j = 0; j < D; j++) acc[j] *= sc[j];  // kappa sums -> dc/dlog eta_j sums
   }
   // block sums, one barrier; slot layout [eta_0 .. eta_{D-1}, c, b_0 .. b_3]
   const int wv_id = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
