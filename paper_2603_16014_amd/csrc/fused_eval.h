@@ -156,8 +156,24 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
   const uint32_t t = threadIdx.x;
   const TIn* w = base + (size_t)col * col_stride + i0;
   const int stride = lds_stride(LB);
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) lds[lds_at(0, stride, i)] = (Real)w[i];
-  lds_fwht<Real>(lds, 1, LB, stride);
+  if (LB == 12) {
+    // 16 loads in flight per thread, index bits 8 .. 11 in registers, bits
+    // 0 .. 7 in two LDS rounds
+    Real v[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = (Real)w[t + 256 * k];
+    reg_fwht<Real, 16>(v);
+#pragma unroll
+    for (int k = 0; k < 16; k++) lds[lds_at(0, stride, (int)t + 256 * k)] = v[k];
+    __syncthreads();
+    lds_round<Real, 4>(lds, 1, LB, 0, stride);
+    __syncthreads();
+    lds_round<Real, 4>(lds, 1, LB, 4, stride);
+    __syncthreads();
+  } else {
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) lds[lds_at(0, stride, i)] = (Real)w[i];
+    lds_fwht<Real>(lds, 1, LB, stride);
+  }
 
   Real acc[D + 1];
   Real acc_b[4] = {0, 0, 0, 0};
@@ -173,10 +189,11 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
     const Real gam = RT<Real>::gamma(P);
     Digits<FAM, D> dg;
     dg.init(gen, colshift + (size_t)col * d, d, t, i0, m);
+    dg.load_columns(gen, d);
     for (int k = 0; k < En; k++) {
       const Real wv = lds[lds_at(0, stride, (int)t + 256 * dg.elem(k))];
       adj_element<Real, KT, D>(dg, wv, gam, sc, P, acc, acc_b);
-      if (k + 1 < En) dg.advance(gen, d, k);
+      if (k + 1 < En) dg.advance_lanes(k);
     }
 #pragma unroll
     for (int j = 0; j < D; j++) acc[j] *= sc[j];  // kappa sums -> dc/dlog eta_j sums

@@ -49,8 +49,24 @@ __global__ __launch_bounds__(256) void fwht_lo_kernel(Real* __restrict__ base, i
   const int nb = 1 << LB;
   const int stride = lds_stride(LB);
   Real* p = base + (size_t)blockIdx.y * vec_stride + ((size_t)blockIdx.x << LB);
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) lds[lds_at(0, stride, i)] = p[i];
-  lds_fwht<Real>(lds, 1, LB, stride);
+  if (LB == 12) {
+    // 16 loads in flight per thread, bits 8 .. 11 in registers
+    const int t = threadIdx.x;
+    Real v[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) v[k] = p[t + 256 * k];
+    reg_fwht<Real, 16>(v);
+#pragma unroll
+    for (int k = 0; k < 16; k++) lds[lds_at(0, stride, t + 256 * k)] = v[k];
+    __syncthreads();
+    lds_round<Real, 4>(lds, 1, LB, 0, stride);
+    __syncthreads();
+    lds_round<Real, 4>(lds, 1, LB, 4, stride);
+    __syncthreads();
+  } else {
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) lds[lds_at(0, stride, i)] = p[i];
+    lds_fwht<Real>(lds, 1, LB, stride);
+  }
   for (int i = threadIdx.x; i < nb; i += blockDim.x) p[i] = lds[lds_at(0, stride, i)];
 }
 
