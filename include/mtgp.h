@@ -234,6 +234,16 @@ size_t mtgp_predict_net_scratch_bytes(const mtgp_plan* plan, int32_t m_star);
 int mtgp_predict_net(const mtgp_plan* plan, const double* theta, const uint32_t* shift_star,
                      int32_t m_star, double* mean, void* ws, void* scratch, void* stream);
 
+/* Multitask Bayesian cubature (Section "Extensions for Bayesian Cubature",
+ * multitask theorem): the posterior N(mu_hat, Sigma) of the task integrals
+ * mu_t = int_[0,1)^d f(t, x) dx under the fitted MTGP,
+ *   mu_hat = tau + gamma R E Ktilde^-1 (y - E^T tau)   (device [T]),
+ *   Sigma  = gamma R - gamma^2 R Pi R, Pi = E Ktilde^-1 E^T   (device [T][T]),
+ * with tau the plan's means (profiled: mu_hat = tau_hat).  Runs one loss
+ * evaluation on ws (data set by mtgp_set_data) plus an O(T^3) kernel. */
+int mtgp_cubature(const mtgp_plan* plan, const double* theta, double* mu_hat, double* Sigma,
+                  void* ws, void* stream);
+
 /* Many independent fits: mtgp_nll_grad for fit i = 0 .. nfits-1 with its own
  * plan, theta, outputs and workspace, all enqueued on one stream (host
  * arrays of device pointers).  Calls into it may be captured once in a HIP

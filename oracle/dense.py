@@ -21,7 +21,9 @@ fast method is exact (Theorem "Fast MTGP computations").
 Pinned by: the multivariate-normal log-density (scipy), the eigenstructure of
 Theorem "Fast MTGP computations" on tiny designs, central finite differences
 of L, interpolation of the posterior mean as xi -> 0, the Bayesian-cubature
-identity E alpha = 0 at tau_hat, the extended-precision twin.
+identity E alpha = 0 at tau_hat, the extended-precision twin; the cubature
+mean and covariance by quadrature of the posterior mean and covariance over
+fine independent point sets.
 """
 import math
 
@@ -176,6 +178,40 @@ def posterior_mean(w, y, Xs, theta=None, X=None, profile=None, res=None):
     for s in range(w.T):
         kv[:, s] = cross_q(w, theta, Xs, X[s]) @ alpha[off[s]:off[s + 1]]
     return res["tau_hat"][None, :] + kv @ R.T
+
+
+def posterior_cov(w, Xa, Xb, ta, tb, theta=None, X=None, res=None):
+    """Cov[f(ta, x_a), f(tb, x_b) | data] for all pairs of the two point sets:
+    R_{ta,tb} Q(x_a, x_b) - k_ta(x_a)^T Ktilde^-1 k_tb(x_b) with
+    k_t(x)[(u, k)] = R_tu Q(x, x_uk) (the noise-free latent function)."""
+    theta = w.theta if theta is None else theta
+    X = pts.task_points(w) if X is None else X
+    cf = sla.cho_factor(gram(w, theta, X), lower=True) if res is None else res["cf"]
+    R = task_cov(theta)
+    ka = np.concatenate([R[ta, u] * cross_q(w, theta, Xa, X[u]) for u in range(w.T)], axis=1)
+    kb = np.concatenate([R[tb, u] * cross_q(w, theta, Xb, X[u]) for u in range(w.T)], axis=1)
+    return R[ta, tb] * cross_q(w, theta, Xa, Xb) - ka @ sla.cho_solve(cf, kb.T)
+
+
+def bayesian_cubature(w, y, theta=None, X=None, profile=None, res=None):
+    """Posterior of the task integrals mu_t = int f(t, x) dx (Section
+    "Extensions for Bayesian Cubature", multitask theorem): with
+    gamma = int Q(x, x') dx' (the DSI and SI kernels here have zero-mean
+    univariate parts, so gamma is the kernel's gamma),
+      mu_hat = tau + gamma R E Ktilde^-1 (y - E^T tau),
+      Sigma  = gamma R - gamma^2 R Pi R,   Pi = E Ktilde^-1 E^T.
+    Returns dict(mu_hat[T], Sigma[T][T], Pi[T][T])."""
+    theta = w.theta if theta is None else theta
+    X = pts.task_points(w) if X is None else X
+    res = nll(w, y, theta, X, profile) if res is None else res
+    n = [x.shape[0] for x in X]
+    E = summing_matrix(n)
+    R = task_cov(theta)
+    g = float(theta["gamma"])
+    Pi = E @ sla.cho_solve(res["cf"], E.T)
+    mu = res["tau_hat"] + g * R @ (E @ res["alpha"])
+    Sigma = g * R - g * g * R @ Pi @ R
+    return dict(mu_hat=mu, Sigma=Sigma, Pi=Pi)
 
 
 def sample_prior(w, rng, theta=None, X=None):

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) void alg1_stage_kernel(const SR* __restrict__ 
 
 // Profiled means from residue class 0: Pi_tu = sqrt(n_t n_u) (Lambda^-1)_{(t,0),(u,0)},
 // (E K^-1 y)_t = sqrt(n_t) (Lambda^-1 yhat)_{(t,0)}; Pi tau = E K^-1 y (Theorem
-// "Fast MTGP computations", item 4).  Writes P->tau_used.  One block.
+// "Fast MTGP computations", item 4).  Writes P->Pi and P->tau_used.  One block.
 __global__ void alg1_tau_kernel(Alg1Desc A1, Params* P, const double* __restrict__ yhat,
                                 int family, int profile, const z2* __restrict__ Afin) {
   __shared__ double Pi[MTGP_MAXT][MTGP_MAXT + 1];
@@ -178,10 +178,6 @@ __global__ void alg1_tau_kernel(Alg1Desc A1, Params* P, const double* __restrict
     }
   }
   __syncthreads();
-  if (!profile) {
-    if (threadIdx.x < T) P->tau_used[threadIdx.x] = P->tau[threadIdx.x];
-    return;
-  }
   // rows (t, 0) of the residue-0 block of Lambda^-1
   for (int e = threadIdx.x; e < T * (T + 1); e += blockDim.x) {
     const int t = e / (T + 1), u = e - t * (T + 1);
@@ -202,6 +198,14 @@ __global__ void alg1_tau_kernel(Alg1Desc A1, Params* P, const double* __restrict
       }
       Pi[t][T] = sqrt(ldexp(1.0, A1.m[t])) * acc;
     }
+  }
+  __syncthreads();
+  // Pi itself (Bayesian cubature reads it)
+  for (int e = threadIdx.x; e < T * T; e += blockDim.x)
+    P->Pi[(e / T) * MTGP_MAXT + e % T] = Pi[e / T][e % T];
+  if (!profile) {
+    if (threadIdx.x < T) P->tau_used[threadIdx.x] = P->tau[threadIdx.x];
+    return;
   }
   __syncthreads();
   if (threadIdx.x == 0) {

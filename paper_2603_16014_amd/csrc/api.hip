@@ -1006,6 +1006,31 @@ int mtgp_predict_net(const mtgp_plan* p, const double* theta, const uint32_t* sh
   return MTGP_OK;
 }
 
+int mtgp_cubature(const mtgp_plan* p, const double* theta, double* mu_hat, double* Sigma,
+                  void* ws, void* stream) {
+  if (!p || !theta || !mu_hat || !Sigma || !ws) return MTGP_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const WsView w = view(p, ws);
+  // the loss leaves the spectrum (no gradient: it is not overwritten), ahat,
+  // tau_used and, for nested sizes, Pi in the parameter block
+  const int rc = dispatch_loss(p, theta, w.misc, nullptr, nullptr, ws, st, true);
+  if (rc) return rc;
+  CubDesc cd;
+  cd.equal = p->equal ? 1 : 0;
+  cd.n = p->n[0];
+  for (int t = 0; t < MTGP_MAXT; t++)
+    for (int u = 0; u < MTGP_MAXT; u++) cd.pair_col[t][u] = p->pm.col[t][u];
+  for (int t = 0; t < p->T; t++) cd.task_off[t] = p->off[t];
+  const KDesc kd = p->kd();
+  if (p->precision == MTGP_FP64)
+    LAUNCH_OK(launch_cubature<double>(reinterpret_cast<const double*>(w.cols), cd, w.ahat, w.P, kd,
+                                      mu_hat, Sigma, st));
+  else
+    LAUNCH_OK(launch_cubature<float>(reinterpret_cast<const float*>(w.cols), cd, w.ahat, w.P, kd,
+                                     mu_hat, Sigma, st));
+  return MTGP_OK;
+}
+
 int mtgp_nll_grad_batched(int32_t nfits, mtgp_plan* const* plans, const double* const* thetas,
                           double* const* out3, double* const* grads, void* const* ws,
                           void* stream) {

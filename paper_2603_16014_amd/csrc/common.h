@@ -35,6 +35,8 @@ struct Params {
   double tau_used[MTGP_MAXT];  // means of the last loss evaluation (tau_hat or tau)
   double R[MTGP_MAXT * MTGP_MAXT];
   double B[MTGP_MAXT * MTGP_MAXS];
+  // Pi = E Ktilde^-1 E^T of the last unequal-size loss (row-major, MAXT wide)
+  double Pi[MTGP_MAXT * MTGP_MAXT];
   float gamma_f;
   float eta_f[MTGP_MAXD];
   float b_f[4];

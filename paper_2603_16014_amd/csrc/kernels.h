@@ -183,6 +183,17 @@ int launch_alg1(SR* cols, const Alg1Desc& A1, Params* P, int family, bool grad,
                 const double* yhat, z2* bufA, z2* bufB, double* logs, double* ahat,
                 double* partials, int* status, hipStream_t st);
 
+// ---- cubature.hip
+struct CubDesc {
+  int equal;
+  int64_t n;                            // equal sizes: common length
+  int8_t pair_col[MTGP_MAXT][MTGP_MAXT];  // column of pair (t <= u)
+  int64_t task_off[MTGP_MAXT];          // task offsets in ahat
+};
+template <typename SR>
+int launch_cubature(const SR* cols, const CubDesc& cd, const double* ahat, const Params* P,
+                    const KDesc& kd, double* mu, double* Sigma, hipStream_t st);
+
 // ---- optim.hip
 int launch_adam(double* theta, const double* grad, double* m1, double* m2, int64_t n, double lr,
                 double b1, double b2, double eps, int64_t* step, const uint8_t* frozen,

@@ -197,6 +197,15 @@ class Plan:
         """Chunks of the overlapped digital-net passes (1 = no overlap)."""
         _lib.check(self.lib.mtgp_plan_set_overlap(self.h, int(chunks)), "mtgp_plan_set_overlap")
 
+    def cubature(self, theta: torch.Tensor):
+        """Bayesian cubature: (mu_hat [T], Sigma [T][T]) of the task integrals."""
+        _need_cuda(theta, torch.float64, "theta")
+        mu = torch.empty(self.T, dtype=torch.float64, device="cuda")
+        Sigma = torch.empty((self.T, self.T), dtype=torch.float64, device="cuda")
+        _lib.check(self.lib.mtgp_cubature(self.h, _ptr(theta), _ptr(mu), _ptr(Sigma),
+                                          _ptr(self.ws), _stream()), "mtgp_cubature")
+        return mu, Sigma
+
     def enable_timing(self, on=True):
         _lib.check(self.lib.mtgp_plan_enable_timing(self.h, int(bool(on))), "mtgp_plan_enable_timing")
 

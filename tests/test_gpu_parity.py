@@ -335,3 +335,32 @@ def test_predict_net_against_oracle(m, m_star, precision):
     # the direct sum at the same points agrees as well
     direct = plan.predict(theta, mt.digits_to_device(Xs)).cpu().numpy()
     assert rel_err(direct, mean) < tol
+
+
+# ------------------------------------------------------------ cubature
+@pytest.mark.parametrize("family,m,profile,precision", [
+    ("dseq", [7, 7, 7], True, "fp64"), ("dseq", [7, 7, 7], False, "fp64"),
+    ("dseq", [8, 6, 5], False, "fp64"), ("dseq", [8, 6, 5], True, "mixed"),
+    ("lat", [7, 7], False, "fp64"), ("lat", [7, 6, 5], False, "fp64"),
+    ("lat", [7, 7, 7], True, "mixed"), ("dseq", [9, 9], False, "mixed")])
+def test_cubature_against_oracle(family, m, profile, precision):
+    import workloads as wl
+    w = wl.with_theta(tiny(family, len(m), m, 3, seed=41, profile=profile),
+                      tau=np.linspace(-0.3, 0.4, len(m)))
+    say("cubature", family, m, profile, precision)
+    X = points.task_points(w)
+    from oracle import dense
+    y = dense.targets(w, np.random.default_rng(w.seed + 1000), X)
+    res = dense.nll(w, y, X=X)
+    ref = dense.bayesian_cubature(w, y, X=X, res=res)
+    plan = mt.Plan.from_workload(w, precision)
+    plan.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
+    theta = plan.pack_theta(w.theta)
+    mu, Sigma = plan.cubature(theta)
+    torch.cuda.synchronize()
+    assert plan.status()[0] == 0
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    assert rel_err(Sigma.cpu().numpy(), ref["Sigma"]) < tol, (Sigma, ref["Sigma"])
+    assert rel_err(mu.cpu().numpy(), ref["mu_hat"]) < tol, (mu, ref["mu_hat"])
+    if profile:
+        np.testing.assert_allclose(mu.cpu().numpy(), res["tau_hat"], rtol=tol, atol=1e-12)

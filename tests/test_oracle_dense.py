@@ -18,6 +18,8 @@ import math
 
 import numpy as np
 import pytest
+
+import workloads
 import scipy.linalg as sla
 import scipy.stats
 
@@ -168,3 +170,89 @@ def test_bayesian_cubature_identity(family):
     r = dense.nll(w, y, X=X)
     Ea = dense.summing_matrix([32, 16, 8]) @ r["alpha"]
     assert np.abs(Ea).max() < 1e-8 * np.abs(r["alpha"]).sum()
+
+
+def _fine_set(family, d, m, seed):
+    """An independent good point set of 2^m points for quadrature.  Nets:
+    the digitally shifted 2-D Hammersley net (generating matrices identity
+    and reversed identity, a (0, m, 2)-net); random unit lower-triangular
+    matrices share the leading digit in every coordinate and integrate the
+    product kernel badly.  Lattices: a random rank-1 lattice."""
+    rng = np.random.default_rng(seed)
+    if family == "dseq":
+        assert d == 2
+        i = np.arange(1 << m, dtype=np.uint64)
+        x1 = pts.van_der_corput_digits(1 << m)
+        x2 = (i << np.uint64(32 - m)).astype(np.uint32)
+        sh = workloads.random_shifts(rng, 1, d)[0]
+        return np.stack([x1 ^ sh[0], x2 ^ sh[1]], axis=1).astype(np.uint32)
+    gen = workloads.random_lattice_gen(rng, d)
+    return pts.lattice_points(gen, 1 << m, workloads.random_shifts(rng, 1, d)[0])
+
+
+@pytest.mark.parametrize("family", ["dseq", "lat"])
+def test_cubature_covariance_is_double_integral_of_posterior_cov(family):
+    """Sigma_tu = int int Cov[f(t,x), f(u,x') | data] dx dx', here by the
+    average over a fine independent point set (quadrature, not the formula)."""
+    w = tiny(family, 2, [5, 4], 2, seed=8)
+    X = pts.task_points(w)
+    y = dense.targets(w, np.random.default_rng(5), X)
+    res = dense.nll(w, y, X=X)
+    bc = dense.bayesian_cubature(w, y, X=X, res=res)
+    Z = _fine_set(family, w.d, 12, 77)
+    quad = np.zeros((2, 2))
+    for a in range(2):
+        for b in range(2):
+            quad[a, b] = dense.posterior_cov(w, Z, Z, a, b, X=X, res=res).mean()
+    scale = np.abs(bc["Sigma"]).max()
+    # the net quadrature of these kernels converges like 2^-m (measured: the
+    # kernel mean itself is off by 6e-3 at m = 12), the lattice one faster
+    tol = 2e-2 if family == "dseq" else 2e-4
+    assert np.abs(quad - bc["Sigma"]).max() < tol * scale, (quad, bc["Sigma"])
+    assert np.allclose(bc["Sigma"], bc["Sigma"].T, rtol=0, atol=1e-14 * scale)
+    assert np.linalg.eigvalsh(bc["Sigma"]).min() > -1e-12 * scale
+
+
+@pytest.mark.parametrize("family", ["dseq", "lat"])
+def test_cubature_mean_is_integral_of_posterior_mean(family):
+    """With fixed means, mu_hat_t = int mu(t, x) dx (quadrature again); with
+    profiled means, mu_hat = tau_hat (the theorem's last statement)."""
+    w = workloads.with_theta(tiny(family, 3, [5, 5, 4], 2, seed=9), tau=np.array([0.3, -0.2, 0.1]))
+    X = pts.task_points(w)
+    y = dense.targets(w, np.random.default_rng(6), X)
+    res = dense.nll(w, y, X=X, profile=False)
+    bc = dense.bayesian_cubature(w, y, X=X, profile=False, res=res)
+    Z = _fine_set(family, w.d, 12, 78)
+    avg = dense.posterior_mean(w, y, Z, X=X, profile=False, res=res).mean(axis=0)
+    tol = 2e-2 if family == "dseq" else 1e-4
+    assert np.abs(avg - bc["mu_hat"]).max() < tol * np.abs(avg).max(), (avg, bc["mu_hat"])
+    resp = dense.nll(w, y, X=X, profile=True)
+    bcp = dense.bayesian_cubature(w, y, X=X, profile=True, res=resp)
+    np.testing.assert_allclose(bcp["mu_hat"], resp["tau_hat"], rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("family,profile", [("dseq", False), ("lat", False), ("dseq", True)])
+def test_cubature_is_gaussian_conditioning_of_the_joint(family, profile):
+    """The integrals and the data are jointly Gaussian with
+    Cov(mu, mu) = gamma R, Cov(mu, y) = gamma R E, Cov(y, y) = Ktilde (the
+    kernel means integrate to gamma).  Conditioning through the inverse of
+    the full joint matrix (a different route from the Schur complement the
+    oracle uses) gives the same mean and covariance."""
+    w = workloads.with_theta(tiny(family, 3, [4, 4, 3], 2, seed=10), tau=np.array([0.2, 0.1, -0.3]))
+    X = pts.task_points(w)
+    y = dense.targets(w, np.random.default_rng(7), X)
+    res = dense.nll(w, y, X=X, profile=profile)
+    bc = dense.bayesian_cubature(w, y, X=X, profile=profile, res=res)
+    n = [x.shape[0] for x in X]
+    E = dense.summing_matrix(n)
+    R = dense.task_cov(w.theta)
+    g = w.theta["gamma"]
+    K = dense.gram(w, w.theta, X)
+    T = w.T
+    J = np.block([[g * R, g * R @ E], [(g * R @ E).T, K]])
+    Ji = np.linalg.inv(J)
+    Sigma = np.linalg.inv(Ji[:T, :T])
+    r = y - E.T @ res["tau_hat"]
+    mu = res["tau_hat"] - Sigma @ Ji[:T, T:] @ r
+    np.testing.assert_allclose(bc["Sigma"], Sigma, rtol=1e-8, atol=1e-10 * np.abs(Sigma).max())
+    np.testing.assert_allclose(bc["mu_hat"], mu, rtol=1e-8, atol=1e-10 * np.abs(mu).max())
