@@ -45,9 +45,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_loss_grad_T8_d10_n2e24_mixed.
 # phase -> (kernel-name pattern in rocprofv3 output, bound)
 PHASE_KERNELS = {
     "gen_fwd_low": ("gen_fwd_kernel", "alu"),
-    "fwd_high": ("fwht_strided_kernel<double, double, float>", "hbm"),
+    "fwd_high": ("fwht_reg_kernel (2 passes)", "hbm"),
     "solve": ("solve_eq_kernel", "hbm"),
-    "adj_high": ("fwht_strided_kernel<double, float, double>", "hbm"),
+    "adj_high": ("fwht_reg_kernel (2 passes)", "hbm"),
     "adj_low_reduce": ("adj_reduce_kernel", "alu"),
 }
 
@@ -367,12 +367,14 @@ def run(args):
         theta = plan.pack_theta(w.theta)
         progress("timing", prec)
         # the measured configuration: overlapped passes (library default)
+        if args.no_overlap:
+            plan.set_overlap(1)
         ms, out3, grad, tau, _, _ = time_evals(plan, theta, args.steps, args.warmup, timing=False)
         progress(f"{prec}: {ms:.3f} ms per loss+gradient")
         # per-kernel durations need the passes in sequence on one stream
         plan.set_overlap(1)
         ms_seq, _, _, _, phases, nph = time_evals(plan, theta, args.steps, 1, timing=True)
-        plan.set_overlap(4)
+        plan.set_overlap(1 if args.no_overlap else 4)
         progress(f"{prec}: {ms_seq:.3f} ms per loss+gradient without overlap")
         results[prec] = dict(ms=ms, out3=out3, grad=grad, phases=phases, nph=nph, ms_seq=ms_seq)
         if prec == "mixed" and args.train_steps > 0:
@@ -489,7 +491,7 @@ def _phase_of(name, cur):
         return "prep"
     if "gen_fwd_kernel" in name or "lat_pass" in name and cur == "prep":
         return "gen_fwd_low"
-    if "fwht_strided_kernel" in name:
+    if "fwht_strided_kernel" in name or "fwht_reg_kernel" in name:
         return "fwd_high" if cur in ("gen_fwd_low", "fwd_high") else "adj_high"
     if "solve_eq" in name or "alg1_" in name:
         return "solve"
@@ -597,6 +599,8 @@ def main():
                     help="Adam steps of the captured training leg (0: skip)")
     ap.add_argument("--no-predict", dest="predict", action="store_false")
     ap.add_argument("--no-transforms", dest="transforms", action="store_false")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run every pass in order on one stream (for per-kernel profiles)")
     ap.add_argument("--fits", type=int, default=256, help="fits of the batched leg (0: skip)")
     ap.add_argument("--fit-steps", type=int, default=50)
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "TRACE_DIR"))
