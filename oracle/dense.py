@@ -11,6 +11,8 @@ fast method is exact (Theorem "Fast MTGP computations").
   r = y - E^T tau; E is the task-summing matrix.
 * Optimal means (Eq. MTGP_optimal_tau): (E K^-1 E^T) tau_hat = E K^-1 y.
 * Posterior mean (Eq. MTGP_post_mean_cov): tau_t + K(t, x)^T Ktilde^-1 (y - E^T tau).
+* GCV loss (Eq. MTGP_MLE_GCV_loss) and its optimal means (Eq. MTGP_optimal_tau),
+  with the exact gradient; Bayesian cubature of the task integrals.
 * Gradient (the paper gives none; it is the exact derivative of L):
   dL/dtheta_k = -alpha^T (dK/dtheta_k) alpha + tr(K^-1 dK/dtheta_k) with
   alpha = K^-1 r, in the log-parameterisation of gamma, eta, b, xi, zeta and
@@ -113,19 +115,13 @@ def nll(w, y, theta=None, X=None, profile=None, K=None):
                 tau_hat=tau, alpha=alpha, cf=cf, K=K)
 
 
-def grad(w, y, theta=None, X=None, profile=None):
-    """Exact gradient of L in the packed parameterisation (dict keyed like theta)."""
-    theta = w.theta if theta is None else theta
-    profile = w.profile_tau if profile is None else profile
-    X = pts.task_points(w) if X is None else X
+def _param_grads(w, theta, X, Wd):
+    """sum_ij Wd_ij dKtilde_ij / dtheta for every non-mean parameter, by
+    assembling dKtilde densely from the analytic kernel derivatives."""
     fam, order, adaptive, _ = _kernel_args(w)
     b = None if theta.get("b") is None else np.asarray(theta["b"], dtype=np.float64)
     eta = np.asarray(theta["eta"], dtype=np.float64)
     R = task_cov(theta)
-    res = nll(w, y, theta, X, profile)
-    alpha = res["alpha"]
-    Kinv = sla.cho_solve(res["cf"], np.eye(res["K"].shape[0]))
-    Wd = Kinv - np.outer(alpha, alpha)       # dL/dK_ij summed against dK_ij
     n = [x.shape[0] for x in X]
     off = np.concatenate([[0], np.cumsum(n)])
     T, d = w.T, w.d
@@ -154,13 +150,70 @@ def grad(w, y, theta=None, X=None, profile=None):
     g_B = (G + G.T) @ B                      # R = B B^T + diag(zeta)
     zeta = np.asarray(theta["zeta"], dtype=np.float64)
     g_zeta = zeta * np.diag(G)
-    if profile:
-        g_tau = np.zeros(T)
-    else:
-        g_tau = -2.0 * (summing_matrix(n) @ alpha)
-    out = dict(tau=g_tau, gamma=g_gamma, eta=g_eta, xi=g_xi, B=g_B, zeta=g_zeta)
+    out = dict(gamma=g_gamma, eta=g_eta, xi=g_xi, B=g_B, zeta=g_zeta)
     if adaptive:
         out["b"] = g_b
+    return out
+
+
+def grad(w, y, theta=None, X=None, profile=None):
+    """Exact gradient of L in the packed parameterisation (dict keyed like theta)."""
+    theta = w.theta if theta is None else theta
+    profile = w.profile_tau if profile is None else profile
+    X = pts.task_points(w) if X is None else X
+    res = nll(w, y, theta, X, profile)
+    alpha = res["alpha"]
+    Kinv = sla.cho_solve(res["cf"], np.eye(res["K"].shape[0]))
+    Wd = Kinv - np.outer(alpha, alpha)       # dL/dK_ij summed against dK_ij
+    out = _param_grads(w, theta, X, Wd)
+    n = [x.shape[0] for x in X]
+    out["tau"] = np.zeros(w.T) if profile else -2.0 * (summing_matrix(n) @ alpha)
+    return out, res
+
+
+def gcv(w, y, theta=None, X=None, profile=None, K=None):
+    """GCV loss (Eq. MTGP_MLE_GCV_loss) L_GCV = r^T Ktilde^-2 r / tr^2(Ktilde^-1),
+    r = y - E^T tau, with tau = tau_hat_GCV solving
+    (E Ktilde^-2 E^T) tau = E Ktilde^-2 y (Eq. MTGP_optimal_tau) when profiled.
+    Returns dict(q = r^T Ktilde^-2 r, s = tr Ktilde^-1, L, tau_hat, a = Ktilde^-1 r,
+    bvec = Ktilde^-2 r, cf, K)."""
+    theta = w.theta if theta is None else theta
+    profile = w.profile_tau if profile is None else profile
+    X = pts.task_points(w) if X is None else X
+    y = np.asarray(y, dtype=np.float64)
+    n = [x.shape[0] for x in X]
+    K = gram(w, theta, X) if K is None else K
+    cf = sla.cho_factor(K, lower=True)
+    Kinv = sla.cho_solve(cf, np.eye(K.shape[0]))
+    E = summing_matrix(n)
+    if profile:
+        K2Et = Kinv @ (Kinv @ E.T)
+        tau = np.linalg.solve(E @ K2Et, K2Et.T @ y)
+    else:
+        tau = np.asarray(theta["tau"], dtype=np.float64)
+    r = y - E.T @ tau
+    a = Kinv @ r
+    bvec = Kinv @ a
+    q = float(a @ a)
+    s = float(np.trace(Kinv))
+    return dict(q=q, s=s, L=q / (s * s), tau_hat=tau, a=a, bvec=bvec, cf=cf, K=K, Kinv=Kinv)
+
+
+def gcv_grad(w, y, theta=None, X=None, profile=None):
+    """Exact gradient of L_GCV: with a = Ktilde^-1 r, b = Ktilde^-2 r,
+    q = a^T a, s = tr Ktilde^-1,
+      dL = sum_ij W_ij dKtilde_ij,  W = -(a b^T + b a^T) / s^2 + (2 q / s^3) Ktilde^-2,
+    profiled tau: dL/dtau = 0 (tau_hat_GCV is stationary); fixed tau:
+    dL/dtau = -2 E b / s^2."""
+    theta = w.theta if theta is None else theta
+    profile = w.profile_tau if profile is None else profile
+    X = pts.task_points(w) if X is None else X
+    res = gcv(w, y, theta, X, profile)
+    a, bv, q, s, Kinv = res["a"], res["bvec"], res["q"], res["s"], res["Kinv"]
+    Wd = -(np.outer(a, bv) + np.outer(bv, a)) / s ** 2 + (2.0 * q / s ** 3) * (Kinv @ Kinv)
+    out = _param_grads(w, theta, X, Wd)
+    n = [x.shape[0] for x in X]
+    out["tau"] = np.zeros(w.T) if profile else -2.0 * (summing_matrix(n) @ bv) / s ** 2
     return out, res
 
 

@@ -256,3 +256,70 @@ def test_cubature_is_gaussian_conditioning_of_the_joint(family, profile):
     mu = res["tau_hat"] - Sigma @ Ji[:T, T:] @ r
     np.testing.assert_allclose(bc["Sigma"], Sigma, rtol=1e-8, atol=1e-10 * np.abs(Sigma).max())
     np.testing.assert_allclose(bc["mu_hat"], mu, rtol=1e-8, atol=1e-10 * np.abs(mu).max())
+
+
+# ----------------------------------------------------------------- GCV
+@pytest.mark.parametrize("family,m,profile", [("dseq", [5, 5], True), ("lat", [5, 4, 3], False),
+                                              ("dseq", [5, 4, 3], True)])
+def test_gcv_loss_by_eigendecomposition(family, m, profile):
+    """q = sum_i (u_i^T r)^2 / lambda_i^2 and s = sum_i 1 / lambda_i from the
+    eigenpairs of Ktilde (a different route from the Cholesky solves)."""
+    w = tiny(family, len(m), m, 2, seed=12, profile=profile)
+    X = pts.task_points(w)
+    y = dense.targets(w, np.random.default_rng(8), X)
+    res = dense.gcv(w, y, X=X)
+    lam, U = np.linalg.eigh(res["K"])
+    n = [x.shape[0] for x in X]
+    r = y - dense.summing_matrix(n).T @ res["tau_hat"]
+    c = U.T @ r
+    q = float(np.sum(c * c / lam ** 2))
+    s = float(np.sum(1.0 / lam))
+    assert abs(q - res["q"]) < 1e-9 * q and abs(s - res["s"]) < 1e-11 * s
+    assert abs(q / s ** 2 - res["L"]) < 1e-9 * res["L"]
+
+
+@pytest.mark.parametrize("family", ["dseq", "lat"])
+def test_gcv_tau_hat(family):
+    """Equal sizes: tau_hat_GCV is the per-task sample mean (closed form, the
+    constant vector is an eigenvector of every equal-size block structure
+    here); nested sizes: it is a stationary point (fixed-tau gradient 0)."""
+    w = tiny(family, 3, [5, 5, 5], 2, seed=13)
+    X = pts.task_points(w)
+    y = dense.targets(w, np.random.default_rng(9), X)
+    res = dense.gcv(w, y, X=X, profile=True)
+    np.testing.assert_allclose(res["tau_hat"], y.reshape(3, -1).mean(axis=1), rtol=1e-9,
+                               atol=1e-9 * np.abs(y).max())
+    w2 = tiny(family, 3, [5, 4, 3], 2, seed=14)
+    X2 = pts.task_points(w2)
+    y2 = dense.targets(w2, np.random.default_rng(10), X2)
+    r2 = dense.gcv(w2, y2, X=X2, profile=True)
+    wf = workloads.with_theta(w2, tau=r2["tau_hat"])
+    g, _ = dense.gcv_grad(wf, y2, X=X2, profile=False)
+    assert np.abs(g["tau"]).max() < 1e-8 * np.abs(g["eta"]).max()
+
+
+@pytest.mark.parametrize("family,profile,adaptive", [("dseq", True, False), ("lat", False, False),
+                                                     ("dseq", False, True)])
+def test_gcv_gradient_central_differences(family, profile, adaptive):
+    w = tiny(family, 2, [4, 3], 2, seed=15, profile=profile, adaptive=adaptive)
+    X = pts.task_points(w)
+    y = dense.targets(w, np.random.default_rng(11), X)
+    g, res = dense.gcv_grad(w, y, X=X)
+    keys = ["tau", "gamma", "eta"] + (["b"] if adaptive else []) + ["xi", "B", "zeta"]
+    logk = {"gamma", "eta", "b", "xi", "zeta"}
+    h = 1e-5
+    for k in keys:
+        base = np.atleast_1d(np.asarray(w.theta[k], dtype=np.float64)).astype(float)
+        flat = base.ravel()
+        gk = np.atleast_1d(np.asarray(g[k], dtype=np.float64)).ravel()
+        for i in range(flat.size):
+            vals = []
+            for sgn in (1, -1):
+                f2 = flat.copy()
+                f2[i] = f2[i] * np.exp(sgn * h) if k in logk else f2[i] + sgn * h
+                v = f2.reshape(base.shape)
+                th = dict(w.theta)
+                th[k] = float(v[0]) if k == "gamma" else v
+                vals.append(dense.gcv(w, y, theta=th, X=X)["L"])
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - gk[i]) < 1e-5 * max(1.0, abs(gk[i])) + 1e-6 * res["L"], (k, i, fd, gk[i])
