@@ -234,6 +234,17 @@ size_t mtgp_predict_net_scratch_bytes(const mtgp_plan* plan, int32_t m_star);
 int mtgp_predict_net(const mtgp_plan* plan, const double* theta, const uint32_t* shift_star,
                      int32_t m_star, double* mean, void* ws, void* scratch, void* stream);
 
+/* GCV loss (Eq. MTGP_MLE_GCV_loss): out3 = (q, s, L_GCV) with
+ * q = r^T Ktilde^-2 r, s = tr Ktilde^-1, L_GCV = q / s^2, r = y - E^T tau,
+ * and optionally its gradient (device [theta size], same packing as
+ * mtgp_nll_grad; NULL: loss only).  tau is the plan's fixed means or, when
+ * profiled, the optimal GCV means (Eq. MTGP_optimal_tau), which for equal
+ * sizes are the per-task sample means (written to tau_hat if non-NULL).
+ * Equal sizes only: nested plans return MTGP_ENOTSUP.  Two passes over the
+ * spectrum (q and s first); same workspace as mtgp_nll_grad. */
+int mtgp_gcv(const mtgp_plan* plan, const double* theta, double* out3, double* grad,
+             double* tau_hat, void* ws, void* stream);
+
 /* Multitask Bayesian cubature (Section "Extensions for Bayesian Cubature",
  * multitask theorem): the posterior N(mu_hat, Sigma) of the task integrals
  * mu_t = int_[0,1)^d f(t, x) dx under the fitted MTGP,

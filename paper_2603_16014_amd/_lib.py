@@ -48,6 +48,7 @@ SIGNATURES = {
     "mtgp_predict_net_scratch_bytes": (c_sz, [vp, c_i32]),
     "mtgp_predict_net": (ctypes.c_int, [vp, vp, ctypes.POINTER(c_u32), c_i32, vp, vp, vp, vp]),
     "mtgp_status": (ctypes.c_int, [vp, vp, ctypes.POINTER(c_i64)]),
+    "mtgp_gcv": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
     "mtgp_cubature": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
     "mtgp_nll_grad_batched": (ctypes.c_int, [c_i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                              ctypes.POINTER(vp), ctypes.POINTER(vp),

@@ -91,6 +91,7 @@ struct mtgp_plan {
     k.s = s;
     k.profile = profile;
     k.unequal = equal ? 0 : 1;
+    k.gcv = 0;
     for (int t = 0; t < MTGP_MAXT; t++) k.m[t] = t < T ? m[t] : 0;
     return k;
   }
@@ -401,6 +402,35 @@ int run_loss(const mtgp_plan* p, const double* theta, double* out3, double* grad
                             p->equal ? nullptr : w.lp2, COLSUM_BLOCKS, w.yhat, n, w.P, kd, out3,
                             grad, tau_hat, st));
   mark_done(p, st);
+  return MTGP_OK;
+}
+
+// GCV loss (and gradient) for equal sizes: pass 1 forms q and s, pass 2
+// (gradient) the weights W that need them; the rest is the MLE pipeline.
+template <typename CR, typename SR>
+int run_gcv(const mtgp_plan* p, const double* theta, double* out3, double* grad, double* tau_hat,
+            void* ws, hipStream_t st) {
+  const WsView w = view(p, ws);
+  KDesc kd = p->kd();
+  kd.gcv = 1;
+  LAUNCH_OK(launch_prep(theta, w.P, kd, w.status, st));
+  int rc = forward_columns<CR, SR>(p, w, st);
+  if (rc) return rc;
+  SR* spec = reinterpret_cast<SR*>(w.cols);
+  const int64_t n = p->n[0];
+  LAUNCH_OK(launch_gcv_eq<SR>(spec, n, p->pm, w.yhat, w.P, kd, false, w.sp, w.status, st));
+  LAUNCH_OK(launch_colsum(w.sp, solve_blocks(n), solve_ns(p->T), w.sp2, COLSUM_BLOCKS, st));
+  LAUNCH_OK(launch_finalize(w.sp2, COLSUM_BLOCKS, nullptr, p->d_colinfo, p->ncol, nullptr, 0,
+                            w.yhat, n, w.P, kd, out3, nullptr, tau_hat, st));
+  if (!grad) return MTGP_OK;
+  LAUNCH_OK(launch_gcv_eq<SR>(spec, n, p->pm, w.yhat, w.P, kd, true, w.sp, w.status, st));
+  const int nadj = adjoint_columns<CR, SR>(p, w, st);
+  if (nadj < 0) return nadj;
+  if (nadj != p->nadj_blocks) return MTGP_EINVAL;
+  LAUNCH_OK(launch_colseg(w.ap, p->d_colinfo, p->ncol, adj_nq(p->d), w.ap2, st));
+  LAUNCH_OK(launch_colsum(w.sp, solve_blocks(n), solve_ns(p->T), w.sp2, COLSUM_BLOCKS, st));
+  LAUNCH_OK(launch_finalize(w.sp2, COLSUM_BLOCKS, w.ap2, p->d_colinfo, p->ncol, nullptr, 0,
+                            w.yhat, n, w.P, kd, out3, grad, tau_hat, st));
   return MTGP_OK;
 }
 
@@ -1004,6 +1034,18 @@ int mtgp_predict_net(const mtgp_plan* p, const double* theta, const uint32_t* sh
   LAUNCH_OK(launch_fwht<double>(wbuf, (int64_t)1 << m_star, p->T, m_star, p->sched, st));
   LAUNCH_OK(launch_prednet_out(wbuf, pn, w.P, mean, st));
   return MTGP_OK;
+}
+
+int mtgp_gcv(const mtgp_plan* p, const double* theta, double* out3, double* grad,
+             double* tau_hat, void* ws, void* stream) {
+  if (!p || !theta || !out3 || !ws) return MTGP_EINVAL;
+  if (!p->equal) return MTGP_ENOTSUP;
+  hipStream_t st = (hipStream_t)stream;
+  switch (p->precision) {
+    case MTGP_FP64: return run_gcv<double, double>(p, theta, out3, grad, tau_hat, ws, st);
+    case MTGP_MIXED: return run_gcv<double, float>(p, theta, out3, grad, tau_hat, ws, st);
+    default: return run_gcv<float, float>(p, theta, out3, grad, tau_hat, ws, st);
+  }
 }
 
 int mtgp_cubature(const mtgp_plan* p, const double* theta, double* mu_hat, double* Sigma,

@@ -37,6 +37,8 @@ struct Params {
   double B[MTGP_MAXT * MTGP_MAXS];
   // Pi = E Ktilde^-1 E^T of the last unequal-size loss (row-major, MAXT wide)
   double Pi[MTGP_MAXT * MTGP_MAXT];
+  // q = r^T Ktilde^-2 r and s = tr Ktilde^-1 of the last GCV loss
+  double gcv_q, gcv_s;
   float gamma_f;
   float eta_f[MTGP_MAXD];
   float b_f[4];
@@ -46,6 +48,7 @@ struct Params {
 struct KDesc {
   int T, d, family, order, adaptive, s, profile;
   int unequal;        // nested unequal sizes (Algorithm 1 path)
+  int gcv;            // the solves computed the GCV loss (q, s) instead of the MLE loss
   int m[MTGP_MAXT];   // per-task log2 sizes
 };
 

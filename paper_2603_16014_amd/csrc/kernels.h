@@ -183,6 +183,11 @@ int launch_alg1(SR* cols, const Alg1Desc& A1, Params* P, int family, bool grad,
                 const double* yhat, z2* bufA, z2* bufB, double* logs, double* ahat,
                 double* partials, int* status, hipStream_t st);
 
+// ---- gcv.hip
+template <typename SR>
+int launch_gcv_eq(SR* cols, int64_t n, const PairMap& pm, const double* yhat, const Params* P,
+                  const KDesc& kd, bool grad, double* partials, int* status, hipStream_t st);
+
 // ---- cubature.hip
 struct CubDesc {
   int equal;

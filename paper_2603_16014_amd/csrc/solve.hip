@@ -463,10 +463,20 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   ldx = block_sum(ldx, red);
   __syncthreads();
   if (threadIdx.x != 0) return;
-  const double quad = sums[0], logdet = sums[1] + ldx;
-  out3[0] = quad;
-  out3[1] = logdet;
-  out3[2] = quad + logdet;
+  if (kd.gcv) {
+    // GCV: sums[0] = q = r^T Ktilde^-2 r, sums[1] = s = tr Ktilde^-1
+    const double q = sums[0], s2 = sums[1];
+    out3[0] = q;
+    out3[1] = s2;
+    out3[2] = q / (s2 * s2);
+    P->gcv_q = q;
+    P->gcv_s = s2;
+  } else {
+    const double quad = sums[0], logdet = sums[1] + ldx;
+    out3[0] = quad;
+    out3[1] = logdet;
+    out3[2] = quad + logdet;
+  }
   const double sqn = sqrt((double)n);
   const int TMp = solve_tm(T);
   const int qG = 2, qX = 2 + TMp, qA = 2 + 2 * TMp;

@@ -197,6 +197,17 @@ class Plan:
         """Chunks of the overlapped digital-net passes (1 = no overlap)."""
         _lib.check(self.lib.mtgp_plan_set_overlap(self.h, int(chunks)), "mtgp_plan_set_overlap")
 
+    def gcv(self, theta: torch.Tensor, grad=True):
+        """GCV loss: (out3 = (q, s, L_GCV), gradient or None, tau_hat)."""
+        _need_cuda(theta, torch.float64, "theta")
+        out3 = torch.empty(3, dtype=torch.float64, device="cuda")
+        g = torch.empty(self.theta_size, dtype=torch.float64, device="cuda") if grad else None
+        tau = torch.empty(self.T, dtype=torch.float64, device="cuda")
+        _lib.check(self.lib.mtgp_gcv(self.h, _ptr(theta), _ptr(out3),
+                                     _ptr(g) if g is not None else None, _ptr(tau),
+                                     _ptr(self.ws), _stream()), "mtgp_gcv")
+        return out3, g, tau
+
     def cubature(self, theta: torch.Tensor):
         """Bayesian cubature: (mu_hat [T], Sigma [T][T]) of the task integrals."""
         _need_cuda(theta, torch.float64, "theta")

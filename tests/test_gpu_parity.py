@@ -364,3 +364,47 @@ def test_cubature_against_oracle(family, m, profile, precision):
     assert rel_err(mu.cpu().numpy(), ref["mu_hat"]) < tol, (mu, ref["mu_hat"])
     if profile:
         np.testing.assert_allclose(mu.cpu().numpy(), res["tau_hat"], rtol=tol, atol=1e-12)
+
+
+# ------------------------------------------------------------------ GCV
+@pytest.mark.parametrize("family,m,profile,precision", [
+    ("dseq", [7, 7, 7], True, "fp64"), ("dseq", [7, 7], False, "fp64"),
+    ("lat", [7, 7, 7], True, "fp64"), ("lat", [6, 6], False, "fp64"),
+    ("dseq", [8, 8, 8, 8], False, "mixed"), ("lat", [7, 7], True, "mixed")])
+def test_gcv_against_oracle(family, m, profile, precision):
+    import workloads as wl
+    w = wl.with_theta(tiny(family, len(m), m, 3, seed=51, profile=profile),
+                      tau=np.linspace(-0.2, 0.3, len(m)))
+    say("gcv", family, m, profile, precision)
+    X = points.task_points(w)
+    from oracle import dense
+    y = dense.targets(w, np.random.default_rng(w.seed + 1000), X)
+    g_ref, res = dense.gcv_grad(w, y, X=X)
+    plan = mt.Plan.from_workload(w, precision)
+    plan.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
+    theta = plan.pack_theta(w.theta)
+    out3, g, tau = plan.gcv(theta, grad=True)
+    torch.cuda.synchronize()
+    assert plan.status()[0] == 0
+    o = out3.cpu().numpy()
+    tolL = 1e-10 if precision == "fp64" else 1e-5
+    assert abs(o[2] - res["L"]) < tolL * res["L"], (o, res["L"])
+    assert abs(o[0] - res["q"]) < tolL * res["q"] and abs(o[1] - res["s"]) < tolL * res["s"]
+    gvec = plan.unpack(g)
+    scale = max(np.abs(np.atleast_1d(v)).max() for v in g_ref.values())
+    tolg = 1e-7 if precision == "fp64" else 1e-4
+    for k, v in g_ref.items():
+        e = np.abs(np.atleast_1d(gvec[k]) - np.atleast_1d(v)).max() / scale
+        assert e < tolg, (k, gvec[k], v, e)
+    # loss only gives the same loss
+    out3b, gb, _ = plan.gcv(theta, grad=False)
+    torch.cuda.synchronize()
+    assert gb is None and abs(float(out3b[2]) - o[2]) <= 1e-12 * o[2]
+
+
+def test_gcv_nested_sizes_not_supported():
+    w = tiny("dseq", 2, [6, 5], 2, seed=52)
+    plan = mt.Plan.from_workload(w, "fp64")
+    plan.set_data(torch.zeros(w.N, dtype=torch.float64, device="cuda"))
+    with pytest.raises(mt._lib.MTGPError):
+        plan.gcv(plan.pack_theta(w.theta))
