@@ -308,9 +308,9 @@ def batched_leg(nfits, steps, nstreams=16, eager_steps=3):
 
 def transforms_leg(ncols=29, m=24, reps=5):
     """Standalone transforms on the kernel-column shape of the workload:
-    mtgp_fwht on [ncols][2^m] in FP32 and FP64, and mtgp_fft on the same
-    number of real elements as rows of 2^21 (its largest size).  Algorithmic
-    bytes: read + write once (FWHT), real read + complex write (FFT)."""
+    mtgp_fwht and mtgp_fft (natural frequency order out) on [ncols][2^m] in
+    FP32 and FP64.  Algorithmic bytes: read + write once (FWHT), real read +
+    complex write (FFT)."""
     import torch
     from paper_2603_16014_amd import mtgp
     out = {}
@@ -324,11 +324,10 @@ def transforms_leg(ncols=29, m=24, reps=5):
             nbytes = 2 * x.numel() * b
             shape = f"[{ncols}][2^{m}]"
         else:
-            lm = min(m, 21)
             x = torch.randn(ncols << m, dtype=dt, device="cuda")
-            fn = lambda: mtgp.fft(x, lm)  # noqa: E731
+            fn = lambda: mtgp.fft(x, m)  # noqa: E731
             nbytes = 3 * x.numel() * b
-            shape = f"[{(ncols << m) >> lm}][2^{lm}]"
+            shape = f"[{ncols}][2^{m}]"
         fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -344,6 +343,38 @@ def transforms_leg(ncols=29, m=24, reps=5):
         del x
         torch.cuda.empty_cache()
     return out
+
+
+def lattice_leg(steps=5, warmup=1):
+    """Loss + gradient on the config-5 shape with shifted rank-1 lattices and
+    the order-2 SI kernel (FFT path), FP64 and mixed, with their agreement."""
+    import torch
+    import workloads
+    from paper_2603_16014_amd import mtgp
+    w = workloads.config5_lat()
+    res, y, keep = {}, None, {}
+    for prec in ("fp64", "mixed"):
+        progress("lattice leg", prec)
+        plan = mtgp.Plan.from_workload(w, prec)
+        if y is None:
+            y = targets_on_device(plan, w)
+        plan.set_data(y)
+        theta = plan.pack_theta(w.theta)
+        ms, out3, grad, _, _, _ = time_evals(plan, theta, steps, warmup, timing=False)
+        _, _, _, _, phases, _ = time_evals(plan, theta, steps, 1, timing=True)
+        progress(f"lattice {prec}: {ms:.3f} ms per loss+gradient")
+        res[prec] = {"evals_per_s": 1000.0 / ms, "ms_per_step": ms,
+                     "phases_ms": {k: round(v, 4) for k, v in phases.items()}}
+        keep[prec] = (out3, grad)
+        del plan
+        torch.cuda.empty_cache()
+    (a3, ag), (b3, bg) = keep["mixed"], keep["fp64"]
+    den = abs(b3[0]) + abs(b3[1])
+    res["mixed_vs_fp64"] = {"L_rel": float(abs(a3[2] - b3[2]) / den),
+                            "grad_rel_maxnorm": float(np.abs(ag - bg).max() / np.abs(bg).max())}
+    res["workload"] = (f"T={w.T}, d={w.d}, n=2^{w.m[0]} shifted rank-1 lattice points per task "
+                       f"(N={w.N}), order-2 SI kernel, rank-2 + diagonal task covariance")
+    return res
 
 
 def run(args):
@@ -462,6 +493,8 @@ def run(args):
         line["posterior_mean"] = results["predict"]
     if args.transforms:
         line["transforms"] = transforms_leg()
+    if args.lattice:
+        line["lattice"] = lattice_leg()
     if args.fits > 0:
         progress("batched leg")
         line["batched_fits"] = batched_leg(args.fits, args.fit_steps)
@@ -599,6 +632,8 @@ def main():
                     help="Adam steps of the captured training leg (0: skip)")
     ap.add_argument("--no-predict", dest="predict", action="store_false")
     ap.add_argument("--no-transforms", dest="transforms", action="store_false")
+    ap.add_argument("--no-lattice", dest="lattice", action="store_false",
+                    help="skip the loss+gradient leg on the lattice (FFT) path")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run every pass in order on one stream (for per-kernel profiles)")
     ap.add_argument("--fits", type=int, default=256, help="fits of the batched leg (0: skip)")

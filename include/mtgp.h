@@ -193,9 +193,9 @@ int mtgp_fwht(void* x, int64_t batch, int32_t log2n, int32_t dtype, void* stream
  * entries).  If bitrev_input is nonzero the input is first read in
  * bit-reversed order, i.e. the transform is the V^dagger of Theorem "Fast GP
  * computations" for lattices times sqrt(n).  dtype as for mtgp_fwht;
- * 0 <= log2n <= 21, batch <= 65535.  For log2n > 12 the two-pass transform
+ * 0 <= log2n <= 30, batch <= 65535.  For log2n > 12 the multi-pass transform
  * needs `scratch` with room for batch * n complex values of dtype (else it
- * may be NULL). */
+ * may be NULL); scratch and X must not overlap. */
 int mtgp_fft(const void* x, void* X, void* scratch, int64_t batch, int32_t log2n, int32_t dtype,
              int32_t bitrev_input, void* stream);
 

@@ -24,11 +24,11 @@ __device__ inline z2 zm(z2 a, z2 b) { return {a.x * b.x - a.y * b.y, a.x * b.y +
 __device__ inline z2 zmc(z2 a, z2 b) { return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }  // a conj(b)
 
 // position of frequency f in a spectrum of length 2^m (digital sequences:
-// natural order; lattices: the four-step layout p = f2 n1 + f1)
+// natural order; lattices: bit-reversed order, the output order of the
+// decimation-in-frequency transform)
 __device__ inline int64_t spec_pos(int family, int64_t f, int m) {
-  if (family == FAM_DSEQ) return f;
-  const int b1 = m < 12 ? m : 12, b2 = m - b1;
-  return ((f & ((1ll << b2) - 1)) << b1) | (f >> b2);
+  if (family == FAM_DSEQ || m == 0) return f;
+  return (int64_t)(__brevll((unsigned long long)f) >> (64 - m));
 }
 
 // lambda of column c (log2 length m) at frequency f, as a complex number

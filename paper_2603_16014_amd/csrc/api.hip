@@ -584,10 +584,6 @@ int mtgp_plan_create(const mtgp_design* des, int32_t precision, mtgp_plan** out)
   const int gl = des->family == MTGP_DSEQ ? 32 : 1;
   p->gen.assign(des->gen, des->gen + (size_t)gl * des->d);
   p->shift.assign(des->shift, des->shift + (size_t)des->T * des->d);
-  if (p->family == MTGP_LAT && p->m[0] > 21) {  // two DFT passes of <= 2^12 and <= 2^9
-    delete p;
-    return MTGP_ENOTSUP;
-  }
   const int T = p->T, d = p->d;
   if (!p->equal) {
     int64_t ms = 0;
@@ -844,28 +840,38 @@ int mtgp_fwht(void* x, int64_t batch, int32_t log2n, int32_t dtype, void* stream
 
 int mtgp_fft(const void* x, void* X, void* scratch, int64_t batch, int32_t log2n, int32_t dtype,
              int32_t bitrev_input, void* stream) {
-  if (!x || !X || batch < 0 || batch > 65535 || log2n < 0 || log2n > 21) return MTGP_EINVAL;
-  if (log2n > 12 && !scratch) return MTGP_EINVAL;
+  if (!x || !X || batch < 0 || batch > 65535 || log2n < 0 || log2n > 30) return MTGP_EINVAL;
+  const bool single = lat_single_pass(log2n);
+  if (!single && !scratch) return MTGP_EINVAL;
   if (dtype != MTGP_DTYPE_F64 && dtype != MTGP_DTYPE_F32) return MTGP_EINVAL;
   if (batch == 0) return MTGP_OK;
   hipStream_t st = (hipStream_t)stream;
   const int src = bitrev_input ? LAT_SRC_Y : LAT_SRC_X;
   const int64_t n = (int64_t)1 << log2n;
+  const int f32 = dtype == MTGP_DTYPE_F32;
+  if (single) {
+    // one LDS pass writes natural frequency order itself
+    if (f32)
+      LAUNCH_OK(launch_lat_single_natural<float>(src, x, 1, static_cast<cx<float>*>(X), (int)batch,
+                                                 log2n, st));
+    else
+      LAUNCH_OK(launch_lat_single_natural<double>(src, x, 0, static_cast<cx<double>*>(X),
+                                                  (int)batch, log2n, st));
+    return MTGP_OK;
+  }
+  // bit-reversed spectrum in scratch, then permuted into X
   KDesc kd{};
   kd.family = FAM_LAT;
   kd.order = 1;
-  const int f32 = dtype == MTGP_DTYPE_F32;
-  // single pass: natural order directly into X; two passes: layout in scratch, then X
-  void* spec = log2n > 12 ? scratch : X;
   if (f32)
-    LAUNCH_OK(launch_lat_forward<float, float>(src, static_cast<cx<float>*>(spec),
-                                               static_cast<cx<float>*>(spec), n, (int)batch, log2n,
-                                               x, 1, 1.0, nullptr, nullptr, nullptr, kd, st));
+    LAUNCH_OK(launch_lat_forward<float, float>(src, static_cast<cx<float>*>(scratch),
+                                               static_cast<cx<float>*>(scratch), n, (int)batch,
+                                               log2n, x, 1, 1.0, nullptr, nullptr, nullptr, kd, st));
   else
-    LAUNCH_OK(launch_lat_forward<double, double>(src, static_cast<cx<double>*>(spec),
-                                                 static_cast<cx<double>*>(spec), n, (int)batch,
+    LAUNCH_OK(launch_lat_forward<double, double>(src, static_cast<cx<double>*>(scratch),
+                                                 static_cast<cx<double>*>(scratch), n, (int)batch,
                                                  log2n, x, 0, 1.0, nullptr, nullptr, nullptr, kd, st));
-  if (log2n > 12) LAUNCH_OK(launch_lat_natural(scratch, f32, X, batch, log2n, st));
+  LAUNCH_OK(launch_lat_natural(scratch, f32, X, batch, log2n, st));
   return MTGP_OK;
 }
 

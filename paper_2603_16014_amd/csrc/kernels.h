@@ -149,6 +149,10 @@ struct alignas(2 * sizeof(R)) cx {
 enum { LAT_SRC_GEN = 0, LAT_SRC_Y = 1, LAT_SRC_X = 2 };  // columns, bit-reversed data, plain data
 int launch_lat_natural(const void* spec, int spec_f32, void* X, int64_t nvec, int m,
                        hipStream_t st);
+int lat_single_pass(int m);
+template <typename R>
+int launch_lat_single_natural(int src, const void* x, int x_f32, cx<R>* X, int nvec, int m,
+                              hipStream_t st);
 enum { LAT_SINK_Z = 0, LAT_SINK_REDUCE = 1, LAT_SINK_REAL = 2 };
 int lat_adj_blocks(int m, size_t cbytes);
 template <typename CR, typename SR>

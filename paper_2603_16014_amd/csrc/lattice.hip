@@ -4,19 +4,25 @@
 // j (point j g / n + shift) and transformed by the unnormalised DFT
 // F_fj = e^{-2 pi i f j / n}.
 //
-// Four-step split n = n1 n2, j = j1 + n1 j2, f = f2 + n2 f1 (n1 <= 2^12):
-//   pass 1 (strided, fused with column generation or the bit-reversed data
-//           load): for each j1, DFT over j2, twiddle e^{-2 pi i f2 j1 / n},
-//           store Y[f2][j1]  (tiles of KC consecutive j1: wide segments);
-//   pass 2 (contiguous): for each f2, DFT over j1, store X[f2][f1].
-// The spectrum therefore lives at position p = f2 n1 + f1 for frequency
-// f = f2 + n2 f1; the per-frequency algebra does not care about the order,
-// and the data transform uses the same layout.  Frequency 0 sits at p = 0.
-// The adjoint u(j) = Re sum_f omega(f) e^{-2 pi i f j / n} runs the mirror
-// image: pass A' (contiguous over f1, twiddle e^{-2 pi i j1 f2 / n}) and
-// pass B' (strided over f2) fused with the derivative reduction.
-// Each in-LDS DFT is radix-2 decimation in frequency (natural input,
-// bit-reversed output) with a per-block twiddle table.
+// Forward: radix-2 decimation in frequency over all m index bits, natural
+// input, bit-reversed output, so the spectrum holds frequency f at position
+// bitrev_m(f) (frequency 0 at position 0; the per-frequency algebra does not
+// care about the order, and the data transform uses the same layout).  The
+// stages of the high index bits run first, in register passes of 4 bits:
+// a thread owns the 2^hb values strided by 2^lo that share its low index, so
+// every load and store of a wave is 64 consecutive elements.  The twiddle of
+// the stage of bit k = lo + s on the pair of register slot r (r < 2^s) is
+//   e^{-i pi (low + r 2^lo) / 2^k} = e^{-i pi low / 2^k} e^{-i pi r / 2^s},
+// a per-thread base (one sincospi per pass, squared down the stages) times a
+// constant.  The first register pass generates the kernel column (or loads
+// the data) itself; the low L bits finish in LDS.
+// Adjoint: u(j) = Re sum_f omega(f) e^{-2 pi i f j / n} from omega stored at
+// bit-reversed positions is the transposed network, decimation in time: the
+// LDS pass over the low bits first, then the register passes upwards, the
+// last one fused with the derivative reduction of the regenerated column (or
+// with storing Re in natural order).
+#include <cmath>
+
 #include "colgen.h"
 
 namespace mtgp {
@@ -25,49 +31,100 @@ template <typename R>
 __device__ inline cx<R> cmul(cx<R> a, cx<R> b) {
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
+template <typename R>
+__device__ inline cx<R> cadd(cx<R> a, cx<R> b) {
+  return {a.x + b.x, a.y + b.y};
+}
+template <typename R>
+__device__ inline cx<R> csub(cx<R> a, cx<R> b) {
+  return {a.x - b.x, a.y - b.y};
+}
+template <typename R>
+__device__ inline cx<R> to_cx(cx<double> a) {
+  return {(R)a.x, (R)a.y};
+}
 
-// e^{-2 pi i k / 2^bits} for 0 <= k < 2^bits, FP64 (the angle is an exact dyadic)
-__device__ inline cx<double> twiddle64(int64_t k, int bits) {
+// e^{-i pi k / 2^e}, FP64 (the angle is an exact dyadic)
+__device__ inline cx<double> expmpi(int64_t k, int e) {
   double s, c;
-  sincospi(-ldexp((double)k, 1 - bits), &s, &c);
+  sincospi(-ldexp((double)k, -e), &s, &c);
   return {c, s};
 }
 
-// In-LDS radix-2 DIF DFT of nseq sequences of length 2^L; afterwards position
-// p holds frequency bitrev_L(p).  tw[k] = e^{-2 pi i k / 2^L}, k < 2^(L-1).
-template <typename R>
-__device__ inline void lds_fft(cx<R>* a, int nseq, int L, int stride, const cx<R>* tw) {
-  if (L == 0) {
-    __syncthreads();
-    return;
+__device__ inline int64_t bitrev64(int64_t p, int L) {
+  return L ? (int64_t)(__brevll((unsigned long long)p) >> (64 - L)) : 0;
+}
+
+// e^{-i pi t / 16}, t < 16: the constant factors of the register passes
+struct LatTab {
+  double c[16], s[16];
+};
+static LatTab lat_tab() {
+  constexpr double kPi = 3.14159265358979323846;
+  LatTab t;
+  for (int k = 0; k < 16; k++) {
+    t.c[k] = std::cos(kPi * k / 16.0);
+    t.s[k] = -std::sin(kPi * k / 16.0);
   }
-  const int hb = L - 1;
-  const int total = nseq << hb;
-  for (int s = L - 1; s >= 0; s--) {
+  t.c[0] = 1.0;
+  t.s[0] = 0.0;
+  t.c[8] = 0.0;
+  t.s[8] = -1.0;
+  return t;
+}
+
+// tw[k] = e^{-i pi k / 2^(L-1)}, k < 2^(L-1), from <= 32 fine and <= 64
+// coarse factors (tmp holds >= 96 entries); ends with a barrier.
+template <typename R>
+__device__ inline void fill_twiddles(cx<R>* tw, int L, cx<double>* tmp) {
+  if (L > 0) {
+    const int h = L - 1;
+    const int fb = h < 5 ? h : 5, nf = 1 << fb, nc = 1 << (h - fb);
+    for (int k = threadIdx.x; k < nf + nc; k += blockDim.x)
+      tmp[k] = k < nf ? expmpi(k, h) : expmpi((int64_t)(k - nf) << fb, h);
     __syncthreads();
-    const int half = 1 << s;
-    for (int g = threadIdx.x; g < total; g += blockDim.x) {
-      const int seq = g >> hb;
-      const int q = g & ((1 << hb) - 1);
-      const int k = q & (half - 1);
-      const int i = ((q >> s) << (s + 1)) | k;
-      cx<R>* pa = a + lds_at(seq, stride, i);
-      cx<R>* pb = a + lds_at(seq, stride, i + half);
-      const cx<R> A = *pa, B = *pb;
-      *pa = {A.x + B.x, A.y + B.y};
-      *pb = cmul<R>({A.x - B.x, A.y - B.y}, tw[k << (hb - s)]);
-    }
+    for (int k = threadIdx.x; k < (1 << h); k += blockDim.x)
+      tw[k] = to_cx<R>(cmul<double>(tmp[nf + (k >> fb)], tmp[k & (nf - 1)]));
   }
   __syncthreads();
 }
 
-__device__ inline int bitrev_bits(int p, int L) { return L ? (int)(__brev((uint32_t)p) >> (32 - L)) : 0; }
-
+// In-LDS radix-2 DIF over the L low bits of one contiguous block (natural in,
+// bit-reversed out; the twiddles of these stages depend on the low bits only).
 template <typename R>
-__device__ inline void fill_twiddles(cx<R>* tw, int L) {
-  for (int k = threadIdx.x; k < (L ? (1 << (L - 1)) : 0); k += blockDim.x) {
-    const cx<double> w = twiddle64(k, L);
-    tw[k] = {(R)w.x, (R)w.y};
+__device__ inline void lds_dif(cx<R>* a, int L, int stride, const cx<R>* tw) {
+  const int hb = L - 1;
+  for (int s = L - 1; s >= 0; s--) {
+    const int half = 1 << s;
+    for (int g = threadIdx.x; g < (1 << hb); g += blockDim.x) {
+      const int k = g & (half - 1);
+      const int i = ((g >> s) << (s + 1)) | k;
+      cx<R>* pa = a + lds_at(0, stride, i);
+      cx<R>* pb = a + lds_at(0, stride, i + half);
+      const cx<R> A = *pa, B = *pb;
+      *pa = cadd(A, B);
+      *pb = cmul<R>(csub(A, B), tw[k << (hb - s)]);
+    }
+    __syncthreads();
+  }
+}
+
+// In-LDS radix-2 DIT over the L low bits (bit-reversed in, natural out).
+template <typename R>
+__device__ inline void lds_dit(cx<R>* a, int L, int stride, const cx<R>* tw) {
+  const int hb = L - 1;
+  for (int s = 0; s < L; s++) {
+    const int half = 1 << s;
+    for (int g = threadIdx.x; g < (1 << hb); g += blockDim.x) {
+      const int k = g & (half - 1);
+      const int i = ((g >> s) << (s + 1)) | k;
+      cx<R>* pa = a + lds_at(0, stride, i);
+      cx<R>* pb = a + lds_at(0, stride, i + half);
+      const cx<R> A = *pa, B = cmul<R>(*pb, tw[k << (hb - s)]);
+      *pa = cadd(A, B);
+      *pb = csub(A, B);
+    }
+    __syncthreads();
   }
 }
 
@@ -81,392 +138,520 @@ __device__ inline R lat_col_value(const uint32_t* __restrict__ gen, const uint32
   return c;
 }
 
-enum { SRC_GEN = LAT_SRC_GEN, SRC_Y = LAT_SRC_Y, SRC_X = LAT_SRC_X };
+enum { SRC_GEN = LAT_SRC_GEN, SRC_Y = LAT_SRC_Y, SRC_X = LAT_SRC_X, SRC_WORK = 3 };
+enum { SINK_WORK = LAT_SINK_Z, SINK_REDUCE = LAT_SINK_REDUCE, SINK_REAL = LAT_SINK_REAL };
 
-// data value at natural index j of vector v: y[bitrev_m(j)] (SRC_Y) or y[j] (SRC_X)
-__device__ inline double load_data(const void* y, int y_f32, int src, int v, uint32_t j, int m) {
-  const size_t idx = (size_t)v * ((size_t)1 << m) + (src == SRC_Y ? (uint32_t)bitrev_bits((int)j, m) : j);
-  return y_f32 ? (double)static_cast<const float*>(y)[idx] : static_cast<const double*>(y)[idx];
-}
-
-// Pass 1: tile = KC consecutive j1 x n2 rows; grid (n1 / KC, nvec).
-// SRC_GEN: value = kernel column c(j); SRC_Y: value = y[bitrev_m(j)] of vector v.
+// real input of the forward transform at natural index j of vector v: the
+// kernel column (SRC_GEN), y[bitrev_m(j)] (SRC_Y) or y[j] (SRC_X)
 template <typename CR, int SRC, int KT>
-__global__ __launch_bounds__(256) void lat_pass1_kernel(cx<CR>* __restrict__ Y, int64_t vstride,
-                                                        const void* __restrict__ y, int y_f32, int m,
-                                                        int b1, int KC,
-                                                        const uint32_t* __restrict__ gen,
-                                                        const uint32_t* __restrict__ colshift,
-                                                        const Params* __restrict__ P, int d) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int b2 = m - b1, n1 = 1 << b1, n2 = 1 << b2;
-  const int stride = lds_stride(b2);
-  cx<CR>* a = reinterpret_cast<cx<CR>*>(smem);
-  cx<CR>* tw = a + (size_t)KC * stride;
-  const int v = blockIdx.y;
-  const int j1_0 = blockIdx.x * KC;
-  fill_twiddles<CR>(tw, b2);
-  const int kcb = __ffs(KC) - 1;
-  for (int q = threadIdx.x; q < (KC << b2); q += blockDim.x) {
-    const int kc = q & (KC - 1), j2 = q >> kcb;
-    const uint32_t j = (uint32_t)(j1_0 + kc) + ((uint32_t)j2 << b1);
-    CR val;
-    if (SRC == SRC_GEN)
-      val = lat_col_value<CR, KT>(gen, colshift + (size_t)v * d, d, j, m, P);
-    else
-      val = (CR)load_data(y, y_f32, SRC, v, j, m);
-    a[lds_at(kc, stride, j2)] = {val, (CR)0};
+__device__ inline CR src_value(const void* y, int y_f32, int v, uint32_t j, int m,
+                               const uint32_t* __restrict__ gen,
+                               const uint32_t* __restrict__ colshift,
+                               const Params* __restrict__ P, int d) {
+  if constexpr (SRC == SRC_GEN) {
+    return lat_col_value<CR, KT>(gen, colshift + (size_t)v * d, d, j, m, P);
+  } else {
+    const size_t idx = (size_t)v * ((size_t)1 << m) +
+                       (SRC == SRC_Y ? (size_t)bitrev64((int64_t)j, m) : (size_t)j);
+    return y_f32 ? (CR) static_cast<const float*>(y)[idx] : (CR) static_cast<const double*>(y)[idx];
   }
-  lds_fft<CR>(a, KC, b2, stride, tw);
-  cx<CR>* out = Y + (size_t)v * vstride;
-  for (int q = threadIdx.x; q < (KC << b2); q += blockDim.x) {
-    const int kc = q & (KC - 1), f2 = q >> kcb;
-    const int j1 = j1_0 + kc;
-    const cx<CR> val = a[lds_at(kc, stride, bitrev_bits(f2, b2))];
-    const cx<double> w = twiddle64((int64_t)f2 * j1, m);
-    out[(size_t)f2 * n1 + j1] = cmul<CR>(val, {(CR)w.x, (CR)w.y});
-  }
-  (void)n2;
 }
 
-// Pass 2: one block per row f2 (grid (n2, nvec)); DFT over j1.  With b1 == m
-// (single pass) the row is produced by SRC (generation / data load) instead.
-template <typename CR, typename TOut, int SRC, int KT>
-__global__ __launch_bounds__(256) void lat_pass2_kernel(const cx<CR>* __restrict__ Y,
-                                                        cx<TOut>* __restrict__ X, int64_t vstride,
-                                                        const void* __restrict__ y, int y_f32,
-                                                        int m, int b1, double scale,
-                                                        const uint32_t* __restrict__ gen,
-                                                        const uint32_t* __restrict__ colshift,
-                                                        const Params* __restrict__ P, int d) {
+// Derivative sums of the adjoint values u(j) of one column against the
+// regenerated column c(j) = gamma prod_q (1 + eta_q K_q(j)):
+// acc[q] = sum_j u(j) eta_q dc(j)/d eta_q (product rule over the dimension
+// factors), acc[D] = sum_j u(j) c(j).  Padding dimensions carry eta = 0, so
+// their factor is exactly 1.
+template <typename CR, int KT, int D>
+struct LatReduce {
+  CR acc[D + 1];
+  CR eta[D];
+  CR gam;
+  uint32_t g[D], sh[D];
+  __device__ inline void init(const uint32_t* __restrict__ gen, const uint32_t* __restrict__ s,
+                              int d, const Params* __restrict__ P) {
+#pragma unroll
+    for (int q = 0; q < D; q++) {
+      acc[q] = 0;
+      eta[q] = q < d ? RT<CR>::eta(P, q) : (CR)0;
+      g[q] = gen[q < d ? q : 0];
+      sh[q] = s[q < d ? q : 0];
+    }
+    acc[D] = 0;
+    gam = RT<CR>::gamma(P);
+  }
+  __device__ inline void add(CR wv, uint32_t j, int m, const Params* __restrict__ P) {
+    CR K[D], f[D], pre[D];
+#pragma unroll
+    for (int q = 0; q < D; q++) {
+      K[q] = kval<CR, KT>(lat_z(g[q], j, m) + sh[q], P);
+      f[q] = fma(eta[q], K[q], (CR)1);
+    }
+    CR run = gam * wv;
+#pragma unroll
+    for (int q = 0; q < D; q++) {
+      pre[q] = run;
+      run *= f[q];
+    }
+    acc[D] += run;
+    CR suf = 1;
+#pragma unroll
+    for (int q = D - 1; q >= 0; q--) {
+      acc[q] = fma(pre[q] * suf * eta[q], K[q], acc[q]);
+      suf *= f[q];
+    }
+  }
+  // block sums with one barrier (red: 4 (D + 1) doubles): out[0] = the
+  // column sum, out[1 + q] = eta_q sums (q < d), out[1 + d ..] = 0
+  __device__ inline void store(int d, double* red, double* out) {
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int q = 0; q <= D; q++) {
+      if (q < d || q == D) {
+        const double v = wave_sum((double)acc[q]);
+        if ((threadIdx.x & 63) == 0) red[w * (D + 1) + q] = v;
+      }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < adj_nq(d); q += blockDim.x) {
+      double s = 0.0;
+      if (q <= d) {
+        const int src = q == 0 ? D : q - 1;
+        for (int i = 0; i < nw; i++) s += red[i * (D + 1) + src];
+      }
+      out[q] = s;
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// register passes over the bits [lo, lo + HB): grid (2^(m - HB - 8), nvec),
+// 256 threads; block x covers 256 consecutive low indices of one high index
+// ---------------------------------------------------------------------------
+// (ublk: the block-uniform part of the index, low: the thread's low index;
+// element r of the thread sits at ublk + (r << lo) + threadIdx.x)
+struct RegIdx {
+  int64_t low, ublk;
+  __device__ inline RegIdx(int lo, int HB) {
+    const int gb = lo - 8;
+    const int64_t grp = blockIdx.x & (((int64_t)1 << gb) - 1);
+    const int64_t hi = (int64_t)blockIdx.x >> gb;
+    low = (grp << 8) + threadIdx.x;
+    ublk = (hi << (lo + HB)) + (grp << 8);
+  }
+  __device__ inline int64_t at(int r, int lo) const { return ublk + ((int64_t)r << lo) + threadIdx.x; }
+};
+
+template <typename CR, typename TOut, int HB, int SRC, int KT>
+__global__ __launch_bounds__(256) void lat_dif_reg_kernel(
+    const LatTab tab, cx<CR>* __restrict__ work, cx<TOut>* __restrict__ out, int64_t vstride,
+    int m, int lo, const void* __restrict__ y, int y_f32, const uint32_t* __restrict__ gen,
+    const uint32_t* __restrict__ colshift, const Params* __restrict__ P, int d) {
+  constexpr int R = 1 << HB;
+  static_assert(HB >= 1 && HB <= 5, "constant twiddles cover 5 bits");
+  const int v = blockIdx.y;
+  const RegIdx ix(lo, HB);
+  cx<CR> a[R];
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int64_t i = ix.at(r, lo);
+    if constexpr (SRC == SRC_WORK)
+      a[r] = (work + (size_t)v * vstride + ix.ublk + ((int64_t)r << lo))[threadIdx.x];
+    else
+      a[r] = {src_value<CR, SRC, KT>(y, y_f32, v, (uint32_t)i, m, gen, colshift, P, d), (CR)0};
+  }
+  cx<double> B = expmpi(ix.low, lo + HB - 1);
+#pragma unroll
+  for (int s = HB - 1; s >= 0; s--) {
+    const cx<CR> b = to_cx<CR>(B);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      if (!(r & (1 << s))) {
+        const int t = (r & ((1 << s) - 1)) << (4 - s);
+        const cx<CR> w = t == 0 ? b : cmul<CR>(b, {(CR)tab.c[t], (CR)tab.s[t]});
+        const cx<CR> A = a[r], C = a[r + (1 << s)];
+        a[r] = cadd(A, C);
+        a[r + (1 << s)] = cmul<CR>(csub(A, C), w);
+      }
+    }
+    B = cmul<double>(B, B);
+  }
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    (out + (size_t)v * vstride + ix.ublk + ((int64_t)r << lo))[threadIdx.x] = {(TOut)a[r].x,
+                                                                               (TOut)a[r].y};
+  }
+}
+
+// SINK_WORK: store back to work; SINK_REAL: real_out[v][j] = Re * scale;
+// SINK_REDUCE: derivative sums (Re values staged in dynamic LDS, R x 256 CR).
+template <typename CR, int HB, int SINK, int KT, int D>
+__global__ __launch_bounds__(256) void lat_dit_reg_kernel(
+    const LatTab tab, cx<CR>* __restrict__ work, double* __restrict__ real_out, int64_t vstride,
+    int m, int lo, double scale, const uint32_t* __restrict__ gen,
+    const uint32_t* __restrict__ colshift, const Params* __restrict__ P, int d,
+    double* __restrict__ partials) {
+  constexpr int R = 1 << HB;
+  static_assert(HB >= 1 && HB <= 5, "constant twiddles cover 5 bits");
   extern __shared__ __align__(16) unsigned char smem[];
-  const int n1 = 1 << b1;
-  const int stride = lds_stride(b1);
+  __shared__ double red[4 * (D + 1)];
+  const int v = blockIdx.y;
+  const RegIdx ix(lo, HB);
+  cx<CR> a[R];
+#pragma unroll
+  for (int r = 0; r < R; r++)
+    a[r] = (work + (size_t)v * vstride + ix.ublk + ((int64_t)r << lo))[threadIdx.x];
+  cx<double> Bs[HB];
+  Bs[HB - 1] = expmpi(ix.low, lo + HB - 1);
+#pragma unroll
+  for (int s = HB - 2; s >= 0; s--) Bs[s] = cmul<double>(Bs[s + 1], Bs[s + 1]);
+#pragma unroll
+  for (int s = 0; s < HB; s++) {
+    const cx<CR> b = to_cx<CR>(Bs[s]);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      if (!(r & (1 << s))) {
+        const int t = (r & ((1 << s) - 1)) << (4 - s);
+        const cx<CR> w = t == 0 ? b : cmul<CR>(b, {(CR)tab.c[t], (CR)tab.s[t]});
+        const cx<CR> A = a[r], C = cmul<CR>(a[r + (1 << s)], w);
+        a[r] = cadd(A, C);
+        a[r + (1 << s)] = csub(A, C);
+      }
+    }
+  }
+  if constexpr (SINK == SINK_WORK) {
+#pragma unroll
+    for (int r = 0; r < R; r++)
+      (work + (size_t)v * vstride + ix.ublk + ((int64_t)r << lo))[threadIdx.x] = a[r];
+  } else if constexpr (SINK == SINK_REAL) {
+#pragma unroll
+    for (int r = 0; r < R; r++)
+      (real_out + ((size_t)v << m) + ix.ublk + ((int64_t)r << lo))[threadIdx.x] =
+          (double)a[r].x * scale;
+  } else {
+    CR* stage = reinterpret_cast<CR*>(smem);
+#pragma unroll
+    for (int r = 0; r < R; r++) stage[r * 256 + threadIdx.x] = a[r].x;
+    // each thread reads back only its own slots: no barrier needed
+    LatReduce<CR, KT, D> lr;
+    lr.init(gen, colshift + (size_t)v * d, d, P);
+#pragma unroll 1
+    for (int r = 0; r < R; r++)
+      lr.add(stage[r * 256 + threadIdx.x], (uint32_t)ix.at(r, lo), m, P);
+    lr.store(d, red, partials + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * adj_nq(d));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LDS passes over the low L bits: grid (2^(m - L), nvec), one contiguous
+// block of 2^L each; dynamic LDS = lat_lds_bytes(L)
+// ---------------------------------------------------------------------------
+// Forward: input from work (SRC_WORK) or generated / loaded (only pass),
+// output at the same positions into out, times scale; natural != 0 (only
+// pass of the standalone transform) writes position p to bitrev_L(p).
+template <typename CR, typename TOut, int SRC, int KT>
+__global__ __launch_bounds__(256) void lat_dif_lds_kernel(
+    const cx<CR>* __restrict__ work, cx<TOut>* __restrict__ out, int64_t vstride, int m, int L,
+    double scale, int natural, const void* __restrict__ y, int y_f32,
+    const uint32_t* __restrict__ gen, const uint32_t* __restrict__ colshift,
+    const Params* __restrict__ P, int d) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ cx<double> tmp[96];
+  const int nb = 1 << L;
+  const int stride = lds_stride(L);
   cx<CR>* a = reinterpret_cast<cx<CR>*>(smem);
   cx<CR>* tw = a + stride;
-  const int v = blockIdx.y, f2 = blockIdx.x;
-  fill_twiddles<CR>(tw, b1);
-  const size_t row = (size_t)v * vstride + (size_t)f2 * n1;
-  for (int j1 = threadIdx.x; j1 < n1; j1 += blockDim.x) {
+  const int v = blockIdx.y;
+  const int64_t b0 = (int64_t)blockIdx.x << L;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
     cx<CR> val;
-    if (b1 < m) {
-      val = Y[row + j1];
-    } else if (SRC == SRC_GEN) {
-      val = {lat_col_value<CR, KT>(gen, colshift + (size_t)v * d, d, (uint32_t)j1, m, P), (CR)0};
-    } else {
-      val = {(CR)load_data(y, y_f32, SRC, v, (uint32_t)j1, m), (CR)0};
-    }
-    a[lds_at(0, stride, j1)] = val;
+    if constexpr (SRC == SRC_WORK)
+      val = work[(size_t)v * vstride + b0 + i];
+    else
+      val = {src_value<CR, SRC, KT>(y, y_f32, v, (uint32_t)(b0 + i), m, gen, colshift, P, d),
+             (CR)0};
+    a[lds_at(0, stride, i)] = val;
   }
-  lds_fft<CR>(a, 1, b1, stride, tw);
-  for (int f1 = threadIdx.x; f1 < n1; f1 += blockDim.x) {
-    const cx<CR> val = a[lds_at(0, stride, bitrev_bits(f1, b1))];
-    X[row + f1] = {(TOut)(val.x * (CR)scale), (TOut)(val.y * (CR)scale)};
-  }
-}
-
-// ---------------------------------------------------------------------------
-// adjoint
-// ---------------------------------------------------------------------------
-enum { SINK_Z = LAT_SINK_Z, SINK_REDUCE = LAT_SINK_REDUCE, SINK_REAL = LAT_SINK_REAL };
-
-// derivative accumulation for one element: wv = adjoint value, u[q] digits
-template <typename R, int KT, int D>
-__device__ inline void accum_derivs(R wv, const uint32_t* u, const R* eta, R gam, int d,
-                                    const Params* __restrict__ P, R* acc_eta, R* acc_b, R& acc_c) {
-  constexpr bool ADAPT = KT == KT_DSIA;
-  R K[D], f[D];
-  R Ka[ADAPT ? D : 1][4];
-#pragma unroll
-  for (int j = 0; j < D; j++) {
-    if (j < d) {
-      if constexpr (ADAPT) {
-        dsi_khat_all<R>(u[j], Ka[j]);
-        K[j] = RT<R>::bw(P, 0) * Ka[j][0] + RT<R>::bw(P, 1) * Ka[j][1] + RT<R>::bw(P, 2) * Ka[j][2] +
-               RT<R>::bw(P, 3) * Ka[j][3];
-      } else {
-        K[j] = kval<R, KT>(u[j], P);
-      }
-      f[j] = fma(eta[j], K[j], (R)1);
-    } else {
-      K[j] = 0;
-      f[j] = 1;
-    }
-  }
-  R pre[D];
-  R run = gam * wv;
-#pragma unroll
-  for (int j = 0; j < D; j++) {
-    pre[j] = run;
-    if (j < d) run *= f[j];
-  }
-  acc_c += run;
-  R suf = 1;
-#pragma unroll
-  for (int j = D - 1; j >= 0; j--) {
-    if (j < d) {
-      const R ps = pre[j] * suf * eta[j];
-      acc_eta[j] = fma(ps, K[j], acc_eta[j]);
-      if constexpr (ADAPT) {
-#pragma unroll
-        for (int q = 0; q < 4; q++) acc_b[q] = fma(ps, Ka[j][q], acc_b[q]);
-      }
-      suf *= f[j];
-    }
+  fill_twiddles<CR>(tw, L, tmp);
+  lds_dif<CR>(a, L, stride, tw);
+  for (int p = threadIdx.x; p < nb; p += blockDim.x) {
+    const cx<CR> val = a[lds_at(0, stride, p)];
+    const int64_t q = natural ? bitrev64(p, L) : p;
+    out[(size_t)v * vstride + b0 + q] = {(TOut)(val.x * (CR)scale), (TOut)(val.y * (CR)scale)};
   }
 }
 
-template <typename R, int KT, int D>
-__device__ inline void reduce_store(const R* acc_eta, const R* acc_b, R acc_c, int d, double* red,
-                                    double* out) {
-  double v = block_sum((double)acc_c, red);
-  if (threadIdx.x == 0) out[0] = v;
-#pragma unroll
-  for (int j = 0; j < D; j++) {
-    if (j < d) {
-      v = block_sum((double)acc_eta[j], red);
-      if (threadIdx.x == 0) out[1 + j] = v;
-    }
-  }
-  for (int q = 0; q < 4; q++) {
-    v = (KT == KT_DSIA) ? block_sum((double)acc_b[q], red) : 0.0;
-    if (threadIdx.x == 0) out[1 + d + q] = v;
-  }
-}
-
-// Pass A' (one block per row f2): DFT over f1 of omega (or its conjugate),
-// then SINK_Z: twiddle e^{-2 pi i j1 f2 / n}, store Z[f2][j1];
-// single pass (b1 == m): SINK_REDUCE (derivative reduction of Re) or
-// SINK_REAL (store Re * scale in natural order).
+// Adjoint: omega (conjugated if conj_in) at its positions, DIT, then
+// SINK_WORK (register passes follow), SINK_REAL or SINK_REDUCE (only pass).
 template <typename CR, typename TIn, int SINK, int KT, int D>
-__global__ __launch_bounds__(256) void lat_adjA_kernel(
-    const cx<TIn>* __restrict__ W, cx<CR>* __restrict__ Z, double* __restrict__ real_out,
-    int64_t vstride, int m, int b1, int conj_in, double scale, const uint32_t* __restrict__ gen,
+__global__ __launch_bounds__(256) void lat_dit_lds_kernel(
+    const cx<TIn>* __restrict__ spec, cx<CR>* __restrict__ work, double* __restrict__ real_out,
+    int64_t vstride, int m, int L, int conj_in, double scale, const uint32_t* __restrict__ gen,
     const uint32_t* __restrict__ colshift, const Params* __restrict__ P, int d,
     double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double red[16];
-  const int n1 = 1 << b1;
-  const int stride = lds_stride(b1);
+  __shared__ cx<double> tmp[96];
+  __shared__ double red[4 * (D + 1)];
+  const int nb = 1 << L;
+  const int stride = lds_stride(L);
   cx<CR>* a = reinterpret_cast<cx<CR>*>(smem);
   cx<CR>* tw = a + stride;
-  const int v = blockIdx.y, f2 = blockIdx.x;
-  fill_twiddles<CR>(tw, b1);
-  const size_t row = (size_t)v * vstride + (size_t)f2 * n1;
-  for (int f1 = threadIdx.x; f1 < n1; f1 += blockDim.x) {
-    const cx<TIn> w = W[row + f1];
-    a[lds_at(0, stride, f1)] = {(CR)w.x, conj_in ? -(CR)w.y : (CR)w.y};
-  }
-  lds_fft<CR>(a, 1, b1, stride, tw);
-  if (SINK == SINK_Z) {
-    for (int j1 = threadIdx.x; j1 < n1; j1 += blockDim.x) {
-      const cx<CR> val = a[lds_at(0, stride, bitrev_bits(j1, b1))];
-      const cx<double> t = twiddle64((int64_t)j1 * f2, m);
-      Z[row + j1] = cmul<CR>(val, {(CR)t.x, (CR)t.y});
-    }
-  } else if (SINK == SINK_REAL) {
-    for (int j1 = threadIdx.x; j1 < n1; j1 += blockDim.x)
-      real_out[(size_t)v * ((size_t)1 << m) + j1] =
-          (double)a[lds_at(0, stride, bitrev_bits(j1, b1))].x * scale;
-  } else {
-    CR acc_eta[D], acc_b[4] = {0, 0, 0, 0}, acc_c = 0, eta[D];
-#pragma unroll
-    for (int j = 0; j < D; j++) {
-      acc_eta[j] = 0;
-      eta[j] = j < d ? RT<CR>::eta(P, j) : (CR)0;
-    }
-    const CR gam = RT<CR>::gamma(P);
-    const uint32_t* sh = colshift + (size_t)v * d;
-    for (int j1 = threadIdx.x; j1 < n1; j1 += blockDim.x) {
-      uint32_t u[D];
-#pragma unroll
-      for (int q = 0; q < D; q++) u[q] = q < d ? lat_z(gen[q], (uint32_t)j1, m) + sh[q] : 0u;
-      accum_derivs<CR, KT, D>(a[lds_at(0, stride, bitrev_bits(j1, b1))].x, u, eta, gam, d, P, acc_eta,
-                              acc_b, acc_c);
-    }
-    reduce_store<CR, KT, D>(acc_eta, acc_b, acc_c, d, red,
-                            partials + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * adj_nq(d));
-  }
-}
-
-// Pass B' (tile = KC consecutive j1 x n2 rows f2; grid (n1 / KC, nvec)): DFT
-// over f2 -> j2, then SINK_REDUCE or SINK_REAL on u(j1 + n1 j2) = Re.
-template <typename CR, int SINK, int KT, int D>
-__global__ __launch_bounds__(256) void lat_adjB_kernel(
-    const cx<CR>* __restrict__ Z, double* __restrict__ real_out, int64_t vstride, int m, int b1,
-    int KC, double scale, const uint32_t* __restrict__ gen, const uint32_t* __restrict__ colshift,
-    const Params* __restrict__ P, int d, double* __restrict__ partials) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double red[16];
-  const int b2 = m - b1, n1 = 1 << b1;
-  const int stride = lds_stride(b2);
-  cx<CR>* a = reinterpret_cast<cx<CR>*>(smem);
-  cx<CR>* tw = a + (size_t)KC * stride;
   const int v = blockIdx.y;
-  const int j1_0 = blockIdx.x * KC;
-  fill_twiddles<CR>(tw, b2);
-  const int kcb = __ffs(KC) - 1;
-  const cx<CR>* zin = Z + (size_t)v * vstride;
-  for (int q = threadIdx.x; q < (KC << b2); q += blockDim.x) {
-    const int kc = q & (KC - 1), f2 = q >> kcb;
-    a[lds_at(kc, stride, f2)] = zin[(size_t)f2 * n1 + j1_0 + kc];
+  const int64_t b0 = (int64_t)blockIdx.x << L;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    const cx<TIn> w = spec[(size_t)v * vstride + b0 + i];
+    a[lds_at(0, stride, i)] = {(CR)w.x, conj_in ? -(CR)w.y : (CR)w.y};
   }
-  lds_fft<CR>(a, KC, b2, stride, tw);
-  if (SINK == SINK_REAL) {
-    for (int q = threadIdx.x; q < (KC << b2); q += blockDim.x) {
-      const int kc = q & (KC - 1), j2 = q >> kcb;
-      const size_t j = (size_t)(j1_0 + kc) + ((size_t)j2 << b1);
-      real_out[(size_t)v * ((size_t)1 << m) + j] =
-          (double)a[lds_at(kc, stride, bitrev_bits(j2, b2))].x * scale;
-    }
-    return;
+  fill_twiddles<CR>(tw, L, tmp);
+  lds_dit<CR>(a, L, stride, tw);
+  if constexpr (SINK == SINK_WORK) {
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+      work[(size_t)v * vstride + b0 + i] = a[lds_at(0, stride, i)];
+  } else if constexpr (SINK == SINK_REAL) {
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+      real_out[(size_t)v * ((size_t)1 << m) + b0 + i] = (double)a[lds_at(0, stride, i)].x * scale;
+  } else {
+    LatReduce<CR, KT, D> lr;
+    lr.init(gen, colshift + (size_t)v * d, d, P);
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+      lr.add(a[lds_at(0, stride, i)].x, (uint32_t)(b0 + i), m, P);
+    lr.store(d, red, partials + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * adj_nq(d));
   }
-  CR acc_eta[D], acc_b[4] = {0, 0, 0, 0}, acc_c = 0, eta[D];
-#pragma unroll
-  for (int j = 0; j < D; j++) {
-    acc_eta[j] = 0;
-    eta[j] = j < d ? RT<CR>::eta(P, j) : (CR)0;
-  }
-  const CR gam = RT<CR>::gamma(P);
-  const uint32_t* sh = colshift + (size_t)v * d;
-  for (int q = threadIdx.x; q < (KC << b2); q += blockDim.x) {
-    const int kc = q & (KC - 1), j2 = q >> kcb;
-    const uint32_t j = (uint32_t)(j1_0 + kc) + ((uint32_t)j2 << b1);
-    uint32_t u[D];
-#pragma unroll
-    for (int qq = 0; qq < D; qq++) u[qq] = qq < d ? lat_z(gen[qq], j, m) + sh[qq] : 0u;
-    accum_derivs<CR, KT, D>(a[lds_at(kc, stride, bitrev_bits(j2, b2))].x, u, eta, gam, d, P,
-                            acc_eta, acc_b, acc_c);
-  }
-  reduce_store<CR, KT, D>(acc_eta, acc_b, acc_c, d, red,
-                          partials + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * adj_nq(d));
 }
 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-static int lat_b1(int m) { return m < 12 ? m : 12; }
-static int lat_kc(int m, int b1, size_t cbytes) {
-  const int b2 = m - b1;
-  int KC = 1;
-  while (2 * KC <= (1 << b1) && (size_t)(2 * KC) * lds_stride(b2) * cbytes <= 32768) KC *= 2;
-  return KC;
+// Schedule: m <= 12 is one LDS pass; otherwise the low L bits in LDS, L in
+// [8, 11] with m - L a multiple of 4, and the other bits in 4-bit register
+// passes (5-bit passes need more than 168 VGPRs in FP64 and lose occupancy).
+constexpr int kLatHB = 4;
+struct LatSched {
+  int L;   // LDS bits
+  int np;  // register passes; pass q covers the bits [L + 4 q, L + 4 q + 4)
+};
+static LatSched lat_sched(int m) {
+  LatSched s{};
+  if (m <= 12) {
+    s.L = m;
+    return s;
+  }
+  s.L = 8 + (m - 8) % 4;
+  s.np = (m - s.L) / 4;
+  return s;
 }
-static size_t lds_pass1(int m, int b1, int KC, size_t cbytes) {
-  const int b2 = m - b1;
-  return ((size_t)KC * lds_stride(b2) + (b2 ? (1u << (b2 - 1)) : 0)) * cbytes;
-}
-static size_t lds_pass2(int b1, size_t cbytes) {
-  return ((size_t)lds_stride(b1) + (b1 ? (1u << (b1 - 1)) : 0)) * cbytes;
+static size_t lat_lds_bytes(int L, size_t cbytes) {
+  return ((size_t)lds_stride(L) + (L ? (1u << (L - 1)) : 0)) * cbytes;
 }
 
-int lat_adj_blocks(int m, size_t cbytes) {
-  const int b1 = lat_b1(m);
-  if (b1 == m) return 1;
-  return (1 << b1) / lat_kc(m, b1, cbytes);
+int lat_adj_blocks(int m, size_t /*cbytes*/) {
+  const LatSched s = lat_sched(m);
+  if (s.np == 0) return 1;
+  return 1 << (m - kLatHB - 8);
 }
 
-#define MTGP_LAT_KT(kt, MACRO, ...)                     \
-  do {                                                  \
-    switch (kt) {                                       \
-      case KT_SI1: MACRO(KT_SI1, __VA_ARGS__); break;   \
-      case KT_SI2: MACRO(KT_SI2, __VA_ARGS__); break;   \
-      default: MACRO(KT_SI3, __VA_ARGS__); break;       \
-    }                                                   \
+#define MTGP_LAT_KT(kt, MACRO, ...)                   \
+  do {                                                \
+    switch (kt) {                                     \
+      case KT_SI1: MACRO(KT_SI1, __VA_ARGS__); break; \
+      case KT_SI2: MACRO(KT_SI2, __VA_ARGS__); break; \
+      default: MACRO(KT_SI3, __VA_ARGS__); break;     \
+    }                                                 \
   } while (0)
 
+template <typename CR, int SRC, int KT>
+static void dif_reg(const LatTab& tab, dim3 grid, hipStream_t st, cx<CR>* work, int64_t vstride,
+                    int m, int lo, const void* y, int y_f32, const uint32_t* gen,
+                    const uint32_t* colshift, const Params* P, int d) {
+  hipLaunchKernelGGL((lat_dif_reg_kernel<CR, CR, kLatHB, SRC, KT>), grid, dim3(256), 0, st, tab,
+                     work, work, vstride, m, lo, y, y_f32, gen, colshift, P, d);
+}
+
 // Forward transform of nvec vectors (columns when src == SRC_GEN, data when
-// SRC_Y) of length 2^m into the spectrum layout; `work` holds pass-1 output.
+// SRC_Y / SRC_X) of length 2^m into the bit-reversed spectrum, times scale;
+// `work` holds the register passes (may alias spec when the types agree).
 template <typename CR, typename SR>
 int launch_lat_forward(int src, cx<CR>* work, cx<SR>* spec, int64_t vstride, int nvec, int m,
                        const void* y, int y_f32, double scale, const uint32_t* gen,
                        const uint32_t* colshift, const Params* P, const KDesc& kd,
                        hipStream_t st) {
   if (nvec <= 0) return 0;
-  const int b1 = lat_b1(m);
   const int kt = kt_of(kd.family, kd.order, kd.adaptive);
-  const size_t cb = sizeof(cx<CR>);
-  if (b1 < m) {
-    const int KC = lat_kc(m, b1, cb);
-    const dim3 grid((1u << b1) / KC, nvec);
-    const size_t lds = lds_pass1(m, b1, KC, cb);
-#define P1(KTV, SRCV)                                                                              \
-  hipLaunchKernelGGL((lat_pass1_kernel<CR, SRCV, KTV>), grid, dim3(256), lds, st, work, vstride, y, \
-                     y_f32, m, b1, KC, gen, colshift, P, kd.d)
-    if (src == SRC_GEN) MTGP_LAT_KT(kt, P1, SRC_GEN);
-    else if (src == SRC_Y) P1(KT_SI1, SRC_Y);
-    else P1(KT_SI1, SRC_X);
-#undef P1
+  const LatSched s = lat_sched(m);
+  const LatTab tab = lat_tab();
+  const dim3 grid(1u << (m - kLatHB - 8), nvec);
+  for (int q = s.np - 1; q >= 0; q--) {  // top pass first
+    const int lo = s.L + kLatHB * q;
+    if (q == s.np - 1) {
+#define FR(KTV, SRCV) \
+  dif_reg<CR, SRCV, KTV>(tab, grid, st, work, vstride, m, lo, y, y_f32, gen, colshift, P, kd.d)
+      if (src == SRC_GEN) MTGP_LAT_KT(kt, FR, SRC_GEN);
+      else if (src == SRC_Y) FR(KT_SI1, SRC_Y);
+      else FR(KT_SI1, SRC_X);
+#undef FR
+    } else {
+      dif_reg<CR, SRC_WORK, KT_SI1>(tab, grid, st, work, vstride, m, lo, y, y_f32, gen, colshift,
+                                    P, kd.d);
+    }
   }
-  const dim3 grid2(1u << (m - b1), nvec);
-  const size_t lds2 = lds_pass2(b1, cb);
-#define P2(KTV, SRCV)                                                                           \
-  hipLaunchKernelGGL((lat_pass2_kernel<CR, SR, SRCV, KTV>), grid2, dim3(256), lds2, st, work,   \
-                     spec, vstride, y, y_f32, m, b1, scale, gen, colshift, P, kd.d)
-  if (src == SRC_GEN) MTGP_LAT_KT(kt, P2, SRC_GEN);
-  else if (src == SRC_Y) P2(KT_SI1, SRC_Y);
-  else P2(KT_SI1, SRC_X);
-#undef P2
+  const dim3 grid2(1u << (m - s.L), nvec);
+  const size_t lds = lat_lds_bytes(s.L, sizeof(cx<CR>));
+#define FL(KTV, SRCV)                                                                          \
+  hipLaunchKernelGGL((lat_dif_lds_kernel<CR, SR, SRCV, KTV>), grid2, dim3(256), lds, st, work, \
+                     spec, vstride, m, s.L, scale, 0, y, y_f32, gen, colshift, P, kd.d)
+  if (s.np > 0) FL(KT_SI1, SRC_WORK);
+  else if (src == SRC_GEN) MTGP_LAT_KT(kt, FL, SRC_GEN);
+  else if (src == SRC_Y) FL(KT_SI1, SRC_Y);
+  else FL(KT_SI1, SRC_X);
+#undef FL
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // Adjoint: u = Re F omega, reduced against the regenerated column derivatives
-// (partials: lat_adj_blocks(m) * nvec rows), or written (SINK_REAL, scaled) to
-// real_out in natural order.
+// (partials: lat_adj_blocks(m) rows per vector, vector-major), or written
+// (SINK_REAL, times scale) to real_out in natural order.  Overwrites work.
 template <typename CR, typename SR>
 int launch_lat_adjoint(int sink, const cx<SR>* spec, cx<CR>* work, double* real_out,
                        int64_t vstride, int nvec, int m, int conj_in, double scale,
                        const uint32_t* gen, const uint32_t* colshift, const Params* P,
                        const KDesc& kd, double* partials, hipStream_t st) {
   if (nvec <= 0) return 0;
-  const int b1 = lat_b1(m);
   const int kt = kt_of(kd.family, kd.order, kd.adaptive);
-  const size_t cb = sizeof(cx<CR>);
-  const size_t ldsA = lds_pass2(b1, cb);
-  const dim3 gridA(1u << (m - b1), nvec);
-#define PA(DD, KTV, SINKV)                                                                        \
-  hipLaunchKernelGGL((lat_adjA_kernel<CR, SR, SINKV, KTV, DD>), gridA, dim3(256), ldsA, st, spec,  \
-                     work, real_out, vstride, m, b1, conj_in, scale, gen, colshift, P, kd.d,     \
-                     partials)
-  if (b1 < m) {
-    PA(4, KT_SI1, SINK_Z);
-    const int KC = lat_kc(m, b1, cb);
-    const dim3 gridB((1u << b1) / KC, nvec);
-    const size_t ldsB = lds_pass1(m, b1, KC, cb);
-#define PB(DD, KTV, SINKV)                                                                        \
-  hipLaunchKernelGGL((lat_adjB_kernel<CR, SINKV, KTV, DD>), gridB, dim3(256), ldsB, st, work,     \
-                     real_out, vstride, m, b1, KC, scale, gen, colshift, P, kd.d, partials)
-#define PB_KT(KTV, DD) PB(DD, KTV, SINK_REDUCE)
-#define PB_D(DD, KTV) PB_KT(KTV, DD)
-    if (sink == SINK_REAL) {
-      PB(4, KT_SI1, SINK_REAL);
-    } else {
-      switch (kt) {
-        case KT_SI1: MTGP_DISPATCH_D(kd.d, PB_D, KT_SI1); break;
-        case KT_SI2: MTGP_DISPATCH_D(kd.d, PB_D, KT_SI2); break;
-        default: MTGP_DISPATCH_D(kd.d, PB_D, KT_SI3); break;
-      }
-    }
-#undef PB_D
-#undef PB_KT
-#undef PB
+  const LatSched s = lat_sched(m);
+  const LatTab tab = lat_tab();
+  const dim3 gridL(1u << (m - s.L), nvec);
+  const size_t lds = lat_lds_bytes(s.L, sizeof(cx<CR>));
+#define AL(DD, KTV, SINKV)                                                                    \
+  hipLaunchKernelGGL((lat_dit_lds_kernel<CR, SR, SINKV, KTV, DD>), gridL, dim3(256), lds, st, \
+                     spec, work, real_out, vstride, m, s.L, conj_in, scale, gen, colshift, P, \
+                     kd.d, partials)
+#define AL_D(DD, KTV) AL(DD, KTV, SINK_REDUCE)
+  if (s.np > 0) {
+    AL(2, KT_SI1, SINK_WORK);
+  } else if (sink == SINK_REAL) {
+    AL(2, KT_SI1, SINK_REAL);
   } else {
-#define PA_D(DD, KTV) PA(DD, KTV, SINK_REDUCE)
-    if (sink == SINK_REAL) {
-      PA(4, KT_SI1, SINK_REAL);
+    switch (kt) {
+      case KT_SI1: MTGP_DISPATCH_D(kd.d, AL_D, KT_SI1); break;
+      case KT_SI2: MTGP_DISPATCH_D(kd.d, AL_D, KT_SI2); break;
+      default: MTGP_DISPATCH_D(kd.d, AL_D, KT_SI3); break;
+    }
+  }
+#undef AL_D
+#undef AL
+  const dim3 grid(1u << (m - kLatHB - 8), nvec);
+  for (int q = 0; q < s.np; q++) {
+    const int lo = s.L + kLatHB * q;
+    const bool last = q == s.np - 1;
+    const size_t stage = last && sink == SINK_REDUCE ? ((size_t)256 << kLatHB) * sizeof(CR) : 0;
+#define AR(DD, KTV, SINKV)                                                                       \
+  hipLaunchKernelGGL((lat_dit_reg_kernel<CR, kLatHB, SINKV, KTV, DD>), grid, dim3(256), stage, st, \
+                     tab, work, real_out, vstride, m, lo, scale, gen, colshift, P, kd.d, partials)
+#define AR_D(DD, KTV) AR(DD, KTV, SINK_REDUCE)
+    if (!last) {
+      AR(2, KT_SI1, SINK_WORK);
+    } else if (sink == SINK_REAL) {
+      AR(2, KT_SI1, SINK_REAL);
     } else {
       switch (kt) {
-        case KT_SI1: MTGP_DISPATCH_D(kd.d, PA_D, KT_SI1); break;
-        case KT_SI2: MTGP_DISPATCH_D(kd.d, PA_D, KT_SI2); break;
-        default: MTGP_DISPATCH_D(kd.d, PA_D, KT_SI3); break;
+        case KT_SI1: MTGP_DISPATCH_D(kd.d, AR_D, KT_SI1); break;
+        case KT_SI2: MTGP_DISPATCH_D(kd.d, AR_D, KT_SI2); break;
+        default: MTGP_DISPATCH_D(kd.d, AR_D, KT_SI3); break;
       }
     }
-#undef PA_D
+#undef AR_D
+#undef AR
   }
-#undef PA
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Standalone transform: 0 when one LDS pass covers 2^m (then the forward
+// writes natural frequency order itself), else the forward needs a scratch
+// spectrum that launch_lat_natural permutes.
+int lat_single_pass(int m) { return lat_sched(m).np == 0; }
+
+// one LDS pass straight into natural frequency order (m <= 12)
+template <typename R>
+int launch_lat_single_natural(int src, const void* x, int x_f32, cx<R>* X, int nvec, int m,
+                              hipStream_t st) {
+  if (nvec <= 0) return 0;
+  const dim3 grid(1, nvec);
+  const size_t lds = lat_lds_bytes(m, sizeof(cx<R>));
+  const int64_t n = (int64_t)1 << m;
+  if (src == SRC_Y)
+    hipLaunchKernelGGL((lat_dif_lds_kernel<R, R, SRC_Y, KT_SI1>), grid, dim3(256), lds, st,
+                       nullptr, X, n, m, m, 1.0, 1, x, x_f32, nullptr, nullptr, nullptr, 0);
+  else
+    hipLaunchKernelGGL((lat_dif_lds_kernel<R, R, SRC_X, KT_SI1>), grid, dim3(256), lds, st,
+                       nullptr, X, n, m, m, 1.0, 1, x, x_f32, nullptr, nullptr, nullptr, 0);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// bit-reversed spectrum -> natural frequency order
+template <typename R>
+__global__ void lat_natural_kernel(const cx<R>* __restrict__ spec, cx<R>* __restrict__ X,
+                                   int64_t nvec, int m) {
+  const int64_t n = (int64_t)1 << m;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nvec * n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = q >> m, f = q & (n - 1);
+    X[q] = spec[v * n + bitrev64(f, m)];
+  }
+}
+
+// The same permutation through 32 x 32 LDS tiles (m >= 10): with f = a 2^(m-5)
+// + b 2^5 + c (a, c of 5 bits), bitrev_m(f) = rev(c) 2^(m-5) + rev(b) 2^5 +
+// rev(a), so the tile of one b reads 32 runs of 32 consecutive spectrum
+// entries and writes 32 runs of 32 consecutive outputs.  Grid (2^(m-10), nvec).
+template <typename R>
+__global__ __launch_bounds__(256) void lat_natural_tiled_kernel(const cx<R>* __restrict__ spec,
+                                                                cx<R>* __restrict__ X, int m) {
+  __shared__ cx<R> t[32][33];
+  const int64_t n = (int64_t)1 << m;
+  const int64_t b = blockIdx.x;
+  const int64_t rb = bitrev64(b, m - 10);
+  const cx<R>* s = spec + (size_t)blockIdx.y * n;
+  cx<R>* x = X + (size_t)blockIdx.y * n;
+  for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
+    const int i = e >> 5, j = e & 31;
+    t[i][j] = s[((int64_t)i << (m - 5)) | (rb << 5) | j];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
+    const int a = e >> 5, c = e & 31;
+    x[((int64_t)a << (m - 5)) | (b << 5) | c] = t[bitrev64(c, 5)][bitrev64(a, 5)];
+  }
+}
+
+int launch_lat_natural(const void* spec, int spec_f32, void* X, int64_t nvec, int m,
+                       hipStream_t st) {
+  if (nvec <= 0) return 0;
+  if (m >= 10) {
+    const dim3 grid(1u << (m - 10), (unsigned)nvec);
+    if (spec_f32)
+      hipLaunchKernelGGL(lat_natural_tiled_kernel<float>, grid, dim3(256), 0, st,
+                         static_cast<const cx<float>*>(spec), static_cast<cx<float>*>(X), m);
+    else
+      hipLaunchKernelGGL(lat_natural_tiled_kernel<double>, grid, dim3(256), 0, st,
+                         static_cast<const cx<double>*>(spec), static_cast<cx<double>*>(X), m);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
+  const int64_t total = nvec << m;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65535) blocks = 65535;
+  if (spec_f32)
+    hipLaunchKernelGGL(lat_natural_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       static_cast<const cx<float>*>(spec), static_cast<cx<float>*>(X), nvec, m);
+  else
+    hipLaunchKernelGGL(lat_natural_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       static_cast<const cx<double>*>(spec), static_cast<cx<double>*>(X), nvec, m);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template int launch_lat_single_natural<double>(int, const void*, int, cx<double>*, int, int,
+                                               hipStream_t);
+template int launch_lat_single_natural<float>(int, const void*, int, cx<float>*, int, int,
+                                              hipStream_t);
 template int launch_lat_forward<double, double>(int, cx<double>*, cx<double>*, int64_t, int, int,
                                                 const void*, int, double, const uint32_t*,
                                                 const uint32_t*, const Params*, const KDesc&,
@@ -479,36 +664,6 @@ template int launch_lat_forward<float, float>(int, cx<float>*, cx<float>*, int64
                                               const void*, int, double, const uint32_t*,
                                               const uint32_t*, const Params*, const KDesc&,
                                               hipStream_t);
-
-// spectrum layout (p = f2 n1 + f1 for f = f2 + n2 f1) -> natural frequency order
-template <typename R>
-__global__ void lat_natural_kernel(const cx<R>* __restrict__ spec, cx<R>* __restrict__ X,
-                                   int64_t nvec, int m, int b1) {
-  const int64_t n = (int64_t)1 << m;
-  const int b2 = m - b1;
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nvec * n;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t v = q >> m, f = q & (n - 1);
-    const int64_t f2 = f & ((1 << b2) - 1), f1 = f >> b2;
-    X[q] = spec[v * n + (f2 << b1) + f1];
-  }
-}
-
-int launch_lat_natural(const void* spec, int spec_f32, void* X, int64_t nvec, int m,
-                       hipStream_t st) {
-  const int64_t total = nvec << m;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 65535) blocks = 65535;
-  if (spec_f32)
-    hipLaunchKernelGGL(lat_natural_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st,
-                       static_cast<const cx<float>*>(spec), static_cast<cx<float>*>(X), nvec, m,
-                       lat_b1(m));
-  else
-    hipLaunchKernelGGL(lat_natural_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st,
-                       static_cast<const cx<double>*>(spec), static_cast<cx<double>*>(X), nvec, m,
-                       lat_b1(m));
-  return hipGetLastError() == hipSuccess ? 0 : -1;
-}
 template int launch_lat_adjoint<double, double>(int, const cx<double>*, cx<double>*, double*,
                                                 int64_t, int, int, int, double, const uint32_t*,
                                                 const uint32_t*, const Params*, const KDesc&,

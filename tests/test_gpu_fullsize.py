@@ -167,3 +167,24 @@ def test_config2_full_size():
     torch.cuda.empty_cache()
     say("config2 full size mixed")
     _mixed_vs_fp64(w, out64, g64, tau64)
+
+
+def test_config5_lattice_full_size():
+    """T=8, d=10, n=2^24 rank-1 lattices (N = 2^27), order-2 SI kernel: the
+    multi-pass FFT at full size."""
+    w = workloads.config5_lat()
+    say("config5 lattice full size fp64")
+    plan, y = _setup(w, "fp64")
+    theta = plan.pack_theta(w.theta)
+    _sampled_columns(w, plan, theta, np.random.default_rng(56), nsample=32)
+    torch.cuda.empty_cache()
+    out64, g64, tau64 = _loss_grad(plan, theta)
+    means = y.view(w.T, -1).mean(dim=1).cpu().numpy()
+    np.testing.assert_allclose(tau64, means, rtol=1e-12, atol=1e-14)
+    T, d = w.T, w.d
+    _fd_check(plan, theta, g64, [T + 1, T + 1 + d, T + 1 + d + T, T + 1 + d + T + 2 * T])
+    del plan, y
+    torch.cuda.empty_cache()
+    say("config5 lattice full size mixed")
+    _mixed_vs_fp64(w, out64, g64, tau64)
+

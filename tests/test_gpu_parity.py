@@ -114,7 +114,8 @@ def test_fwht_large_sampled(dtype, log2n):
 
 # ---------------------------------------------------------------------- fft
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("log2n,batch", [(0, 2), (3, 3), (9, 2), (12, 2), (13, 2), (16, 3), (20, 1)])
+@pytest.mark.parametrize("log2n,batch", [(0, 2), (3, 3), (9, 2), (12, 2), (13, 2), (14, 2), (15, 1),
+                                          (16, 3), (20, 1), (22, 1), (24, 1)])
 @pytest.mark.parametrize("bitrev", [False, True])
 def test_fft_vs_numpy(dtype, log2n, batch, bitrev):
     say("fft", dtype, log2n, batch, bitrev)

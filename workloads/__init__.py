@@ -82,9 +82,9 @@ def random_dseq_gen(rng: np.random.Generator, d: int) -> np.ndarray:
     return gen
 
 
-def random_lattice_gen(rng: np.random.Generator, d: int) -> np.ndarray:
-    """Odd generating-vector entries below 2**16."""
-    g = rng.integers(0, 1 << 15, size=d, dtype=np.int64) * 2 + 1
+def random_lattice_gen(rng: np.random.Generator, d: int, bits: int = 16) -> np.ndarray:
+    """Odd generating-vector entries below 2**bits."""
+    g = rng.integers(0, 1 << (bits - 1), size=d, dtype=np.int64) * 2 + 1
     return g.astype(np.uint32).reshape(d, 1)
 
 
@@ -197,6 +197,21 @@ def config5() -> Workload:
                  B=B, zeta=np.full(T, 0.1))
     return Workload("config5_dseq_T8_d10_n2^24", DSEQ, T, d, [24] * T, 2, False, gen, shift,
                     theta, True, 5, "corr_sines", _corr_sine_params(rng, T, d), 1e-6, 1 << 20)
+
+
+def config5_lat() -> Workload:
+    """The config-5 shape on the lattice path: T=8, d=10, n=2^24 rank-1
+    lattice per task, order-2 SI kernel (the paper names shift-invariant
+    kernels on lattices as the untested variant of its method)."""
+    rng = np.random.default_rng(6)
+    T, d = 8, 10
+    gen = random_lattice_gen(rng, d, bits=24)
+    shift = random_shifts(rng, T, d)
+    B = rng.normal(0.0, math.sqrt(0.5), size=(T, 2))
+    theta = dict(tau=np.zeros(T), gamma=1.0, eta=np.full(d, 0.5), b=None, xi=np.full(T, 1e-3),
+                 B=B, zeta=np.full(T, 0.1))
+    return Workload("config5_lat_T8_d10_n2^24", LAT, T, d, [24] * T, 2, False, gen, shift,
+                    theta, True, 6, "corr_sines", _corr_sine_params(rng, T, d), 1e-6, 1 << 20)
 
 
 def config4_fits(nfits: int = 256, seed: int = 4, kmin: int = 8, kmax: int = 14) -> list:
