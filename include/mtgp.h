@@ -16,8 +16,10 @@
  * Task t has n_t = 2^m_t points, n_1 >= ... >= n_T, a common generator and
  * its own shift; the Gram matrix factors as Ktilde = V Lambda V^dagger
  * (Theorem "Fast MTGP computations") and Lambda is inverted per frequency
- * (equal sizes) or by block Gaussian elimination in task order (Algorithm
- * "Inverse and log-determinant of Lambda") for nested unequal sizes.
+ * (equal sizes) or, for nested unequal sizes, by elimination in task order:
+ * by default as a fill-free sparse LDL^H factorisation (the task-order
+ * pivots of Algorithm "Inverse and log-determinant of Lambda" without its
+ * dense blocks), or by the algorithm as printed (mtgp_plan_set_elimination).
  *
  * Conventions for every entry point:
  *   - Pointers named `stream` are hipStream_t values passed as void*.
@@ -82,6 +84,8 @@ enum { MTGP_DSEQ = 0, MTGP_LAT = 1 };
  *               exactly that. */
 enum { MTGP_FP64 = 0, MTGP_MIXED = 1, MTGP_F32 = 2 };
 enum { MTGP_DTYPE_F64 = 0, MTGP_DTYPE_F32 = 1 };
+/* Elimination for nested unequal sizes (mtgp_plan_set_elimination). */
+enum { MTGP_ELIM_SPARSE = 0, MTGP_ELIM_ALG1 = 1 };
 
 typedef struct mtgp_plan mtgp_plan;
 
@@ -118,6 +122,21 @@ int mtgp_plan_destroy(mtgp_plan* plan);
  * 2^24-point columns). */
 int mtgp_plan_set_schedule(mtgp_plan* plan, int32_t pass_a_bits, int32_t pass_b_bits,
                            int64_t pass_b_tile_bytes);
+
+/* Elimination used by nested unequal sizes (ignored for equal sizes; both
+ * eliminate the tasks in order with the same pivots, so results agree up to
+ * rounding):
+ *   MTGP_ELIM_SPARSE (default): Lambda = L D L^H with L on Lambda's own
+ *     pattern (task-order elimination creates no fill because the later
+ *     neighbours of a node (t, f), the nodes (u, f mod n_u), u > t, are
+ *     coupled to each other); O(N T^2) work and sum_t (T - t) n_t stored
+ *     entries, with Lambda^-1 on the pattern from the factor for the gradient.
+ *   MTGP_ELIM_ALG1: Algorithm "Inverse and log-determinant of Lambda" with
+ *     dense running-inverse blocks of size m_T = sum_t n_t / n_T (requires
+ *     m_T <= 2048, else MTGP_ENOTSUP; two buffers of N m_T complex values).
+ * Changes mtgp_workspace_bytes, so call it before sizing the workspace.
+ * Errors: MTGP_EINVAL (mode), MTGP_ENOTSUP. */
+int mtgp_plan_set_elimination(mtgp_plan* plan, int32_t mode);
 
 /* Overlap of the digital-net passes (tuning only; results are bitwise the
  * same): the columns of each length group are processed in `chunks` chunks

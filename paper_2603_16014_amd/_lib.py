@@ -27,6 +27,7 @@ SIGNATURES = {
     "mtgp_plan_destroy": (ctypes.c_int, [vp]),
     "mtgp_plan_set_schedule": (ctypes.c_int, [vp, c_i32, c_i32, c_i64]),
     "mtgp_plan_set_overlap": (ctypes.c_int, [vp, c_i32]),
+    "mtgp_plan_set_elimination": (ctypes.c_int, [vp, c_i32]),
     "mtgp_plan_enable_timing": (ctypes.c_int, [vp, c_i32]),
     "mtgp_phase_times": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), c_i32,
                                         ctypes.POINTER(c_i32)]),

@@ -23,23 +23,6 @@ namespace mtgp {
 __device__ inline z2 zm(z2 a, z2 b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __device__ inline z2 zmc(z2 a, z2 b) { return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }  // a conj(b)
 
-// position of frequency f in a spectrum of length 2^m (digital sequences:
-// natural order; lattices: bit-reversed order, the output order of the
-// decimation-in-frequency transform)
-__device__ inline int64_t spec_pos(int family, int64_t f, int m) {
-  if (family == FAM_DSEQ || m == 0) return f;
-  return (int64_t)(__brevll((unsigned long long)f) >> (64 - m));
-}
-
-// lambda of column c (log2 length m) at frequency f, as a complex number
-template <typename SR>
-__device__ inline z2 lam_at(const SR* cols, const Alg1Desc& A1, int family, int c, int64_t f) {
-  const int m = A1.col_m[c];
-  const int64_t pos = A1.col_off[c] + spec_pos(family, f, m);
-  if (family == FAM_DSEQ) return {(double)cols[pos], 0.0};
-  return {(double)cols[2 * pos], (double)cols[2 * pos + 1]};
-}
-
 // (task, frequency) of row q of the stage-s block with residue r
 __device__ inline void decode_row(const Alg1Desc& A1, int s, int64_t r, int64_t q, int& task,
                                   int64_t& freq) {
@@ -319,6 +302,14 @@ __global__ __launch_bounds__(256) void alg1_final_kernel(SR* __restrict__ cols, 
           vals[2 + TM + i] += w;
         }
       }
+    }
+    // every read of the diagonal columns above precedes the writes below
+    // (tasks of equal length share one diagonal column)
+    __syncthreads();
+    for (int64_t q = threadIdx.x; q < ms; q += blockDim.x) {
+      const int t = tsk[q];
+      const int64_t f = frq[q];
+      const z2 aq = ah[q];
       if (A1.diag_first[t] == t) {
         double wsum = 0.0;
         // rows of the other tasks with the same length and the same frequency

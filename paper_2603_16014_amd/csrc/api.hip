@@ -62,6 +62,7 @@ struct mtgp_plan {
   Sched sched;
   Alg1Desc a1;      // stage descriptors of the unequal-size elimination
   int64_t a1_ms;    // final block size N / n_T
+  int elim = MTGP_ELIM_SPARSE;  // unequal sizes: fill-free LDL^H or Algorithm 1
   // optional phase timing (profiling aid; not thread safe)
   // Overlap of the VALU-bound fused passes (caller's stream) with the
   // HBM-bound strided passes (aux stream) over chunks of columns; fork and
@@ -370,10 +371,15 @@ int run_loss(const mtgp_plan* p, const double* theta, double* out3, double* grad
   const int64_t n = p->n[0];
   int64_t nsolve;
   mark(p, 3, st);
-  if (!p->equal) {
+  if (!p->equal && p->elim == MTGP_ELIM_ALG1) {
     LAUNCH_OK(launch_alg1<SR>(spec, p->a1, w.P, kd.family, grad != nullptr, w.yhat, w.a1a, w.a1b,
                               w.logs, want_ahat ? w.ahat : nullptr, w.sp, w.status, st));
     nsolve = p->n[p->T - 1];
+  } else if (!p->equal) {
+    LAUNCH_OK(launch_zerofill<SR>(spec, p->a1, p->N, w.P, kd.family, grad != nullptr, w.yhat,
+                                  w.a1a, w.logs, want_ahat ? w.ahat : nullptr, w.sp, w.status,
+                                  st));
+    nsolve = zf_final_blocks(p->N);
   } else if (p->family == MTGP_LAT) {
     LAUNCH_OK(launch_solve_eq_c<SR>(spec, n, p->pm, w.yhat, w.P, kd, grad != nullptr, w.sp,
                                     want_ahat ? w.ahat : nullptr, w.status, st));
@@ -465,9 +471,14 @@ void layout(mtgp_plan* p) {
   o = align_up(o + (cplx == 2 ? (size_t)p->N * sizeof(double) : 0));
   p->o_pwork = o;
   o = align_up(o + (cplx == 2 ? (size_t)p->N * 2 * sizeof(double) : 0));
-  const size_t a1 = p->equal ? 0 : (size_t)p->N * (size_t)p->a1_ms * sizeof(z2);
+  // unequal sizes: Algorithm 1 keeps two running-inverse buffers of N m_T
+  // entries; the fill-free elimination one buffer of pattern values and
+  // right-hand sides
+  const bool a1dense = !p->equal && p->elim == MTGP_ELIM_ALG1;
+  const size_t a1 = a1dense ? (size_t)p->N * (size_t)p->a1_ms * sizeof(z2) : 0;
+  const size_t zf = !p->equal && !a1dense ? (size_t)zf_elems(p->a1, p->N) * sizeof(z2) : 0;
   p->o_a1a = o;
-  o = align_up(o + a1);
+  o = align_up(o + (a1dense ? a1 : zf));
   p->o_a1b = o;
   o = align_up(o + a1);
   p->o_logs = o;
@@ -476,7 +487,8 @@ void layout(mtgp_plan* p) {
   o = align_up(o + (size_t)COLSUM_BLOCKS * sizeof(double));
   p->o_sp = o;
   {
-    const int64_t rows = p->equal ? solve_blocks(p->n[0]) : p->n[p->T - 1];
+    const int64_t rows = p->equal ? solve_blocks(p->n[0])
+                                  : std::max<int64_t>(p->n[p->T - 1], zf_final_blocks(p->N));
     o = align_up(o + (size_t)rows * solve_ns(T) * sizeof(double));
   }
   p->o_sp2 = o;
@@ -588,11 +600,7 @@ int mtgp_plan_create(const mtgp_design* des, int32_t precision, mtgp_plan** out)
   if (!p->equal) {
     int64_t ms = 0;
     for (int t = 0; t < T; t++) ms += p->n[t] >> p->m[T - 1];
-    if (ms > ALG1_MAX_BLOCK) {  // the elimination keeps N / n_T x N / n_T blocks
-      delete p;
-      return MTGP_ENOTSUP;
-    }
-    p->a1_ms = ms;
+    p->a1_ms = ms;  // Algorithm 1 (optional) needs ms <= ALG1_MAX_BLOCK
   } else {
     p->a1_ms = 0;
   }
@@ -672,6 +680,16 @@ int mtgp_plan_create(const mtgp_design* des, int32_t precision, mtgp_plan** out)
       }
     p->a1.diag_first[s] = (int8_t)first;
   }
+  {
+    int64_t po = 0, co = 0;
+    for (int a = 0; a < T; a++) {
+      p->a1.so[a] = po;
+      po += (int64_t)(T - a) * p->n[a];
+      p->a1.coff[a] = co;
+      co += p->n[a] >> p->m[T - 1];
+    }
+    p->a1.so[T] = po;
+  }
   for (int t = 0; t < T; t++)
     for (int u = 0; u < T; u++) p->a1.pair_col[t][u] = p->pm.col[t][u];
   for (int c = 0; c < p->ncol; c++) {
@@ -722,6 +740,14 @@ int mtgp_plan_set_schedule(mtgp_plan* p, int32_t pass_a_bits, int32_t pass_b_bit
   p->sched.b_tile = (size_t)pass_b_tile_bytes;
   layout(p);
   return upload_colinfo(p);
+}
+
+int mtgp_plan_set_elimination(mtgp_plan* p, int32_t mode) {
+  if (!p || (mode != MTGP_ELIM_SPARSE && mode != MTGP_ELIM_ALG1)) return MTGP_EINVAL;
+  if (mode == MTGP_ELIM_ALG1 && !p->equal && p->a1_ms > ALG1_MAX_BLOCK) return MTGP_ENOTSUP;
+  p->elim = mode;
+  layout(p);
+  return MTGP_OK;
 }
 
 int mtgp_plan_set_overlap(mtgp_plan* p, int32_t chunks) {

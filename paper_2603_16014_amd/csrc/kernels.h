@@ -180,12 +180,50 @@ struct Alg1Desc {
   int8_t diag_first[MTGP_MAXT];  // first task with the same length
   int col_m[MTGP_MAXCOL];
   int64_t col_off[MTGP_MAXCOL];
+  // fill-free elimination: pattern row a (pairs (a, b >= a), n_a entries
+  // each) starts at so[a], so[T] = total; class-0 node (t, k) (frequency
+  // k n_T) sits at coff[t] + k of each of the T unit right-hand sides
+  int64_t so[MTGP_MAXT + 1];
+  int64_t coff[MTGP_MAXT];
 };
 constexpr int64_t ALG1_MAX_BLOCK = 2048;  // largest final block N / n_T handled
 template <typename SR>
 int launch_alg1(SR* cols, const Alg1Desc& A1, Params* P, int family, bool grad,
                 const double* yhat, z2* bufA, z2* bufB, double* logs, double* ahat,
                 double* partials, int* status, hipStream_t st);
+
+// position of frequency f in a spectrum of length 2^m (digital sequences:
+// natural order; lattices: bit-reversed order, the output order of the
+// decimation-in-frequency transform)
+__device__ inline int64_t spec_pos(int family, int64_t f, int m) {
+  if (family == FAM_DSEQ || m == 0) return f;
+  return (int64_t)(__brevll((unsigned long long)f) >> (64 - m));
+}
+
+// lambda of column c (log2 length m) at frequency f, as a complex number
+template <typename SR>
+__device__ inline z2 lam_at(const SR* cols, const Alg1Desc& A1, int family, int c, int64_t f) {
+  const int m = A1.col_m[c];
+  const int64_t pos = A1.col_off[c] + spec_pos(family, f, m);
+  if (family == FAM_DSEQ) return {(double)cols[pos], 0.0};
+  return {(double)cols[2 * pos], (double)cols[2 * pos + 1]};
+}
+
+// ---- elim.hip
+// Workspace of the fill-free elimination (complex entries): pattern values
+// so[T], the data right-hand side N, the unit right-hand sides T msz[T-1].
+inline int64_t zf_elems(const Alg1Desc& A1, int64_t N) {
+  return A1.so[A1.T] + N + (int64_t)A1.T * A1.msz[A1.T - 1];
+}
+constexpr int ZF_FINAL_BLOCKS = 2048;  // partial rows of the final pass (at most)
+inline int64_t zf_final_blocks(int64_t N) {
+  const int64_t b = (N + 255) / 256;
+  return b < ZF_FINAL_BLOCKS ? b : ZF_FINAL_BLOCKS;
+}
+template <typename SR>
+int launch_zerofill(SR* cols, const Alg1Desc& A1, int64_t N, Params* P, int family, bool grad,
+                    const double* yhat, z2* buf, double* logs, double* ahat, double* partials,
+                    int* status, hipStream_t st);
 
 // ---- gcv.hip
 template <typename SR>

@@ -18,6 +18,7 @@ DSEQ, LAT = 0, 1
 FP64, MIXED, F32 = 0, 1, 2
 FAMILIES = {"dseq": DSEQ, "lat": LAT, DSEQ: DSEQ, LAT: LAT}
 PRECISIONS = {"fp64": FP64, "mixed": MIXED, "f32": F32, FP64: FP64, MIXED: MIXED, F32: F32}
+ELIMINATIONS = {"sparse": 0, "alg1": 1, 0: 0, 1: 1}  # nested unequal sizes
 LOG_KEYS = ("gamma", "eta", "b", "xi", "zeta")
 
 
@@ -47,7 +48,7 @@ class Plan:
     """A fast-MTGP design (points + kernel family) bound to the current device."""
 
     def __init__(self, family, m, gen, shift, kernel_order=2, adaptive=False, rank_s=1,
-                 profile_tau=True, precision="fp64", schedule=None):
+                 profile_tau=True, precision="fp64", schedule=None, elimination=None):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible: the MTGP library has no CPU path")
@@ -78,6 +79,9 @@ class Plan:
             a, b, tile = schedule
             _lib.check(self.lib.mtgp_plan_set_schedule(h, int(a), int(b), int(tile)),
                        "mtgp_plan_set_schedule")
+        if elimination is not None:
+            _lib.check(self.lib.mtgp_plan_set_elimination(h, ELIMINATIONS[elimination]),
+                       "mtgp_plan_set_elimination")
         self.theta_size = int(self.lib.mtgp_theta_size(h))
         self.N = int(self.lib.mtgp_num_points(h))
         self.ncol = int(self.lib.mtgp_num_columns(h))
@@ -86,9 +90,11 @@ class Plan:
         self.n = [1 << v for v in self.m]
 
     @classmethod
-    def from_workload(cls, w, precision="fp64", profile_tau=None, schedule=None):
+    def from_workload(cls, w, precision="fp64", profile_tau=None, schedule=None,
+                      elimination=None):
         return cls(w.family, w.m, w.gen, w.shift, w.kernel_order, w.adaptive, w.rank_s,
-                   w.profile_tau if profile_tau is None else profile_tau, precision, schedule)
+                   w.profile_tau if profile_tau is None else profile_tau, precision, schedule,
+                   elimination)
 
     def __del__(self):
         h = getattr(self, "h", None)

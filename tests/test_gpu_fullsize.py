@@ -145,7 +145,21 @@ def test_config3_full_size():
     out64, g64, tau64 = _loss_grad(plan, theta)
     T, d = w.T, w.d
     _fd_check(plan, theta, g64, [T + 1, T + 1 + d + T - 1, T + 1 + d + T + 1])
-    del plan, y
+    del plan
+    torch.cuda.empty_cache()
+    # the fill-free elimination (default) against Algorithm 1 as printed
+    say("config3 full size fp64, Algorithm 1")
+    from paper_2603_16014_amd import mtgp
+    pa = mtgp.Plan.from_workload(w, "fp64", elimination="alg1")
+    pa.set_data(y)
+    oa, ga, ta = _loss_grad(pa, theta)
+    den = abs(out64[0]) + abs(out64[1])
+    assert abs(oa[2] - out64[2]) < 1e-12 * den, (oa, out64)
+    # the two eliminations sum different partial products in FP64; the eta
+    # entries (~5e5) cancel over 2^20 frequencies: 1.7e-9 measured
+    assert np.abs(ga - g64).max() < 1e-8 * np.abs(g64).max()
+    np.testing.assert_allclose(ta, tau64, rtol=1e-10, atol=1e-14)
+    del pa, y
     torch.cuda.empty_cache()
     say("config3 full size mixed")
     _mixed_vs_fp64(w, out64, g64, tau64)

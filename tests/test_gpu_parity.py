@@ -169,13 +169,16 @@ def _case_id(c):
 
 @pytest.mark.parametrize("case", CASES, ids=[_case_id(c) for c in CASES])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_loss_grad_parity(case, precision):
+@pytest.mark.parametrize("elimination", ["sparse", "alg1"])
+def test_loss_grad_parity(case, precision, elimination):
     family, T, m, d, order, adaptive, profile, sched = case
+    if elimination == "alg1" and len(set(m)) == 1:
+        pytest.skip("equal sizes: no elimination")
     w = tiny(family, T, m, d, order=order, adaptive=adaptive, seed=31 + T, profile=profile,
              xi=1e-3, rank=min(T, 2))
-    say("loss+grad", _case_id(case), precision)
+    say("loss+grad", _case_id(case), precision, elimination)
     ref = oracle_for(w, want_grad=True)
-    plan = mt.Plan.from_workload(w, precision, schedule=sched)
+    plan = mt.Plan.from_workload(w, precision, schedule=sched, elimination=elimination)
     theta = plan.pack_theta(w.theta)
     plan.set_data(torch.from_numpy(ref["y"]).cuda())
     out3, grad, tau = plan.nll_grad(theta)
@@ -203,8 +206,8 @@ def test_loss_grad_parity(case, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_lattice_two_pass_against_oracle(precision):
-    # m = 13 > 12 runs the two-pass DFT (pass 1 over the high index bits fused
-    # with generation, pass 2 contiguous) and the two-pass adjoint
+    # m = 13 > 12 runs the multi-pass DFT (a register pass over the high
+    # index bits fused with generation, then the LDS pass) and its adjoint
     w = tiny("lat", 1, [13], 2, seed=51, xi=1e-3)
     say("lattice two-pass", precision)
     ref = oracle_for(w, want_grad=False, M=64, xs_seed=5)
@@ -280,6 +283,32 @@ def test_predict_parity(precision, family, T, m, d, adaptive):
 
 
 # ---------------------------------------------------------------- errors
+@pytest.mark.parametrize("family", ["dseq", "lat"])
+def test_sparse_elimination_beyond_dense_block_limit(family):
+    """m = (12, 1): the final dense block of Algorithm 1 would have
+    2^11 + 1 > 2048 rows (refused); the fill-free elimination has no such
+    limit and matches the dense oracle."""
+    w = tiny(family, 2, [12, 1], 2, seed=71, xi=1e-3, rank=2)
+    say("sparse elimination beyond the dense block limit", family)
+    with pytest.raises(Exception, match="not supported"):
+        mt.Plan.from_workload(w, "fp64", elimination="alg1")
+    ref = oracle_for(w, want_grad=True)
+    plan = mt.Plan.from_workload(w, "fp64")
+    theta = plan.pack_theta(w.theta)
+    plan.set_data(torch.from_numpy(ref["y"]).cuda())
+    out3, grad, tau = plan.nll_grad(theta)
+    assert plan.status() == (0, -1)
+    r = ref["res"]
+    den = abs(r["quad"]) + abs(r["logdet"])
+    assert abs(float(out3[2]) - r["L"]) < 1e-10 * den
+    np.testing.assert_allclose(tau.cpu().numpy(), r["tau_hat"], rtol=1e-9, atol=1e-12)
+    g = plan.unpack(grad)
+    scale = max(np.abs(np.concatenate([np.atleast_1d(v).ravel() for v in ref["grad"].values()])).max(),
+                1e-300)
+    for k, v in ref["grad"].items():
+        assert rel_err(g[k], v, scale) < 1e-7, k
+
+
 def test_invalid_designs_rejected():
     say("invalid designs")
     rng = np.random.default_rng(0)
