@@ -69,7 +69,7 @@ struct mtgp_plan {
   // join through events, so the sequence can be captured in a HIP graph.
   // Events are re-recorded round-robin: a wait takes the event's state at the
   // time it is enqueued, so reuse after the matching wait is safe.
-  static constexpr int kMaxChunks = 8;
+  static constexpr int kMaxChunks = 32;
   static constexpr int kEvents = 32;
   int nchunks = 4;
   hipStream_t aux = nullptr;

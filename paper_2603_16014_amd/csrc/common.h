@@ -278,10 +278,29 @@ __device__ inline void flag_bad(int* status, int64_t idx) {
 // ---------------------------------------------------------------------------
 // block reductions (FP64)
 // ---------------------------------------------------------------------------
+// Value of another lane of the row under a DPP control (rows whose bit in
+// ROW_MASK is clear read 0).
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_read(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave, returned in every lane; every lane must be
+// active.  DPP row operations (no LDS traffic): quad permutes and row mirrors
+// give each lane its 16-lane row sum, two row broadcasts carry rows 0-2 into
+// lane 63, which is read back through a scalar register.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_read<0xb1, 0xf>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_read<0x4e, 0xf>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_read<0x141, 0xf>(v);  // row_half_mirror: sums of 8
+  v += dpp_read<0x140, 0xf>(v);  // row_mirror: sums of 16
+  v += dpp_read<0x142, 0xa>(v);  // row_bcast15 into rows 1 and 3
+  v += dpp_read<0x143, 0xc>(v);  // row_bcast31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // Sums v over the block; every thread gets the result.  `red` holds >= 16 doubles.
@@ -316,6 +335,17 @@ __device__ inline void block_sum_store(const double* vals, int nq, double* red, 
     for (int i = 0; i < nw; i++) s += red[i * NQ + q];
     out[q] = s;
   }
+}
+
+// As block_sum_store over the first nred slots; the slots [nred, NQ) are
+// nonzero only in thread 0 of block 0 (the thread of frequency 0), so each
+// block's thread 0 stores its own values there instead of a block sum.
+template <int NQ>
+__device__ inline void block_sum_store_head(const double* vals, int nred, double* red,
+                                            double* out) {
+  block_sum_store<NQ>(vals, nred, red, out);
+  if (threadIdx.x == 0)
+    for (int q = nred; q < NQ; q++) out[q] = vals[q];
 }
 
 }  // namespace mtgp

@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
       cols[(int64_t)pm.col[0][0] * n + f] = (Real)wdiag;
     }
   }
-  block_sum_store<NQ>(vals, NQ, red, partials + (size_t)blockIdx.x * NQ);
+  block_sum_store_head<NQ>(vals, 2 + 2 * TM, red, partials + (size_t)blockIdx.x * NQ);
 }
 
 template <typename Real>
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
       cols[at0 + 1] = (SR)0;
     }
   }
-  block_sum_store<NQ>(vals, NQ, red, partials + (size_t)blockIdx.x * NQ);
+  block_sum_store_head<NQ>(vals, 2 + 2 * TM, red, partials + (size_t)blockIdx.x * NQ);
 }
 
 template <typename SR>
