@@ -243,10 +243,12 @@ int mtgp_predict(const mtgp_plan* plan, const double* theta, const uint32_t* xs,
                  double* mean, void* ws, void* stream);
 
 /* Posterior mean on a structured test net: the first 2^m_star points of the
- * plan's sequence with shift shift_star[d] (host), in radical-inverse order:
+ * plan's sequence with shift shift_star[d] (host; a digital shift for nets,
+ * a lattice shift times 2^32 for lattices), in radical-inverse order:
  * mean[2^m_star][T].  Uses the cross-block structure of Theorem "Fast MTGP
- * computations" for each (test net, task) pair, O(N log N + T n* log n*)
- * instead of O(M N d).  `scratch` is a device buffer of
+ * computations" for each (test net, task) pair (for lattices: a cyclic
+ * convolution on the finer of the two lattices, folded onto the test
+ * frequencies), O(N log N + T n* log n*) instead of O(M N d).  `scratch` is a device buffer of
  * mtgp_predict_net_scratch_bytes(plan, m_star) bytes.  Requires
  * mtgp_set_data; 0 <= m_star <= 30. */
 size_t mtgp_predict_net_scratch_bytes(const mtgp_plan* plan, int32_t m_star);

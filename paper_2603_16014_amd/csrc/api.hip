@@ -1007,6 +1007,10 @@ int mtgp_predict(const mtgp_plan* p, const double* theta, const uint32_t* xs, in
 // spectra, the pair-shift table
 static size_t prednet_layout(const mtgp_plan* p, int m_star, PredNet& pn, size_t& o_w,
                              size_t& o_sh) {
+  // columns (complex for lattices), then the folded test spectra: nets
+  // [T][n*]; lattices [T][n*] complex, the adjoint's working copy and the
+  // real means [T][n*]
+  const size_t cplx = p->family == MTGP_LAT ? 2 : 1;
   pn.T = p->T;
   pn.m_star = m_star;
   size_t o = 0;
@@ -1015,11 +1019,11 @@ static size_t prednet_layout(const mtgp_plan* p, int m_star, PredNet& pn, size_t
     pn.col_off[u] = (int64_t)(o / sizeof(double));
     pn.task_off[u] = p->off[u];
     const int L = m_star > p->m[u] ? m_star : p->m[u];
-    o += ((size_t)1 << L) * sizeof(double);
+    o += ((size_t)1 << L) * sizeof(double) * cplx;
   }
   o = align_up(o);
   o_w = o;
-  o = align_up(o + ((size_t)1 << m_star) * p->T * sizeof(double));
+  o = align_up(o + ((size_t)1 << m_star) * p->T * sizeof(double) * (cplx == 2 ? 5 : 1));
   o_sh = o;
   o = align_up(o + (size_t)p->T * p->d * sizeof(uint32_t));
   return o;
@@ -1036,7 +1040,6 @@ int mtgp_predict_net(const mtgp_plan* p, const double* theta, const uint32_t* sh
                      int32_t m_star, double* mean, void* ws, void* scratch, void* stream) {
   if (!p || !theta || !shift_star || !mean || !ws || !scratch || m_star < 0 || m_star > 30)
     return MTGP_EINVAL;
-  if (p->family != MTGP_DSEQ) return MTGP_ENOTSUP;
   hipStream_t st = (hipStream_t)stream;
   const WsView w = view(p, ws);
   // loss pass with ahat (and tau_used) at theta
@@ -1049,11 +1052,34 @@ int mtgp_predict_net(const mtgp_plan* p, const double* theta, const uint32_t* sh
   double* lam = reinterpret_cast<double*>(sb);
   double* wbuf = reinterpret_cast<double*>(sb + o_w);
   uint32_t* shd = reinterpret_cast<uint32_t*>(sb + o_sh);
+  const bool lat = p->family == MTGP_LAT;
   std::vector<uint32_t> sh((size_t)p->T * p->d);
   for (int u = 0; u < p->T; u++)
-    for (int j = 0; j < p->d; j++) sh[(size_t)u * p->d + j] = shift_star[j] ^ p->shift[(size_t)u * p->d + j];
+    for (int j = 0; j < p->d; j++) {
+      const uint32_t a = shift_star[j], b = p->shift[(size_t)u * p->d + j];
+      sh[(size_t)u * p->d + j] = lat ? a - b : a ^ b;
+    }
   LAUNCH_OK(launch_prednet_shifts(sh.data(), (int)sh.size(), shd, st));
   const KDesc kd = p->kd();
+  if (lat) {
+    const int64_t ns = (int64_t)1 << m_star;
+    for (int u = 0; u < p->T; u++) {
+      const int L = m_star > p->m[u] ? m_star : p->m[u];
+      cx<double>* col = reinterpret_cast<cx<double>*>(lam + pn.col_off[u]);
+      LAUNCH_OK(launch_lat_forward<double, double>(LAT_SRC_GEN, col, col, (int64_t)1 << L, 1, L,
+                                                   nullptr, 0, 1.0, p->d_gen,
+                                                   shd + (size_t)u * p->d, w.P, kd, st));
+    }
+    double* wwork = wbuf + 2 * ns * p->T;
+    double* ureal = wwork + 2 * ns * p->T;
+    LAUNCH_OK(launch_prednet_lat_fold(lam, pn, w.ahat, w.P, wbuf, st));
+    LAUNCH_OK(launch_lat_adjoint<double, double>(
+        LAT_SINK_REAL, reinterpret_cast<const cx<double>*>(wbuf),
+        reinterpret_cast<cx<double>*>(wwork), ureal, ns, p->T, m_star, 1, 1.0, p->d_gen, shd, w.P,
+        kd, nullptr, st));
+    LAUNCH_OK(launch_prednet_lat_out(ureal, pn, w.P, mean, st));
+    return MTGP_OK;
+  }
   for (int u = 0; u < p->T; u++) {
     const int L = m_star > p->m[u] ? m_star : p->m[u];
     double* col = lam + pn.col_off[u];

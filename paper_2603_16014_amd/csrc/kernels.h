@@ -258,5 +258,9 @@ int launch_prednet_fold(const double* lam, const PredNet& pn, const double* ahat
                         double* w, hipStream_t st);
 int launch_prednet_out(const double* w, const PredNet& pn, const Params* P, double* mean,
                        hipStream_t st);
+int launch_prednet_lat_fold(const double* lam, const PredNet& pn, const double* ahat,
+                            const Params* P, double* w, hipStream_t st);
+int launch_prednet_lat_out(const double* ureal, const PredNet& pn, const Params* P, double* mean,
+                           hipStream_t st);
 
 }  // namespace mtgp

@@ -344,15 +344,19 @@ def test_not_pd_reported():
 
 
 # -------------------------------------------------------- structured test net
-@pytest.mark.parametrize("m,m_star,precision", [
-    ([8, 8], 6, "fp64"), ([8, 8], 10, "fp64"), ([8, 8], 8, "fp64"),
-    ([8, 6, 4], 5, "fp64"), ([8, 6, 4], 9, "mixed"), ([7, 7, 7], 4, "mixed")])
-def test_predict_net_against_oracle(m, m_star, precision):
-    w = tiny("dseq", len(m), m, 3, seed=71, xi=1e-3)
-    say("predict_net", m, m_star, precision)
+@pytest.mark.parametrize("family,m,m_star,precision", [
+    ("dseq", [8, 8], 6, "fp64"), ("dseq", [8, 8], 10, "fp64"), ("dseq", [8, 8], 8, "fp64"),
+    ("dseq", [8, 6, 4], 5, "fp64"), ("dseq", [8, 6, 4], 9, "mixed"), ("dseq", [7, 7, 7], 4, "mixed"),
+    ("lat", [8, 8], 6, "fp64"), ("lat", [8, 8], 10, "fp64"), ("lat", [8, 8], 8, "fp64"),
+    ("lat", [8, 6, 4], 5, "fp64"), ("lat", [8, 6, 4], 9, "mixed"), ("lat", [7, 7, 7], 0, "fp64"),
+    ("lat", [12, 9], 13, "fp64"), ("lat", [11, 11], 10, "mixed")])
+def test_predict_net_against_oracle(family, m, m_star, precision):
+    w = tiny(family, len(m), m, 3, seed=71, xi=1e-3)
+    say("predict_net", family, m, m_star, precision)
     rng = np.random.default_rng(9)
     shift_star = workloads.random_shifts(rng, 1, w.d)[0]
-    Xs = points.dseq_points(w.gen, 1 << m_star, shift_star)
+    Xs = (points.dseq_points(w.gen, 1 << m_star, shift_star) if family == "dseq"
+          else points.lattice_points(w.gen, 1 << m_star, shift_star))
     ref = oracle_for(w, want_grad=False)
     from oracle import dense
     mu_ref = dense.posterior_mean(w, ref["y"], Xs, X=ref["X"], res=ref["res"])
