@@ -248,8 +248,8 @@ int mtgp_predict(const mtgp_plan* plan, const double* theta, const uint32_t* xs,
  * mean[2^m_star][T].  Uses the cross-block structure of Theorem "Fast MTGP
  * computations" for each (test net, task) pair (for lattices: a cyclic
  * convolution on the finer of the two lattices, folded onto the test
- * frequencies), O(N log N + T n* log n*) instead of O(M N d).  `scratch` is a device buffer of
- * mtgp_predict_net_scratch_bytes(plan, m_star) bytes.  Requires
+ * frequencies), O(N log N + T n* log n*) instead of O(M N d).  `scratch` is
+ * a device buffer of mtgp_predict_net_scratch_bytes(plan, m_star) bytes.  Requires
  * mtgp_set_data; 0 <= m_star <= 30. */
 size_t mtgp_predict_net_scratch_bytes(const mtgp_plan* plan, int32_t m_star);
 int mtgp_predict_net(const mtgp_plan* plan, const double* theta, const uint32_t* shift_star,
@@ -261,8 +261,11 @@ int mtgp_predict_net(const mtgp_plan* plan, const double* theta, const uint32_t*
  * mtgp_nll_grad; NULL: loss only).  tau is the plan's fixed means or, when
  * profiled, the optimal GCV means (Eq. MTGP_optimal_tau), which for equal
  * sizes are the per-task sample means (written to tau_hat if non-NULL).
- * Equal sizes only: nested plans return MTGP_ENOTSUP.  Two passes over the
- * spectrum (q and s first); same workspace as mtgp_nll_grad. */
+ * Equal sizes: two passes over the spectrum (q and s first).  Nested sizes
+ * (MTGP_ELIM_SPARSE only): the loss and means through the fill-free
+ * elimination, s from the diagonal of its selected inverse; a non-NULL grad
+ * returns MTGP_ENOTSUP (the gradient needs Lambda^-2 off Lambda's pattern).
+ * Same workspace as mtgp_nll_grad. */
 int mtgp_gcv(const mtgp_plan* plan, const double* theta, double* out3, double* grad,
              double* tau_hat, void* ws, void* stream);
 

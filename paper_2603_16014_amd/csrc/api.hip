@@ -440,6 +440,27 @@ int run_gcv(const mtgp_plan* p, const double* theta, double* out3, double* grad,
   return MTGP_OK;
 }
 
+// GCV loss at nested sizes (no gradient): the fill-free elimination with
+// the inverse's diagonal, GCV means from residue class 0.
+template <typename CR, typename SR>
+int run_gcv_nested(const mtgp_plan* p, const double* theta, double* out3, double* tau_hat,
+                   void* ws, hipStream_t st) {
+  const WsView w = view(p, ws);
+  KDesc kd = p->kd();
+  kd.gcv = 1;
+  LAUNCH_OK(launch_prep(theta, w.P, kd, w.status, st));
+  int rc = forward_columns<CR, SR>(p, w, st);
+  if (rc) return rc;
+  SR* spec = reinterpret_cast<SR*>(w.cols);
+  LAUNCH_OK(launch_zerofill_gcv<SR>(spec, p->a1, p->N, w.P, kd.family, w.yhat, w.a1a, w.logs,
+                                    w.sp, w.status, st));
+  const int64_t nb = zf_final_blocks(p->N);
+  LAUNCH_OK(launch_colsum(w.sp, nb, solve_ns(p->T), w.sp2, COLSUM_BLOCKS, st));
+  LAUNCH_OK(launch_finalize(w.sp2, COLSUM_BLOCKS, nullptr, p->d_colinfo, p->ncol, nullptr, 0,
+                            w.yhat, p->n[0], w.P, kd, out3, nullptr, tau_hat, st));
+  return MTGP_OK;
+}
+
 int dispatch_loss(const mtgp_plan* p, const double* theta, double* out3, double* grad,
                   double* tau_hat, void* ws, hipStream_t st, bool want_ahat) {
   switch (p->precision) {
@@ -1097,8 +1118,15 @@ int mtgp_predict_net(const mtgp_plan* p, const double* theta, const uint32_t* sh
 int mtgp_gcv(const mtgp_plan* p, const double* theta, double* out3, double* grad,
              double* tau_hat, void* ws, void* stream) {
   if (!p || !theta || !out3 || !ws) return MTGP_EINVAL;
-  if (!p->equal) return MTGP_ENOTSUP;
+  if (!p->equal && (grad || p->elim != MTGP_ELIM_SPARSE)) return MTGP_ENOTSUP;
   hipStream_t st = (hipStream_t)stream;
+  if (!p->equal) {
+    switch (p->precision) {
+      case MTGP_FP64: return run_gcv_nested<double, double>(p, theta, out3, tau_hat, ws, st);
+      case MTGP_MIXED: return run_gcv_nested<double, float>(p, theta, out3, tau_hat, ws, st);
+      default: return run_gcv_nested<float, float>(p, theta, out3, tau_hat, ws, st);
+    }
+  }
   switch (p->precision) {
     case MTGP_FP64: return run_gcv<double, double>(p, theta, out3, grad, tau_hat, ws, st);
     case MTGP_MIXED: return run_gcv<double, float>(p, theta, out3, grad, tau_hat, ws, st);

@@ -221,6 +221,10 @@ inline int64_t zf_final_blocks(int64_t N) {
   return b < ZF_FINAL_BLOCKS ? b : ZF_FINAL_BLOCKS;
 }
 template <typename SR>
+int launch_zerofill_gcv(SR* cols, const Alg1Desc& A1, int64_t N, Params* P, int family,
+                        const double* yhat, z2* buf, double* logs, double* partials, int* status,
+                        hipStream_t st);
+template <typename SR>
 int launch_zerofill(SR* cols, const Alg1Desc& A1, int64_t N, Params* P, int family, bool grad,
                     const double* yhat, z2* buf, double* logs, double* ahat, double* partials,
                     int* status, hipStream_t st);

@@ -436,9 +436,31 @@ def test_gcv_against_oracle(family, m, profile, precision):
     assert gb is None and abs(float(out3b[2]) - o[2]) <= 1e-12 * o[2]
 
 
-def test_gcv_nested_sizes_not_supported():
-    w = tiny("dseq", 2, [6, 5], 2, seed=52)
-    plan = mt.Plan.from_workload(w, "fp64")
-    plan.set_data(torch.zeros(w.N, dtype=torch.float64, device="cuda"))
+@pytest.mark.parametrize("family,m,profile,precision", [
+    ("dseq", [7, 5, 4], True, "fp64"), ("dseq", [7, 5, 4], False, "fp64"),
+    ("dseq", [8, 8, 6, 3], True, "mixed"), ("lat", [7, 6, 4], True, "fp64"),
+    ("lat", [7, 6, 4], False, "mixed"), ("dseq", [6, 0], True, "fp64")])
+def test_gcv_nested_loss_against_oracle(family, m, profile, precision):
+    """Nested sizes: GCV loss and GCV means through the fill-free elimination;
+    the gradient is refused."""
+    import workloads as wl
+    w = wl.with_theta(tiny(family, len(m), m, 3, seed=53, profile=profile),
+                      tau=np.linspace(-0.2, 0.3, len(m)))
+    say("gcv nested", family, m, profile, precision)
+    X = points.task_points(w)
+    from oracle import dense
+    y = dense.targets(w, np.random.default_rng(w.seed + 1000), X)
+    res = dense.gcv(w, y, X=X)
+    plan = mt.Plan.from_workload(w, precision)
+    plan.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
+    theta = plan.pack_theta(w.theta)
+    out3, g, tau = plan.gcv(theta, grad=False)
+    torch.cuda.synchronize()
+    assert plan.status()[0] == 0 and g is None
+    o = out3.cpu().numpy()
+    tolL = 1e-10 if precision == "fp64" else 1e-5
+    assert abs(o[2] - res["L"]) < tolL * res["L"], (o, res["L"])
+    assert abs(o[0] - res["q"]) < tolL * res["q"] and abs(o[1] - res["s"]) < tolL * res["s"]
+    np.testing.assert_allclose(tau.cpu().numpy(), res["tau_hat"], rtol=tolL * 100, atol=1e-12)
     with pytest.raises(mt._lib.MTGPError):
-        plan.gcv(plan.pack_theta(w.theta))
+        plan.gcv(theta, grad=True)
