@@ -26,12 +26,17 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
                                                       const uint32_t* __restrict__ colshift,
                                                       const Params* __restrict__ P, int d) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ Kap2Entry k2tab[uses_kap2_table<Real, KT>() ? 33 : 1];
   Real* lds = reinterpret_cast<Real*>(smem);
   const int nb = 1 << LB;
   const int col = blockIdx.y;
   const uint32_t i0 = (uint32_t)blockIdx.x << LB;
   const uint32_t t = threadIdx.x;
   const int stride = lds_stride(LB);
+  if constexpr (uses_kap2_table<Real, KT>()) {
+    fill_kap2_table(k2tab);
+    __syncthreads();
+  }
   Digits<FAM_DSEQ, D> dg;
   Real sc[D];  // eta K = sc kappa; padding slots: sc = 0, factor exactly 1
 #pragma unroll
@@ -46,7 +51,7 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
     for (int k = 0; k < E; k++) {
       Real c = gam;
 #pragma unroll
-      for (int j = 0; j < D; j++) c *= fma(sc[j], kappa<Real, KT>(dg.u(j), P), (Real)1);
+      for (int j = 0; j < D; j++) c *= fma(sc[j], kappa_t<Real, KT>(dg.u(j), P, k2tab), (Real)1);
       v[Digits<FAM_DSEQ, D>::elem(k)] = c;
       if (k + 1 < E) dg.advance(gen, d, k);
     }
@@ -65,7 +70,7 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
       for (int k = 0; k < En; k++) {
         Real c = gam;
 #pragma unroll
-        for (int j = 0; j < D; j++) c *= fma(sc[j], kappa<Real, KT>(dg.u(j), P), (Real)1);
+        for (int j = 0; j < D; j++) c *= fma(sc[j], kappa_t<Real, KT>(dg.u(j), P, k2tab), (Real)1);
         lds[lds_at(0, stride, (int)t + 256 * dg.elem(k))] = c;
         if (k + 1 < En) dg.advance(gen, d, k);
       }
@@ -99,7 +104,8 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
 template <typename Real, int KT, int D>
 __device__ inline void adj_element(const Digits<kt_family(KT), D>& dg, Real wv, Real gam,
                                    const Real (&sc)[D], const Params* __restrict__ P,
-                                   Real (&acc)[D + 1], Real (&acc_b)[4]) {
+                                   const Kap2Entry* k2tab, Real (&acc)[D + 1],
+                                   Real (&acc_b)[4]) {
   constexpr bool ADAPT = KT == KT_DSIA;
   Real kap[D], f[D];
   Real Ka[ADAPT ? D : 1][4];
@@ -110,7 +116,7 @@ __device__ inline void adj_element(const Digits<kt_family(KT), D>& dg, Real wv, 
       kap[j] = RT<Real>::bw(P, 0) * Ka[j][0] + RT<Real>::bw(P, 1) * Ka[j][1] +
                RT<Real>::bw(P, 2) * Ka[j][2] + RT<Real>::bw(P, 3) * Ka[j][3];
     } else {
-      kap[j] = kappa<Real, KT>(dg.u(j), P);
+      kap[j] = kappa_t<Real, KT>(dg.u(j), P, k2tab);
     }
     f[j] = fma(sc[j], kap[j], (Real)1);
   }
@@ -149,6 +155,7 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
   constexpr int NQ = D + 5;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[4 * NQ];
+  __shared__ Kap2Entry k2tab[uses_kap2_table<Real, KT>() ? 33 : 1];
   Real* lds = reinterpret_cast<Real*>(smem);
   const int nb = 1 << LB;
   const int col = blockIdx.y;
@@ -156,6 +163,8 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
   const uint32_t t = threadIdx.x;
   const TIn* w = base + (size_t)col * col_stride + i0;
   const int stride = lds_stride(LB);
+  // the barriers of the transform below order the table's fill before its use
+  if constexpr (uses_kap2_table<Real, KT>()) fill_kap2_table(k2tab);
   if (LB == 12) {
     // 16 loads in flight per thread, index bits 8 .. 11 in registers, bits
     // 0 .. 7 in two LDS rounds
@@ -192,7 +201,7 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
     dg.load_columns(gen, d);
     for (int k = 0; k < En; k++) {
       const Real wv = lds[lds_at(0, stride, (int)t + 256 * dg.elem(k))];
-      adj_element<Real, KT, D>(dg, wv, gam, sc, P, acc, acc_b);
+      adj_element<Real, KT, D>(dg, wv, gam, sc, P, k2tab, acc, acc_b);
       if (k + 1 < En) dg.advance_lanes(k);
     }
 #pragma unroll
