@@ -8,8 +8,8 @@
 // input, bit-reversed output, so the spectrum holds frequency f at position
 // bitrev_m(f) (frequency 0 at position 0; the per-frequency algebra does not
 // care about the order, and the data transform uses the same layout).  The
-// stages of the high index bits run first, in register passes of 4 bits:
-// a thread owns the 2^hb values strided by 2^lo that share its low index, so
+// stages of the high index bits run first, in register passes of 5 bits:
+// a thread owns the 32 values strided by 2^lo that share its low index, so
 // every load and store of a wave is 64 consecutive elements.  The twiddle of
 // the stage of bit k = lo + s on the pair of register slot r (r < 2^s) is
 //   e^{-i pi (low + r 2^lo) / 2^k} = e^{-i pi low / 2^k} e^{-i pi r / 2^s},
@@ -423,12 +423,14 @@ __global__ __launch_bounds__(256) void lat_dit_lds_kernel(
 // host side
 // ---------------------------------------------------------------------------
 // Schedule: m <= 12 is one LDS pass; otherwise the low L bits in LDS, L in
-// [8, 11] with m - L a multiple of 4, and the other bits in 4-bit register
-// passes (5-bit passes need more than 168 VGPRs in FP64 and lose occupancy).
-constexpr int kLatHB = 4;
+// [8, 12] with m - L a multiple of 5, and the other bits in 5-bit register
+// passes (in FP64 a 5-bit pass needs 200-256 VGPRs, 1-2 waves per SIMD, but
+// 32 loads in flight per thread; measured faster than 4-bit passes at
+// 3 waves per SIMD, which need one pass more at 2^24).
+constexpr int kLatHB = 5;
 struct LatSched {
   int L;   // LDS bits
-  int np;  // register passes; pass q covers the bits [L + 4 q, L + 4 q + 4)
+  int np;  // register passes; pass q covers the bits [L + 5 q, L + 5 q + 5)
 };
 static LatSched lat_sched(int m) {
   LatSched s{};
@@ -436,8 +438,8 @@ static LatSched lat_sched(int m) {
     s.L = m;
     return s;
   }
-  s.L = 8 + (m - 8) % 4;
-  s.np = (m - s.L) / 4;
+  s.L = 8 + (m - 8) % kLatHB;
+  s.np = (m - s.L) / kLatHB;
   return s;
 }
 static size_t lat_lds_bytes(int L, size_t cbytes) {
