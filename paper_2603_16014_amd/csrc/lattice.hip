@@ -420,6 +420,168 @@ __global__ __launch_bounds__(256) void lat_dit_lds_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// wave passes over the low L in {8, 9, 10} bits of a multi-pass transform:
+// grid (2^(m - L) / 4, nvec), 256 threads; wave w of a block owns the
+// sub-block of 2^L consecutive elements 4 blockIdx.x + w and keeps
+// E = 2^(L - 6) of them per lane.  Rounds of R = L - 6 bits (the last one
+// ragged when R does not divide L) run their radix-2 stages in registers; the
+// wave's LDS region re-gathers the values between rounds.  In a round over
+// the bits [lo, lo + r), value k = g 2^r + kk of a lane is element
+//   (hi << (lo + r)) | (kk << lo) | low,  (hi, low) from q = lane + 64 g,
+// so the top round's elements (kk << lo) | lane, and hence the loads of the
+// forward and the stores of the adjoint, are coalesced.
+// ---------------------------------------------------------------------------
+template <int L>
+struct WavePass {
+  static constexpr int R = L - 6, E = 1 << R;
+  static constexpr int NR = (L + R - 1) / R;  // rounds
+  // forward rounds from the top: bits [max(hi - R, 0), hi), hi = L - R q;
+  // adjoint rounds from the bottom: bits [R q, min(R q + R, L))
+  __device__ static inline int dif_lo(int q) { return L - R * q - R > 0 ? L - R * q - R : 0; }
+  __device__ static inline int dif_bits(int q) { return L - R * q - dif_lo(q); }
+  __device__ static inline int dit_lo(int q) { return R * q; }
+  __device__ static inline int dit_bits(int q) { return L - R * q < R ? L - R * q : R; }
+  __device__ static inline int elem(int lane, int k, int lo, int r) {
+    const int g = k >> r, kk = k & ((1 << r) - 1);
+    const int q = lane + 64 * g;
+    const int low = q & ((1 << lo) - 1), hi = q >> lo;
+    return (hi << (lo + r)) | (kk << lo) | low;
+  }
+};
+
+template <typename CR, typename SR, int L>
+__global__ __launch_bounds__(256) void lat_dif_wave_kernel(const cx<CR>* __restrict__ work,
+                                                           cx<SR>* __restrict__ out,
+                                                           int64_t vstride, double scale) {
+  using WP = WavePass<L>;
+  constexpr int E = WP::E, R = WP::R;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ cx<double> tmp[96];
+  const int stride = lds_stride(L);
+  cx<CR>* tw = reinterpret_cast<cx<CR>*>(smem);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  cx<CR>* sub = tw + (1 << (L - 1)) + wv * stride;
+  const int64_t b0 = ((int64_t)blockIdx.x * 4 + wv) << L;
+  const cx<CR>* in = work + (size_t)blockIdx.y * vstride + b0;
+  fill_twiddles<CR>(tw, L, tmp);
+  cx<CR> v[E];
+  for (int q = 0; q < WP::NR; q++) {
+    const int lo = WP::dif_lo(q), r = WP::dif_bits(q);
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+      const int i = WP::elem(lane, k, lo, r);
+      v[k] = q == 0 ? in[i] : sub[lds_at(0, stride, i)];
+    }
+#pragma unroll
+    for (int sb = R - 1; sb >= 0; sb--) {
+      if (sb >= r) continue;
+#pragma unroll
+      for (int k = 0; k < E; k++) {
+        if (k & (1 << sb)) continue;
+        const int i = WP::elem(lane, k, lo, r), kb = lo + sb;
+        const cx<CR> w = tw[(i & ((1 << kb) - 1)) << (L - 1 - kb)];
+        const cx<CR> A = v[k], C = v[k + (1 << sb)];
+        v[k] = cadd(A, C);
+        v[k + (1 << sb)] = cmul<CR>(csub(A, C), w);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < E; k++) sub[lds_at(0, stride, WP::elem(lane, k, lo, r))] = v[k];
+    __syncthreads();
+  }
+  cx<SR>* o = out + (size_t)blockIdx.y * vstride + b0;
+#pragma unroll
+  for (int k = 0; k < E; k++) {
+    const cx<CR> val = sub[lds_at(0, stride, lane + 64 * k)];
+    o[lane + 64 * k] = {(SR)(val.x * (CR)scale), (SR)(val.y * (CR)scale)};
+  }
+}
+
+template <typename CR, typename SR, int L>
+__global__ __launch_bounds__(256) void lat_dit_wave_kernel(const cx<SR>* __restrict__ spec,
+                                                           cx<CR>* __restrict__ work,
+                                                           int64_t vstride, int conj_in) {
+  using WP = WavePass<L>;
+  constexpr int E = WP::E, R = WP::R;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ cx<double> tmp[96];
+  const int stride = lds_stride(L);
+  cx<CR>* tw = reinterpret_cast<cx<CR>*>(smem);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  cx<CR>* sub = tw + (1 << (L - 1)) + wv * stride;
+  const int64_t b0 = ((int64_t)blockIdx.x * 4 + wv) << L;
+  const cx<SR>* in = spec + (size_t)blockIdx.y * vstride + b0;
+#pragma unroll
+  for (int k = 0; k < E; k++) {
+    const cx<SR> w = in[lane + 64 * k];
+    sub[lds_at(0, stride, lane + 64 * k)] = {(CR)w.x, conj_in ? -(CR)w.y : (CR)w.y};
+  }
+  fill_twiddles<CR>(tw, L, tmp);  // ends with a barrier
+  cx<CR> v[E];
+  cx<CR>* o = work + (size_t)blockIdx.y * vstride + b0;
+  for (int q = 0; q < WP::NR; q++) {
+    const int lo = WP::dit_lo(q), r = WP::dit_bits(q);
+#pragma unroll
+    for (int k = 0; k < E; k++) v[k] = sub[lds_at(0, stride, WP::elem(lane, k, lo, r))];
+#pragma unroll
+    for (int sb = 0; sb < R; sb++) {
+      if (sb >= r) continue;
+#pragma unroll
+      for (int k = 0; k < E; k++) {
+        if (k & (1 << sb)) continue;
+        const int i = WP::elem(lane, k, lo, r), kb = lo + sb;
+        const cx<CR> w = tw[(i & ((1 << kb) - 1)) << (L - 1 - kb)];
+        const cx<CR> A = v[k], C = cmul<CR>(v[k + (1 << sb)], w);
+        v[k] = cadd(A, C);
+        v[k + (1 << sb)] = csub(A, C);
+      }
+    }
+    if (q + 1 < WP::NR) {
+#pragma unroll
+      for (int k = 0; k < E; k++) sub[lds_at(0, stride, WP::elem(lane, k, lo, r))] = v[k];
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int k = 0; k < E; k++) o[WP::elem(lane, k, lo, r)] = v[k];
+    }
+  }
+}
+
+static size_t wave_lds_bytes(int L, size_t cbytes) {
+  return ((size_t)4 * lds_stride(L) + (1u << (L - 1))) * cbytes;
+}
+
+template <typename CR, typename SR>
+static void launch_dif_wave(int L, dim3 grid, hipStream_t st, const cx<CR>* work, cx<SR>* spec,
+                            int64_t vstride, double scale) {
+  const size_t lds = wave_lds_bytes(L, sizeof(cx<CR>));
+  if (L == 8)
+    hipLaunchKernelGGL((lat_dif_wave_kernel<CR, SR, 8>), grid, dim3(256), lds, st, work, spec,
+                       vstride, scale);
+  else if (L == 9)
+    hipLaunchKernelGGL((lat_dif_wave_kernel<CR, SR, 9>), grid, dim3(256), lds, st, work, spec,
+                       vstride, scale);
+  else
+    hipLaunchKernelGGL((lat_dif_wave_kernel<CR, SR, 10>), grid, dim3(256), lds, st, work, spec,
+                       vstride, scale);
+}
+
+template <typename CR, typename SR>
+static void launch_dit_wave(int L, dim3 grid, hipStream_t st, const cx<SR>* spec, cx<CR>* work,
+                            int64_t vstride, int conj_in) {
+  const size_t lds = wave_lds_bytes(L, sizeof(cx<CR>));
+  if (L == 8)
+    hipLaunchKernelGGL((lat_dit_wave_kernel<CR, SR, 8>), grid, dim3(256), lds, st, spec, work,
+                       vstride, conj_in);
+  else if (L == 9)
+    hipLaunchKernelGGL((lat_dit_wave_kernel<CR, SR, 9>), grid, dim3(256), lds, st, spec, work,
+                       vstride, conj_in);
+  else
+    hipLaunchKernelGGL((lat_dit_wave_kernel<CR, SR, 10>), grid, dim3(256), lds, st, spec, work,
+                       vstride, conj_in);
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 // Schedule: m <= 12 is one LDS pass; otherwise the low L bits in LDS, L in
@@ -496,6 +658,10 @@ int launch_lat_forward(int src, cx<CR>* work, cx<SR>* spec, int64_t vstride, int
                                     P, kd.d);
     }
   }
+  if (s.np > 0 && s.L <= 10) {  // multi-pass: the wave pass over the low bits
+    launch_dif_wave<CR, SR>(s.L, dim3(1u << (m - s.L - 2), nvec), st, work, spec, vstride, scale);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
   const dim3 grid2(1u << (m - s.L), nvec);
   const size_t lds = lat_lds_bytes(s.L, sizeof(cx<CR>));
 #define FL(KTV, SRCV)                                                                          \
@@ -523,12 +689,16 @@ int launch_lat_adjoint(int sink, const cx<SR>* spec, cx<CR>* work, double* real_
   const LatTab tab = lat_tab();
   const dim3 gridL(1u << (m - s.L), nvec);
   const size_t lds = lat_lds_bytes(s.L, sizeof(cx<CR>));
+  const bool wave = s.np > 0 && s.L <= 10;  // multi-pass: the wave pass over the low bits
+  if (wave) launch_dit_wave<CR, SR>(s.L, dim3(1u << (m - s.L - 2), nvec), st, spec, work, vstride,
+                                    conj_in);
 #define AL(DD, KTV, SINKV)                                                                    \
   hipLaunchKernelGGL((lat_dit_lds_kernel<CR, SR, SINKV, KTV, DD>), gridL, dim3(256), lds, st, \
                      spec, work, real_out, vstride, m, s.L, conj_in, scale, gen, colshift, P, \
                      kd.d, partials)
 #define AL_D(DD, KTV) AL(DD, KTV, SINK_REDUCE)
-  if (s.np > 0) {
+  if (wave) {
+  } else if (s.np > 0) {
     AL(2, KT_SI1, SINK_WORK);
   } else if (sink == SINK_REAL) {
     AL(2, KT_SI1, SINK_REAL);
