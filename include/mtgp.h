@@ -203,7 +203,8 @@ int mtgp_kernel_cols(const mtgp_plan* plan, const double* theta, void* cols, voi
  * vectors of length 2^log2n, natural (Sylvester) order:
  * X_f = sum_i (-1)^popcount(f & i) x_i  (the V^dagger of Theorem "Fast GP
  * computations" for DSEQ, up to the factor 2^(-log2n/2)).  dtype is
- * MTGP_DTYPE_F64 or MTGP_DTYPE_F32; 0 <= log2n <= 30. */
+ * MTGP_DTYPE_F64 or MTGP_DTYPE_F32; 0 <= log2n <= 30; batch 0 does nothing
+ * (x may then be NULL). */
 int mtgp_fwht(void* x, int64_t batch, int32_t log2n, int32_t dtype, void* stream);
 
 /* Unnormalised forward DFT X_f = sum_j x_j e^{-2 pi i f j / n} of `batch`
@@ -214,7 +215,8 @@ int mtgp_fwht(void* x, int64_t batch, int32_t log2n, int32_t dtype, void* stream
  * computations" for lattices times sqrt(n).  dtype as for mtgp_fwht;
  * 0 <= log2n <= 30, batch <= 65535.  For log2n > 12 the multi-pass transform
  * needs `scratch` with room for batch * n complex values of dtype (else it
- * may be NULL); scratch and X must not overlap. */
+ * may be NULL); scratch and X must not overlap.  batch 0 does nothing (the
+ * pointers may then be NULL). */
 int mtgp_fft(const void* x, void* X, void* scratch, int64_t batch, int32_t log2n, int32_t dtype,
              int32_t bitrev_input, void* stream);
 
@@ -238,7 +240,7 @@ int mtgp_nll_grad(const mtgp_plan* plan, const double* theta, double* out3, doub
 /* Posterior mean (Eq. MTGP_post_mean_cov) at M arbitrary inputs xs[M][d]
  * (digits): mean[M][T], mean[m][t] = tau_t + sum_t' R_tt' sum_k
  * Q(x*_m, x_t'k) alpha_t'k with alpha = Ktilde^-1 (y - E^T tau).  Direct
- * sum, O(M N d).  Requires mtgp_set_data. */
+ * sum, O(M N d).  Requires mtgp_set_data.  M = 0 does nothing. */
 int mtgp_predict(const mtgp_plan* plan, const double* theta, const uint32_t* xs, int64_t M,
                  double* mean, void* ws, void* stream);
 

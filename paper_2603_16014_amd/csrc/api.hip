@@ -873,7 +873,10 @@ int mtgp_kernel_cols(const mtgp_plan* p, const double* theta, void* cols, void* 
 }
 
 int mtgp_fwht(void* x, int64_t batch, int32_t log2n, int32_t dtype, void* stream) {
-  if (!x || batch < 0 || log2n < 0 || log2n > 30) return MTGP_EINVAL;
+  if (batch < 0 || log2n < 0 || log2n > 30) return MTGP_EINVAL;
+  if (dtype != MTGP_DTYPE_F64 && dtype != MTGP_DTYPE_F32) return MTGP_EINVAL;
+  if (batch == 0) return MTGP_OK;
+  if (!x) return MTGP_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = (int64_t)1 << log2n;
   const Sched sc;
@@ -887,11 +890,11 @@ int mtgp_fwht(void* x, int64_t batch, int32_t log2n, int32_t dtype, void* stream
 
 int mtgp_fft(const void* x, void* X, void* scratch, int64_t batch, int32_t log2n, int32_t dtype,
              int32_t bitrev_input, void* stream) {
-  if (!x || !X || batch < 0 || batch > 65535 || log2n < 0 || log2n > 30) return MTGP_EINVAL;
-  const bool single = lat_single_pass(log2n);
-  if (!single && !scratch) return MTGP_EINVAL;
+  if (batch < 0 || batch > 65535 || log2n < 0 || log2n > 30) return MTGP_EINVAL;
   if (dtype != MTGP_DTYPE_F64 && dtype != MTGP_DTYPE_F32) return MTGP_EINVAL;
   if (batch == 0) return MTGP_OK;
+  const bool single = lat_single_pass(log2n);
+  if (!x || !X || (!single && !scratch)) return MTGP_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const int src = bitrev_input ? LAT_SRC_Y : LAT_SRC_X;
   const int64_t n = (int64_t)1 << log2n;
@@ -963,6 +966,7 @@ int mtgp_nll_grad(const mtgp_plan* p, const double* theta, double* out3, double*
 int mtgp_predict(const mtgp_plan* p, const double* theta, const uint32_t* xs, int64_t M,
                  double* mean, void* ws, void* stream) {
   if (!p || !theta || !ws || M < 0 || (M > 0 && (!xs || !mean))) return MTGP_EINVAL;
+  if (M == 0) return MTGP_OK;
     hipStream_t st = (hipStream_t)stream;
   const WsView w = view(p, ws);
   int rc = dispatch_loss(p, theta, w.misc, nullptr, nullptr, ws, st, true);
