@@ -19,6 +19,7 @@ FP64, MIXED, F32 = 0, 1, 2
 FAMILIES = {"dseq": DSEQ, "lat": LAT, DSEQ: DSEQ, LAT: LAT}
 PRECISIONS = {"fp64": FP64, "mixed": MIXED, "f32": F32, FP64: FP64, MIXED: MIXED, F32: F32}
 ELIMINATIONS = {"sparse": 0, "alg1": 1, 0: 0, 1: 1}  # nested unequal sizes
+DEFAULT_SCHEDULE = (12, 6, 36864)  # the library's default transform schedule
 LOG_KEYS = ("gamma", "eta", "b", "xi", "zeta")
 
 
@@ -75,10 +76,13 @@ class Plan:
         _lib.check(self.lib.mtgp_plan_create(ctypes.byref(des), self.precision, ctypes.byref(h)),
                    "mtgp_plan_create")
         self.h = h
+        self.schedule = DEFAULT_SCHEDULE
         if schedule is not None:
             a, b, tile = schedule
             _lib.check(self.lib.mtgp_plan_set_schedule(h, int(a), int(b), int(tile)),
                        "mtgp_plan_set_schedule")
+            self.schedule = (int(a), int(b), int(tile))
+        self.overlap = 4
         if elimination is not None:
             _lib.check(self.lib.mtgp_plan_set_elimination(h, ELIMINATIONS[elimination]),
                        "mtgp_plan_set_elimination")
@@ -202,6 +206,21 @@ class Plan:
     def set_overlap(self, chunks: int):
         """Chunks of the overlapped digital-net passes (1 = no overlap)."""
         _lib.check(self.lib.mtgp_plan_set_overlap(self.h, int(chunks)), "mtgp_plan_set_overlap")
+        self.overlap = int(chunks)
+
+    def set_schedule(self, pass_a_bits: int, pass_b_bits: int, pass_b_tile_bytes: int):
+        """Transform schedule of the digital-net passes (mtgp_plan_set_schedule).
+        The workspace grows if the new schedule needs more; the data transform
+        of set_data is then formed again."""
+        _lib.check(self.lib.mtgp_plan_set_schedule(self.h, int(pass_a_bits), int(pass_b_bits),
+                                                   int(pass_b_tile_bytes)),
+                   "mtgp_plan_set_schedule")
+        self.schedule = (int(pass_a_bits), int(pass_b_bits), int(pass_b_tile_bytes))
+        need = int(self.lib.mtgp_workspace_bytes(self.h))
+        if need > self.ws.numel():
+            self.ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+            if getattr(self, "_y", None) is not None:
+                self.set_data(self._y)
 
     def gcv(self, theta: torch.Tensor, grad=True):
         """GCV loss: (out3 = (q, s, L_GCV), gradient or None, tau_hat)."""
