@@ -81,3 +81,26 @@ def test_empty_inputs():
     torch.cuda.synchronize()
     assert X.numel() == 0
     assert plan.status() == (0, -1)
+
+
+@pytest.mark.parametrize("family,m,elimination", [("dseq", [6, 4], "sparse"), ("dseq", [6, 4], "alg1"),
+                                                  ("lat", [6, 4], "sparse"), ("lat", [5, 5], None)])
+def test_not_positive_definite_reported(family, m, elimination):
+    """A non-finite Lambda is reported through the status word (code -2 and
+    a frequency index) by every factorisation, and a valid call clears it."""
+    from paper_2603_16014_amd import mtgp as mt
+    w = tiny(family, len(m), m, 2, seed=86)
+    say("not PD", family, m, elimination)
+    ref = oracle_for(w, want_grad=False)
+    plan = mt.Plan.from_workload(w, elimination=elimination)
+    plan.set_data(torch.from_numpy(ref["y"]).cuda())
+    th = dict(w.theta)
+    th["eta"] = np.full(w.d, 1e300)
+    plan.nll(plan.pack_theta(th))
+    torch.cuda.synchronize()
+    code, bad = plan.status()
+    assert code == -2 and 0 <= bad < w.N
+    plan.nll(plan.pack_theta(w.theta))
+    torch.cuda.synchronize()
+    assert plan.status() == (0, -1)
+
