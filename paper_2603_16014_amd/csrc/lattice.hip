@@ -138,6 +138,35 @@ __device__ inline R lat_col_value(const uint32_t* __restrict__ gen, const uint32
   return c;
 }
 
+// eta K of the shift-invariant kernels in y = x (x - 1), x = u 2^-32:
+//   order 1: B2 = y + 1/6,   order 2: B4 = y^2 - 1/30,
+//   order 3: B6 = y^2 (y - 1/2) + 1/42,
+// so that eta K = fma(ka, p(y), kb) with per-dimension constants
+// ka = eta c_alpha, kb = eta c_alpha B_{2 alpha}(0) (c_alpha as in si_kern).
+template <typename R, int KT>
+struct SiFactor {
+  R ka, kb;
+  __device__ inline void init(R eta) {
+    if constexpr (KT == KT_SI1) {
+      ka = eta * (R)19.739208802178716;
+      kb = ka * (R)(1.0 / 6.0);
+    } else if constexpr (KT == KT_SI2) {
+      ka = eta * (R)-64.939394022668291;
+      kb = ka * (R)(-1.0 / 30.0);
+    } else {
+      ka = eta * (R)85.456817206693727;
+      kb = ka * (R)(1.0 / 42.0);
+    }
+  }
+  __device__ inline R eta_k(uint32_t u) const {
+    const R x = RT<R>::unit(u);
+    const R y = fma(x, x, -x);
+    if constexpr (KT == KT_SI1) return fma(ka, y, kb);
+    else if constexpr (KT == KT_SI2) return fma(ka, y * y, kb);
+    else return fma(ka, y * y * (y - (R)0.5), kb);
+  }
+};
+
 enum { SRC_GEN = LAT_SRC_GEN, SRC_Y = LAT_SRC_Y, SRC_X = LAT_SRC_X, SRC_WORK = 3 };
 enum { SINK_WORK = LAT_SINK_Z, SINK_REDUCE = LAT_SINK_REDUCE, SINK_REAL = LAT_SINK_REAL };
 
@@ -165,27 +194,33 @@ __device__ inline CR src_value(const void* y, int y_f32, int v, uint32_t j, int 
 template <typename CR, int KT, int D>
 struct LatReduce {
   CR acc[D + 1];
-  CR eta[D];
+  SiFactor<CR, KT> fk[D];
   CR gam;
-  uint32_t g[D], sh[D];
+  uint32_t u[D], step[D];
+  // digits of the thread's first element j0, advanced by step(j_step) per
+  // element (padding dimensions: eta = 0, factor exactly 1)
   __device__ inline void init(const uint32_t* __restrict__ gen, const uint32_t* __restrict__ s,
-                              int d, const Params* __restrict__ P) {
+                              int d, const Params* __restrict__ P, uint32_t j0, uint32_t j_step,
+                              int m) {
 #pragma unroll
     for (int q = 0; q < D; q++) {
       acc[q] = 0;
-      eta[q] = q < d ? RT<CR>::eta(P, q) : (CR)0;
-      g[q] = gen[q < d ? q : 0];
-      sh[q] = s[q < d ? q : 0];
+      fk[q].init(q < d ? RT<CR>::eta(P, q) : (CR)0);
+      const uint32_t g = gen[q < d ? q : 0];
+      u[q] = lat_z(g, j0, m) + s[q < d ? q : 0];
+      step[q] = lat_z(g, j_step, m);
     }
     acc[D] = 0;
     gam = RT<CR>::gamma(P);
   }
-  __device__ inline void add(CR wv, uint32_t j, int m, const Params* __restrict__ P) {
-    CR K[D], f[D], pre[D];
+  // adds the element at the current digits, then advances them
+  __device__ inline void add(CR wv) {
+    CR eK[D], f[D], pre[D];
 #pragma unroll
     for (int q = 0; q < D; q++) {
-      K[q] = kval<CR, KT>(lat_z(g[q], j, m) + sh[q], P);
-      f[q] = fma(eta[q], K[q], (CR)1);
+      eK[q] = fk[q].eta_k(u[q]);
+      f[q] = eK[q] + (CR)1;
+      u[q] += step[q];
     }
     CR run = gam * wv;
 #pragma unroll
@@ -197,7 +232,7 @@ struct LatReduce {
     CR suf = 1;
 #pragma unroll
     for (int q = D - 1; q >= 0; q--) {
-      acc[q] = fma(pre[q] * suf * eta[q], K[q], acc[q]);
+      acc[q] = fma(pre[q] * suf, eK[q], acc[q]);
       suf *= f[q];
     }
   }
@@ -252,13 +287,36 @@ __global__ __launch_bounds__(256) void lat_dif_reg_kernel(
   const int v = blockIdx.y;
   const RegIdx ix(lo, HB);
   cx<CR> a[R];
+  if constexpr (SRC == SRC_GEN) {
+    // c(j) = gamma prod_q (1 + eta_q K_q(j)), dimensions outside: the digit
+    // of element r advances by the constant step(2^lo) from element 0
+    CR c[R];
 #pragma unroll
-  for (int r = 0; r < R; r++) {
-    const int64_t i = ix.at(r, lo);
-    if constexpr (SRC == SRC_WORK)
-      a[r] = (work + (size_t)v * vstride + ix.ublk + ((int64_t)r << lo))[threadIdx.x];
-    else
-      a[r] = {src_value<CR, SRC, KT>(y, y_f32, v, (uint32_t)i, m, gen, colshift, P, d), (CR)0};
+    for (int r = 0; r < R; r++) c[r] = RT<CR>::gamma(P);
+    const uint32_t* sh = colshift + (size_t)v * d;
+    const uint32_t i0 = (uint32_t)ix.at(0, lo);
+    for (int q = 0; q < d; q++) {
+      SiFactor<CR, KT> fk;
+      fk.init(RT<CR>::eta(P, q));
+      uint32_t u = lat_z(gen[q], i0, m) + sh[q];
+      const uint32_t step = lat_z(gen[q], 1u << lo, m);
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        c[r] = fma(c[r], fk.eta_k(u), c[r]);
+        u += step;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) a[r] = {c[r], (CR)0};
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const int64_t i = ix.at(r, lo);
+      if constexpr (SRC == SRC_WORK)
+        a[r] = (work + (size_t)v * vstride + ix.ublk + ((int64_t)r << lo))[threadIdx.x];
+      else
+        a[r] = {src_value<CR, SRC, KT>(y, y_f32, v, (uint32_t)i, m, gen, colshift, P, d), (CR)0};
+    }
   }
   cx<double> B = expmpi(ix.low, lo + HB - 1);
 #pragma unroll
@@ -334,10 +392,9 @@ __global__ __launch_bounds__(256) void lat_dit_reg_kernel(
     for (int r = 0; r < R; r++) stage[r * 256 + threadIdx.x] = a[r].x;
     // each thread reads back only its own slots: no barrier needed
     LatReduce<CR, KT, D> lr;
-    lr.init(gen, colshift + (size_t)v * d, d, P);
+    lr.init(gen, colshift + (size_t)v * d, d, P, (uint32_t)ix.at(0, lo), 1u << lo, m);
 #pragma unroll 1
-    for (int r = 0; r < R; r++)
-      lr.add(stage[r * 256 + threadIdx.x], (uint32_t)ix.at(r, lo), m, P);
+    for (int r = 0; r < R; r++) lr.add(stage[r * 256 + threadIdx.x]);
     lr.store(d, red, partials + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * adj_nq(d));
   }
 }
@@ -412,9 +469,8 @@ __global__ __launch_bounds__(256) void lat_dit_lds_kernel(
       real_out[(size_t)v * ((size_t)1 << m) + b0 + i] = (double)a[lds_at(0, stride, i)].x * scale;
   } else {
     LatReduce<CR, KT, D> lr;
-    lr.init(gen, colshift + (size_t)v * d, d, P);
-    for (int i = threadIdx.x; i < nb; i += blockDim.x)
-      lr.add(a[lds_at(0, stride, i)].x, (uint32_t)(b0 + i), m, P);
+    lr.init(gen, colshift + (size_t)v * d, d, P, (uint32_t)(b0 + threadIdx.x), blockDim.x, m);
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) lr.add(a[lds_at(0, stride, i)].x);
     lr.store(d, red, partials + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * adj_nq(d));
   }
 }
