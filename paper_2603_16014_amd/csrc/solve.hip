@@ -76,27 +76,31 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
                                                        double* __restrict__ partials,
                                                        double* __restrict__ ahat,
                                                        int* __restrict__ status) {
-  constexpr int NQ = 2 + 3 * TM;
-  __shared__ double red[4 * NQ];
+  constexpr int NQ = 2 + 3 * TM, NR = 2 + 2 * TM;  // row size, block-summed slots
+  __shared__ double red[4 * NR];
   const int T = kd.T;
-  double vals[NQ];
+  double* row = partials + (size_t)blockIdx.x * NQ;
+  // the ahat(0) slots: zero in every row; the frequency-0 thread (thread 0
+  // of block 0) overwrites row 0's below
+  if (threadIdx.x == 0)
+    for (int q = NR; q < NQ; q++) row[q] = 0.0;
+  double vals[NR];
 #pragma unroll
-  for (int q = 0; q < NQ; q++) vals[q] = 0.0;
+  for (int q = 0; q < NR; q++) vals[q] = 0.0;
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f < n) {
     constexpr int NP = TM * (TM + 1) / 2;
-    Real lamd[TM];  // diagonal-column values lambda_tt(f)
+    // equal sizes: every diagonal pair uses the one diagonal column
+    const double lam0 = (double)cols[(int64_t)pm.col[0][0] * n + f];
     double A[NP], r[TM];
 #pragma unroll
     for (int i = 0; i < TM; i++) {
 #pragma unroll
       for (int j = 0; j <= i; j++) {
         if (i < T) {
-          const Real l = cols[(int64_t)pm.col[j][i] * n + f];
-          if (i == j) lamd[i] = l;
-          A[pk<TM>(i, j)] = P->R[j * MTGP_MAXT + i] * (double)l + (i == j ? P->xi[i] : 0.0);
+          const double l = i == j ? lam0 : (double)cols[(int64_t)pm.col[j][i] * n + f];
+          A[pk<TM>(i, j)] = P->R[j * MTGP_MAXT + i] * l + (i == j ? P->xi[i] : 0.0);
         } else {
-          if (i == j) lamd[i] = 0;
           A[pk<TM>(i, j)] = (i == j) ? 1.0 : 0.0;
         }
       }
@@ -156,7 +160,7 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
     }
     if (f == 0) {
 #pragma unroll
-      for (int i = 0; i < TM; i++) vals[2 + 2 * TM + i] += a[i];
+      for (int i = 0; i < TM; i++) row[NR + i] = a[i];
     }
     if (ahat) {
 #pragma unroll
@@ -187,7 +191,7 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
           const double w = v - a[t] * a[u];
           if (u < T) {
             if (t == u) {
-              vals[2 + t] += w * (double)lamd[t];
+              vals[2 + t] += w * lam0;
               vals[2 + TM + t] += w;
               wdiag += P->R[t * MTGP_MAXT + t] * w;
             } else {
@@ -199,7 +203,7 @@ __global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, 
       cols[(int64_t)pm.col[0][0] * n + f] = (Real)wdiag;
     }
   }
-  block_sum_store_head<NQ>(vals, 2 + 2 * TM, red, partials + (size_t)blockIdx.x * NQ);
+  block_sum_store<NR>(vals, NR, red, row);
 }
 
 template <typename Real>
@@ -258,32 +262,33 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
                                                          double* __restrict__ ahat,
                                                          int* __restrict__ status) {
   constexpr int NP = TM * (TM + 1) / 2;
-  constexpr int NQ = 2 + 3 * TM;
-  __shared__ double red[4 * NQ];
+  constexpr int NQ = 2 + 3 * TM, NR = 2 + 2 * TM;  // row size, block-summed slots
+  __shared__ double red[4 * NR];
   const int T = kd.T;
-  double vals[NQ];
+  double* row = partials + (size_t)blockIdx.x * NQ;
+  // the ahat(0) slots: zero in every row; the frequency-0 thread (thread 0
+  // of block 0) overwrites row 0's below
+  if (threadIdx.x == 0)
+    for (int q = NR; q < NQ; q++) row[q] = 0.0;
+  double vals[NR];
 #pragma unroll
-  for (int q = 0; q < NQ; q++) vals[q] = 0.0;
+  for (int q = 0; q < NR; q++) vals[q] = 0.0;
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f < n) {
     zc A[NP], r[TM];
-    double lamd[TM];  // diagonal-column values (real)
+    // equal sizes: every diagonal pair uses the one diagonal column (real)
+    const double lam0 = (double)cols[((size_t)pm.col[0][0] * n + f) * 2];
 #pragma unroll
     for (int i = 0; i < TM; i++) {
 #pragma unroll
       for (int j = 0; j <= i; j++) {
         if (i < T) {
           const size_t at = ((size_t)pm.col[j][i] * n + f) * 2;
-          zc l = {(double)cols[at], (double)cols[at + 1]};
-          if (i == j) {
-            l.y = 0.0;
-            lamd[i] = l.x;
-          }
+          const zc l = i == j ? zc{lam0, 0.0} : zc{(double)cols[at], (double)cols[at + 1]};
           // lower entry (i, j), i > j: conj(Lambda_ji) = R_ji conj(lambda_ji)
           const double R = P->R[j * MTGP_MAXT + i];
           A[pk<TM>(i, j)] = {R * l.x + (i == j ? P->xi[i] : 0.0), -R * l.y};
         } else {
-          if (i == j) lamd[i] = 0.0;
           A[pk<TM>(i, j)] = {i == j ? 1.0 : 0.0, 0.0};
         }
       }
@@ -345,7 +350,7 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
     }
     if (f == 0) {
 #pragma unroll
-      for (int i = 0; i < TM; i++) vals[2 + 2 * TM + i] += a[i].x;
+      for (int i = 0; i < TM; i++) row[NR + i] = a[i].x;
     }
     if (ahat) {
 #pragma unroll
@@ -385,7 +390,7 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
           const zc w = zsub(v, zmulc(a[t], a[u]));  // W_tu = Ainv_tu - a_t conj(a_u)
           if (u < T) {
             if (t == u) {
-              vals[2 + t] += w.x * lamd[t];
+              vals[2 + t] += w.x * lam0;
               vals[2 + TM + t] += w.x;
               wdiag += P->R[t * MTGP_MAXT + t] * w.x;
             } else {
@@ -401,7 +406,7 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
       cols[at0 + 1] = (SR)0;
     }
   }
-  block_sum_store_head<NQ>(vals, 2 + 2 * TM, red, partials + (size_t)blockIdx.x * NQ);
+  block_sum_store<NR>(vals, NR, red, row);
 }
 
 template <typename SR>
