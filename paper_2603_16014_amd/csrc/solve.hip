@@ -69,8 +69,10 @@ __device__ constexpr int pk(int i, int j) {
 // reciprocals and no square roots per frequency.  Per-block sums go to
 // partials[block][solve_ns(T)] in the layout of solve_ns, TM = solve_tm(T)
 // (T padded to 1/2/4/8/16); ahat_t(0) is nonzero in block 0 only.
+// Four waves per SIMD (at most 128 VGPRs, a 20-byte spill per lane at TM = 8)
+// measured faster than three without the spill: the kernel is latency-bound.
 template <typename Real, int TM, bool GRAD>
-__global__ __launch_bounds__(256) void solve_eq_kernel(Real* __restrict__ cols, int64_t n,
+__global__ __launch_bounds__(256, 4) void solve_eq_kernel(Real* __restrict__ cols, int64_t n,
                                                        PairMap pm, const double* __restrict__ yhat,
                                                        const Params* __restrict__ P, KDesc kd,
                                                        double* __restrict__ partials,
