@@ -139,15 +139,102 @@ __global__ __launch_bounds__(256) void fwht_reg_kernel(const TIn* in, TOut* out,
   for (int r = 0; r < R; r++) out[base + ((int64_t)r << lo)] = (TOut)v[r];
 }
 
+// Raw buffer access: one resource per block window, the lane's byte offset in
+// a vector register and the row's byte offset as a scalar.  Only the data
+// stays in vector registers across the butterflies (a 64-bit address per row
+// would double their count), so HB = 6 in double precision fits three waves
+// per SIMD.  The window must be shorter than 2^31 bytes.
+constexpr int kBufDword3 = 0x00020000;  // gfx9-family raw buffer format word
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+template <typename T>
+__device__ inline void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+}
+
+template <typename TC, typename TIn, typename TOut, int HB>
+__global__ __launch_bounds__(256) void fwht_reg_buf_kernel(const TIn* in, TOut* out,
+                                                           int64_t vec_stride, int lo) {
+  constexpr int R = 1 << HB;
+  const int64_t tile = blockIdx.x;
+  const int gb = lo - 8;
+  const int64_t grp = tile & (((int64_t)1 << gb) - 1);
+  const int64_t hi = tile >> gb;
+  const int64_t ub = (int64_t)blockIdx.y * vec_stride + (hi << (lo + HB)) + (grp << 8);
+  const int nb_in = (int)(sizeof(TIn) << (lo + HB)), nb_out = (int)(sizeof(TOut) << (lo + HB));
+  const __amdgpu_buffer_rsrc_t ri =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(in + ub), (short)0, nb_in, kBufDword3);
+  const __amdgpu_buffer_rsrc_t ro =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(out + ub), (short)0, nb_out, kBufDword3);
+  constexpr int HB1 = HB / 2, R1 = 1 << HB1, R2 = R >> HB1;
+  TC v[R];
+  // rows r = a * R1 + b: the transform over the bits of b for each a as the
+  // rows arrive, then over the bits of a for each b, each group stored as
+  // soon as it is done, so at most the R values of the thread are live
+#pragma unroll
+  for (int a = 0; a < R2; a++) {
+#pragma unroll
+    for (int b = 0; b < R1; b++) {
+      const int r = a * R1 + b;
+      v[r] = (TC)buf_load<TIn>(ri, threadIdx.x * (uint32_t)sizeof(TIn), ((uint32_t)r << lo) * sizeof(TIn));
+    }
+#pragma unroll
+    for (int h = 1; h < R1; h <<= 1)
+#pragma unroll
+      for (int b = 0; b < R1; b++)
+        if (!(b & h)) {
+          const TC x = v[a * R1 + b], y = v[a * R1 + b + h];
+          v[a * R1 + b] = x + y;
+          v[a * R1 + b + h] = x - y;
+        }
+  }
+#pragma unroll
+  for (int b = 0; b < R1; b++) {
+#pragma unroll
+    for (int h = 1; h < R2; h <<= 1)
+#pragma unroll
+      for (int a = 0; a < R2; a++)
+        if (!(a & h)) {
+          const TC x = v[a * R1 + b], y = v[(a + h) * R1 + b];
+          v[a * R1 + b] = x + y;
+          v[(a + h) * R1 + b] = x - y;
+        }
+#pragma unroll
+    for (int a = 0; a < R2; a++) {
+      const int r = a * R1 + b;
+      buf_store<TOut>((TOut)v[r], ro, threadIdx.x * (uint32_t)sizeof(TOut),
+                      ((uint32_t)r << lo) * sizeof(TOut));
+    }
+  }
+}
+
 template <typename TC, typename TIn, typename TOut>
 void launch_reg_pass(const TIn* in, TOut* out, int64_t vec_stride, int nv, int m, int lo, int hb,
                      hipStream_t st) {
   const dim3 grid((unsigned)((int64_t)1 << (m - hb - 8)), (unsigned)nv);
+  // buffer addressing needs the window of a block (2^(lo+hb) elements of the
+  // wider type) below 2^31 bytes
+  const bool buf = lo + hb + 3 <= 30;
   switch (hb) {
-#define MTGP_REGP(H)                                                                          \
-  case H:                                                                                     \
-    hipLaunchKernelGGL((fwht_reg_kernel<TC, TIn, TOut, H>), grid, dim3(256), 0, st, in, out, \
-                       vec_stride, lo);                                                       \
+#define MTGP_REGP(H)                                                                              \
+  case H:                                                                                         \
+    if (buf)                                                                                      \
+      hipLaunchKernelGGL((fwht_reg_buf_kernel<TC, TIn, TOut, H>), grid, dim3(256), 0, st, in,    \
+                         out, vec_stride, lo);                                                    \
+    else                                                                                          \
+      hipLaunchKernelGGL((fwht_reg_kernel<TC, TIn, TOut, H>), grid, dim3(256), 0, st, in, out,   \
+                         vec_stride, lo);                                                         \
     break;
     MTGP_REGP(1)
     MTGP_REGP(2)
