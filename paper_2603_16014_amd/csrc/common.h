@@ -276,6 +276,42 @@ __device__ inline void flag_bad(int* status, int64_t idx) {
 }
 
 // ---------------------------------------------------------------------------
+// raw buffer access
+// ---------------------------------------------------------------------------
+// A resource covers one window (at most 2^31 bytes) from a base address; an
+// access takes the lane's byte offset in a vector register and a wave-uniform
+// byte offset as a scalar, so strided rows cost one scalar each instead of a
+// 64-bit vector address each.  Accesses outside the window read 0 and drop
+// the store.
+constexpr int kBufDword3 = 0x00020000;  // gfx9-family raw buffer format word
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, kBufDword3);
+}
+
+template <typename T>
+__device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 16)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  else if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+template <typename T>
+__device__ inline void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 16)
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
+  else if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+}
+
+// ---------------------------------------------------------------------------
 // block reductions (FP64)
 // ---------------------------------------------------------------------------
 // Value of another lane of the row under a DPP control (rows whose bit in

@@ -277,7 +277,10 @@ struct RegIdx {
   __device__ inline int64_t at(int r, int lo) const { return ublk + ((int64_t)r << lo) + threadIdx.x; }
 };
 
-template <typename CR, typename TOut, int HB, int SRC, int KT>
+// BUF: the rows of a block are read and written through raw buffer
+// resources over its window of 2^(lo + HB) elements (below 2^31 bytes), one
+// scalar offset per row instead of a 64-bit vector address per row.
+template <typename CR, typename TOut, int HB, int SRC, int KT, bool BUF>
 __global__ __launch_bounds__(256) void lat_dif_reg_kernel(
     const LatTab tab, cx<CR>* __restrict__ work, cx<TOut>* __restrict__ out, int64_t vstride,
     int m, int lo, const void* __restrict__ y, int y_f32, const uint32_t* __restrict__ gen,
@@ -286,6 +289,7 @@ __global__ __launch_bounds__(256) void lat_dif_reg_kernel(
   static_assert(HB >= 1 && HB <= 5, "constant twiddles cover 5 bits");
   const int v = blockIdx.y;
   const RegIdx ix(lo, HB);
+  const int64_t vb = (int64_t)v * vstride + ix.ublk;
   cx<CR> a[R];
   if constexpr (SRC == SRC_GEN) {
     // c(j) = gamma prod_q (1 + eta_q K_q(j)), dimensions outside: the digit
@@ -312,8 +316,12 @@ __global__ __launch_bounds__(256) void lat_dif_reg_kernel(
 #pragma unroll
     for (int r = 0; r < R; r++) {
       const int64_t i = ix.at(r, lo);
-      if constexpr (SRC == SRC_WORK)
-        a[r] = (work + (size_t)v * vstride + ix.ublk + ((int64_t)r << lo))[threadIdx.x];
+      if constexpr (SRC == SRC_WORK && BUF)
+        a[r] = buf_load<cx<CR>>(buf_rsrc(work + vb, (int)(sizeof(cx<CR>) << (lo + HB))),
+                                threadIdx.x * (uint32_t)sizeof(cx<CR>),
+                                ((uint32_t)r << lo) * (uint32_t)sizeof(cx<CR>));
+      else if constexpr (SRC == SRC_WORK)
+        a[r] = (work + vb + ((int64_t)r << lo))[threadIdx.x];
       else
         a[r] = {src_value<CR, SRC, KT>(y, y_f32, v, (uint32_t)i, m, gen, colshift, P, d), (CR)0};
     }
@@ -336,14 +344,19 @@ __global__ __launch_bounds__(256) void lat_dif_reg_kernel(
   }
 #pragma unroll
   for (int r = 0; r < R; r++) {
-    (out + (size_t)v * vstride + ix.ublk + ((int64_t)r << lo))[threadIdx.x] = {(TOut)a[r].x,
-                                                                               (TOut)a[r].y};
+    const cx<TOut> o = {(TOut)a[r].x, (TOut)a[r].y};
+    if constexpr (BUF)
+      buf_store<cx<TOut>>(o, buf_rsrc(out + vb, (int)(sizeof(cx<TOut>) << (lo + HB))),
+                          threadIdx.x * (uint32_t)sizeof(cx<TOut>),
+                          ((uint32_t)r << lo) * (uint32_t)sizeof(cx<TOut>));
+    else
+      (out + vb + ((int64_t)r << lo))[threadIdx.x] = o;
   }
 }
 
 // SINK_WORK: store back to work; SINK_REAL: real_out[v][j] = Re * scale;
 // SINK_REDUCE: derivative sums (Re values staged in dynamic LDS, R x 256 CR).
-template <typename CR, int HB, int SINK, int KT, int D>
+template <typename CR, int HB, int SINK, int KT, int D, bool BUF>
 __global__ __launch_bounds__(256) void lat_dit_reg_kernel(
     const LatTab tab, cx<CR>* __restrict__ work, double* __restrict__ real_out, int64_t vstride,
     int m, int lo, double scale, const uint32_t* __restrict__ gen,
@@ -355,10 +368,17 @@ __global__ __launch_bounds__(256) void lat_dit_reg_kernel(
   __shared__ double red[4 * (D + 1)];
   const int v = blockIdx.y;
   const RegIdx ix(lo, HB);
+  const int64_t vb = (int64_t)v * vstride + ix.ublk;
+  const int nb = (int)(sizeof(cx<CR>) << (lo + HB));
+  constexpr uint32_t cb = sizeof(cx<CR>);
   cx<CR> a[R];
 #pragma unroll
-  for (int r = 0; r < R; r++)
-    a[r] = (work + (size_t)v * vstride + ix.ublk + ((int64_t)r << lo))[threadIdx.x];
+  for (int r = 0; r < R; r++) {
+    if constexpr (BUF)
+      a[r] = buf_load<cx<CR>>(buf_rsrc(work + vb, nb), threadIdx.x * cb, ((uint32_t)r << lo) * cb);
+    else
+      a[r] = (work + vb + ((int64_t)r << lo))[threadIdx.x];
+  }
   cx<double> Bs[HB];
   Bs[HB - 1] = expmpi(ix.low, lo + HB - 1);
 #pragma unroll
@@ -379,8 +399,12 @@ __global__ __launch_bounds__(256) void lat_dit_reg_kernel(
   }
   if constexpr (SINK == SINK_WORK) {
 #pragma unroll
-    for (int r = 0; r < R; r++)
-      (work + (size_t)v * vstride + ix.ublk + ((int64_t)r << lo))[threadIdx.x] = a[r];
+    for (int r = 0; r < R; r++) {
+      if constexpr (BUF)
+        buf_store<cx<CR>>(a[r], buf_rsrc(work + vb, nb), threadIdx.x * cb, ((uint32_t)r << lo) * cb);
+      else
+        (work + vb + ((int64_t)r << lo))[threadIdx.x] = a[r];
+    }
   } else if constexpr (SINK == SINK_REAL) {
 #pragma unroll
     for (int r = 0; r < R; r++)
@@ -679,12 +703,22 @@ int lat_adj_blocks(int m, size_t /*cbytes*/) {
     }                                                 \
   } while (0)
 
+// raw buffer addressing while the window of a block fits in 2^30 bytes
+template <typename CR>
+static bool lat_buf(int lo) {
+  return ((int64_t)sizeof(cx<CR>) << (lo + kLatHB)) <= ((int64_t)1 << 30);
+}
+
 template <typename CR, int SRC, int KT>
 static void dif_reg(const LatTab& tab, dim3 grid, hipStream_t st, cx<CR>* work, int64_t vstride,
                     int m, int lo, const void* y, int y_f32, const uint32_t* gen,
                     const uint32_t* colshift, const Params* P, int d) {
-  hipLaunchKernelGGL((lat_dif_reg_kernel<CR, CR, kLatHB, SRC, KT>), grid, dim3(256), 0, st, tab,
-                     work, work, vstride, m, lo, y, y_f32, gen, colshift, P, d);
+  if (lat_buf<CR>(lo))
+    hipLaunchKernelGGL((lat_dif_reg_kernel<CR, CR, kLatHB, SRC, KT, true>), grid, dim3(256), 0, st,
+                       tab, work, work, vstride, m, lo, y, y_f32, gen, colshift, P, d);
+  else
+    hipLaunchKernelGGL((lat_dif_reg_kernel<CR, CR, kLatHB, SRC, KT, false>), grid, dim3(256), 0,
+                       st, tab, work, work, vstride, m, lo, y, y_f32, gen, colshift, P, d);
 }
 
 // Forward transform of nvec vectors (columns when src == SRC_GEN, data when
@@ -772,9 +806,16 @@ int launch_lat_adjoint(int sink, const cx<SR>* spec, cx<CR>* work, double* real_
     const int lo = s.L + kLatHB * q;
     const bool last = q == s.np - 1;
     const size_t stage = last && sink == SINK_REDUCE ? ((size_t)256 << kLatHB) * sizeof(CR) : 0;
+    const bool buf = lat_buf<CR>(lo);
 #define AR(DD, KTV, SINKV)                                                                       \
-  hipLaunchKernelGGL((lat_dit_reg_kernel<CR, kLatHB, SINKV, KTV, DD>), grid, dim3(256), stage, st, \
-                     tab, work, real_out, vstride, m, lo, scale, gen, colshift, P, kd.d, partials)
+  if (buf)                                                                                       \
+    hipLaunchKernelGGL((lat_dit_reg_kernel<CR, kLatHB, SINKV, KTV, DD, true>), grid, dim3(256),  \
+                       stage, st, tab, work, real_out, vstride, m, lo, scale, gen, colshift, P,  \
+                       kd.d, partials);                                                          \
+  else                                                                                           \
+    hipLaunchKernelGGL((lat_dit_reg_kernel<CR, kLatHB, SINKV, KTV, DD, false>), grid, dim3(256), \
+                       stage, st, tab, work, real_out, vstride, m, lo, scale, gen, colshift, P,  \
+                       kd.d, partials)
 #define AR_D(DD, KTV) AR(DD, KTV, SINK_REDUCE)
     if (!last) {
       AR(2, KT_SI1, SINK_WORK);

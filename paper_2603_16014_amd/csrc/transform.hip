@@ -139,30 +139,9 @@ __global__ __launch_bounds__(256) void fwht_reg_kernel(const TIn* in, TOut* out,
   for (int r = 0; r < R; r++) out[base + ((int64_t)r << lo)] = (TOut)v[r];
 }
 
-// Raw buffer access: one resource per block window, the lane's byte offset in
-// a vector register and the row's byte offset as a scalar.  Only the data
-// stays in vector registers across the butterflies (a 64-bit address per row
-// would double their count), so HB = 6 in double precision fits three waves
-// per SIMD.  The window must be shorter than 2^31 bytes.
-constexpr int kBufDword3 = 0x00020000;  // gfx9-family raw buffer format word
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-
-template <typename T>
-__device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  if constexpr (sizeof(T) == 8)
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-  else
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-
-template <typename T>
-__device__ inline void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  if constexpr (sizeof(T) == 8)
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
-  else
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
-}
-
+// Raw buffer addressing (see buf_load): only the data stays in vector
+// registers across the butterflies (a 64-bit address per row would double
+// their count), so HB = 6 in double precision fits three waves per SIMD.
 template <typename TC, typename TIn, typename TOut, int HB>
 __global__ __launch_bounds__(256) void fwht_reg_buf_kernel(const TIn* in, TOut* out,
                                                            int64_t vec_stride, int lo) {
@@ -173,10 +152,8 @@ __global__ __launch_bounds__(256) void fwht_reg_buf_kernel(const TIn* in, TOut* 
   const int64_t hi = tile >> gb;
   const int64_t ub = (int64_t)blockIdx.y * vec_stride + (hi << (lo + HB)) + (grp << 8);
   const int nb_in = (int)(sizeof(TIn) << (lo + HB)), nb_out = (int)(sizeof(TOut) << (lo + HB));
-  const __amdgpu_buffer_rsrc_t ri =
-      __builtin_amdgcn_make_buffer_rsrc((void*)(in + ub), (short)0, nb_in, kBufDword3);
-  const __amdgpu_buffer_rsrc_t ro =
-      __builtin_amdgcn_make_buffer_rsrc((void*)(out + ub), (short)0, nb_out, kBufDword3);
+  const __amdgpu_buffer_rsrc_t ri = buf_rsrc(in + ub, nb_in);
+  const __amdgpu_buffer_rsrc_t ro = buf_rsrc(out + ub, nb_out);
   constexpr int HB1 = HB / 2, R1 = 1 << HB1, R2 = R >> HB1;
   TC v[R];
   // rows r = a * R1 + b: the transform over the bits of b for each a as the
