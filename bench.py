@@ -45,9 +45,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_loss_grad_T8_d10_n2e24_mixed.
 # phase -> (kernel-name pattern in rocprofv3 output, bound)
 PHASE_KERNELS = {
     "gen_fwd_low": ("gen_fwd_kernel", "alu"),
-    "fwd_high": ("fwht_reg_kernel (2 passes)", "hbm"),
+    "fwd_high": ("fwht_reg_buf_kernel (2 passes)", "hbm"),
     "solve": ("solve_eq_kernel", "hbm"),
-    "adj_high": ("fwht_reg_kernel (2 passes)", "hbm"),
+    "adj_high": ("fwht_reg_buf_kernel (2 passes)", "hbm"),
     "adj_low_reduce": ("adj_reduce_kernel", "alu"),
 }
 
@@ -540,7 +540,7 @@ def _phase_of(name, cur):
         return "prep"
     if "gen_fwd_kernel" in name or "lat_pass" in name and cur == "prep":
         return "gen_fwd_low"
-    if "fwht_strided_kernel" in name or "fwht_reg_kernel" in name:
+    if "fwht_strided_kernel" in name or "fwht_reg_" in name:
         return "fwd_high" if cur in ("gen_fwd_low", "fwd_high") else "adj_high"
     if "solve_eq" in name or "alg1_" in name:
         return "solve"
