@@ -116,10 +116,14 @@ int mtgp_plan_destroy(mtgp_plan* plan);
  * pass_a_bits index bits (1..13; fused with kernel-column generation) and
  * passes over at most pass_b_bits (1..12) further bits each.  Passes of at
  * most 6 bits above bit 8 keep each thread's 2^bits strided values in
- * registers; wider passes use an LDS tile of about pass_b_tile_bytes
- * (4096..147456).  Changes mtgp_workspace_bytes, so call it before sizing
- * the workspace.  Defaults: 12, 6, 36864 (measured best on MI355X for
- * 2^24-point columns). */
+ * registers; passes of exactly 8, 10 or 12 bits (above bit 8 - bits/2, with
+ * a block's window below 2^30 bytes) go through registers and one LDS tile
+ * of 256 x 2^(bits/2) values in a single pass; other wider passes use an LDS
+ * tile of about pass_b_tile_bytes (4096..147456).  Changes
+ * mtgp_workspace_bytes, so call it before sizing the workspace.  Defaults:
+ * 12, 6, 36864 (measured best on MI355X for 2^24-point columns, where the
+ * 12-bit single pass halves the HBM traffic of the high bits but holds one
+ * block per CU). */
 int mtgp_plan_set_schedule(mtgp_plan* plan, int32_t pass_a_bits, int32_t pass_b_bits,
                            int64_t pass_b_tile_bytes);
 

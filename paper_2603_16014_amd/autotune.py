@@ -19,7 +19,7 @@ from . import mtgp
 # passes for pass_b_bits <= 6, LDS-tiled ones above
 CANDIDATES = [
     (12, 6, 36864), (13, 6, 36864), (12, 5, 36864), (12, 4, 36864), (11, 6, 36864),
-    (10, 7, 36864), (12, 12, 73728), (12, 12, 147456),
+    (10, 7, 36864), (12, 12, 36864),
 ]
 OVERLAPS = (1, 4, 8)
 

@@ -196,6 +196,122 @@ __global__ __launch_bounds__(256) void fwht_reg_buf_kernel(const TIn* in, TOut* 
   }
 }
 
+// Walsh-Hadamard transform of the 2^B register values of a thread: over the
+// low B/2 index bits within each group of 2^(B/2), then over the high bits
+// (group by group, so fewer temporaries are live than stage by stage).
+template <typename TC, int B>
+__device__ inline void reg_fwht_split(TC (&v)[1 << B]) {
+  constexpr int B1 = B / 2, R1 = 1 << B1, R2 = (1 << B) >> B1;
+#pragma unroll
+  for (int a = 0; a < R2; a++)
+#pragma unroll
+    for (int h = 1; h < R1; h <<= 1)
+#pragma unroll
+      for (int b = 0; b < R1; b++)
+        if (!(b & h)) {
+          const TC x = v[a * R1 + b], y = v[a * R1 + b + h];
+          v[a * R1 + b] = x + y;
+          v[a * R1 + b + h] = x - y;
+        }
+#pragma unroll
+  for (int b = 0; b < R1; b++)
+#pragma unroll
+    for (int h = 1; h < R2; h <<= 1)
+#pragma unroll
+      for (int a = 0; a < R2; a++)
+        if (!(a & h)) {
+          const TC x = v[a * R1 + b], y = v[(a + h) * R1 + b];
+          v[a * R1 + b] = x + y;
+          v[(a + h) * R1 + b] = x - y;
+        }
+}
+
+// One pass over all H high bits [lo, lo + H), H in {8, 10, 12}: a block takes
+// KC = 256 / 2^(H/2) adjacent low indices (a run of KC elements per row) over
+// all 2^H rows hi = h1 + 2^(H/2) h2 of one vector.  Phase 1: thread (c, h1)
+// holds the rows of every h2 in registers and transforms over h2 while its
+// loads are in flight; phase 2 reads the rows of one h2 per thread back from
+// an LDS tile and transforms over h1; phase 3 re-reads the tile in the
+// phase-1 order, so the stores have the loads' pattern (rows 2^lo apart
+// inside one 2^(lo + H/2) span).  Half the HBM traffic of two register
+// passes, but the tile fills most of a CU's LDS (one block per CU, phases in
+// sequence), so it does not always win; the schedule picks.  The blocks that
+// share a 128-byte line sit on one XCD, next to each other in dispatch order
+// (dispatch is round-robin over the 8 XCDs).
+template <typename TC, typename TIn, typename TOut, int H>
+__global__ __launch_bounds__(256) void fwht_hi_kernel(const TIn* in, TOut* out,
+                                                      int64_t vec_stride, int lo) {
+  constexpr int H1 = H / 2, R = 1 << H1, KB = 8 - H1, KC = 1 << KB;
+  // LDS slot of (row hi, column c): one run of padding per 2^H1 rows puts the
+  // 64 lanes of a phase-2 access on distinct banks
+  constexpr int PAD = KC;
+  extern __shared__ __align__(16) unsigned char smem[];
+  TC* lds = reinterpret_cast<TC*>(smem);
+  const int ncg = 1 << (lo - KB);  // column groups per vector
+  int cg = blockIdx.x;
+  if ((ncg & 31) == 0) {
+    const int x = cg & 7, sl = cg >> 3;
+    cg = ((sl >> 2) << 5) + (x << 2) + (sl & 3);
+  }
+  const int64_t vb = (int64_t)blockIdx.y * vec_stride + ((int64_t)cg << KB);
+  const int c = threadIdx.x & (KC - 1), u = threadIdx.x >> KB;
+  const __amdgpu_buffer_rsrc_t ri = buf_rsrc(in + vb, (int)(sizeof(TIn) << (lo + H)));
+  const __amdgpu_buffer_rsrc_t ro = buf_rsrc(out + vb, (int)(sizeof(TOut) << (lo + H)));
+  const uint32_t lane_in = ((uint32_t)c + ((uint32_t)u << lo)) * (uint32_t)sizeof(TIn);
+  const uint32_t lane_out = ((uint32_t)c + ((uint32_t)u << lo)) * (uint32_t)sizeof(TOut);
+  TC v[R];
+  // phase 1: rows u + R k
+#pragma unroll
+  for (int k = 0; k < R; k++)
+    v[k] = (TC)buf_load<TIn>(ri, lane_in, ((uint32_t)k << (lo + H1)) * (uint32_t)sizeof(TIn));
+  reg_fwht_split<TC, H1>(v);
+#pragma unroll
+  for (int k = 0; k < R; k++) lds[(u + (k << H1)) * KC + c + k * PAD] = v[k];
+  __syncthreads();
+  // phase 2: rows q + R u (each thread reads and rewrites only its own slots)
+#pragma unroll
+  for (int q = 0; q < R; q++) v[q] = lds[(q + (u << H1)) * KC + c + u * PAD];
+  reg_fwht_split<TC, H1>(v);
+#pragma unroll
+  for (int q = 0; q < R; q++) lds[(q + (u << H1)) * KC + c + u * PAD] = v[q];
+  __syncthreads();
+  // phase 3: rows u + R k again
+#pragma unroll
+  for (int k = 0; k < R; k++)
+    buf_store<TOut>((TOut)lds[(u + (k << H1)) * KC + c + k * PAD], ro, lane_out,
+                    ((uint32_t)k << (lo + H1)) * (uint32_t)sizeof(TOut));
+}
+
+static size_t fwht_hi_lds_bytes(int H, size_t tc_bytes) {
+  const int R = 1 << (H / 2), KC = 256 / R;
+  return ((size_t)KC << H) * tc_bytes + (size_t)R * KC * tc_bytes;
+}
+
+// one pass over the hb high bits when hb is 8, 10 or 12, the KC columns of a
+// block fit in the low part and a block's window stays below 2^30 bytes
+static bool fwht_hi_ok(int lo, int hb, size_t in_bytes, size_t out_bytes) {
+  if (hb != 8 && hb != 10 && hb != 12) return false;
+  const int KB = 8 - hb / 2;
+  const size_t w = (in_bytes > out_bytes ? in_bytes : out_bytes) << (lo + hb);
+  return lo >= KB && w <= ((size_t)1 << 30);
+}
+
+template <typename TC, typename TIn, typename TOut>
+void launch_hi_pass(const TIn* in, TOut* out, int64_t vec_stride, int nv, int lo, int hb,
+                    hipStream_t st) {
+  const dim3 grid(1u << (lo - (8 - hb / 2)), (unsigned)nv);
+  const size_t lds = fwht_hi_lds_bytes(hb, sizeof(TC));
+  if (hb == 12)
+    hipLaunchKernelGGL((fwht_hi_kernel<TC, TIn, TOut, 12>), grid, dim3(256), lds, st, in, out,
+                       vec_stride, lo);
+  else if (hb == 10)
+    hipLaunchKernelGGL((fwht_hi_kernel<TC, TIn, TOut, 10>), grid, dim3(256), lds, st, in, out,
+                       vec_stride, lo);
+  else
+    hipLaunchKernelGGL((fwht_hi_kernel<TC, TIn, TOut, 8>), grid, dim3(256), lds, st, in, out,
+                       vec_stride, lo);
+}
+
 template <typename TC, typename TIn, typename TOut>
 void launch_reg_pass(const TIn* in, TOut* out, int64_t vec_stride, int nv, int m, int lo, int hb,
                      hipStream_t st) {
@@ -247,6 +363,24 @@ int launch_strided(const TIn* first, TC* work, TOut* last, int64_t vec_stride, i
   while (lo < m) {
     const int hb = (m - lo) < sc.b_bits ? (m - lo) : sc.b_bits;
     const bool is_last = lo + hb >= m;
+    if (fwht_hi_ok(lo, hb, sizeof(TC) > sizeof(TIn) ? sizeof(TC) : sizeof(TIn),
+                   sizeof(TC) > sizeof(TOut) ? sizeof(TC) : sizeof(TOut))) {
+      for (int64_t v0 = 0; v0 < nvec; v0 += 65535) {
+        const int nv = (int)((nvec - v0) < 65535 ? (nvec - v0) : 65535);
+        const int64_t o = v0 * vec_stride;
+        if (is_first && is_last)
+          launch_hi_pass<TC, TIn, TOut>(first + o, last + o, vec_stride, nv, lo, hb, st);
+        else if (is_first)
+          launch_hi_pass<TC, TIn, TC>(first + o, work + o, vec_stride, nv, lo, hb, st);
+        else if (is_last)
+          launch_hi_pass<TC, TC, TOut>(work + o, last + o, vec_stride, nv, lo, hb, st);
+        else
+          launch_hi_pass<TC, TC, TC>(work + o, work + o, vec_stride, nv, lo, hb, st);
+      }
+      is_first = false;
+      lo += hb;
+      continue;
+    }
     if (hb <= 6 && lo >= 8) {
       for (int64_t v0 = 0; v0 < nvec; v0 += 65535) {
         const int nv = (int)((nvec - v0) < 65535 ? (nvec - v0) : 65535);

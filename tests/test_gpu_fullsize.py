@@ -21,10 +21,10 @@ from _gpu_common import say
 pytestmark = pytest.mark.gpu
 
 
-def _setup(w, precision):
+def _setup(w, precision, schedule=None):
     import bench
     from paper_2603_16014_amd import mtgp
-    plan = mtgp.Plan.from_workload(w, precision)
+    plan = mtgp.Plan.from_workload(w, precision, schedule=schedule)
     y = bench.targets_on_device(plan, w)
     plan.set_data(y)
     return plan, y
@@ -132,6 +132,25 @@ def test_config5_full_size():
     torch.cuda.empty_cache()
     say("config5 full size mixed")
     _mixed_vs_fp64(w, out64, g64, tau64)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_config5_single_pass_high_bits(precision):
+    """The 12 high index bits of the 2^24-point columns in one register + LDS
+    pass (schedule 12, 12) against the two 6-bit register passes."""
+    w = workloads.config5()
+    say("config5 single-pass high bits", precision)
+    res = []
+    for sched in (None, (12, 12, 36864)):
+        plan, y = _setup(w, precision, sched)
+        res.append(_loss_grad(plan, plan.pack_theta(w.theta)))
+        del plan, y
+        torch.cuda.empty_cache()
+    (o0, g0, t0), (o1, g1, t1) = res
+    den = abs(o0[0]) + abs(o0[1])
+    assert abs(o1[2] - o0[2]) < 1e-10 * den, (o0, o1)
+    assert np.abs(g1 - g0).max() < 1e-8 * np.abs(g0).max()
+    np.testing.assert_allclose(t1, t0, rtol=1e-12, atol=1e-14)
 
 
 def test_config3_full_size():

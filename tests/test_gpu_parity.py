@@ -148,6 +148,8 @@ CASES = [
     ("dseq", 4, [7, 7, 7, 7], 3, 2, True, True, (4, 2, 4096)),
     ("dseq", 5, [6, 6, 6, 6, 6], 2, 2, False, True, None),
     ("dseq", 8, [6] * 8, 10, 2, False, True, (3, 3, 4096)),
+    # an 8-bit high part in one register + LDS pass
+    ("dseq", 1, [12], 2, 2, False, True, (4, 8, 4096)),
     ("lat", 1, [8], 2, 2, False, True, None),
     ("lat", 3, [7, 7, 7], 3, 1, False, False, None),
     ("lat", 4, [8, 8, 8, 8], 6, 2, False, True, None),
@@ -158,6 +160,7 @@ CASES = [
     ("dseq", 5, [9, 7, 5, 3, 1], 8, 4, False, True, None),
     ("dseq", 4, [9, 8, 8, 6], 3, 2, True, True, (4, 2, 4096)),
     ("dseq", 2, [10, 6], 3, 1, False, False, None),
+    ("dseq", 2, [12, 10], 2, 2, False, True, (4, 8, 4096)),
     ("lat", 3, [7, 5, 4], 3, 2, False, True, None),
     ("lat", 4, [8, 7, 7, 5], 2, 1, False, False, None),
 ]
@@ -220,6 +223,32 @@ def test_lattice_two_pass_against_oracle(precision):
     assert abs(float(out3[2]) - r["L"]) < (1e-10 if precision == "fp64" else 1e-5) * den
     mean = plan.predict(theta, mt.digits_to_device(ref["xs"])).cpu().numpy()
     assert rel_err(mean, ref["mean"]) < (1e-9 if precision == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("m,sched", [(13, (3, 10, 4096)), (16, (6, 10, 4096)), (16, (8, 8, 4096)),
+                                     (19, (7, 12, 36864)), (20, (12, 8, 36864))])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_single_pass_high_bits_match_register_passes(m, sched, precision):
+    # the one-pass kernel over 8, 10 or 12 high bits (at m = 19 with the XCD
+    # placement of line-sharing blocks) against the default schedule, whose
+    # register passes are pinned to the oracle above
+    w = tiny("dseq", 3, [m, m, m], 3, seed=63, xi=1e-2, rank=2)
+    say("single-pass high bits", m, sched, precision)
+    y = torch.from_numpy(np.random.default_rng(4).normal(size=w.N)).cuda()
+    res = []
+    for sc in (None, sched):
+        plan = mt.Plan.from_workload(w, precision, schedule=sc)
+        plan.set_data(y)
+        out3, grad, tau = plan.nll_grad(plan.pack_theta(w.theta))
+        torch.cuda.synchronize()
+        assert plan.status() == (0, -1)
+        res.append((out3.cpu().numpy(), grad.cpu().numpy(), tau.cpu().numpy()))
+        del plan
+    (o0, g0, t0), (o1, g1, t1) = res
+    den = abs(o0[0]) + abs(o0[1])
+    assert abs(o1[2] - o0[2]) < (1e-12 if precision == "fp64" else 1e-10) * den
+    assert np.abs(g1 - g0).max() < (1e-9 if precision == "fp64" else 1e-7) * np.abs(g0).max()
+    np.testing.assert_allclose(t1, t0, rtol=1e-12, atol=1e-14)
 
 
 @pytest.mark.parametrize("family,m", [("dseq", 14), ("lat", 14)])
