@@ -45,7 +45,7 @@ __device__ inline void decode_row(const Alg1Desc& A1, int s, int64_t r, int64_t 
 template <typename SR>
 __device__ inline z2 coupling(const SR* cols, const Alg1Desc& A1, const Params* P, int family,
                               int tp, int64_t g, int t) {
-  const z2 l = lam_at<SR>(cols, A1, family, A1.pair_col[tp][t], g);
+  const z2 l = lam_at<SR>(cols, A1, family, A1.pc(tp, t), g);
   const double s = sqrt(ldexp(1.0, A1.m[t] - A1.m[tp])) * P->R[tp * MTGP_MAXT + t];
   return {s * l.x, s * l.y};
 }
@@ -53,7 +53,7 @@ __device__ inline z2 coupling(const SR* cols, const Alg1Desc& A1, const Params* 
 template <typename SR>
 __device__ inline double diag_entry(const SR* cols, const Alg1Desc& A1, const Params* P, int family,
                                     int t, int64_t f) {
-  return P->R[t * MTGP_MAXT + t] * lam_at<SR>(cols, A1, family, A1.pair_col[t][t], f).x + P->xi[t];
+  return P->R[t * MTGP_MAXT + t] * lam_at<SR>(cols, A1, family, A1.pc(t, t), f).x + P->xi[t];
 }
 
 // Stage 0: A = 1 / Lambda_{(0,f),(0,f)} for each f < n_0.
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256) void alg1_final_kernel(SR* __restrict__ cols, 
       const int64_t f = frq[q];
       const z2 aq = ah[q];
       const double w = A[q * ms + q].x - (aq.x * aq.x + aq.y * aq.y);
-      const double lam = lam_at<SR>(cols, A1, family, A1.pair_col[t][t], f).x;
+      const double lam = lam_at<SR>(cols, A1, family, A1.pc(t, t), f).x;
 #pragma unroll
       for (int i = 0; i < TM; i++) {
         if (i == t) {
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(256) void alg1_final_kernel(SR* __restrict__ cols, 
       const int t = tsk[q];
       const int64_t f = frq[q];
       const z2 aq = ah[q];
-      if (A1.diag_first[t] == t) {
+      if (A1.df(t) == t) {
         double wsum = 0.0;
         // rows of the other tasks with the same length and the same frequency
         for (int64_t q2 = 0; q2 < ms; q2++) {
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(256) void alg1_final_kernel(SR* __restrict__ cols, 
             wsum += P->R[t2 * MTGP_MAXT + t2] * (A[q2 * ms + q2].x - (a2.x * a2.x + a2.y * a2.y));
           }
         }
-        const int c = A1.pair_col[t][t];
+        const int c = A1.pc(t, t);
         const int64_t pos = A1.col_off[c] + spec_pos(family, f, A1.m[t]);
         if (family == FAM_DSEQ) {
           cols[pos] = (SR)wsum;
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(256) void alg1_final_kernel(SR* __restrict__ cols, 
         const z2 wtu = {Atu.x - aa.x, Atu.y - aa.y};
         const double sc = sqrt(ldexp(1.0, A1.m[u] - A1.m[t]));
         const double R2 = 2.0 * sc;
-        const int c = A1.pair_col[t][u];
+        const int c = A1.pc(t, u);
         const int64_t pos = A1.col_off[c] + spec_pos(family, f, A1.m[t]);
         if (family == FAM_DSEQ) {
           cols[pos] = (SR)(R2 * wtu.x);

@@ -78,7 +78,7 @@ __global__ void zf_init_kernel(const SR* __restrict__ cols, Alg1Desc A, const Pa
       const int64_t r = i - A.so[a];
       const int b = a + (int)(r >> A.m[a]);
       const int64_t g = r & ((1ll << A.m[a]) - 1);
-      const z2 l = lam_at<SR>(cols, A, family, A.pair_col[a][b], g);
+      const z2 l = lam_at<SR>(cols, A, family, A.pc(a, b), g);
       if (b == a) {
         S[i] = {P->R[a * MTGP_MAXT + a] * l.x + P->xi[a], 0.0};
       } else {
@@ -367,8 +367,8 @@ __global__ __launch_bounds__(256) void zf_final_kernel(SR* __restrict__ cols, Al
         if (i == t) vals[2 + 2 * TM + i] = a.x;
     }
     if (!grad) continue;
-    if (A.diag_first[t] == t) {
-      const int c = A.pair_col[t][t];
+    if (A.df(t) == t) {
+      const int c = A.pc(t, t);
       const double lam = lam_at<SR>(cols, A, family, c, f).x;
       double wsum = 0.0;
 #pragma unroll
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(256) void zf_final_kernel(SR* __restrict__ cols, Al
       const z2 au = ahat_at(A, P, rr, U, u, f & ((1ll << A.m[u]) - 1));
       const z2 wtu = zsub(zconj(S[pidx(A, t, u, f)]), zmulc(a, au));
       const double R2 = 2.0 * sqrt(ldexp(1.0, A.m[u] - A.m[t]));
-      const int64_t pos = A.col_off[A.pair_col[t][u]] + spec_pos(family, f, A.m[t]);
+      const int64_t pos = A.col_off[A.pc(t, u)] + spec_pos(family, f, A.m[t]);
       if (family == FAM_DSEQ) {
         cols[pos] = (SR)(R2 * wtu.x);
       } else {

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void gcv_eq_kernel(SR* __restrict__ cols, int6
 #pragma unroll
       for (int j = 0; j <= i; j++) {
         if (i < T) {
-          S l = col_at<S, SR>(cols, pm.col[j][i], n, f);
+          S l = col_at<S, SR>(cols, pm.at(j, i), n, f);
           if (i == j) {
             l = real_s<S>(re(l));
             lamd[i] = re(l);
@@ -240,12 +240,12 @@ __global__ __launch_bounds__(256) void gcv_eq_kernel(SR* __restrict__ cols, int6
               vals[2 + TM + t] += re(w);
               wdiag += P->R[t * MTGP_MAXT + t] * re(w);
             } else {
-              col_put<SR>(cols, pm.col[t][u], n, f, scl(cj(w), 2.0));
+              col_put<SR>(cols, pm.at(t, u), n, f, scl(cj(w), 2.0));
             }
           }
         }
       }
-      col_put<SR>(cols, pm.col[0][0], n, f, real_s<S>(wdiag));
+      col_put<SR>(cols, pm.at(0, 0), n, f, real_s<S>(wdiag));
     }
   }
   block_sum_store<NQ>(vals, NQ, red, partials + (size_t)blockIdx.x * NQ);

@@ -92,27 +92,35 @@ __global__ __launch_bounds__(256, 4) void solve_eq_kernel(Real* __restrict__ col
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f < n) {
     constexpr int NP = TM * (TM + 1) / 2;
-    // equal sizes: every diagonal pair uses the one diagonal column
-    const double lam0 = (double)cols[(int64_t)pm.col[0][0] * n + f];
-    double A[NP], r[TM];
+    // every load first and without branches (a load behind a branch of its
+    // own is waited for before the next one issues); rows past T read the
+    // diagonal column and become identity rows below.  Equal sizes: every
+    // diagonal pair uses the one diagonal column.
+    const double lam0 = (double)cols[(int64_t)pm.at(0, 0) * n + f];
+    Real lv[NP];
+    double yv[TM];
 #pragma unroll
     for (int i = 0; i < TM; i++) {
 #pragma unroll
+      for (int j = 0; j < i; j++) {
+        const int ci = i < T ? pm.at(j, i) : pm.at(0, 0);
+        lv[pk<TM>(i, j)] = cols[(int64_t)ci * n + f];
+      }
+      yv[i] = yhat[(int64_t)(i < T ? i : 0) * n + f];
+    }
+    double A[NP], r[TM];
+#pragma unroll
+    for (int i = 0; i < TM; i++) {
+      const bool in = i < T;
+#pragma unroll
       for (int j = 0; j <= i; j++) {
-        if (i < T) {
-          const double l = i == j ? lam0 : (double)cols[(int64_t)pm.col[j][i] * n + f];
-          A[pk<TM>(i, j)] = P->R[j * MTGP_MAXT + i] * l + (i == j ? P->xi[i] : 0.0);
-        } else {
-          A[pk<TM>(i, j)] = (i == j) ? 1.0 : 0.0;
-        }
+        const double l = i == j ? lam0 : (double)lv[pk<TM>(i, j)];
+        const double a = P->R[j * MTGP_MAXT + i] * l + (i == j ? P->xi[i] : 0.0);
+        A[pk<TM>(i, j)] = in ? a : (i == j ? 1.0 : 0.0);
       }
-      if (i < T) {
-        double y = yhat[(int64_t)i * n + f];
-        if (f == 0) y = kd.profile ? 0.0 : y - sqrt((double)n) * P->tau[i];
-        r[i] = y;
-      } else {
-        r[i] = 0.0;
-      }
+      double y = yv[i];
+      if (f == 0) y = kd.profile ? 0.0 : y - sqrt((double)n) * P->tau[i];
+      r[i] = in ? y : 0.0;
     }
     // L D L^T in place: strictly lower part of A becomes L
     double invD[TM], Dv[TM];
@@ -197,12 +205,12 @@ __global__ __launch_bounds__(256, 4) void solve_eq_kernel(Real* __restrict__ col
               vals[2 + TM + t] += w;
               wdiag += P->R[t * MTGP_MAXT + t] * w;
             } else {
-              cols[(int64_t)pm.col[t][u] * n + f] = (Real)(2.0 * w);
+              cols[(int64_t)pm.at(t, u) * n + f] = (Real)(2.0 * w);
             }
           }
         }
       }
-      cols[(int64_t)pm.col[0][0] * n + f] = (Real)wdiag;
+      cols[(int64_t)pm.at(0, 0) * n + f] = (Real)wdiag;
     }
   }
   block_sum_store<NR>(vals, NR, red, row);
@@ -277,30 +285,39 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
   for (int q = 0; q < NR; q++) vals[q] = 0.0;
   const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (f < n) {
-    zc A[NP], r[TM];
-    // equal sizes: every diagonal pair uses the one diagonal column (real)
-    const double lam0 = (double)cols[((size_t)pm.col[0][0] * n + f) * 2];
+    // every load first and without branches (see the real solve); equal
+    // sizes: every diagonal pair uses the one diagonal column (real)
+    const double lam0 = (double)cols[((size_t)pm.at(0, 0) * n + f) * 2];
+    SR lv[NP][2];
+    zc yv[TM];
 #pragma unroll
     for (int i = 0; i < TM; i++) {
 #pragma unroll
+      for (int j = 0; j < i; j++) {
+        const int ci = i < T ? pm.at(j, i) : pm.at(0, 0);
+        const size_t at = ((size_t)ci * n + f) * 2;
+        lv[pk<TM>(i, j)][0] = cols[at];
+        lv[pk<TM>(i, j)][1] = cols[at + 1];
+      }
+      const size_t ay = ((size_t)(i < T ? i : 0) * n + f) * 2;
+      yv[i] = {yhat[ay], yhat[ay + 1]};
+    }
+    zc A[NP], r[TM];
+#pragma unroll
+    for (int i = 0; i < TM; i++) {
+      const bool in = i < T;
+#pragma unroll
       for (int j = 0; j <= i; j++) {
-        if (i < T) {
-          const size_t at = ((size_t)pm.col[j][i] * n + f) * 2;
-          const zc l = i == j ? zc{lam0, 0.0} : zc{(double)cols[at], (double)cols[at + 1]};
-          // lower entry (i, j), i > j: conj(Lambda_ji) = R_ji conj(lambda_ji)
-          const double R = P->R[j * MTGP_MAXT + i];
-          A[pk<TM>(i, j)] = {R * l.x + (i == j ? P->xi[i] : 0.0), -R * l.y};
-        } else {
-          A[pk<TM>(i, j)] = {i == j ? 1.0 : 0.0, 0.0};
-        }
+        const zc l = i == j ? zc{lam0, 0.0}
+                            : zc{(double)lv[pk<TM>(i, j)][0], (double)lv[pk<TM>(i, j)][1]};
+        // lower entry (i, j), i > j: conj(Lambda_ji) = R_ji conj(lambda_ji)
+        const double R = P->R[j * MTGP_MAXT + i];
+        const zc a = {R * l.x + (i == j ? P->xi[i] : 0.0), -R * l.y};
+        A[pk<TM>(i, j)] = in ? a : zc{i == j ? 1.0 : 0.0, 0.0};
       }
-      if (i < T) {
-        zc yv = {yhat[((size_t)i * n + f) * 2], yhat[((size_t)i * n + f) * 2 + 1]};
-        if (f == 0) yv = kd.profile ? zc{0.0, 0.0} : zc{yv.x - sqrt((double)n) * P->tau[i], yv.y};
-        r[i] = yv;
-      } else {
-        r[i] = {0.0, 0.0};
-      }
+      zc y = yv[i];
+      if (f == 0) y = kd.profile ? zc{0.0, 0.0} : zc{y.x - sqrt((double)n) * P->tau[i], y.y};
+      r[i] = in ? y : zc{0.0, 0.0};
     }
     double invD[TM], Dv[TM];
     double prod = 1.0;
@@ -396,14 +413,14 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
               vals[2 + TM + t] += w.x;
               wdiag += P->R[t * MTGP_MAXT + t] * w.x;
             } else {
-              const size_t at = ((size_t)pm.col[t][u] * n + f) * 2;
+              const size_t at = ((size_t)pm.at(t, u) * n + f) * 2;
               cols[at] = (SR)(2.0 * w.x);
               cols[at + 1] = (SR)(-2.0 * w.y);
             }
           }
         }
       }
-      const size_t at0 = ((size_t)pm.col[0][0] * n + f) * 2;
+      const size_t at0 = ((size_t)pm.at(0, 0) * n + f) * 2;
       cols[at0] = (SR)wdiag;
       cols[at0 + 1] = (SR)0;
     }
