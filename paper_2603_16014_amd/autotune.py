@@ -22,6 +22,7 @@ CANDIDATES = [
     (10, 7, 36864), (12, 12, 36864),
 ]
 OVERLAPS = (1, 4, 8)
+FINALISTS = 3  # schedules also timed with each overlap setting
 
 
 def cache_path():
@@ -87,28 +88,35 @@ def tune(plan, theta, reps=3, candidates=None, overlaps=OVERLAPS, use_cache=True
                     "cached": True, "timings": {}}
     cands = list(candidates or CANDIDATES)
     timings = {}
-    best = None
+    # every schedule with the passes in sequence, then every overlap setting
+    # for the fastest few: a schedule that wins in sequence (one block per CU
+    # in its widest pass, say) can lose once passes of several chunks share
+    # the CUs
     plan.set_overlap(1)
+    seq = []
     for c in cands:
         plan.set_schedule(*c)
         ms = _time(plan, theta, reps)
         timings[str(c)] = ms
-        if best is None or ms < best[1]:
-            best = (c, ms)
+        seq.append((ms, c))
+    seq.sort(key=lambda x: x[0])
+    best = (seq[0][1], 1, seq[0][0])
+    for _, c in seq[:FINALISTS]:
+        plan.set_schedule(*c)
+        for ov in overlaps:
+            if ov == 1:
+                continue
+            plan.set_overlap(ov)
+            ms = _time(plan, theta, reps)
+            timings[f"{c} overlap {ov}"] = ms
+            if ms < best[2]:
+                best = (c, ov, ms)
+        plan.set_overlap(1)
     plan.set_schedule(*best[0])
-    best_ov, best_ms = 1, best[1]
-    for ov in overlaps:
-        if ov == 1:
-            continue
-        plan.set_overlap(ov)
-        ms = _time(plan, theta, reps)
-        timings[f"overlap {ov}"] = ms
-        if ms < best_ms:
-            best_ov, best_ms = ov, ms
-    plan.set_overlap(best_ov)
+    plan.set_overlap(best[1])
     if use_cache:
         table = _load(path)
-        table[key] = {"schedule": list(best[0]), "overlap": best_ov, "ms": best_ms}
+        table[key] = {"schedule": list(best[0]), "overlap": best[1], "ms": best[2]}
         _store(path, table)
-    return {"schedule": best[0], "overlap": best_ov, "ms": best_ms, "cached": False,
+    return {"schedule": best[0], "overlap": best[1], "ms": best[2], "cached": False,
             "timings": timings}
