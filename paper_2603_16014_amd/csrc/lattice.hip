@@ -664,15 +664,27 @@ static void launch_dit_wave(int L, dim3 grid, hipStream_t st, const cx<SR>* spec
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-// Schedule: m <= 12 is one LDS pass; otherwise the low L bits in LDS, L in
-// [8, 12] with m - L a multiple of 5, and the other bits in 5-bit register
-// passes (in FP64 a 5-bit pass needs 200-256 VGPRs, 1-2 waves per SIMD, but
-// 32 loads in flight per thread; measured faster than 4-bit passes at
-// 3 waves per SIMD, which need one pass more at 2^24).
-constexpr int kLatHB = 5;
+// Schedule: m <= 12 is one LDS pass.  Otherwise the low L bits (8..10) go
+// through the wave pass and the other bits through as few register passes
+// as possible, 5 bits wide where the bits allow and 4 bits for the rest
+// (the top passes).  In FP64 a 5-bit pass needs 200-256 VGPRs, 1-2 waves per
+// SIMD, but keeps 32 loads in flight per thread, and runs faster than
+// 4-bit passes at 3 waves per SIMD, which need one pass more at 2^24.  An
+// LDS pass over 11 or 12 low bits (one block of 2^L per vector chunk, L
+// radix-2 stages between barriers) measured 4.6 times slower per byte than
+// the wave pass, so a 4-bit register pass replaces it where m - 10 is not
+// covered by 5-bit passes.
+constexpr int kLatHB = 5;  // widest register pass
+constexpr int kLatMaxPasses = 5;
 struct LatSched {
-  int L;   // LDS bits
-  int np;  // register passes; pass q covers the bits [L + 5 q, L + 5 q + 5)
+  int L;                   // LDS / wave-pass bits
+  int np;                  // register passes
+  int hb[kLatMaxPasses];   // pass q covers the bits [lo(q), lo(q) + hb[q])
+  int lo(int q) const {
+    int l = L;
+    for (int i = 0; i < q; i++) l += hb[i];
+    return l;
+  }
 };
 static LatSched lat_sched(int m) {
   LatSched s{};
@@ -680,18 +692,25 @@ static LatSched lat_sched(int m) {
     s.L = m;
     return s;
   }
-  s.L = 8 + (m - 8) % kLatHB;
-  s.np = (m - s.L) / kLatHB;
+  s.np = (m - 10 + kLatHB - 1) / kLatHB;  // fewest passes with L <= 10
+  s.L = m - kLatHB * s.np < 8 ? 8 : m - kLatHB * s.np;
+  int rest = m - s.L;
+  for (int q = 0; q < s.np; q++) {  // 5 bits first, the remainder spread over the top passes
+    const int w = (rest + (s.np - q) - 1) / (s.np - q);
+    s.hb[q] = w;
+    rest -= w;
+  }
   return s;
 }
 static size_t lat_lds_bytes(int L, size_t cbytes) {
   return ((size_t)lds_stride(L) + (L ? (1u << (L - 1)) : 0)) * cbytes;
 }
 
+// blocks per vector of the last adjoint pass (the top register pass)
 int lat_adj_blocks(int m, size_t /*cbytes*/) {
   const LatSched s = lat_sched(m);
   if (s.np == 0) return 1;
-  return 1 << (m - kLatHB - 8);
+  return 1 << (m - s.hb[s.np - 1] - 8);
 }
 
 #define MTGP_LAT_KT(kt, MACRO, ...)                   \
@@ -705,20 +724,27 @@ int lat_adj_blocks(int m, size_t /*cbytes*/) {
 
 // raw buffer addressing while the window of a block fits in 2^30 bytes
 template <typename CR>
-static bool lat_buf(int lo) {
-  return ((int64_t)sizeof(cx<CR>) << (lo + kLatHB)) <= ((int64_t)1 << 30);
+static bool lat_buf(int lo, int hb) {
+  return ((int64_t)sizeof(cx<CR>) << (lo + hb)) <= ((int64_t)1 << 30);
 }
 
 template <typename CR, int SRC, int KT>
-static void dif_reg(const LatTab& tab, dim3 grid, hipStream_t st, cx<CR>* work, int64_t vstride,
-                    int m, int lo, const void* y, int y_f32, const uint32_t* gen,
+static void dif_reg(const LatTab& tab, int nvec, hipStream_t st, cx<CR>* work, int64_t vstride,
+                    int m, int lo, int hb, const void* y, int y_f32, const uint32_t* gen,
                     const uint32_t* colshift, const Params* P, int d) {
-  if (lat_buf<CR>(lo))
-    hipLaunchKernelGGL((lat_dif_reg_kernel<CR, CR, kLatHB, SRC, KT, true>), grid, dim3(256), 0, st,
-                       tab, work, work, vstride, m, lo, y, y_f32, gen, colshift, P, d);
-  else
-    hipLaunchKernelGGL((lat_dif_reg_kernel<CR, CR, kLatHB, SRC, KT, false>), grid, dim3(256), 0,
-                       st, tab, work, work, vstride, m, lo, y, y_f32, gen, colshift, P, d);
+  const dim3 grid(1u << (m - hb - 8), nvec);
+  const bool buf = lat_buf<CR>(lo, hb);
+#define MTGP_DIF_REG(HB, BUF)                                                                   \
+  hipLaunchKernelGGL((lat_dif_reg_kernel<CR, CR, HB, SRC, KT, BUF>), grid, dim3(256), 0, st, tab, \
+                     work, work, vstride, m, lo, y, y_f32, gen, colshift, P, d)
+  if (hb == kLatHB) {
+    if (buf) MTGP_DIF_REG(kLatHB, true);
+    else MTGP_DIF_REG(kLatHB, false);
+  } else {
+    if (buf) MTGP_DIF_REG(4, true);
+    else MTGP_DIF_REG(4, false);
+  }
+#undef MTGP_DIF_REG
 }
 
 // Forward transform of nvec vectors (columns when src == SRC_GEN, data when
@@ -733,19 +759,19 @@ int launch_lat_forward(int src, cx<CR>* work, cx<SR>* spec, int64_t vstride, int
   const int kt = kt_of(kd.family, kd.order, kd.adaptive);
   const LatSched s = lat_sched(m);
   const LatTab tab = lat_tab();
-  const dim3 grid(1u << (m - kLatHB - 8), nvec);
   for (int q = s.np - 1; q >= 0; q--) {  // top pass first
-    const int lo = s.L + kLatHB * q;
+    const int lo = s.lo(q), hb = s.hb[q];
     if (q == s.np - 1) {
-#define FR(KTV, SRCV) \
-  dif_reg<CR, SRCV, KTV>(tab, grid, st, work, vstride, m, lo, y, y_f32, gen, colshift, P, kd.d)
+#define FR(KTV, SRCV)                                                                          \
+  dif_reg<CR, SRCV, KTV>(tab, nvec, st, work, vstride, m, lo, hb, y, y_f32, gen, colshift, P, \
+                         kd.d)
       if (src == SRC_GEN) MTGP_LAT_KT(kt, FR, SRC_GEN);
       else if (src == SRC_Y) FR(KT_SI1, SRC_Y);
       else FR(KT_SI1, SRC_X);
 #undef FR
     } else {
-      dif_reg<CR, SRC_WORK, KT_SI1>(tab, grid, st, work, vstride, m, lo, y, y_f32, gen, colshift,
-                                    P, kd.d);
+      dif_reg<CR, SRC_WORK, KT_SI1>(tab, nvec, st, work, vstride, m, lo, hb, y, y_f32, gen,
+                                    colshift, P, kd.d);
     }
   }
   if (s.np > 0 && s.L <= 10) {  // multi-pass: the wave pass over the low bits
@@ -801,21 +827,29 @@ int launch_lat_adjoint(int sink, const cx<SR>* spec, cx<CR>* work, double* real_
   }
 #undef AL_D
 #undef AL
-  const dim3 grid(1u << (m - kLatHB - 8), nvec);
   for (int q = 0; q < s.np; q++) {
-    const int lo = s.L + kLatHB * q;
+    const int lo = s.lo(q), hb = s.hb[q];
+    const dim3 grid(1u << (m - hb - 8), nvec);
     const bool last = q == s.np - 1;
-    const size_t stage = last && sink == SINK_REDUCE ? ((size_t)256 << kLatHB) * sizeof(CR) : 0;
-    const bool buf = lat_buf<CR>(lo);
-#define AR(DD, KTV, SINKV)                                                                       \
+    const size_t stage = last && sink == SINK_REDUCE ? ((size_t)256 << hb) * sizeof(CR) : 0;
+    const bool buf = lat_buf<CR>(lo, hb);
+#define AR_HB(HB, DD, KTV, SINKV)                                                                \
   if (buf)                                                                                       \
-    hipLaunchKernelGGL((lat_dit_reg_kernel<CR, kLatHB, SINKV, KTV, DD, true>), grid, dim3(256),  \
+    hipLaunchKernelGGL((lat_dit_reg_kernel<CR, HB, SINKV, KTV, DD, true>), grid, dim3(256),      \
                        stage, st, tab, work, real_out, vstride, m, lo, scale, gen, colshift, P,  \
                        kd.d, partials);                                                          \
   else                                                                                           \
-    hipLaunchKernelGGL((lat_dit_reg_kernel<CR, kLatHB, SINKV, KTV, DD, false>), grid, dim3(256), \
+    hipLaunchKernelGGL((lat_dit_reg_kernel<CR, HB, SINKV, KTV, DD, false>), grid, dim3(256),     \
                        stage, st, tab, work, real_out, vstride, m, lo, scale, gen, colshift, P,  \
                        kd.d, partials)
+#define AR(DD, KTV, SINKV)                 \
+  do {                                     \
+    if (hb == kLatHB) {                    \
+      AR_HB(kLatHB, DD, KTV, SINKV);       \
+    } else {                               \
+      AR_HB(4, DD, KTV, SINKV);            \
+    }                                      \
+  } while (0)
 #define AR_D(DD, KTV) AR(DD, KTV, SINK_REDUCE)
     if (!last) {
       AR(2, KT_SI1, SINK_WORK);
@@ -830,6 +864,7 @@ int launch_lat_adjoint(int sink, const cx<SR>* spec, cx<CR>* work, double* real_
     }
 #undef AR_D
 #undef AR
+#undef AR_HB
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -115,7 +115,7 @@ def test_fwht_large_sampled(dtype, log2n):
 # ---------------------------------------------------------------------- fft
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("log2n,batch", [(0, 2), (3, 3), (9, 2), (12, 2), (13, 2), (14, 2), (15, 1),
-                                          (16, 3), (20, 1), (22, 1), (24, 1)])
+                                          (16, 3), (17, 2), (20, 1), (21, 1), (22, 1), (24, 1)])
 @pytest.mark.parametrize("bitrev", [False, True])
 def test_fft_vs_numpy(dtype, log2n, batch, bitrev):
     say("fft", dtype, log2n, batch, bitrev)
@@ -251,7 +251,7 @@ def test_single_pass_high_bits_match_register_passes(m, sched, precision):
     np.testing.assert_allclose(t1, t0, rtol=1e-12, atol=1e-14)
 
 
-@pytest.mark.parametrize("family,m", [("dseq", 14), ("lat", 14)])
+@pytest.mark.parametrize("family,m", [("dseq", 14), ("lat", 14), ("lat", 16), ("lat", 17)])
 def test_gradient_matches_fd_of_gpu_loss_beyond_oracle_sizes(family, m):
     # a property at any size: the adjoint gradient equals central finite
     # differences of the same (FP64) loss, here at N = 3 * 2^14
