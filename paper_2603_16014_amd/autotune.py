@@ -21,7 +21,7 @@ CANDIDATES = [
     (12, 6, 36864), (13, 6, 36864), (12, 5, 36864), (12, 4, 36864), (11, 6, 36864),
     (10, 7, 36864), (12, 12, 36864),
 ]
-OVERLAPS = (1, 4, 8)
+OVERLAPS = (1, 4, 8, 16)
 FINALISTS = 3  # schedules also timed with each overlap setting
 
 
