@@ -112,6 +112,49 @@ def test_fwht_large_sampled(dtype, log2n):
     assert rel_err(back, x) < (1e-13 if dtype == torch.float64 else 1e-5) * log2n
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_fwht_2e28_wide_window_addressing(dtype):
+    # at 2^28 the top register pass covers a window above 2^30 bytes per
+    # block and runs with 64-bit row addresses instead of buffer resources
+    log2n = 28
+    say("fwht 2^28", dtype)
+    rng = np.random.default_rng(128)
+    n = 1 << log2n
+    x = rng.normal(size=n)
+    xt = torch.from_numpy(x).to(dtype).cuda()
+    mt.fwht(xt, log2n)
+    got = xt.double().cpu().numpy()
+    i = np.arange(n, dtype=np.uint64)
+    for f in (int(rng.integers(0, n)), n - 1, 3 << 26):
+        sign = 1.0 - 2.0 * (np.bitwise_count(i & np.uint64(f)) & 1)
+        ref = float(np.dot(sign, x))
+        tol = (1e-12 if dtype == torch.float64 else 3e-5) * np.sqrt(n)
+        assert abs(got[f] - ref) < tol, (f, got[f], ref)
+    del i, sign
+    mt.fwht(xt, log2n)
+    back = xt.double().cpu().numpy() / n
+    assert rel_err(back, x) < (1e-13 if dtype == torch.float64 else 1e-5) * log2n
+
+
+def test_fft_2e27_wide_window_addressing():
+    # at 2^27 the top lattice register pass covers a window above 2^30 bytes
+    # per block (64-bit row addresses); sampled DFT values and Parseval
+    log2n = 27
+    say("fft 2^27")
+    rng = np.random.default_rng(127)
+    n = 1 << log2n
+    x = rng.normal(size=n)
+    X = mt.fft(torch.from_numpy(x).cuda(), log2n).cpu().numpy()[0]
+    j = np.arange(n, dtype=np.int64)
+    for k in (1, int(rng.integers(0, n)), n - 3):
+        ang = (-2.0 * np.pi / n) * ((j * k) % n).astype(np.float64)
+        ref = complex(np.dot(x, np.cos(ang)), np.dot(x, np.sin(ang)))
+        assert abs(X[k] - ref) < 1e-10 * np.sqrt(n), (k, X[k], ref)
+    del j, ang
+    e_x, e_X = float(np.dot(x, x)), float(np.vdot(X, X).real) / n
+    assert abs(e_X - e_x) < 1e-12 * e_x
+
+
 # ---------------------------------------------------------------------- fft
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("log2n,batch", [(0, 2), (3, 3), (9, 2), (12, 2), (13, 2), (14, 2), (15, 1),

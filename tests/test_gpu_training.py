@@ -174,15 +174,17 @@ def test_nll_grad_batched_entry_point():
 
 
 @pytest.mark.parametrize("m,precision", [([8, 8, 8], "fp64"), ([14, 14, 14], "mixed"),
-                                         ([13, 13, 12, 9], "fp64"), ([14, 12, 12], "mixed")])
+                                         ([13, 13, 12, 9], "fp64"), ([14, 12, 12], "mixed"),
+                                         ([14] * 6, "mixed")])
 def test_overlap_is_bitwise_identical(m, precision):
-    """Chunked overlap of the digital-net passes changes only the schedule."""
+    """Chunked overlap of the digital-net passes changes only the schedule
+    (six equal tasks: 16 kernel columns, so 16 and 32 chunks are exercised)."""
     from _designs import tiny
     say("overlap", m, precision)
     w = tiny("dseq", len(m), m, 3, seed=31)
     plan, theta = _plan(w, precision)
     ref = None
-    for chunks in (1, 2, 3, 8, 4):
+    for chunks in (1, 2, 3, 8, 4, 16, 32):
         plan.set_overlap(chunks)
         out3, grad, tau = plan.nll_grad(theta)
         torch.cuda.synchronize()
