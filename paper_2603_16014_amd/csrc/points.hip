@@ -15,7 +15,7 @@
 // order of the transform
 // (radical-inverse order for digital sequences, natural lattice order j with
 // point j g / n + Delta for lattices).
-#include "kernels.h"
+#include "colgen.h"
 
 namespace mtgp {
 
@@ -45,13 +45,20 @@ int launch_gen_points(const uint32_t* gen, const uint32_t* shift, int family, in
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <typename Real, int FAM, int ADAPT, int D>
+// The kernel type and the dimension width are compile-time: each factor is
+// f_j = 1 + sc_j kappa_j (the scaled form of the fused column kernels, with
+// the order-2 FP64 table in LDS), padding dimensions have sc = 0 and give
+// f = 1 exactly.
+template <typename Real, int KT, int D>
 __global__ __launch_bounds__(256) void predict_direct_kernel(
     const uint32_t* __restrict__ gen, const uint32_t* __restrict__ shifts, PredTasks pt,
     PredChunks pc, const double* __restrict__ alpha, const uint32_t* __restrict__ xs, int64_t M,
     const Params* __restrict__ P, KDesc kd, double* __restrict__ part) {
+  constexpr int FAM = kt_family(KT);
   __shared__ uint32_t xk[256 * D];
   __shared__ double ak[256];
+  __shared__ Kap2Entry k2tab[uses_kap2_table<Real, KT>() ? 33 : 1];
+  if constexpr (uses_kap2_table<Real, KT>()) fill_kap2_table(k2tab);  // ordered by the loop's barriers
   const int d = kd.d;
   const int64_t mi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const bool active = mi < M;
@@ -63,11 +70,11 @@ __global__ __launch_bounds__(256) void predict_direct_kernel(
   const int64_t k_lo = (int64_t)(c - pc.cstart[u]) * pc.chunk;
   const int64_t k_hi = k_lo + pc.chunk < nu ? k_lo + pc.chunk : nu;
   uint32_t xm[D];
-  Real eta[D];
+  Real sc[D];
 #pragma unroll
   for (int j = 0; j < D; j++) {
     xm[j] = (active && j < d) ? xs[mi * d + j] : 0u;
-    eta[j] = j < d ? RT<Real>::eta(P, j) : (Real)0;
+    sc[j] = kscale<Real, KT>(j < d ? RT<Real>::eta(P, j) : (Real)0);
   }
   const Real gam = RT<Real>::gamma(P);
   const uint32_t* sh = shifts + (size_t)u * d;
@@ -76,9 +83,12 @@ __global__ __launch_bounds__(256) void predict_direct_kernel(
     __syncthreads();
     const int64_t k = k0 + threadIdx.x;
     if (k < k_hi) {
-      for (int j = 0; j < d; j++) {
-        xk[threadIdx.x * D + j] = (FAM == FAM_DSEQ) ? (dseq_z(gen + 32 * j, (uint32_t)k) ^ sh[j])
-                                                    : (lat_z(gen[j], (uint32_t)k, pt.m[u]) + sh[j]);
+      for (int j = 0; j < D; j++) {
+        uint32_t x = 0u;
+        if (j < d)
+          x = (FAM == FAM_DSEQ) ? (dseq_z(gen + 32 * j, (uint32_t)k) ^ sh[j])
+                                : (lat_z(gen[j], (uint32_t)k, pt.m[u]) + sh[j]);
+        xk[threadIdx.x * D + j] = x;
       }
       ak[threadIdx.x] = alpha[pt.off[u] + k];
     }
@@ -88,10 +98,9 @@ __global__ __launch_bounds__(256) void predict_direct_kernel(
       Real qv = gam;
 #pragma unroll
       for (int j = 0; j < D; j++) {
-        // padding slots: eta = 0, so the factor is exactly 1
-        const uint32_t x2 = xk[q * D + (j < d ? j : 0)];
+        const uint32_t x2 = xk[q * D + j];
         const uint32_t uu = (FAM == FAM_DSEQ) ? (xm[j] ^ x2) : (xm[j] - x2);
-        qv = fma(qv * eta[j], univ_value<Real, FAM, ADAPT>(kd.order, uu, P), qv);
+        qv *= fma(sc[j], kappa_t<Real, KT>(uu, P, k2tab), (Real)1);
       }
       acc += (double)qv * ak[q];
     }
@@ -127,23 +136,20 @@ int launch_predict_direct(const uint32_t* gen, const uint32_t* shifts, const Pre
                           hipStream_t st) {
   if (M <= 0) return 0;
   const dim3 grid((unsigned)((M + 255) / 256), (unsigned)pc.cstart[kd.T]), block(256);
-#define MTGP_PRED(F, A, DD)                                                                      \
-  hipLaunchKernelGGL((predict_direct_kernel<Real, F, A, DD>), grid, block, 0, st, gen, shifts,   \
+#define MTGP_PRED(DD, KTV)                                                                       \
+  hipLaunchKernelGGL((predict_direct_kernel<Real, KTV, DD>), grid, block, 0, st, gen, shifts,     \
                      pt, pc, alpha, xs, M, P, kd, part)
-#define MTGP_PRED_D(F, A)                     \
-  do {                                        \
-    if (kd.d <= 4) MTGP_PRED(F, A, 4);        \
-    else if (kd.d <= 8) MTGP_PRED(F, A, 8);   \
-    else if (kd.d <= 12) MTGP_PRED(F, A, 12); \
-    else if (kd.d <= 16) MTGP_PRED(F, A, 16); \
-    else MTGP_PRED(F, A, 32);                 \
-  } while (0)
-  if (kd.family == FAM_DSEQ) {
-    if (kd.adaptive) MTGP_PRED_D(FAM_DSEQ, 1); else MTGP_PRED_D(FAM_DSEQ, 0);
-  } else {
-    MTGP_PRED_D(FAM_LAT, 0);
+  switch (kt_of(kd.family, kd.order, kd.adaptive)) {
+    case KT_DSI1: MTGP_DISPATCH_D(kd.d, MTGP_PRED, KT_DSI1); break;
+    case KT_DSI2: MTGP_DISPATCH_D(kd.d, MTGP_PRED, KT_DSI2); break;
+    case KT_DSI3: MTGP_DISPATCH_D(kd.d, MTGP_PRED, KT_DSI3); break;
+    case KT_DSI4: MTGP_DISPATCH_D(kd.d, MTGP_PRED, KT_DSI4); break;
+    case KT_DSIA: MTGP_DISPATCH_D(kd.d, MTGP_PRED, KT_DSIA); break;
+    case KT_SI1: MTGP_DISPATCH_D(kd.d, MTGP_PRED, KT_SI1); break;
+    case KT_SI2: MTGP_DISPATCH_D(kd.d, MTGP_PRED, KT_SI2); break;
+    case KT_SI3: MTGP_DISPATCH_D(kd.d, MTGP_PRED, KT_SI3); break;
+    default: return -1;
   }
-#undef MTGP_PRED_D
 #undef MTGP_PRED
   if (hipGetLastError() != hipSuccess) return -1;
   hipLaunchKernelGGL(predict_reduce_kernel, dim3((unsigned)((M + 255) / 256)), block, 0, st, part,
