@@ -6,9 +6,11 @@
 //           columns the block is generated in registers first (fused column
 //           evaluation, Eq. prod_kernel), so raw columns never reach HBM.
 //   pass B: bits [lo, lo + hb); for hb <= 6 each thread holds the 2^hb
-//           strided rows of one low index in registers (no LDS), wider
-//           passes use tiles of KC consecutive low indices times 2^hb
-//           strided rows, LDS resident.
+//           strided rows of one low index in registers (no LDS, rows
+//           addressed through raw buffer resources); hb = 8, 10, 12 run in
+//           one pass through registers and one LDS tile (fwht_hi_kernel);
+//           other wider passes use tiles of KC consecutive low indices
+//           times 2^hb strided rows, LDS resident.
 // The stages of a Walsh-Hadamard transform commute, so the split needs no
 // twiddles and the output stays in natural (Sylvester) order.
 #include "colgen.h"
