@@ -17,6 +17,9 @@ kernels  SI Bernoulli kernels (Eq. SI_kernel_1d_ex), adaptive-smoothness DSI
 dense    Gram matrix, MLE loss, optimal means, gradient, posterior mean
          (Eqs. MTGP_post_mean_cov, MTGP_MLE_GCV_loss, MTGP_optimal_tau).
 hp       ctypes front-end of the extended-precision twin.
+spectral equal-size MLE loss through the per-frequency blocks of Theorem
+         "Fast MTGP computations" (numpy Walsh / DFT, O(T^3 n + T^2 n log n));
+         pinned to ``dense``, it carries loss parity beyond dense sizes.
 
 Parity status per function is listed in the module docstrings; every
 function here is pinned by a ``-m "not gpu"`` test except where its

@@ -268,6 +268,33 @@ def test_lattice_two_pass_against_oracle(precision):
     assert rel_err(mean, ref["mean"]) < (1e-9 if precision == "fp64" else 1e-4)
 
 
+@pytest.mark.parametrize("family,m,T,d", [("dseq", 16, 3, 3), ("dseq", 20, 2, 3), ("lat", 17, 3, 3),
+                                          ("lat", 21, 2, 3), ("dseq", 18, 8, 10), ("lat", 18, 8, 10)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_loss_against_spectral_oracle_beyond_dense_sizes(family, m, T, d, precision):
+    # the spectral oracle (pinned to the dense one on small designs) at sizes
+    # the dense oracle cannot factor: N = T 2^m up to 2^22, lattice schedules
+    # with 4-bit register passes (m = 17, 21), and the config-5 task and
+    # dimension counts (T = 8, d = 10) at 2^18 points per task
+    from oracle import dense, points, spectral
+    w = tiny(family, T, [m] * T, d, seed=65 + m, xi=1e-2, rank=2)
+    say("loss vs spectral oracle", family, m, T, precision)
+    y = dense.targets(w, np.random.default_rng(w.seed + 1000), points.task_points(w))
+    ref = spectral.nll_equal(w, y)
+    plan = mt.Plan.from_workload(w, precision)
+    plan.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
+    out3, tau = plan.nll(plan.pack_theta(w.theta))
+    torch.cuda.synchronize()
+    assert plan.status() == (0, -1)
+    out3 = out3.cpu().numpy()
+    den = abs(ref["quad"]) + abs(ref["logdet"])
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert abs(out3[2] - ref["L"]) < tol * den, (out3, ref["L"])
+    assert abs(out3[1] - ref["logdet"]) < tol * den
+    np.testing.assert_allclose(tau.cpu().numpy(), ref["tau_hat"],
+                               rtol=1e-9 if precision == "fp64" else 1e-5, atol=1e-12)
+
+
 @pytest.mark.parametrize("m,sched", [(13, (3, 10, 4096)), (16, (6, 10, 4096)), (16, (8, 8, 4096)),
                                      (19, (7, 12, 36864)), (20, (12, 8, 36864))])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
