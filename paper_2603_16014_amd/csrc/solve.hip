@@ -472,14 +472,40 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   __shared__ double red[16];
   __shared__ double sums[64];
   __shared__ double Gm[MTGP_MAXT * MTGP_MAXT];
+  // the small tables of the chain rule, staged by all threads: the serial
+  // code below then reads LDS instead of a chain of dependent global loads
+  // (column pair -> R entry), about two memory latencies per column
+  __shared__ double s_cs[MTGP_MAXCOL * (MTGP_MAXD + 5)];
+  __shared__ int s_tu[2 * MTGP_MAXCOL];
+  __shared__ double s_R[MTGP_MAXT * MTGP_MAXT];
+  __shared__ double s_B[MTGP_MAXT * MTGP_MAXS];
   const int T = kd.T, d = kd.d, s = kd.s;
   const int ns = solve_ns(T);
   const int nq = adj_nq(d);
-  for (int q = 0; q < ns; q++) {
+  if (grad) {
+    for (int i = threadIdx.x; i < ncol * nq; i += blockDim.x) s_cs[i] = cs[i];
+    for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+      s_tu[2 * c] = ci[c].t;
+      s_tu[2 * c + 1] = ci[c].u;
+    }
+    for (int i = threadIdx.x; i < T * s; i += blockDim.x) s_B[i] = P->B[i];
+  }
+  for (int i = threadIdx.x; i < MTGP_MAXT * MTGP_MAXT; i += blockDim.x) s_R[i] = P->R[i];
+  // all ns slots in one pass (fixed order): thread (g, q) sums the rows
+  // g, g + ng, ... of slot q, then one thread per slot adds the ng groups
+  __shared__ double part[256];
+  const int ng = blockDim.x / ns;  // ns <= 2 + 3 MTGP_MAXT, so ng >= 5
+  if ((int)threadIdx.x < ng * ns) {
+    const int q = threadIdx.x % ns, g = threadIdx.x / ns;
     double v = 0.0;
-    for (int b = threadIdx.x; b < nsolve; b += blockDim.x) v += sp[(size_t)b * ns + q];
-    v = block_sum(v, red);
-    if (threadIdx.x == 0) sums[q] = v;
+    for (int b = g; b < nsolve; b += ng) v += sp[(size_t)b * ns + q];
+    part[threadIdx.x] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < ns) {
+    double v = 0.0;
+    for (int g = 0; g < ng; g++) v += part[g * ns + threadIdx.x];
+    sums[threadIdx.x] = v;
   }
   double ldx = 0.0;  // log pivots of the elimination stages (unequal sizes)
   if (lp)
@@ -518,9 +544,9 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   double geta[MTGP_MAXD + 4];
   for (int q = 0; q < d + 4; q++) geta[q] = 0.0;
   for (int c = 0; c < ncol; c++) {
-    const int t = ci[c].t, u = ci[c].u;
-    const double* row = cs + (size_t)c * nq;
-    const double Rc = t == u ? 1.0 : P->R[t * MTGP_MAXT + u];
+    const int t = s_tu[2 * c], u = s_tu[2 * c + 1];
+    const double* row = s_cs + (size_t)c * nq;
+    const double Rc = t == u ? 1.0 : s_R[t * MTGP_MAXT + u];
     if (t != u) Gm[t * MTGP_MAXT + u] = Gm[u * MTGP_MAXT + t] = 0.5 * row[0];
     for (int q = 0; q < d + 4; q++) geta[q] += Rc * row[1 + q];
   }
@@ -531,7 +557,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   o += T;
   double gg = 0.0;
   for (int t = 0; t < T; t++)
-    for (int u = 0; u < T; u++) gg += P->R[t * MTGP_MAXT + u] * G(t, u);
+    for (int u = 0; u < T; u++) gg += s_R[t * MTGP_MAXT + u] * G(t, u);
   grad[o++] = gg;
   for (int j = 0; j < d; j++) grad[o + j] = geta[j];
   o += d;
@@ -544,7 +570,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
   for (int t = 0; t < T; t++)
     for (int k = 0; k < s; k++) {
       double acc = 0.0;
-      for (int u = 0; u < T; u++) acc += 2.0 * G(t, u) * P->B[u * s + k];
+      for (int u = 0; u < T; u++) acc += 2.0 * G(t, u) * s_B[u * s + k];
       grad[o + t * s + k] = acc;
     }
   o += T * s;
