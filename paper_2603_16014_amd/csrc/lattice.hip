@@ -260,6 +260,58 @@ struct LatReduce {
 };
 
 // ---------------------------------------------------------------------------
+// radix-2^HB butterflies of one register pass over the bits [lo, lo + HB)
+// on the 2^HB values a[r] (row r at index low + (r << lo)) that share the
+// index `low` below lo.  The twiddle of the stage at bit lo + s is
+// e^{-i pi low / 2^(lo+s)} (a per-thread base, squared from stage to stage)
+// times e^{-i pi (r mod 2^s) / 2^s} (constant table).
+// ---------------------------------------------------------------------------
+template <typename CR, int HB>
+__device__ inline void dif_regs(cx<CR> (&a)[1 << HB], const LatTab& tab, int64_t low, int lo) {
+  constexpr int R = 1 << HB;
+  cx<double> B = expmpi(low, lo + HB - 1);
+#pragma unroll
+  for (int s = HB - 1; s >= 0; s--) {
+    const cx<CR> b = to_cx<CR>(B);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      if (!(r & (1 << s))) {
+        const int t = (r & ((1 << s) - 1)) << (4 - s);
+        const cx<CR> w = t == 0 ? b : cmul<CR>(b, {(CR)tab.c[t], (CR)tab.s[t]});
+        const cx<CR> A = a[r], C = a[r + (1 << s)];
+        a[r] = cadd(A, C);
+        a[r + (1 << s)] = cmul<CR>(csub(A, C), w);
+      }
+    }
+    B = cmul<double>(B, B);
+  }
+}
+
+// the transpose (decimation in time, stages from bit lo upwards)
+template <typename CR, int HB>
+__device__ inline void dit_regs(cx<CR> (&a)[1 << HB], const LatTab& tab, int64_t low, int lo) {
+  constexpr int R = 1 << HB;
+  cx<double> Bs[HB];
+  Bs[HB - 1] = expmpi(low, lo + HB - 1);
+#pragma unroll
+  for (int s = HB - 2; s >= 0; s--) Bs[s] = cmul<double>(Bs[s + 1], Bs[s + 1]);
+#pragma unroll
+  for (int s = 0; s < HB; s++) {
+    const cx<CR> b = to_cx<CR>(Bs[s]);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      if (!(r & (1 << s))) {
+        const int t = (r & ((1 << s) - 1)) << (4 - s);
+        const cx<CR> w = t == 0 ? b : cmul<CR>(b, {(CR)tab.c[t], (CR)tab.s[t]});
+        const cx<CR> A = a[r], C = cmul<CR>(a[r + (1 << s)], w);
+        a[r] = cadd(A, C);
+        a[r + (1 << s)] = csub(A, C);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // register passes over the bits [lo, lo + HB): grid (2^(m - HB - 8), nvec),
 // 256 threads; block x covers 256 consecutive low indices of one high index
 // ---------------------------------------------------------------------------
@@ -326,22 +378,7 @@ __global__ __launch_bounds__(256) void lat_dif_reg_kernel(
         a[r] = {src_value<CR, SRC, KT>(y, y_f32, v, (uint32_t)i, m, gen, colshift, P, d), (CR)0};
     }
   }
-  cx<double> B = expmpi(ix.low, lo + HB - 1);
-#pragma unroll
-  for (int s = HB - 1; s >= 0; s--) {
-    const cx<CR> b = to_cx<CR>(B);
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-      if (!(r & (1 << s))) {
-        const int t = (r & ((1 << s) - 1)) << (4 - s);
-        const cx<CR> w = t == 0 ? b : cmul<CR>(b, {(CR)tab.c[t], (CR)tab.s[t]});
-        const cx<CR> A = a[r], C = a[r + (1 << s)];
-        a[r] = cadd(A, C);
-        a[r + (1 << s)] = cmul<CR>(csub(A, C), w);
-      }
-    }
-    B = cmul<double>(B, B);
-  }
+  dif_regs<CR, HB>(a, tab, ix.low, lo);
 #pragma unroll
   for (int r = 0; r < R; r++) {
     const cx<TOut> o = {(TOut)a[r].x, (TOut)a[r].y};
@@ -379,24 +416,7 @@ __global__ __launch_bounds__(256) void lat_dit_reg_kernel(
     else
       a[r] = (work + vb + ((int64_t)r << lo))[threadIdx.x];
   }
-  cx<double> Bs[HB];
-  Bs[HB - 1] = expmpi(ix.low, lo + HB - 1);
-#pragma unroll
-  for (int s = HB - 2; s >= 0; s--) Bs[s] = cmul<double>(Bs[s + 1], Bs[s + 1]);
-#pragma unroll
-  for (int s = 0; s < HB; s++) {
-    const cx<CR> b = to_cx<CR>(Bs[s]);
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-      if (!(r & (1 << s))) {
-        const int t = (r & ((1 << s) - 1)) << (4 - s);
-        const cx<CR> w = t == 0 ? b : cmul<CR>(b, {(CR)tab.c[t], (CR)tab.s[t]});
-        const cx<CR> A = a[r], C = cmul<CR>(a[r + (1 << s)], w);
-        a[r] = cadd(A, C);
-        a[r + (1 << s)] = csub(A, C);
-      }
-    }
-  }
+  dit_regs<CR, HB>(a, tab, ix.low, lo);
   if constexpr (SINK == SINK_WORK) {
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -419,6 +439,147 @@ __global__ __launch_bounds__(256) void lat_dit_reg_kernel(
     lr.init(gen, colshift + (size_t)v * d, d, P, (uint32_t)ix.at(0, lo), 1u << lo, m);
 #pragma unroll 1
     for (int r = 0; r < R; r++) lr.add(stage[r * 256 + threadIdx.x]);
+    lr.store(d, red, partials + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * adj_nq(d));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tile passes: the two top 5-bit register passes, bits [lo, lo + 10), in one
+// pass.  A block takes the 8 adjacent low indices j0 .. j0 + 7 (runs of 128
+// bytes per row) over all 1024 rows hi = h1 + 32 h2 (h1: bits lo .. lo + 4,
+// h2: bits lo + 5 .. lo + 9).  Phase 1: thread (c, h1) runs the pass over
+// h2 on its 32 rows (the index below lo + 5 is j0 + c + (h1 << lo)); the
+// values go through an LDS tile; phase 2: thread (c, h2) runs the pass over
+// h1 (index below lo: j0 + c).  The arithmetic is that of the two register
+// passes; the HBM traffic of one.  Grid (2^(m - 13), nvec): 2^(lo - 3) column
+// groups times the 2^(m - lo - 10) values of the index above lo + 10; 256 threads,
+// dynamic LDS lat_tile_lds_bytes; rows through raw buffer resources over a
+// window of 2^(lo + 10) elements (below 2^30 bytes).
+// ---------------------------------------------------------------------------
+constexpr int kTileKC = 8, kTileR = 32, kTilePad = kTileKC;
+__host__ __device__ inline int tile_at(int hi, int c) {
+  // one run of padding per 32 rows keeps a phase-2 access on distinct banks
+  return hi * kTileKC + c + (hi >> 5) * kTilePad;
+}
+static size_t lat_tile_lds_bytes(size_t cbytes) {
+  return ((size_t)kTileR * kTileR * kTileKC + (size_t)kTileR * kTilePad) * cbytes;
+}
+
+template <typename CR, int SRC, int KT>
+__global__ __launch_bounds__(256) void lat_dif_tile_kernel(
+    const LatTab tab, cx<CR>* __restrict__ work, int64_t vstride, int m, int lo,
+    const void* __restrict__ y, int y_f32, const uint32_t* __restrict__ gen,
+    const uint32_t* __restrict__ colshift, const Params* __restrict__ P, int d) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<CR>* tile = reinterpret_cast<cx<CR>*>(smem);
+  const int v = blockIdx.y;
+  // block x: column group (the low lo - 3 bits) and the index above lo + 10
+  const int cgb = lo - 3;
+  const int64_t j0 = (int64_t)(blockIdx.x & ((1u << cgb) - 1)) * kTileKC;
+  const int64_t hiw = ((int64_t)blockIdx.x >> cgb) << (lo + 10);
+  const int c = threadIdx.x & (kTileKC - 1), h = threadIdx.x >> 3;
+  constexpr uint32_t cb = sizeof(cx<CR>);
+  const __amdgpu_buffer_rsrc_t rw =
+      buf_rsrc(work + (int64_t)v * vstride + hiw + j0, (int)(cb << (lo + 10)));
+  cx<CR> a[kTileR];
+  // phase 1: thread (c, h1 = h), rows h2 = r at index hiw + low1 + (r << (lo + 5))
+  {
+    const int64_t low1 = j0 + c + ((int64_t)h << lo);
+    if constexpr (SRC == SRC_GEN) {
+      CR cv[kTileR];
+#pragma unroll
+      for (int r = 0; r < kTileR; r++) cv[r] = RT<CR>::gamma(P);
+      const uint32_t* sh = colshift + (size_t)v * d;
+      for (int q = 0; q < d; q++) {
+        SiFactor<CR, KT> fk;
+        fk.init(RT<CR>::eta(P, q));
+        uint32_t u = lat_z(gen[q], (uint32_t)(hiw + low1), m) + sh[q];
+        const uint32_t step = lat_z(gen[q], 1u << (lo + 5), m);
+#pragma unroll
+        for (int r = 0; r < kTileR; r++) {
+          cv[r] = fma(cv[r], fk.eta_k(u), cv[r]);
+          u += step;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kTileR; r++) a[r] = {cv[r], (CR)0};
+    } else {
+#pragma unroll
+      for (int r = 0; r < kTileR; r++)
+        a[r] = {src_value<CR, SRC, KT>(y, y_f32, v,
+                                       (uint32_t)(hiw + low1 + ((int64_t)r << (lo + 5))), m, gen,
+                                       colshift, P, d),
+                (CR)0};
+    }
+    dif_regs<CR, 5>(a, tab, low1, lo + 5);
+#pragma unroll
+    for (int r = 0; r < kTileR; r++) tile[tile_at(h + kTileR * r, c)] = a[r];
+  }
+  __syncthreads();
+  // phase 2: thread (c, h2 = h), rows h1 = r
+#pragma unroll
+  for (int r = 0; r < kTileR; r++) a[r] = tile[tile_at(r + kTileR * h, c)];
+  dif_regs<CR, 5>(a, tab, j0 + c, lo);
+#pragma unroll
+  for (int r = 0; r < kTileR; r++)  // lane part in the vector offset, row part scalar
+    buf_store<cx<CR>>(a[r], rw, ((uint32_t)c + ((uint32_t)h << (lo + 5))) * cb,
+                      ((uint32_t)r << lo) * cb);
+}
+
+// Adjoint: phase 1 runs the DIT pass over h1 (bits lo .. lo + 4), phase 2 the
+// one over h2 and the sink: SINK_WORK stores, SINK_REAL writes Re * scale,
+// SINK_REDUCE accumulates the derivative sums (one partial row per block).
+template <typename CR, int SINK, int KT, int D>
+__global__ __launch_bounds__(256) void lat_dit_tile_kernel(
+    const LatTab tab, cx<CR>* __restrict__ work, double* __restrict__ real_out, int64_t vstride,
+    int m, int lo, double scale, const uint32_t* __restrict__ gen,
+    const uint32_t* __restrict__ colshift, const Params* __restrict__ P, int d,
+    double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[4 * (D + 1)];
+  cx<CR>* tile = reinterpret_cast<cx<CR>*>(smem);
+  const int v = blockIdx.y;
+  // block x: column group (the low lo - 3 bits) and the index above lo + 10
+  const int cgb = lo - 3;
+  const int64_t j0 = (int64_t)(blockIdx.x & ((1u << cgb) - 1)) * kTileKC;
+  const int64_t hiw = ((int64_t)blockIdx.x >> cgb) << (lo + 10);
+  const int c = threadIdx.x & (kTileKC - 1), h = threadIdx.x >> 3;
+  constexpr uint32_t cb = sizeof(cx<CR>);
+  const __amdgpu_buffer_rsrc_t rw =
+      buf_rsrc(work + (int64_t)v * vstride + hiw + j0, (int)(cb << (lo + 10)));
+  cx<CR> a[kTileR];
+  // phase 1: thread (c, h2 = h), rows h1 = r
+#pragma unroll
+  for (int r = 0; r < kTileR; r++)  // lane part in the vector offset, row part scalar
+    a[r] = buf_load<cx<CR>>(rw, ((uint32_t)c + ((uint32_t)h << (lo + 5))) * cb,
+                            ((uint32_t)r << lo) * cb);
+  dit_regs<CR, 5>(a, tab, j0 + c, lo);
+#pragma unroll
+  for (int r = 0; r < kTileR; r++) tile[tile_at(r + kTileR * h, c)] = a[r];
+  __syncthreads();
+  // phase 2: thread (c, h1 = h), rows h2 = r at index low1 + (r << (lo + 5))
+  const int64_t low1 = j0 + c + ((int64_t)h << lo);
+#pragma unroll
+  for (int r = 0; r < kTileR; r++) a[r] = tile[tile_at(h + kTileR * r, c)];
+  dit_regs<CR, 5>(a, tab, low1, lo + 5);
+  if constexpr (SINK == SINK_WORK) {
+#pragma unroll
+    for (int r = 0; r < kTileR; r++)
+      buf_store<cx<CR>>(a[r], rw, ((uint32_t)c + ((uint32_t)h << lo)) * cb,
+                        ((uint32_t)r << (lo + 5)) * cb);
+  } else if constexpr (SINK == SINK_REAL) {
+#pragma unroll
+    for (int r = 0; r < kTileR; r++)
+      real_out[((size_t)v << m) + hiw + low1 + ((int64_t)r << (lo + 5))] = (double)a[r].x * scale;
+  } else {
+    // the thread rewrites only the tile slots it read, so no barrier
+    CR* stage = reinterpret_cast<CR*>(smem);
+#pragma unroll
+    for (int r = 0; r < kTileR; r++) stage[2 * tile_at(h + kTileR * r, c)] = a[r].x;
+    LatReduce<CR, KT, D> lr;
+    lr.init(gen, colshift + (size_t)v * d, d, P, (uint32_t)(hiw + low1), 1u << (lo + 5), m);
+#pragma unroll 1
+    for (int r = 0; r < kTileR; r++) lr.add(stage[2 * tile_at(h + kTileR * r, c)]);
     lr.store(d, red, partials + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * adj_nq(d));
   }
 }
@@ -706,6 +867,14 @@ static size_t lat_lds_bytes(int L, size_t cbytes) {
   return ((size_t)lds_stride(L) + (L ? (1u << (L - 1)) : 0)) * cbytes;
 }
 
+// the two top register passes as one tile pass: both 5 bits wide, the window
+// of a block (2^(lo + 10) elements) below 2^30 bytes; its grid has as many
+// blocks per vector as the top register pass (2^(lo - 3) = 2^(m - 13))
+static bool lat_tile(const LatSched& s, size_t cbytes) {
+  if (s.np < 2 || s.hb[s.np - 1] != 5 || s.hb[s.np - 2] != 5) return false;
+  return (cbytes << (s.lo(s.np - 2) + 10)) <= ((size_t)1 << 30);
+}
+
 // blocks per vector of the last adjoint pass (the top register pass)
 int lat_adj_blocks(int m, size_t /*cbytes*/) {
   const LatSched s = lat_sched(m);
@@ -759,7 +928,20 @@ int launch_lat_forward(int src, cx<CR>* work, cx<SR>* spec, int64_t vstride, int
   const int kt = kt_of(kd.family, kd.order, kd.adaptive);
   const LatSched s = lat_sched(m);
   const LatTab tab = lat_tab();
-  for (int q = s.np - 1; q >= 0; q--) {  // top pass first
+  const bool tile = lat_tile(s, sizeof(cx<CR>));
+  if (tile) {  // the two top passes in one
+    const int lo = s.lo(s.np - 2);
+    const dim3 gridT(1u << (m - 13), nvec);  // 2^(lo - 3) groups x 2^(m - lo - 10)
+    const size_t lds = lat_tile_lds_bytes(sizeof(cx<CR>));
+#define FT(KTV, SRCV)                                                                          \
+  hipLaunchKernelGGL((lat_dif_tile_kernel<CR, SRCV, KTV>), gridT, dim3(256), lds, st, tab, work, \
+                     vstride, m, lo, y, y_f32, gen, colshift, P, kd.d)
+    if (src == SRC_GEN) MTGP_LAT_KT(kt, FT, SRC_GEN);
+    else if (src == SRC_Y) FT(KT_SI1, SRC_Y);
+    else FT(KT_SI1, SRC_X);
+#undef FT
+  }
+  for (int q = tile ? s.np - 3 : s.np - 1; q >= 0; q--) {  // top pass first
     const int lo = s.lo(q), hb = s.hb[q];
     if (q == s.np - 1) {
 #define FR(KTV, SRCV)                                                                          \
@@ -827,7 +1009,36 @@ int launch_lat_adjoint(int sink, const cx<SR>* spec, cx<CR>* work, double* real_
   }
 #undef AL_D
 #undef AL
-  for (int q = 0; q < s.np; q++) {
+  // tile pass: with three or more register passes, the two lowest (work to
+  // work; the reducing top pass keeps its register pass at 3 waves per SIMD),
+  // with two, both of them with the final sink
+  const bool low_tile = s.np >= 3 && s.hb[0] == 5 && s.hb[1] == 5 &&
+                        (sizeof(cx<CR>) << (s.lo(0) + 10)) <= ((size_t)1 << 30);
+  const bool top_tile = s.np == 2 && lat_tile(s, sizeof(cx<CR>));
+  if (low_tile || top_tile) {
+    const int lo = s.lo(0);
+    const dim3 gridT(1u << (m - 13), nvec);  // 2^(lo - 3) groups x 2^(m - lo - 10)
+    const size_t lds = lat_tile_lds_bytes(sizeof(cx<CR>));
+#define AT(DD, KTV, SINKV)                                                                     \
+  hipLaunchKernelGGL((lat_dit_tile_kernel<CR, SINKV, KTV, DD>), gridT, dim3(256), lds, st, tab, \
+                     work, real_out, vstride, m, lo, scale, gen, colshift, P, kd.d, partials)
+#define AT_D(DD, KTV) AT(DD, KTV, SINK_REDUCE)
+    if (low_tile) {
+      AT(2, KT_SI1, SINK_WORK);
+    } else if (sink == SINK_REAL) {
+      AT(2, KT_SI1, SINK_REAL);
+    } else {
+      switch (kt) {
+        case KT_SI1: MTGP_DISPATCH_D(kd.d, AT_D, KT_SI1); break;
+        case KT_SI2: MTGP_DISPATCH_D(kd.d, AT_D, KT_SI2); break;
+        default: MTGP_DISPATCH_D(kd.d, AT_D, KT_SI3); break;
+      }
+    }
+#undef AT_D
+#undef AT
+    if (top_tile) return hipGetLastError() == hipSuccess ? 0 : -1;
+  }
+  for (int q = low_tile ? 2 : 0; q < s.np; q++) {
     const int lo = s.lo(q), hb = s.hb[q];
     const dim3 grid(1u << (m - hb - 8), nvec);
     const bool last = q == s.np - 1;
