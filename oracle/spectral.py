@@ -26,8 +26,24 @@ Both V^dagger 1 = sqrt(n) e_0, so the normal equations of the optimal means
 (Eq. MTGP_optimal_tau) involve frequency 0 only:
   n Lambda(0)^-1 tau_hat = sqrt(n) Lambda(0)^-1 yhat(0).
 
+Nested sizes (any task order).  With n_t >= n_u the points of task u are
+the first n_u points of the same sequence as task t, so block (t, u) is the
+first n_u columns of the n_t x n_t convolution with c_tu of length n_t, and
+in the spectral bases of the two tasks it is
+
+  [V_t^dagger K_tu V_u](f, g) = sqrt(n_u / n_t) R_tu lambda_tu(f) [f = g mod n_u]
+
+(for nets H_t[f, k] = H_u[f mod n_u, k] when k < n_u; for lattices the
+points of u sit at every (n_t / n_u)-th natural position of t).  Frequencies
+therefore fall into independent residue classes r mod n_min, each a dense
+Hermitian matrix over the members (t, f = r + n_min k), k < n_t / n_min.
+The MLE and GCV losses are sums over the classes; the means live in class 0
+(V_t^dagger 1 = sqrt(n_t) e_0).  `mle` and `gcv` take this route for any
+sizes, equal sizes included.
+
 Pinned by: the dense oracle (tests/test_oracle_spectral.py) on small
-designs of both families, every kernel order, fixed and profiled means.
+designs of both families, every kernel order, fixed and profiled means,
+equal and nested sizes in several task orders.
 """
 import numpy as np
 
@@ -122,3 +138,136 @@ def nll_equal(w, y, theta=None, profile=None):
     a = np.linalg.solve(Lam, rhat[..., None])[..., 0]
     quad = float(np.real(np.sum(np.conj(rhat) * a)))
     return dict(quad=quad, logdet=logdet, L=quad + logdet, tau_hat=tau)
+
+
+# ------------------------------------------------------------- nested sizes
+def _task_spectrum(w, t, v):
+    """V_t^dagger v for one task's vector v (oracle point order)."""
+    n = 1 << w.m[t]
+    v = np.asarray(v, dtype=np.float64)
+    if w.family == "dseq":
+        return walsh(v) / np.sqrt(n)
+    nat = np.empty_like(v)
+    nat[_bitrev(n)] = v
+    return np.fft.fft(nat) / np.sqrt(n)
+
+
+class _Classes:
+    """Residue-class blocks of Ktilde in the tasks' spectral bases."""
+
+    def __init__(self, w, theta):
+        self.w, self.T = w, w.T
+        self.n = [1 << m for m in w.m]
+        self.nmin = min(self.n)
+        self.size = [nt // self.nmin for nt in self.n]          # members per class
+        self.off = np.concatenate([[0], np.cumsum(self.size)]).astype(np.int64)
+        self.c = int(self.off[-1])
+        self.real = w.family == "dseq"
+        self.R = task_cov(theta)
+        self.xi = np.asarray(theta["xi"], dtype=np.float64)
+        self.lam = {}
+        for t in range(self.T):
+            for u in range(self.T):
+                big = self.n[t] > self.n[u] or (self.n[t] == self.n[u] and t <= u)
+                if big:
+                    c = _column(self.w, theta, t, u)
+                    self.lam[(t, u)] = walsh(c) if self.real else np.fft.fft(c)
+
+    def matrices(self, r):
+        """Dense class matrices for the classes in r, shape [len(r), c, c]."""
+        r = np.asarray(r, dtype=np.int64)
+        M = np.zeros((r.size, self.c, self.c), dtype=np.float64 if self.real else np.complex128)
+        for (t, u), lam in self.lam.items():
+            k = np.arange(self.size[t])
+            l = k % self.size[u]
+            vals = np.sqrt(self.n[u] / self.n[t]) * self.R[t, u] * lam[r[:, None] + self.nmin * k[None, :]]
+            if self.real:
+                vals = vals.real
+            M[:, self.off[t] + k, self.off[u] + l] += vals
+            if t != u:
+                M[:, self.off[u] + l, self.off[t] + k] += np.conj(vals)
+        for t in range(self.T):
+            i = self.off[t] + np.arange(self.size[t])
+            M[:, i, i] += self.xi[t]
+        return M
+
+    def data(self, y):
+        """yhat[r, member] for every class r (shape [n_min, c])."""
+        offs = np.concatenate([[0], np.cumsum(self.n)])
+        out = np.zeros((self.nmin, self.c), dtype=np.float64 if self.real else np.complex128)
+        for t in range(self.T):
+            sp = _task_spectrum(self.w, t, y[offs[t]:offs[t + 1]])
+            # frequency f = r + n_min k is member k of class r
+            out[:, self.off[t]:self.off[t + 1]] = sp.reshape(self.size[t], self.nmin).T
+        return out
+
+    def mean_columns(self):
+        """Class-0 image of E^T: column t is sqrt(n_t) at member (t, 0)."""
+        A = np.zeros((self.c, self.T))
+        for t in range(self.T):
+            A[self.off[t], t] = np.sqrt(self.n[t])
+        return A
+
+    def chunks(self, budget=1 << 28):
+        step = max(1, budget // (16 * self.c * self.c))
+        for r0 in range(0, self.nmin, step):
+            yield np.arange(r0, min(self.nmin, r0 + step))
+
+
+def _profiled_tau(cl, yh0, power):
+    """Normal equations in class 0: (A^H M0^-p A) tau = A^H M0^-p yhat(0).
+    Also returns the 2-norm condition numbers of M0 and of A^H M0^-p A, whose
+    product (times the unit roundoff) bounds the relative error of tau in
+    FP64 arithmetic after p solves with M0."""
+    A = cl.mean_columns()
+    M0 = cl.matrices([0])[0]
+    X = np.linalg.solve(M0, np.column_stack([A, yh0]))
+    if power == 2:
+        X = np.linalg.solve(M0, X)
+    G = A.T @ X
+    Gm = np.real(G[:, :cl.T])
+    tau = np.linalg.solve(Gm, np.real(G[:, cl.T]))
+    return tau, float(np.linalg.cond(M0)), float(np.linalg.cond(Gm))
+
+
+def mle(w, y, theta=None, profile=None):
+    """quad, logdet, L = quad + logdet and tau_hat for any nested sizes; y in
+    the dense oracle's point order.  cond_M0 and cond_normal are the condition
+    numbers of the class-0 block and of the normal equations of tau."""
+    theta = w.theta if theta is None else theta
+    profile = w.profile_tau if profile is None else profile
+    cl = _Classes(w, theta)
+    yh = cl.data(np.asarray(y, dtype=np.float64))
+    tau, cond0, condn = _profiled_tau(cl, yh[0], 1)
+    if not profile:
+        tau = np.asarray(theta["tau"], dtype=np.float64)
+    yh[0] -= cl.mean_columns() @ tau
+    quad = logdet = 0.0
+    for r in cl.chunks():
+        Lc = np.linalg.cholesky(cl.matrices(r))
+        logdet += float(2.0 * np.sum(np.log(np.real(np.diagonal(Lc, axis1=1, axis2=2)))))
+        z = np.linalg.solve(Lc, yh[r][..., None])[..., 0]       # Lc z = rhat
+        quad += float(np.sum(np.abs(z) ** 2))
+    return dict(quad=quad, logdet=logdet, L=quad + logdet, tau_hat=tau, cond_M0=cond0,
+                cond_normal=condn)
+
+
+def gcv(w, y, theta=None, profile=None):
+    """GCV pieces q = r^H Ktilde^-2 r, s = tr Ktilde^-1, L = q / s^2 and the
+    GCV means (E Ktilde^-2 E^T) tau = E Ktilde^-2 y, for any nested sizes."""
+    theta = w.theta if theta is None else theta
+    profile = w.profile_tau if profile is None else profile
+    cl = _Classes(w, theta)
+    yh = cl.data(np.asarray(y, dtype=np.float64))
+    tau, cond0, condn = _profiled_tau(cl, yh[0], 2)
+    if not profile:
+        tau = np.asarray(theta["tau"], dtype=np.float64)
+    yh[0] -= cl.mean_columns() @ tau
+    q = s = 0.0
+    for r in cl.chunks():
+        M = cl.matrices(r)
+        a = np.linalg.solve(M, yh[r][..., None])[..., 0]
+        q += float(np.sum(np.abs(a) ** 2))
+        Minv = np.linalg.inv(M)
+        s += float(np.sum(np.real(np.diagonal(Minv, axis1=1, axis2=2))))
+    return dict(q=q, s=s, L=q / (s * s), tau_hat=tau, cond_M0=cond0, cond_normal=condn)

@@ -295,6 +295,63 @@ def test_loss_against_spectral_oracle_beyond_dense_sizes(family, m, T, d, precis
                                rtol=1e-9 if precision == "fp64" else 1e-5, atol=1e-12)
 
 
+NESTED_BEYOND = [
+    # (family, m, d, order, adaptive): N from 8.6e4 to 1.8e5, classes of 21 to 41 members
+    ("dseq", [16, 14, 12], 3, 2, False),
+    ("dseq", [15, 15, 11, 9], 4, 4, False),
+    ("dseq", [16, 13, 13], 3, 2, True),
+    ("lat", [17, 15, 12], 3, 2, False),
+    ("lat", [16, 13, 13, 11], 3, 1, False),
+]
+
+
+@pytest.mark.parametrize("case", NESTED_BEYOND,
+                         ids=[f"{c[0]}-m{'_'.join(map(str, c[1]))}-o{c[3]}{'a' if c[4] else ''}"
+                              for c in NESTED_BEYOND])
+@pytest.mark.parametrize("precision,elimination", [("fp64", "sparse"), ("fp64", "alg1"),
+                                                   ("mixed", "sparse")])
+def test_nested_loss_against_spectral_oracle_beyond_dense_sizes(case, precision, elimination):
+    # nested sizes beyond the dense oracle: the class-by-class spectral oracle
+    # (dense Hermitian blocks per residue class, pinned to the dense oracle)
+    # against both eliminations, MLE and GCV
+    from oracle import dense, points, spectral
+    family, m, d, order, adaptive = case
+    w = tiny(family, len(m), m, d, order=order, adaptive=adaptive, seed=70 + sum(m), xi=1e-2,
+             rank=2)
+    say("nested loss vs spectral oracle", family, m, precision, elimination)
+    y = dense.targets(w, np.random.default_rng(w.seed + 1000), points.task_points(w))
+    plan = mt.Plan.from_workload(w, precision, elimination=elimination)
+    plan.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
+    theta = plan.pack_theta(w.theta)
+    out3, tau = plan.nll(theta)
+    torch.cuda.synchronize()
+    assert plan.status() == (0, -1)
+    out3 = out3.cpu().numpy()
+    ref = spectral.mle(w, y)
+    den = abs(ref["quad"]) + abs(ref["logdet"])
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert abs(out3[2] - ref["L"]) < tol * den, (out3, ref["L"])
+    assert abs(out3[1] - ref["logdet"]) < tol * den
+    np.testing.assert_allclose(tau.cpu().numpy(), ref["tau_hat"],
+                               rtol=1e-9 if precision == "fp64" else 1e-5, atol=1e-12)
+    if elimination != "sparse":
+        return  # GCV at nested sizes runs on the fill-free elimination
+    og, _, taug = plan.gcv(theta, grad=False)
+    torch.cuda.synchronize()
+    assert plan.status() == (0, -1)
+    og = og.cpu().numpy()
+    rg = spectral.gcv(w, y)
+    assert abs(og[2] - rg["L"]) < tol * rg["L"], (og, rg["L"])
+    assert abs(og[0] - rg["q"]) < tol * rg["q"] and abs(og[1] - rg["s"]) < tol * rg["s"]
+    # the GCV means solve normal equations in Ktilde^-2: two solves with the
+    # class-0 block (condition 1e5..7e7 here) before the T x T system, so the
+    # FP64 bound is u kappa(M0) kappa(E Ktilde^-2 E^T), not a fixed figure
+    rtol = tol * 100
+    if precision == "fp64":
+        rtol = max(rtol, 4 * np.finfo(np.float64).eps * rg["cond_M0"] * rg["cond_normal"])
+    np.testing.assert_allclose(taug.cpu().numpy(), rg["tau_hat"], rtol=rtol, atol=1e-12)
+
+
 @pytest.mark.parametrize("m,sched", [(13, (3, 10, 4096)), (16, (6, 10, 4096)), (16, (8, 8, 4096)),
                                      (19, (7, 12, 36864)), (20, (12, 8, 36864))])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

@@ -50,3 +50,51 @@ def test_unequal_sizes_refused():
     w = tiny("dseq", 2, [5, 4], 2, seed=1)
     with pytest.raises(ValueError):
         spectral.nll_equal(w, np.zeros(w.N))
+
+
+NESTED = [
+    # (family, m, d, order, adaptive, profile): descending, ascending and
+    # mixed task orders, a one-point task, equal sizes through the same route
+    ("dseq", [5, 3, 2], 2, 2, False, True),
+    ("dseq", [3, 5, 4], 2, 1, False, False),
+    ("dseq", [6, 0], 3, 4, False, True),
+    ("dseq", [4, 4, 2, 3], 2, 2, True, True),
+    ("lat", [5, 3, 2], 2, 2, False, True),
+    ("lat", [4, 6, 6], 2, 3, False, False),
+    ("lat", [2, 5, 3], 3, 1, False, True),
+    ("lat", [5, 5], 2, 2, False, True),
+]
+
+
+def _nested_id(c):
+    return f"{c[0]}-m{'_'.join(map(str, c[1]))}-o{c[3]}{'a' if c[4] else ''}-{'prof' if c[5] else 'fixed'}"
+
+
+@pytest.mark.parametrize("case", NESTED, ids=[_nested_id(c) for c in NESTED])
+def test_nested_spectral_mle_and_gcv_equal_dense(case):
+    fam, m, d, order, adaptive, profile = case
+    T = len(m)
+    w = tiny(fam, T, m, d, order=order, adaptive=adaptive, seed=40 + sum(m), profile=profile,
+             rank=min(T, 2))
+    X = points.task_points(w)
+    y = dense.targets(w, np.random.default_rng(4), X)
+    a = dense.nll(w, y, X=X)
+    b = spectral.mle(w, y)
+    den = abs(a["quad"]) + abs(a["logdet"])
+    assert abs(a["L"] - b["L"]) < 1e-11 * den, (a["L"], b["L"])
+    assert abs(a["logdet"] - b["logdet"]) < 1e-11 * den
+    np.testing.assert_allclose(b["tau_hat"], a["tau_hat"], rtol=1e-10, atol=1e-12)
+    g = dense.gcv(w, y, X=X)
+    h = spectral.gcv(w, y)
+    assert abs(g["L"] - h["L"]) < 1e-10 * g["L"]
+    assert abs(g["q"] - h["q"]) < 1e-10 * g["q"] and abs(g["s"] - h["s"]) < 1e-10 * g["s"]
+    np.testing.assert_allclose(h["tau_hat"], g["tau_hat"], rtol=1e-9, atol=1e-12)
+
+
+def test_class_route_equals_per_frequency_route_at_equal_sizes():
+    w = tiny("lat", 3, [7, 7, 7], 2, seed=9, rank=2)
+    y = np.random.default_rng(5).normal(size=w.N)
+    a = spectral.nll_equal(w, y)
+    b = spectral.mle(w, y)
+    assert abs(a["L"] - b["L"]) < 1e-12 * abs(a["L"])
+    np.testing.assert_allclose(b["tau_hat"], a["tau_hat"], rtol=1e-11)
