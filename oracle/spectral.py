@@ -78,11 +78,9 @@ def _bitrev(n):
     return r
 
 
-def _column(w, theta, t, u):
-    """c_tu[j] in the order in which block (t, u) is a convolution."""
+def _column_digits(w, t, u):
+    """Kernel-argument digits [n_t][d] of c_tu in its convolution order."""
     n = 1 << w.m[t]
-    b = None if theta.get("b") is None else np.asarray(theta["b"], dtype=np.float64)
-    eta = np.asarray(theta["eta"], dtype=np.float64)
     if w.family == "dseq":
         z = pts.dseq_unshifted(w.gen, n)
         dig = z ^ (np.asarray(w.shift[t], dtype=np.uint32) ^ np.asarray(w.shift[u], dtype=np.uint32))[None, :]
@@ -93,6 +91,15 @@ def _column(w, theta, t, u):
         base = ((j[:, None] * g[None, :]) << np.uint64(32 - w.m[t])) & np.uint64(0xFFFFFFFF)
         ds = (np.asarray(w.shift[t], dtype=np.int64) - np.asarray(w.shift[u], dtype=np.int64)) & 0xFFFFFFFF
         dig = ((base + ds.astype(np.uint64)[None, :]) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    return dig
+
+
+def _column(w, theta, t, u):
+    """c_tu[j] in the order in which block (t, u) is a convolution."""
+    n = 1 << w.m[t]
+    b = None if theta.get("b") is None else np.asarray(theta["b"], dtype=np.float64)
+    eta = np.asarray(theta["eta"], dtype=np.float64)
+    dig = _column_digits(w, t, u)
     q = np.full(n, float(theta["gamma"]))
     for k in range(w.d):
         q *= 1.0 + eta[k] * kn.univariate(w.family, w.kernel_order, w.adaptive, b, dig[:, k])
@@ -271,3 +278,71 @@ def gcv(w, y, theta=None, profile=None):
         Minv = np.linalg.inv(M)
         s += float(np.sum(np.real(np.diagonal(Minv, axis1=1, axis2=2))))
     return dict(q=q, s=s, L=q / (s * s), tau_hat=tau, cond_M0=cond0, cond_normal=condn)
+
+
+def mle_grad(w, y, theta=None, profile=None):
+    """Exact gradient of the MLE loss in the packed parameterisation (dict
+    keyed like theta), for any nested sizes:
+
+      dL/dtheta = sum_r tr( (M_r^-1 - a_r a_r^H) dM_r/dtheta ),  a_r = M_r^-1 rhat_r,
+
+    where dM_r takes the spectra of the derivative columns dc_tu / dtheta
+    (log gamma, log eta_j, log b_alpha) and of c_tu (for R = B B^T +
+    diag(zeta)), and xi_t on the diagonal.  Profiled means contribute nothing
+    (tau_hat is stationary); fixed means give -2 Re(A^T a_0).  Also returns
+    the loss pieces of `mle`."""
+    theta = w.theta if theta is None else theta
+    profile = w.profile_tau if profile is None else profile
+    res = mle(w, y, theta, profile)
+    cl = _Classes(w, theta)
+    yh = cl.data(np.asarray(y, dtype=np.float64))
+    A = cl.mean_columns()
+    yh[0] -= A @ res["tau_hat"]
+    T, d = w.T, w.d
+    # Z[(t, u)][f] = W_(u, f mod n_u),(t, f) over the stored pairs; xi terms
+    Z = {key: np.zeros(cl.n[key[0]], dtype=np.float64 if cl.real else np.complex128)
+         for key in cl.lam}
+    g_xi = np.zeros(T)
+    g_tau = np.zeros(T)
+    xi = np.asarray(theta["xi"], dtype=np.float64)
+    for r in cl.chunks():
+        M = cl.matrices(r)
+        Minv = np.linalg.inv(M)
+        a = np.einsum("rij,rj->ri", Minv, yh[r])
+        W = Minv - a[:, :, None] * np.conj(a[:, None, :])
+        if r[0] == 0:
+            g_tau = -2.0 * np.real(A.T @ a[0])
+        for (t, u) in cl.lam:
+            k = np.arange(cl.size[t])
+            l = k % cl.size[u]
+            Z[(t, u)][r[:, None] + cl.nmin * k[None, :]] = W[:, cl.off[u] + l, cl.off[t] + k]
+        for t in range(T):
+            i = cl.off[t] + np.arange(cl.size[t])
+            g_xi[t] += xi[t] * float(np.sum(np.real(W[:, i, i])))
+    b = None if theta.get("b") is None else np.asarray(theta["b"], dtype=np.float64)
+    eta = np.asarray(theta["eta"], dtype=np.float64)
+    R = cl.R
+    spec = walsh if cl.real else (lambda v: np.fft.fft(v))
+    G = np.zeros((T, T))
+    g_eta = np.zeros(d)
+    g_b = np.zeros(4) if w.adaptive else None
+    for (t, u), lam in cl.lam.items():
+        mult = 1.0 if t == u else 2.0
+        sc = np.sqrt(cl.n[u] / cl.n[t])
+        z = Z[(t, u)]
+        G[t, u] = G[u, t] = float(np.real(np.sum(z * sc * lam)))
+        _, dq_eta, dq_b = kn.product_kernel_grads(w.family, w.kernel_order, w.adaptive, b,
+                                                  theta["gamma"], eta, _column_digits(w, t, u))
+        for j in range(d):
+            g_eta[j] += mult * sc * R[t, u] * float(np.real(np.sum(z * spec(dq_eta[j]))))
+        if w.adaptive:
+            for al in range(4):
+                g_b[al] += mult * sc * R[t, u] * float(np.real(np.sum(z * spec(dq_b[al]))))
+    # Q is proportional to gamma; R = B B^T + diag(zeta)
+    B = np.asarray(theta["B"], dtype=np.float64)
+    zeta = np.asarray(theta["zeta"], dtype=np.float64)
+    out = dict(tau=np.zeros(T) if profile else g_tau, gamma=float(np.sum(R * G)), eta=g_eta,
+               xi=g_xi, B=(G + G.T) @ B, zeta=zeta * np.diag(G))
+    if w.adaptive:
+        out["b"] = g_b
+    return out, res

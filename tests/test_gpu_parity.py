@@ -268,22 +268,26 @@ def test_lattice_two_pass_against_oracle(precision):
     assert rel_err(mean, ref["mean"]) < (1e-9 if precision == "fp64" else 1e-4)
 
 
-@pytest.mark.parametrize("family,m,T,d", [("dseq", 16, 3, 3), ("dseq", 20, 2, 3), ("lat", 17, 3, 3),
-                                          ("lat", 21, 2, 3), ("dseq", 18, 8, 10), ("lat", 18, 8, 10)])
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_loss_against_spectral_oracle_beyond_dense_sizes(family, m, T, d, precision):
-    # the spectral oracle (pinned to the dense one on small designs) at sizes
-    # the dense oracle cannot factor: N = T 2^m up to 2^22, lattice schedules
-    # with 4-bit register passes (m = 17, 21), and the config-5 task and
-    # dimension counts (T = 8, d = 10) at 2^18 points per task
+_SPECTRAL_REFS = {}
+
+
+def _spectral_reference(w):
+    """Seeded targets and the spectral oracle's loss and gradient, computed
+    once per design (the precisions and eliminations share them)."""
     from oracle import dense, points, spectral
-    w = tiny(family, T, [m] * T, d, seed=65 + m, xi=1e-2, rank=2)
-    say("loss vs spectral oracle", family, m, T, precision)
-    y = dense.targets(w, np.random.default_rng(w.seed + 1000), points.task_points(w))
-    ref = spectral.nll_equal(w, y)
-    plan = mt.Plan.from_workload(w, precision)
+    key = (w.name, w.seed)
+    if key not in _SPECTRAL_REFS:
+        y = dense.targets(w, np.random.default_rng(w.seed + 1000), points.task_points(w))
+        g, r = spectral.mle_grad(w, y)
+        _SPECTRAL_REFS[key] = (y, r, g)
+    return _SPECTRAL_REFS[key]
+
+
+def _check_against_spectral(w, y, ref, gref, precision, elimination):
+    plan = mt.Plan.from_workload(w, precision, elimination=elimination)
     plan.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
-    out3, tau = plan.nll(plan.pack_theta(w.theta))
+    theta = plan.pack_theta(w.theta)
+    out3, grad, tau = plan.nll_grad(theta)
     torch.cuda.synchronize()
     assert plan.status() == (0, -1)
     out3 = out3.cpu().numpy()
@@ -293,6 +297,29 @@ def test_loss_against_spectral_oracle_beyond_dense_sizes(family, m, T, d, precis
     assert abs(out3[1] - ref["logdet"]) < tol * den
     np.testing.assert_allclose(tau.cpu().numpy(), ref["tau_hat"],
                                rtol=1e-9 if precision == "fp64" else 1e-5, atol=1e-12)
+    g = plan.unpack(grad)
+    scale = max(np.abs(np.atleast_1d(v)).max() for v in gref.values())
+    tolg = 1e-7 if precision == "fp64" else 1e-4
+    for k, v in gref.items():
+        e = np.abs(np.atleast_1d(g[k]) - np.atleast_1d(v)).max() / scale
+        assert e < tolg, (k, g[k], v, e)
+    return plan, theta
+
+
+@pytest.mark.parametrize("family,m,T,d", [("dseq", 16, 3, 3), ("dseq", 20, 2, 3), ("lat", 17, 3, 3),
+                                          ("lat", 21, 2, 3), ("dseq", 18, 8, 10), ("lat", 18, 8, 10)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_loss_against_spectral_oracle_beyond_dense_sizes(family, m, T, d, precision):
+    # the spectral oracle (pinned to the dense one on small designs) at sizes
+    # the dense oracle cannot factor: N = T 2^m up to 2^22, lattice schedules
+    # with 4-bit register passes (m = 17, 21), and the config-5 task and
+    # dimension counts (T = 8, d = 10) at 2^18 points per task
+    from oracle import spectral
+    w = tiny(family, T, [m] * T, d, seed=65 + m, xi=1e-2, rank=2)
+    say("loss + gradient vs spectral oracle", family, m, T, precision)
+    y, ref, gref = _spectral_reference(w)
+    assert abs(spectral.nll_equal(w, y)["L"] - ref["L"]) < 1e-12 * abs(ref["L"])
+    _check_against_spectral(w, y, ref, gref, precision, "sparse")
 
 
 NESTED_BEYOND = [
@@ -314,26 +341,14 @@ def test_nested_loss_against_spectral_oracle_beyond_dense_sizes(case, precision,
     # nested sizes beyond the dense oracle: the class-by-class spectral oracle
     # (dense Hermitian blocks per residue class, pinned to the dense oracle)
     # against both eliminations, MLE and GCV
-    from oracle import dense, points, spectral
+    from oracle import spectral
     family, m, d, order, adaptive = case
     w = tiny(family, len(m), m, d, order=order, adaptive=adaptive, seed=70 + sum(m), xi=1e-2,
              rank=2)
-    say("nested loss vs spectral oracle", family, m, precision, elimination)
-    y = dense.targets(w, np.random.default_rng(w.seed + 1000), points.task_points(w))
-    plan = mt.Plan.from_workload(w, precision, elimination=elimination)
-    plan.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
-    theta = plan.pack_theta(w.theta)
-    out3, tau = plan.nll(theta)
-    torch.cuda.synchronize()
-    assert plan.status() == (0, -1)
-    out3 = out3.cpu().numpy()
-    ref = spectral.mle(w, y)
-    den = abs(ref["quad"]) + abs(ref["logdet"])
+    say("nested loss + gradient vs spectral oracle", family, m, precision, elimination)
+    y, ref, gref = _spectral_reference(w)
+    plan, theta = _check_against_spectral(w, y, ref, gref, precision, elimination)
     tol = 1e-10 if precision == "fp64" else 1e-5
-    assert abs(out3[2] - ref["L"]) < tol * den, (out3, ref["L"])
-    assert abs(out3[1] - ref["logdet"]) < tol * den
-    np.testing.assert_allclose(tau.cpu().numpy(), ref["tau_hat"],
-                               rtol=1e-9 if precision == "fp64" else 1e-5, atol=1e-12)
     if elimination != "sparse":
         return  # GCV at nested sizes runs on the fill-free elimination
     og, _, taug = plan.gcv(theta, grad=False)

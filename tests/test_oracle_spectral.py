@@ -98,3 +98,24 @@ def test_class_route_equals_per_frequency_route_at_equal_sizes():
     b = spectral.mle(w, y)
     assert abs(a["L"] - b["L"]) < 1e-12 * abs(a["L"])
     np.testing.assert_allclose(b["tau_hat"], a["tau_hat"], rtol=1e-11)
+
+
+GRAD_CASES = NESTED + [("dseq", [5, 5, 5], 2, 3, True, True), ("lat", [6, 6], 3, 2, False, False)]
+
+
+@pytest.mark.parametrize("case", GRAD_CASES, ids=[_nested_id(c) for c in GRAD_CASES])
+def test_spectral_gradient_equals_dense(case):
+    fam, m, d, order, adaptive, profile = case
+    T = len(m)
+    w = tiny(fam, T, m, d, order=order, adaptive=adaptive, seed=40 + sum(m), profile=profile,
+             rank=min(T, 2))
+    X = points.task_points(w)
+    y = dense.targets(w, np.random.default_rng(4), X)
+    ga, _ = dense.grad(w, y, X=X)
+    gb, res = spectral.mle_grad(w, y)
+    scale = max(np.abs(np.atleast_1d(v)).max() for v in ga.values())
+    assert set(ga) == set(gb)
+    for k in ga:
+        err = np.abs(np.atleast_1d(ga[k]) - np.atleast_1d(gb[k])).max() / scale
+        assert err < 1e-10, (k, ga[k], gb[k])
+    assert res["L"] == spectral.mle(w, y)["L"]
