@@ -346,3 +346,48 @@ def mle_grad(w, y, theta=None, profile=None):
     if w.adaptive:
         out["b"] = g_b
     return out, res
+
+
+def weights(w, y, theta=None, profile=None):
+    """alpha = Ktilde^-1 (y - E^T tau) in the dense oracle's point order,
+    from a_r = M_r^-1 rhat_r mapped back per task (alpha_t = V_t ahat_t), with
+    tau_hat, E alpha = A^T a_0 and Pi = E Ktilde^-1 E^T = A^T M0^-1 A."""
+    theta = w.theta if theta is None else theta
+    profile = w.profile_tau if profile is None else profile
+    cl = _Classes(w, theta)
+    yh = cl.data(np.asarray(y, dtype=np.float64))
+    tau, _, _ = _profiled_tau(cl, yh[0], 1)
+    if not profile:
+        tau = np.asarray(theta["tau"], dtype=np.float64)
+    A = cl.mean_columns()
+    yh[0] -= A @ tau
+    ahat = [np.zeros(nt, dtype=yh.dtype) for nt in cl.n]
+    for r in cl.chunks():
+        a = np.linalg.solve(cl.matrices(r), yh[r][..., None])[..., 0]
+        for t in range(w.T):
+            k = np.arange(cl.size[t])
+            ahat[t][r[:, None] + cl.nmin * k[None, :]] = a[:, cl.off[t] + k]
+        if r[0] == 0:
+            Ea = np.real(A.T @ a[0])
+    alpha = []
+    for t in range(w.T):
+        n = cl.n[t]
+        if cl.real:
+            alpha.append(walsh(ahat[t]) / np.sqrt(n))
+        else:
+            nat = np.fft.ifft(ahat[t]) * np.sqrt(n)     # V_t = F^H / sqrt(n)
+            alpha.append(np.real(nat[_bitrev(n)]))      # point i at natural bitrev(i)
+    M0 = cl.matrices([0])[0]
+    Pi = np.real(A.T @ np.linalg.solve(M0, A))
+    return dict(alpha=np.concatenate(alpha), tau_hat=tau, E_alpha=Ea, Pi=Pi)
+
+
+def cubature(w, y, theta=None, profile=None):
+    """Bayesian cubature of the task integrals (gamma = int Q(x, x') dx'):
+    mu_hat = tau + gamma R E alpha, Sigma = gamma R - gamma^2 R Pi R."""
+    theta = w.theta if theta is None else theta
+    res = weights(w, y, theta, profile)
+    R = task_cov(theta)
+    g = float(theta["gamma"])
+    return dict(mu_hat=res["tau_hat"] + g * R @ res["E_alpha"],
+                Sigma=g * R - g * g * R @ res["Pi"] @ R, Pi=res["Pi"])

@@ -367,6 +367,46 @@ def test_nested_loss_against_spectral_oracle_beyond_dense_sizes(case, precision,
     np.testing.assert_allclose(taug.cpu().numpy(), rg["tau_hat"], rtol=rtol, atol=1e-12)
 
 
+@pytest.mark.parametrize("case", NESTED_BEYOND + [("dseq", [17, 17], 3, 2, False)],
+                         ids=lambda c: f"{c[0]}-m{'_'.join(map(str, c[1]))}-o{c[3]}")
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cubature_and_mean_against_spectral_oracle_beyond_dense_sizes(case, precision):
+    # Bayesian cubature (E alpha, Pi = E Ktilde^-1 E^T from class 0) and the
+    # posterior mean at random points (the dense kernel sums with alpha mapped
+    # back from the spectral oracle's class solves), N up to 2.6e5
+    import workloads as wl
+    from oracle import dense, points, spectral
+    family, m, d, order, adaptive = case
+    w = wl.with_theta(tiny(family, len(m), m, d, order=order, adaptive=adaptive,
+                           seed=80 + sum(m), xi=1e-2, rank=2),
+                      tau=np.linspace(-0.3, 0.4, len(m)))
+    say("cubature + mean vs spectral oracle", family, m, precision)
+    X = points.task_points(w)
+    y = dense.targets(w, np.random.default_rng(w.seed + 1000), X)
+    sw = spectral.weights(w, y)
+    cs = spectral.cubature(w, y)
+    xs = np.random.default_rng(w.seed).integers(0, 2 ** 32, size=(16, w.d),
+                                                 dtype=np.uint64).astype(np.uint32)
+    ms = dense.posterior_mean(w, y, xs, X=X, res=dict(alpha=sw["alpha"], tau_hat=sw["tau_hat"]))
+    plan = mt.Plan.from_workload(w, precision)
+    plan.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
+    theta = plan.pack_theta(w.theta)
+    mu, Sigma = plan.cubature(theta)
+    mean = plan.predict(theta, mt.digits_to_device(xs))
+    torch.cuda.synchronize()
+    assert plan.status()[0] == 0
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    # Sigma = gamma R - gamma^2 R Pi R cancels to ~1e-8 of gamma R at these
+    # sizes; with FP32 spectra Pi is exact to ~1e-7, so the mixed path is held
+    # to the scale of the cancelling terms, FP64 to Sigma's own
+    gR = float(w.theta["gamma"]) * np.abs(np.asarray(w.theta["B"]) @ np.asarray(w.theta["B"]).T
+                                          + np.diag(w.theta["zeta"])).max()
+    scale = None if precision == "fp64" else gR
+    assert rel_err(Sigma.cpu().numpy(), cs["Sigma"], scale) < tol, (Sigma, cs["Sigma"])
+    assert rel_err(mu.cpu().numpy(), cs["mu_hat"]) < tol, (mu, cs["mu_hat"])
+    assert rel_err(mean.cpu().numpy(), ms) < tol, rel_err(mean.cpu().numpy(), ms)
+
+
 @pytest.mark.parametrize("m,sched", [(13, (3, 10, 4096)), (16, (6, 10, 4096)), (16, (8, 8, 4096)),
                                      (19, (7, 12, 36864)), (20, (12, 8, 36864))])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

@@ -119,3 +119,26 @@ def test_spectral_gradient_equals_dense(case):
         err = np.abs(np.atleast_1d(ga[k]) - np.atleast_1d(gb[k])).max() / scale
         assert err < 1e-10, (k, ga[k], gb[k])
     assert res["L"] == spectral.mle(w, y)["L"]
+
+
+@pytest.mark.parametrize("case", NESTED, ids=[_nested_id(c) for c in NESTED])
+def test_spectral_weights_cubature_and_mean_equal_dense(case):
+    import workloads as wl
+    fam, m, d, order, adaptive, profile = case
+    T = len(m)
+    w = wl.with_theta(tiny(fam, T, m, d, order=order, adaptive=adaptive, seed=40 + sum(m),
+                           profile=profile, rank=min(T, 2)), tau=np.linspace(-0.3, 0.4, T))
+    X = points.task_points(w)
+    y = dense.targets(w, np.random.default_rng(4), X)
+    res = dense.nll(w, y, X=X)
+    sw = spectral.weights(w, y)
+    scale = np.abs(res["alpha"]).max()
+    assert np.abs(sw["alpha"] - res["alpha"]).max() < 1e-10 * scale
+    cd = dense.bayesian_cubature(w, y, X=X, res=res)
+    cs = spectral.cubature(w, y)
+    np.testing.assert_allclose(cs["mu_hat"], cd["mu_hat"], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(cs["Sigma"], cd["Sigma"], rtol=0, atol=1e-10 * np.abs(cd["Sigma"]).max())
+    xs = np.random.default_rng(9).integers(0, 2 ** 32, size=(8, w.d), dtype=np.uint64).astype(np.uint32)
+    md = dense.posterior_mean(w, y, xs, X=X, res=res)
+    ms = dense.posterior_mean(w, y, xs, X=X, res=dict(alpha=sw["alpha"], tau_hat=sw["tau_hat"]))
+    assert np.abs(md - ms).max() < 1e-10 * np.abs(md).max()
