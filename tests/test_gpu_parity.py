@@ -307,13 +307,16 @@ def _check_against_spectral(w, y, ref, gref, precision, elimination):
 
 
 @pytest.mark.parametrize("family,m,T,d", [("dseq", 16, 3, 3), ("dseq", 20, 2, 3), ("lat", 17, 3, 3),
-                                          ("lat", 21, 2, 3), ("dseq", 18, 8, 10), ("lat", 18, 8, 10)])
+                                          ("lat", 21, 2, 3), ("dseq", 18, 8, 10), ("lat", 18, 8, 10),
+                                          ("lat", 23, 2, 3)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_loss_against_spectral_oracle_beyond_dense_sizes(family, m, T, d, precision):
     # the spectral oracle (pinned to the dense one on small designs) at sizes
-    # the dense oracle cannot factor: N = T 2^m up to 2^22, lattice schedules
-    # with 4-bit register passes (m = 17, 21), and the config-5 task and
-    # dimension counts (T = 8, d = 10) at 2^18 points per task
+    # the dense oracle cannot factor: N = T 2^m up to 2^24, lattice schedules
+    # with 4-bit register passes (m = 17, 21), the LDS-tiled lattice passes
+    # (m = 18: both register passes in one tile each way; m = 23: the top two
+    # forward and the two adjoint passes above the wave pass), and the
+    # config-5 task and dimension counts (T = 8, d = 10) at 2^18 points per task
     from oracle import spectral
     w = tiny(family, T, [m] * T, d, seed=65 + m, xi=1e-2, rank=2)
     say("loss + gradient vs spectral oracle", family, m, T, precision)
