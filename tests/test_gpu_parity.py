@@ -308,7 +308,7 @@ def _check_against_spectral(w, y, ref, gref, precision, elimination):
 
 @pytest.mark.parametrize("family,m,T,d", [("dseq", 16, 3, 3), ("dseq", 20, 2, 3), ("lat", 17, 3, 3),
                                           ("lat", 21, 2, 3), ("dseq", 18, 8, 10), ("lat", 18, 8, 10),
-                                          ("lat", 23, 2, 3)])
+                                          ("lat", 23, 2, 3), ("dseq", 23, 2, 3)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_loss_against_spectral_oracle_beyond_dense_sizes(family, m, T, d, precision):
     # the spectral oracle (pinned to the dense one on small designs) at sizes
