@@ -8,19 +8,22 @@
 // input, bit-reversed output, so the spectrum holds frequency f at position
 // bitrev_m(f) (frequency 0 at position 0; the per-frequency algebra does not
 // care about the order, and the data transform uses the same layout).  The
-// stages of the high index bits run first, in register passes of 5 bits:
-// a thread owns the 32 values strided by 2^lo that share its low index, so
-// every load and store of a wave is 64 consecutive elements.  The twiddle of
-// the stage of bit k = lo + s on the pair of register slot r (r < 2^s) is
+// stages of the high index bits run first, in register passes of 5 bits (4
+// where the bit count asks for it): a thread owns the 2^hb values strided by
+// 2^lo that share its low index, so every load and store of a wave is 64
+// consecutive elements.  The twiddle of the stage of bit k = lo + s on the
+// pair of register slot r (r < 2^s) is
 //   e^{-i pi (low + r 2^lo) / 2^k} = e^{-i pi low / 2^k} e^{-i pi r / 2^s},
 // a per-thread base (one sincospi per pass, squared down the stages) times a
-// constant.  The first register pass generates the kernel column (or loads
-// the data) itself; the low L bits finish in LDS.
+// constant.  Two adjacent 5-bit passes can run as one tile pass (8 columns x
+// 2^10 rows through LDS, each element read and written once for both).  The
+// first pass generates the kernel column (or loads the data) itself; the low
+// L in [8, 10] bits finish in a wave-level pass.
 // Adjoint: u(j) = Re sum_f omega(f) e^{-2 pi i f j / n} from omega stored at
 // bit-reversed positions is the transposed network, decimation in time: the
-// LDS pass over the low bits first, then the register passes upwards, the
-// last one fused with the derivative reduction of the regenerated column (or
-// with storing Re in natural order).
+// wave pass over the low bits first, then the register (or tile) passes
+// upwards, the last one fused with the derivative reduction of the
+// regenerated column (or with storing Re in natural order).
 #include <cmath>
 
 #include "colgen.h"
