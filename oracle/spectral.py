@@ -280,38 +280,19 @@ def gcv(w, y, theta=None, profile=None):
     return dict(q=q, s=s, L=q / (s * s), tau_hat=tau, cond_M0=cond0, cond_normal=condn)
 
 
-def mle_grad(w, y, theta=None, profile=None):
-    """Exact gradient of the MLE loss in the packed parameterisation (dict
-    keyed like theta), for any nested sizes:
-
-      dL/dtheta = sum_r tr( (M_r^-1 - a_r a_r^H) dM_r/dtheta ),  a_r = M_r^-1 rhat_r,
-
-    where dM_r takes the spectra of the derivative columns dc_tu / dtheta
-    (log gamma, log eta_j, log b_alpha) and of c_tu (for R = B B^T +
-    diag(zeta)), and xi_t on the diagonal.  Profiled means contribute nothing
-    (tau_hat is stationary); fixed means give -2 Re(A^T a_0).  Also returns
-    the loss pieces of `mle`."""
-    theta = w.theta if theta is None else theta
-    profile = w.profile_tau if profile is None else profile
-    res = mle(w, y, theta, profile)
-    cl = _Classes(w, theta)
-    yh = cl.data(np.asarray(y, dtype=np.float64))
-    A = cl.mean_columns()
-    yh[0] -= A @ res["tau_hat"]
+def _param_grad(w, theta, cl, chunk_w):
+    """sum_r tr(W_r dM_r / dtheta) for every non-mean parameter, with W_r =
+    chunk_w(r, M_r) Hermitian: dM_r takes the spectra of the derivative
+    columns dc_tu / dtheta (log gamma, log eta_j, log b_alpha) and of c_tu
+    (for R = B B^T + diag(zeta)), and xi_t on the diagonal."""
     T, d = w.T, w.d
     # Z[(t, u)][f] = W_(u, f mod n_u),(t, f) over the stored pairs; xi terms
     Z = {key: np.zeros(cl.n[key[0]], dtype=np.float64 if cl.real else np.complex128)
          for key in cl.lam}
     g_xi = np.zeros(T)
-    g_tau = np.zeros(T)
     xi = np.asarray(theta["xi"], dtype=np.float64)
     for r in cl.chunks():
-        M = cl.matrices(r)
-        Minv = np.linalg.inv(M)
-        a = np.einsum("rij,rj->ri", Minv, yh[r])
-        W = Minv - a[:, :, None] * np.conj(a[:, None, :])
-        if r[0] == 0:
-            g_tau = -2.0 * np.real(A.T @ a[0])
+        W = chunk_w(r, cl.matrices(r))
         for (t, u) in cl.lam:
             k = np.arange(cl.size[t])
             l = k % cl.size[u]
@@ -341,10 +322,73 @@ def mle_grad(w, y, theta=None, profile=None):
     # Q is proportional to gamma; R = B B^T + diag(zeta)
     B = np.asarray(theta["B"], dtype=np.float64)
     zeta = np.asarray(theta["zeta"], dtype=np.float64)
-    out = dict(tau=np.zeros(T) if profile else g_tau, gamma=float(np.sum(R * G)), eta=g_eta,
-               xi=g_xi, B=(G + G.T) @ B, zeta=zeta * np.diag(G))
+    out = dict(gamma=float(np.sum(R * G)), eta=g_eta, xi=g_xi, B=(G + G.T) @ B,
+               zeta=zeta * np.diag(G))
     if w.adaptive:
         out["b"] = g_b
+    return out
+
+
+def mle_grad(w, y, theta=None, profile=None):
+    """Exact gradient of the MLE loss in the packed parameterisation (dict
+    keyed like theta), for any nested sizes:
+
+      dL/dtheta = sum_r tr( (M_r^-1 - a_r a_r^H) dM_r/dtheta ),  a_r = M_r^-1 rhat_r.
+
+    Profiled means contribute nothing (tau_hat is stationary); fixed means
+    give -2 Re(A^T a_0).  Also returns the loss pieces of `mle`."""
+    theta = w.theta if theta is None else theta
+    profile = w.profile_tau if profile is None else profile
+    res = mle(w, y, theta, profile)
+    cl = _Classes(w, theta)
+    yh = cl.data(np.asarray(y, dtype=np.float64))
+    A = cl.mean_columns()
+    yh[0] -= A @ res["tau_hat"]
+    keep = {}
+
+    def chunk_w(r, M):
+        Minv = np.linalg.inv(M)
+        a = np.einsum("rij,rj->ri", Minv, yh[r])
+        if r[0] == 0:
+            keep["a0"] = a[0]
+        return Minv - a[:, :, None] * np.conj(a[:, None, :])
+
+    out = _param_grad(w, theta, cl, chunk_w)
+    out["tau"] = np.zeros(w.T) if profile else -2.0 * np.real(A.T @ keep["a0"])
+    return out, res
+
+
+def gcv_grad(w, y, theta=None, profile=None):
+    """Exact gradient of L_GCV = q / s^2 (q = r^H Ktilde^-2 r, s = tr
+    Ktilde^-1), for any nested sizes: with a_r = M_r^-1 rhat_r and
+    b_r = M_r^-1 a_r,
+
+      dL/dtheta = sum_r tr( W_r dM_r/dtheta ),
+      W_r = -(a_r b_r^H + b_r a_r^H) / s^2 + (2 q / s^3) M_r^-2.
+
+    Profiled GCV means contribute nothing; fixed means give
+    -2 Re(A^T b_0) / s^2.  Also returns the loss pieces of `gcv`."""
+    theta = w.theta if theta is None else theta
+    profile = w.profile_tau if profile is None else profile
+    res = gcv(w, y, theta, profile)
+    q, s2 = res["q"], res["s"]
+    cl = _Classes(w, theta)
+    yh = cl.data(np.asarray(y, dtype=np.float64))
+    A = cl.mean_columns()
+    yh[0] -= A @ res["tau_hat"]
+    keep = {}
+
+    def chunk_w(r, M):
+        Minv = np.linalg.inv(M)
+        a = np.einsum("rij,rj->ri", Minv, yh[r])
+        b = np.einsum("rij,rj->ri", Minv, a)
+        if r[0] == 0:
+            keep["b0"] = b[0]
+        ab = a[:, :, None] * np.conj(b[:, None, :])
+        return -(ab + np.conj(np.swapaxes(ab, 1, 2))) / s2 ** 2 + (2.0 * q / s2 ** 3) * (Minv @ Minv)
+
+    out = _param_grad(w, theta, cl, chunk_w)
+    out["tau"] = np.zeros(w.T) if profile else -2.0 * np.real(A.T @ keep["b0"]) / s2 ** 2
     return out, res
 
 

@@ -410,6 +410,40 @@ def test_cubature_and_mean_against_spectral_oracle_beyond_dense_sizes(case, prec
     assert rel_err(mean.cpu().numpy(), ms) < tol, rel_err(mean.cpu().numpy(), ms)
 
 
+@pytest.mark.parametrize("family,m,T,d,profile", [("dseq", 16, 3, 3, True), ("lat", 17, 3, 3, True),
+                                                  ("dseq", 18, 2, 4, False), ("lat", 18, 2, 4, False)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gcv_gradient_against_spectral_oracle_beyond_dense_sizes(family, m, T, d, profile, precision):
+    # the exact GCV gradient (equal sizes) against the spectral oracle's
+    # per-frequency form at N = T 2^m up to 4.2e5
+    import workloads as wl
+    from oracle import dense, points, spectral
+    w = wl.with_theta(tiny(family, T, [m] * T, d, seed=90 + m, xi=1e-2, rank=2, profile=profile),
+                      tau=np.linspace(-0.3, 0.4, T))
+    say("gcv gradient vs spectral oracle", family, m, T, precision)
+    key = ("gcv", w.name, w.seed)
+    if key not in _SPECTRAL_REFS:
+        y = dense.targets(w, np.random.default_rng(w.seed + 1000), points.task_points(w))
+        g, r = spectral.gcv_grad(w, y)
+        _SPECTRAL_REFS[key] = (y, r, g)
+    y, ref, gref = _SPECTRAL_REFS[key]
+    plan = mt.Plan.from_workload(w, precision)
+    plan.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
+    theta = plan.pack_theta(w.theta)
+    out3, g, tau = plan.gcv(theta, grad=True)
+    torch.cuda.synchronize()
+    assert plan.status() == (0, -1)
+    o = out3.cpu().numpy()
+    tolL = 1e-10 if precision == "fp64" else 1e-5
+    assert abs(o[2] - ref["L"]) < tolL * ref["L"], (o, ref["L"])
+    gvec = plan.unpack(g)
+    scale = max(np.abs(np.atleast_1d(v)).max() for v in gref.values())
+    tolg = 1e-7 if precision == "fp64" else 1e-4
+    for k, v in gref.items():
+        e = np.abs(np.atleast_1d(gvec[k]) - np.atleast_1d(v)).max() / scale
+        assert e < tolg, (k, gvec[k], v, e)
+
+
 @pytest.mark.parametrize("m,sched", [(13, (3, 10, 4096)), (16, (6, 10, 4096)), (16, (8, 8, 4096)),
                                      (19, (7, 12, 36864)), (20, (12, 8, 36864))])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

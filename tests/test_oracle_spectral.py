@@ -142,3 +142,23 @@ def test_spectral_weights_cubature_and_mean_equal_dense(case):
     md = dense.posterior_mean(w, y, xs, X=X, res=res)
     ms = dense.posterior_mean(w, y, xs, X=X, res=dict(alpha=sw["alpha"], tau_hat=sw["tau_hat"]))
     assert np.abs(md - ms).max() < 1e-10 * np.abs(md).max()
+
+
+@pytest.mark.parametrize("case", GRAD_CASES, ids=[_nested_id(c) for c in GRAD_CASES])
+def test_spectral_gcv_gradient_equals_dense(case):
+    import workloads as wl
+    fam, m, d, order, adaptive, profile = case
+    T = len(m)
+    w = wl.with_theta(tiny(fam, T, m, d, order=order, adaptive=adaptive, seed=40 + sum(m),
+                           profile=profile, rank=min(T, 2)), tau=np.linspace(-0.3, 0.4, T))
+    X = points.task_points(w)
+    y = dense.targets(w, np.random.default_rng(4), X)
+    ga, _ = dense.gcv_grad(w, y, X=X)
+    gb, res = spectral.gcv_grad(w, y)
+    scale = max(np.abs(np.atleast_1d(v)).max() for v in ga.values())
+    assert set(ga) == set(gb)
+    for k in ga:
+        # GCV weights carry Ktilde^-2: the squared conditioning of the MLE case
+        err = np.abs(np.atleast_1d(ga[k]) - np.atleast_1d(gb[k])).max() / scale
+        assert err < 1e-9, (k, ga[k], gb[k])
+    assert res["L"] == spectral.gcv(w, y)["L"]
