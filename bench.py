@@ -538,7 +538,7 @@ def _phase_of(name, cur):
     partial-sum reductions and chain rule)."""
     if "mtgp::prep_kernel" in name:
         return "prep"
-    if "gen_fwd_kernel" in name or "lat_pass" in name and cur == "prep":
+    if "gen_fwd_kernel" in name:
         return "gen_fwd_low"
     if "fwht_strided_kernel" in name or "fwht_reg_" in name:
         return "fwd_high" if cur in ("gen_fwd_low", "fwd_high") else "adj_high"
