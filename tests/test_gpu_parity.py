@@ -629,6 +629,36 @@ def test_predict_net_against_oracle(family, m, m_star, precision):
     assert rel_err(direct, mean) < tol
 
 
+@pytest.mark.parametrize("family,m,m_star", [("dseq", [16, 14, 12], 10), ("dseq", [15, 15], 17),
+                                             ("lat", [17, 15, 12], 9), ("lat", [16, 16], 18)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_predict_net_against_spectral_oracle_beyond_dense_sizes(family, m, m_star, precision):
+    # the structured posterior mean on a test net coarser or finer than the
+    # tasks, at N up to 1.3e5: sampled test points against the dense kernel
+    # sums with alpha from the spectral oracle's class solves
+    from oracle import dense, spectral
+    w = tiny(family, len(m), m, 3, seed=72 + m_star, xi=1e-2, rank=2)
+    say("predict_net vs spectral oracle", family, m, m_star, precision)
+    rng = np.random.default_rng(11)
+    shift_star = workloads.random_shifts(rng, 1, w.d)[0]
+    ns = 1 << m_star
+    Xs = (points.dseq_points(w.gen, ns, shift_star) if family == "dseq"
+          else points.lattice_points(w.gen, ns, shift_star))
+    idx = np.unique(np.concatenate([[0, ns - 1], rng.integers(0, ns, size=64)]))
+    X = points.task_points(w)
+    y = dense.targets(w, np.random.default_rng(w.seed + 1000), X)
+    sw = spectral.weights(w, y)
+    mu_ref = dense.posterior_mean(w, y, Xs[idx], X=X,
+                                  res=dict(alpha=sw["alpha"], tau_hat=sw["tau_hat"]))
+    plan = mt.Plan.from_workload(w, precision)
+    theta = plan.pack_theta(w.theta)
+    plan.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
+    mean = plan.predict_net(theta, shift_star, m_star).cpu().numpy()
+    assert plan.status() == (0, -1)
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    assert rel_err(mean[idx], mu_ref) < tol, rel_err(mean[idx], mu_ref)
+
+
 # ------------------------------------------------------------ cubature
 @pytest.mark.parametrize("family,m,profile,precision", [
     ("dseq", [7, 7, 7], True, "fp64"), ("dseq", [7, 7, 7], False, "fp64"),
