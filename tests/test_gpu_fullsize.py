@@ -209,6 +209,17 @@ def test_config2_full_size():
     out64, g64, tau64 = _loss_grad(plan, theta)
     means = y.view(w.T, -1).mean(dim=1).cpu().numpy()
     np.testing.assert_allclose(tau64, means, rtol=1e-12, atol=1e-14)
+    # loss and gradient at full size against the spectral oracle
+    from oracle import spectral
+    say("config2 spectral oracle (host)")
+    gref, ref = spectral.mle_grad(w, y.cpu().numpy())
+    den = abs(ref["quad"]) + abs(ref["logdet"])
+    assert abs(out64[2] - ref["L"]) < 1e-10 * den, (out64, ref["L"])
+    gd = plan.unpack(g64)
+    scale = max(np.abs(np.atleast_1d(v)).max() for v in gref.values())
+    for k, v in gref.items():
+        e = np.abs(np.atleast_1d(gd[k]) - np.atleast_1d(v)).max() / scale
+        assert e < 1e-7, (k, gd[k], v, e)
     T, d = w.T, w.d
     _fd_check(plan, theta, g64, [T + 1, T + 3, T + 1 + d, T + 1 + d + T])
     del plan, y
