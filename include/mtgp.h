@@ -34,8 +34,17 @@
  *   - The caller owns every buffer.  `ws` is a device buffer of
  *     mtgp_workspace_bytes(plan) bytes; it holds the transformed data written
  *     by mtgp_set_data and scratch for the other calls, so calls that share a
- *     `ws` must be ordered on one stream.  Plans are immutable after creation
- *     and may be shared between threads.
+ *     `ws` must be ordered on one stream.
+ *   - Threads.  The compute calls (mtgp_kernel_cols .. mtgp_cubature) do not
+ *     change a plan, except for the overlap fork of digital-net plans: the
+ *     plan's own stream and a ring of events, taken under a lock inside the
+ *     plan.  So several host threads may issue compute calls on one plan at
+ *     once, each with its own `ws` and stream; their overlapped high passes
+ *     then queue one after the other on the plan's stream (correct, but not
+ *     concurrent).  The configuration calls (mtgp_plan_set_*, enable_timing,
+ *     destroy) and mtgp_phase_times must not run concurrently with any other
+ *     call on the same plan, and phase timing records into the plan, so a
+ *     timed plan must be used from one thread.
  *   - Return value: MTGP_OK or a negative MTGP_E* code (see mtgp_strerror).
  *
  * Hyperparameter vector theta (FP64, device), packed in this order:
@@ -73,10 +82,16 @@ enum { MTGP_DSEQ = 0, MTGP_LAT = 1 };
 /* Precision modes.  Per-frequency factorisations, log-det and quadratic-form
  * reductions are FP64 in all of them.
  *   MTGP_FP64:  everything FP64.
- *   MTGP_MIXED: kernel columns and forward-transform arithmetic FP64, the
- *               finished spectrum stored in FP32 (relative rounding only),
- *               adjoint weights, adjoint transforms and the derivative
- *               reduction in FP32 (FP64 block sums).
+ *   MTGP_MIXED: all arithmetic FP64 (kernel columns, transforms, adjoint,
+ *               derivative reduction); only the finished spectrum and the
+ *               adjoint weights are stored in FP32 (a relative rounding per
+ *               entry), which halves the bytes of the solve and of the last
+ *               forward / first adjoint transform pass.  FP32 arithmetic in
+ *               the columns or transforms was measured to make Lambda
+ *               indefinite on the T=8, d=10, n=2^24 net design (the
+ *               transform's absolute rounding ~eps32 ||c||_2 exceeds the
+ *               noise variance), and FP32 element sums in the adjoint moved
+ *               the gradient by 6.8%, so neither is used here.
  *   MTGP_F32:   kernel columns and all transform arithmetic in FP32.  The
  *               transform's absolute rounding error (~eps32 ||c||_2 sqrt(m))
  *               exceeds small noise variances xi at large n, which makes
@@ -144,7 +159,7 @@ int mtgp_plan_set_elimination(mtgp_plan* plan, int32_t mode);
 
 /* Overlap of the digital-net passes (tuning only; results are bitwise the
  * same): the columns of each length group are processed in `chunks` chunks
- * (1..8; default 4).  The VALU-bound fused passes (generation + low
+ * (1..32, at most the group's column count; default 4).  The VALU-bound fused passes (generation + low
  * transform bits, adjoint low bits + derivative reduction) run on the
  * caller's stream and the HBM-bound high transform passes on a stream owned
  * by the plan, forked from and joined back into the caller's stream through

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -68,14 +69,26 @@ struct mtgp_plan {
   // HBM-bound strided passes (aux stream) over chunks of columns; fork and
   // join through events, so the sequence can be captured in a HIP graph.
   // Events are re-recorded round-robin: a wait takes the event's state at the
-  // time it is enqueued, so reuse after the matching wait is safe.
+  // time it is enqueued, so reuse after the matching wait is safe.  Each
+  // record and its wait are taken together under a lock, so calls on one
+  // plan from several host threads never re-record an event between another
+  // call's record and wait.
   static constexpr int kMaxChunks = 32;
   static constexpr int kEvents = 32;
   int nchunks = 4;
   hipStream_t aux = nullptr;
   hipEvent_t xev[kEvents] = {};
+  mutable std::mutex xev_lock;
   mutable int xev_next = 0;
-  hipEvent_t next_ev() const { return xev[xev_next++ % kEvents]; }
+  // makes `to` wait for the work enqueued so far on `from`
+  hipError_t fork(hipStream_t from, hipStream_t to) const {
+    std::lock_guard<std::mutex> g(xev_lock);
+    const hipEvent_t e = xev[xev_next];
+    xev_next = (xev_next + 1) % kEvents;
+    hipError_t r = hipEventRecord(e, from);
+    if (r == hipSuccess) r = hipStreamWaitEvent(to, e, 0);
+    return r;
+  }
   // a ring of event sets lets many calls be timed without a host wait
   static constexpr int kRing = 64;
   bool timing = false;
@@ -218,9 +231,7 @@ int run_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
   }
   // generation + low pass of chunk k on st, its high passes on aux once the
   // chunk is written; aux joins st before the solve
-  hipEvent_t e = p->next_ev();
-  HIP_OK(hipEventRecord(e, st));
-  HIP_OK(hipStreamWaitEvent(p->aux, e, 0));
+  HIP_OK(p->fork(st, p->aux));
   for (const auto& g : p->groups) {
     const int64_t len = (int64_t)1 << g.m;
     const bool high = g.m > p->sched.lb(g.m);
@@ -237,16 +248,12 @@ int run_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
       }
       LAUNCH_OK(launch_gen_fwd<CR, CR>(work + o, len, c1 - c0, g.m, p->d_gen, sh, w.P, kd,
                                        p->sched, st));
-      e = p->next_ev();
-      HIP_OK(hipEventRecord(e, st));
-      HIP_OK(hipStreamWaitEvent(p->aux, e, 0));
+      HIP_OK(p->fork(st, p->aux));
       LAUNCH_OK(launch_strided<CR, CR, SR>(work + o, work + o, spec + o, len, c1 - c0, g.m,
                                            p->sched, p->aux));
     }
   }
-  e = p->next_ev();
-  HIP_OK(hipEventRecord(e, p->aux));
-  HIP_OK(hipStreamWaitEvent(st, e, 0));
+  HIP_OK(p->fork(p->aux, st));
   mark(p, 2, st);
   return MTGP_OK;
 }
@@ -303,9 +310,7 @@ int adjoint_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
     }
     // high passes of chunk k on aux, then its fused low pass + reduction on
     // st; partial rows keep the column order of the non-overlapped sequence
-    hipEvent_t e = p->next_ev();
-    HIP_OK(hipEventRecord(e, st));
-    HIP_OK(hipStreamWaitEvent(p->aux, e, 0));
+    HIP_OK(p->fork(st, p->aux));
     mark(p, 5, st);
     for (const auto& g : p->groups) {
       const int64_t len = (int64_t)1 << g.m;
@@ -325,9 +330,7 @@ int adjoint_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
         }
         LAUNCH_OK(launch_strided<CR, SR, CR>(spec + o, work + o, work + o, len, c1 - c0, g.m,
                                              p->sched, p->aux));
-        e = p->next_ev();
-        HIP_OK(hipEventRecord(e, p->aux));
-        HIP_OK(hipStreamWaitEvent(st, e, 0));
+        HIP_OK(p->fork(p->aux, st));
         LAUNCH_OK(launch_adj_reduce<CR, CR>(work + o, len, c1 - c0, g.m, p->d_gen, sh, w.P, kd,
                                             part, p->sched, st));
       }
@@ -335,9 +338,7 @@ int adjoint_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
     }
     // join aux back (its last chunk was already waited for; this covers
     // groups without high passes)
-    e = p->next_ev();
-    HIP_OK(hipEventRecord(e, p->aux));
-    HIP_OK(hipStreamWaitEvent(st, e, 0));
+    HIP_OK(p->fork(p->aux, st));
     return nadj;
   }
   cx<SR>* spec = reinterpret_cast<cx<SR>*>(w.cols);
@@ -661,11 +662,11 @@ int mtgp_plan_create(const mtgp_design* des, int32_t precision, mtgp_plan** out)
     p->col_u.push_back(cs.u);
     for (int j = 0; j < d; j++) p->col_shift.push_back(cs.t == cs.u ? 0u : pair_shift(cs.t, cs.u, j));
   }
-  for (int t = 0; t < T; t++) p->pm.col[t][t] = (int8_t)newidx[diag_of_m[p->m[t]]];
+  for (int t = 0; t < T; t++) p->pm.col[t][t] = (uint8_t)newidx[diag_of_m[p->m[t]]];
   {
     int q = (int)std::count_if(specs.begin(), specs.end(), [](const ColSpec& c) { return c.t == c.u; });
     for (int t = 0; t < T; t++)
-      for (int u = t + 1; u < T; u++, q++) p->pm.col[t][u] = p->pm.col[u][t] = (int8_t)newidx[q];
+      for (int u = t + 1; u < T; u++, q++) p->pm.col[t][u] = p->pm.col[u][t] = (uint8_t)newidx[q];
   }
   p->col_off.resize(p->ncol);
   int64_t acc = 0;
@@ -699,7 +700,7 @@ int mtgp_plan_create(const mtgp_design* des, int32_t precision, mtgp_plan** out)
         first = t;
         break;
       }
-    p->a1.diag_first[s] = (int8_t)first;
+    p->a1.diag_first[s] = (uint8_t)first;
   }
   {
     int64_t po = 0, co = 0;
@@ -713,6 +714,18 @@ int mtgp_plan_create(const mtgp_design* des, int32_t precision, mtgp_plan** out)
   }
   for (int t = 0; t < T; t++)
     for (int u = 0; u < T; u++) p->a1.pair_col[t][u] = p->pm.col[t][u];
+  // every pair must read back (as the kernels read it) the column it was given
+  for (int t = 0; t < T; t++)
+    for (int u = 0; u < T; u++) {
+      const int c = p->pm.at(t, u);
+      const int lo = t < u ? t : u, hi = t < u ? u : t;
+      if (c < 0 || c >= p->ncol || c != p->a1.pc(t, u) || p->col_m[c] != p->m[lo] ||
+          (lo != hi && (p->col_t[c] != lo || p->col_u[c] != hi)) ||
+          (lo == hi && p->col_t[c] != p->col_u[c])) {
+        mtgp_plan_destroy(p);
+        return MTGP_EINVAL;
+      }
+    }
   for (int c = 0; c < p->ncol; c++) {
     p->a1.col_m[c] = p->col_m[c];
     p->a1.col_off[c] = p->col_off[c];

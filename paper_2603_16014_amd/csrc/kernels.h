@@ -31,18 +31,20 @@ __device__ inline Real univ_value(int order, uint32_t u, const Params* __restric
 }
 
 // Task-pair -> column index map, and per-column scale / multiplicity.
-// Entry i of a 4-byte-aligned int8 row, taken from its dword: kernel
+// Entry i of a 4-byte-aligned uint8 row, taken from its dword: kernel
 // arguments are read by dword scalar loads, while a byte read is a vector
 // load that the address arithmetic using it has to wait for, one at a time.
-__host__ __device__ inline int i8_at(const int8_t* row, int i) {
+// Column indices reach MTGP_MAXCOL - 1 = 135, so the entries are unsigned
+// and read back zero-extended.
+__host__ __device__ inline int u8_at(const uint8_t* row, int i) {
   uint32_t w;
   __builtin_memcpy(&w, row + (i & ~3), 4);
-  return (int)(int8_t)(w >> (8 * (i & 3)));
+  return (int)((w >> (8 * (i & 3))) & 0xffu);
 }
 
 struct alignas(4) PairMap {
-  int8_t col[MTGP_MAXT][MTGP_MAXT];
-  __host__ __device__ inline int at(int j, int i) const { return i8_at(col[j], i); }
+  uint8_t col[MTGP_MAXT][MTGP_MAXT];
+  __host__ __device__ inline int at(int j, int i) const { return u8_at(col[j], i); }
 };
 
 // Transform schedule: pass A covers a_bits low index bits, each pass B at
@@ -186,8 +188,8 @@ struct Alg1Desc {
   int64_t msz[MTGP_MAXT];        // block size after stage s: sum_{t<=s} n_t / n_s
   int64_t stage_off[MTGP_MAXT];  // offset of stage s in the log-pivot buffer
   int64_t task_off[MTGP_MAXT];   // offset of task t in yhat / ahat (elements)
-  alignas(4) int8_t pair_col[MTGP_MAXT][MTGP_MAXT];
-  alignas(4) int8_t diag_first[MTGP_MAXT];  // first task with the same length
+  alignas(4) uint8_t pair_col[MTGP_MAXT][MTGP_MAXT];
+  alignas(4) uint8_t diag_first[MTGP_MAXT];  // first task with the same length
   int col_m[MTGP_MAXCOL];
   int64_t col_off[MTGP_MAXCOL];
   // fill-free elimination: pattern row a (pairs (a, b >= a), n_a entries
@@ -195,8 +197,8 @@ struct Alg1Desc {
   // k n_T) sits at coff[t] + k of each of the T unit right-hand sides
   int64_t so[MTGP_MAXT + 1];
   int64_t coff[MTGP_MAXT];
-  __host__ __device__ inline int pc(int t, int u) const { return i8_at(pair_col[t], u); }
-  __host__ __device__ inline int df(int t) const { return i8_at(diag_first, t); }
+  __host__ __device__ inline int pc(int t, int u) const { return u8_at(pair_col[t], u); }
+  __host__ __device__ inline int df(int t) const { return u8_at(diag_first, t); }
 };
 constexpr int64_t ALG1_MAX_BLOCK = 2048;  // largest final block N / n_T handled
 template <typename SR>
@@ -250,7 +252,7 @@ int launch_gcv_eq(SR* cols, int64_t n, const PairMap& pm, const double* yhat, co
 struct CubDesc {
   int equal;
   int64_t n;                            // equal sizes: common length
-  int8_t pair_col[MTGP_MAXT][MTGP_MAXT];  // column of pair (t <= u)
+  uint8_t pair_col[MTGP_MAXT][MTGP_MAXT];  // column of pair (t <= u)
   int64_t task_off[MTGP_MAXT];          // task offsets in ahat
 };
 template <typename SR>

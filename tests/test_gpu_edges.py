@@ -64,6 +64,20 @@ def test_sixteen_nested_tasks_down_to_one_point(family, elimination):
     _check_loss_grad(tiny(family, 16, m, 2, seed=84, rank=2), elimination=elimination)
 
 
+@pytest.mark.parametrize("family,elimination", [("dseq", "sparse"), ("dseq", "alg1"),
+                                                ("lat", "sparse"), ("lat", "alg1")])
+def test_sixteen_tasks_nine_distinct_sizes(family, elimination):
+    """Sixteen tasks with nine distinct lengths: 9 diagonal columns + 120
+    pair columns = 129, so column indices reach 128 (they must not wrap to
+    negative values in the pair tables)."""
+    from paper_2603_16014_amd import mtgp as mt
+    m = [8, 7, 6, 5, 4, 3, 2, 1, 0, 0, 0, 0, 0, 0, 0, 0]
+    say("nested T=16, 9 distinct sizes", family, elimination)
+    plan, _ = _check_loss_grad(tiny(family, 16, m, 2, seed=87, rank=2), elimination=elimination)
+    assert plan.ncol == 129
+    assert max(plan.column_info(c)[0] for c in range(plan.ncol)) == 8
+
+
 def test_empty_inputs():
     """Zero test points, zero transform rows: valid calls that do nothing."""
     from paper_2603_16014_amd import mtgp as mt

@@ -134,6 +134,60 @@ def test_config5_full_size():
     _mixed_vs_fp64(w, out64, g64, tau64)
 
 
+def test_config5_against_oracle():
+    """T=8, d=10, n=2^24 digital nets (N = 2^27): quad, log det, L and tau_hat
+    of both precisions against the C spectral oracle (per-frequency 8 x 8
+    Cholesky solves of Theorem "Fast MTGP computations", the shared diagonal
+    column transformed once), on targets the oracle computes at its own
+    points; posterior means at sampled points of the 2^20-point test net
+    (the bench's posterior-mean leg) against the oracle's plain sum
+    tau_t + sum_u R_tu sum_k Q(x, x_uk) alpha_uk over all 2^27 points.
+
+    Tolerances: L to 1e-10 (FP64) / 1e-5 (mixed) of |quad| + |log det|, as
+    stated for the loss.  log det dominates that scale (|log det| ~ 3e8
+    against quad ~ 3e3), so quad is also held on its own, to 1e-7 of |quad|
+    (FP64): each term rhat^2 / (lambda + xi) carries the transforms'
+    absolute eigenvalue rounding, ~ eps64 sqrt(m) ||c||_2 ~ 3e-9, against
+    xi = 1e-3.  Means to 1e-9 (FP64) / 1e-4 (mixed) of max |mean|."""
+    from oracle import spectral_big as sb
+    from paper_2603_16014_amd import mtgp
+    w = workloads.config5()
+    say("config5 oracle: targets and loss on the host "
+        f"({sb.threads()} threads, about half a minute)")
+    y_host = sb.targets(w, np.random.default_rng(w.seed + 3000))
+    ref = sb.mle(w, y_host, want_alpha=True)
+    m_star = 20
+    rng = np.random.default_rng(w.seed + 2000)
+    shift_star = workloads.random_shifts(rng, 1, w.d)[0]
+    ns = 1 << m_star
+    idx = np.unique(np.concatenate([[0, 1, ns - 1], rng.integers(0, ns, size=5)]))
+    xs = sb.points(w, ns)[idx] ^ shift_star[None, :]
+    say(f"config5 oracle: posterior mean at {idx.size} test-net points on the host")
+    mu_ref = sb.posterior_mean(w, ref, xs)
+    den = abs(ref["quad"]) + abs(ref["logdet"])
+    y = torch.from_numpy(y_host).cuda()
+    del y_host
+    for precision, tol_L, tol_mu in (("fp64", 1e-10, 1e-9), ("mixed", 1e-5, 1e-4)):
+        say("config5 oracle: GPU", precision)
+        plan = mtgp.Plan.from_workload(w, precision)
+        plan.set_data(y)
+        theta = plan.pack_theta(w.theta)
+        o, g, tau = _loss_grad(plan, theta)
+        assert abs(o[2] - ref["L"]) < tol_L * den, (precision, o, ref["L"])
+        assert abs(o[1] - ref["logdet"]) < tol_L * den, (precision, o[1], ref["logdet"])
+        if precision == "fp64":
+            assert abs(o[0] - ref["quad"]) < 1e-7 * abs(ref["quad"]), (o[0], ref["quad"])
+        np.testing.assert_allclose(tau, ref["tau_hat"], rtol=1e-10, atol=1e-13)
+        mu = plan.predict_net(theta, shift_star, m_star)
+        torch.cuda.synchronize()
+        got = mu[torch.as_tensor(idx, device="cuda")].cpu().numpy()
+        err = np.abs(got - mu_ref).max() / np.abs(mu_ref).max()
+        say(f"config5 oracle {precision}: L {o[2]!r} vs {ref['L']!r}, mean err {err:.3g}")
+        assert err < tol_mu, (precision, err)
+        del plan, mu
+        torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_config5_single_pass_high_bits(precision):
     """The 12 high index bits of the 2^24-point columns in one register + LDS
