@@ -180,11 +180,67 @@ def load_traffic(precision):
     return {k: v["hbm_bytes"] for k, v in blob.get("phases", {}).items()}
 
 
+def _timed(fn, min_s=1.0, max_reps=5):
+    """Mean wall time of fn() over repeats until min_s has passed."""
+    t0, reps = time.perf_counter(), 0
+    while True:
+        fn()
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= min_s or reps >= max_reps:
+            return el / reps
+
+
+def dense_baseline():
+    """The dense FP64 oracle (Gram assembly, LAPACK Cholesky, solves) timed on
+    the host: the small net workload at its full size (T=2, d=2, n=2^10,
+    N=2048; loss, loss + gradient, posterior mean at 1024 points), with all
+    BLAS threads and with one, and the large workload's shape (T=8, d=10)
+    scaled to 2^9 points per task (N=4096; loss).  The O(N^3) extrapolation
+    to N=2^27 is labelled as one."""
+    import threadpoolctl
+    import workloads
+    from oracle import dense, points
+    info = threadpoolctl.threadpool_info()
+    blas = sorted({f"{i.get('internal_api')} {i.get('version')}" for i in info
+                   if i.get("user_api") == "blas"})
+    threads = max([i.get("num_threads", 1) for i in info] + [1])
+    out = {"blas": blas, "blas_threads": threads, "os_cpu_count": os.cpu_count(),
+           "affinity_cpus": len(os.sched_getaffinity(0))}
+    w1 = workloads.config1()
+    X = points.task_points(w1)
+    y = dense.targets(w1, np.random.default_rng(w1.seed), X)
+    xs = workloads.uniform_digits(np.random.default_rng(0), 1024, w1.d)
+    small = {"workload": f"T={w1.T}, d={w1.d}, n=2^{w1.m[0]} digital nets, N={w1.N}"}
+    for label, limit in (("all_threads", None), ("1_thread", 1)):
+        progress(f"cpu baseline: dense oracle N={w1.N}, {label}")
+        with threadpoolctl.threadpool_limits(limits=limit):
+            small[label] = {
+                "nll_s": _timed(lambda: dense.nll(w1, y, X=X)),
+                "nll_grad_s": _timed(lambda: dense.grad(w1, y, X=X), max_reps=2),
+                "predict_1024_s": _timed(lambda: dense.posterior_mean(w1, y, xs, X=X), max_reps=2),
+            }
+    out["small_net_full_size"] = small
+    w5 = workloads.config5()
+    ws = workloads.scaled(w5, [9] * w5.T)
+    Xs = points.task_points(ws)
+    ys = dense.targets(ws, np.random.default_rng(1), Xs)
+    progress(f"cpu baseline: dense oracle N={ws.N} (large workload's shape)")
+    t = _timed(lambda: dense.nll(ws, ys, X=Xs), min_s=0.0, max_reps=1)
+    out["large_shape_scaled"] = {
+        "workload": f"T={ws.T}, d={ws.d}, n=2^9 per task, N={ws.N}", "nll_s": t,
+        "extrapolated_nll_s_at_full_size": t * (w5.N / ws.N) ** 3,
+        "extrapolation": "O(N^3) from N=4096 to N=2^27; the Gram matrix alone would need "
+                         f"{8 * w5.N ** 2 / 2 ** 50:.0f} PiB"}
+    return out
+
+
 def cpu_baseline(w, budget_s=25.0):
     """The spectral oracle (numpy, FP64: Walsh / DFT of the kernel columns and
     of their derivative columns, per-frequency T x T solves) computing the MLE
     loss and gradient on the workload's shape at 2^16 points per task; the
-    rate is scaled to the full size by the n log n cost of its transforms."""
+    rate is scaled to the full size by the n log n cost of its transforms.
+    The dense oracle's own timings go beside it."""
     import workloads
     from oracle import dense, points, spectral
     import threadpoolctl
@@ -209,8 +265,11 @@ def cpu_baseline(w, budget_s=25.0):
     return {"value": 1.0 / per_full, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"spectral FP64 oracle (numpy) loss+gradient at T={w.T}, d={w.d}, "
                       f"n=2^{m} per task (N={ws.N}): {reps} evals in {el:.1f} s = {per:.2f} "
-                      f"s/eval; value = that rate scaled by n log n to n=2^{mf} (x{scale:.0f})",
-            "sample_evals_per_s": 1.0 / per}
+                      f"s/eval; value = that rate scaled by n log n to n=2^{mf} (x{scale:.0f}), "
+                      "an extrapolation",
+            "sample_evals_per_s": 1.0 / per,
+            "os_cpu_count": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "dense": dense_baseline()}
 
 
 def train_leg(plan, theta, steps, lr=0.05):

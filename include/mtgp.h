@@ -320,8 +320,10 @@ int mtgp_adam_step(double* theta, const double* grad, double* m1, double* m2, in
 /* Reads the device status word of ws (synchronously, after the caller has
  * synchronised the stream).  Returns MTGP_OK or MTGP_ENOTPD; *bad_index (may
  * be NULL) receives the first frequency (or residue class) whose pivot was
- * not positive or not finite, else -1.  The status is cleared by each
- * mtgp_nll / mtgp_nll_grad / mtgp_predict call. */
+ * not positive or not finite, else -1.  The status is cleared by
+ * mtgp_set_data and at the start of every call that evaluates the loss
+ * (mtgp_nll, mtgp_nll_grad, mtgp_predict with M > 0, mtgp_predict_net,
+ * mtgp_gcv, mtgp_cubature). */
 int mtgp_status(const mtgp_plan* plan, const void* ws, int64_t* bad_index);
 
 const char* mtgp_strerror(int code);

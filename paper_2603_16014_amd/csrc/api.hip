@@ -942,6 +942,8 @@ int mtgp_set_data(const mtgp_plan* p, const double* y, void* ws, void* stream) {
   if (!p || !y || !ws) return MTGP_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const WsView w = view(p, ws);
+  // a fresh workspace reads as "no error" until the first evaluation
+  LAUNCH_OK(launch_clear_status(w.status, st));
   if (p->family == MTGP_LAT) {
     // yhat_t = n_t^-1/2 F (bit reversal of y_t), in the spectrum layout of length n_t
     const KDesc kd = p->kd();

@@ -95,6 +95,7 @@ int launch_adj_reduce(const TIn* base, int64_t col_stride, int ncols, int m, con
                       const Sched& sc, hipStream_t st);
 
 // ---- solve.hip
+int launch_clear_status(int* status, hipStream_t st);
 int launch_prep(const double* theta, Params* P, const KDesc& kd, int* status, hipStream_t st);
 // T padded to the factorisation template size, and the number of FP64
 // partial sums per block of the solves (equal sizes and the elimination):

@@ -52,6 +52,20 @@ __global__ void prep_kernel(const double* __restrict__ theta, Params* __restrict
   *reinterpret_cast<unsigned long long*>(status + 2) = ~0ull;
 }
 
+__global__ void clear_status_kernel(int* status) {
+  if (threadIdx.x == 0) {
+    status[0] = 0;
+    status[1] = 0;
+    *reinterpret_cast<unsigned long long*>(status + 2) = ~0ull;
+  }
+}
+
+// A fill kernel rather than a memset, so a captured graph holds no memset node.
+int launch_clear_status(int* status, hipStream_t st) {
+  hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, st, status);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_prep(const double* theta, Params* P, const KDesc& kd, int* status, hipStream_t st) {
   hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(64), 0, st, theta, P, kd, status);
   return hipGetLastError() == hipSuccess ? 0 : -1;
