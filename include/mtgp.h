@@ -75,7 +75,8 @@ enum {
   MTGP_ENOTPD = -2,   /* Lambda not positive definite at some frequency / NaN */
   MTGP_EHIP = -3,     /* a HIP runtime call failed */
   MTGP_ENOMEM = -4,   /* plan creation could not allocate its small tables */
-  MTGP_ENOTSUP = -5   /* combination not supported by this build */
+  MTGP_ENOTSUP = -5,  /* combination not supported by this build */
+  MTGP_ETOOBIG = -6   /* input exceeds the static scratch of an allocation-free entry point */
 };
 
 enum { MTGP_DSEQ = 0, MTGP_LAT = 1 };
@@ -238,6 +239,25 @@ int mtgp_fwht(void* x, int64_t batch, int32_t log2n, int32_t dtype, void* stream
  * pointers may then be NULL). */
 int mtgp_fft(const void* x, void* X, void* scratch, int64_t batch, int32_t log2n, int32_t dtype,
              int32_t bitrev_input, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mtgp_fft
+ * without the scratch argument.  Same transform, arguments and results as
+ * mtgp_fft.  The multi-pass sizes (log2n > 12) stage the bit-reversed
+ * spectrum in a static device array of MTGP_FFT_NOALLOC_SCRATCH_BYTES bytes
+ * (32 MiB) that each GPU the library runs on holds until the process ends;
+ * batch * 2^log2n complex values of dtype (16 B for F64, 8 B for F32) must
+ * fit in it, else MTGP_ETOOBIG and nothing is enqueued.  The call allocates
+ * nothing: the array's device address is looked up once per device, on that
+ * device's first call (hipGetSymbolAddress; MTGP_EHIP if that fails), so
+ * make one call outside any capture before capturing.  Every call on a GPU
+ * shares that GPU's array, and every entry of it is written before it is
+ * read, so nothing carries over between calls; calls that overlap in time on
+ * one GPU (two streams, two threads) race on it and must be ordered by the
+ * caller. */
+#define MTGP_FFT_NOALLOC_SCRATCH_BYTES 33554432
+int mtgp_fft_noalloc(const void* x, void* X, int64_t batch, int32_t log2n, int32_t dtype,
+                     int32_t bitrev_input, void* stream);
 
 /* Transforms the data once per data set: yhat_t = V^dagger_{m_t} y_t
  * (Theorem "Fast MTGP computations"), kept inside ws for later calls. */

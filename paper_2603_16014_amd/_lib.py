@@ -42,6 +42,7 @@ SIGNATURES = {
     "mtgp_kernel_cols": (ctypes.c_int, [vp, vp, vp, vp, vp]),
     "mtgp_fwht": (ctypes.c_int, [vp, c_i64, c_i32, c_i32, vp]),
     "mtgp_fft": (ctypes.c_int, [vp, vp, vp, c_i64, c_i32, c_i32, c_i32, vp]),
+    "mtgp_fft_noalloc": (ctypes.c_int, [vp, vp, c_i64, c_i32, c_i32, c_i32, vp]),
     "mtgp_set_data": (ctypes.c_int, [vp, vp, vp, vp]),
     "mtgp_nll": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
     "mtgp_nll_grad": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),

@@ -566,6 +566,73 @@ bool valid_family_order(const mtgp_design* d) {
   return false;
 }
 
+// Forward DFT of real rows (mtgp_fft); `scratch` holds the bit-reversed
+// spectrum of the multi-pass sizes and is unused (may be NULL) for the
+// single-pass ones.
+int fft_run(const void* x, void* X, void* scratch, int64_t batch, int32_t log2n, int32_t dtype,
+            int32_t bitrev_input, hipStream_t st) {
+  if (batch < 0 || batch > 65535 || log2n < 0 || log2n > 30) return MTGP_EINVAL;
+  if (dtype != MTGP_DTYPE_F64 && dtype != MTGP_DTYPE_F32) return MTGP_EINVAL;
+  if (batch == 0) return MTGP_OK;
+  const bool single = lat_single_pass(log2n);
+  if (!x || !X || (!single && !scratch)) return MTGP_EINVAL;
+  const int src = bitrev_input ? LAT_SRC_Y : LAT_SRC_X;
+  const int64_t n = (int64_t)1 << log2n;
+  const int f32 = dtype == MTGP_DTYPE_F32;
+  if (single) {
+    // one LDS pass writes natural frequency order itself
+    if (f32)
+      LAUNCH_OK(launch_lat_single_natural<float>(src, x, 1, static_cast<cx<float>*>(X), (int)batch,
+                                                 log2n, st));
+    else
+      LAUNCH_OK(launch_lat_single_natural<double>(src, x, 0, static_cast<cx<double>*>(X),
+                                                  (int)batch, log2n, st));
+    return MTGP_OK;
+  }
+  // bit-reversed spectrum in scratch (every entry written before it is
+  // read), then permuted into X
+  KDesc kd{};
+  kd.family = FAM_LAT;
+  kd.order = 1;
+  if (f32)
+    LAUNCH_OK(launch_lat_forward<float, float>(src, static_cast<cx<float>*>(scratch),
+                                               static_cast<cx<float>*>(scratch), n, (int)batch,
+                                               log2n, x, 1, 1.0, nullptr, nullptr, nullptr, kd, st));
+  else
+    LAUNCH_OK(launch_lat_forward<double, double>(src, static_cast<cx<double>*>(scratch),
+                                                 static_cast<cx<double>*>(scratch), n, (int)batch,
+                                                 log2n, x, 0, 1.0, nullptr, nullptr, nullptr, kd, st));
+  LAUNCH_OK(launch_lat_natural(scratch, f32, X, batch, log2n, st));
+  return MTGP_OK;
+}
+
+// Scratch of mtgp_fft_noalloc: one static device array, which every GPU
+// the library runs on holds (its own copy at its own address) until the
+// process ends.  Host code never passes the array's name to a kernel or a
+// copy (on the host it only stands for the symbol); it uses the device
+// address that hipGetSymbolAddress returns, looked up once per device on
+// that device's first call and kept in fft_scratch_dev.
+__device__ __align__(256) static unsigned char fft_noalloc_scratch[MTGP_FFT_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex fft_scratch_lock;
+void* fft_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's copy of fft_noalloc_scratch.
+int fft_scratch_ptr(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return MTGP_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return MTGP_ENOTSUP;
+  std::lock_guard<std::mutex> g(fft_scratch_lock);
+  if (!fft_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(fft_noalloc_scratch)) != hipSuccess || !ptr)
+      return MTGP_EHIP;
+    fft_scratch_dev[dev] = ptr;
+  }
+  *out = fft_scratch_dev[dev];
+  return MTGP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -578,6 +645,7 @@ const char* mtgp_strerror(int code) {
     case MTGP_EHIP: return "HIP runtime error";
     case MTGP_ENOMEM: return "out of memory";
     case MTGP_ENOTSUP: return "not supported by this build";
+    case MTGP_ETOOBIG: return "input larger than the static scratch of an allocation-free entry point";
   }
   return "unknown error";
 }
@@ -903,39 +971,24 @@ int mtgp_fwht(void* x, int64_t batch, int32_t log2n, int32_t dtype, void* stream
 
 int mtgp_fft(const void* x, void* X, void* scratch, int64_t batch, int32_t log2n, int32_t dtype,
              int32_t bitrev_input, void* stream) {
+  return fft_run(x, X, scratch, batch, log2n, dtype, bitrev_input, (hipStream_t)stream);
+}
+
+int mtgp_fft_noalloc(const void* x, void* X, int64_t batch, int32_t log2n, int32_t dtype,
+                     int32_t bitrev_input, void* stream) {
   if (batch < 0 || batch > 65535 || log2n < 0 || log2n > 30) return MTGP_EINVAL;
   if (dtype != MTGP_DTYPE_F64 && dtype != MTGP_DTYPE_F32) return MTGP_EINVAL;
   if (batch == 0) return MTGP_OK;
-  const bool single = lat_single_pass(log2n);
-  if (!x || !X || (!single && !scratch)) return MTGP_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
-  const int src = bitrev_input ? LAT_SRC_Y : LAT_SRC_X;
-  const int64_t n = (int64_t)1 << log2n;
-  const int f32 = dtype == MTGP_DTYPE_F32;
-  if (single) {
-    // one LDS pass writes natural frequency order itself
-    if (f32)
-      LAUNCH_OK(launch_lat_single_natural<float>(src, x, 1, static_cast<cx<float>*>(X), (int)batch,
-                                                 log2n, st));
-    else
-      LAUNCH_OK(launch_lat_single_natural<double>(src, x, 0, static_cast<cx<double>*>(X),
-                                                  (int)batch, log2n, st));
-    return MTGP_OK;
+  void* scr = nullptr;
+  if (!lat_single_pass(log2n)) {
+    const size_t cbytes = dtype == MTGP_DTYPE_F64 ? 2 * sizeof(double) : 2 * sizeof(float);
+    // batch <= 65535 and log2n <= 30, so the product fits in 64 bits
+    if ((uint64_t)batch * ((uint64_t)1 << log2n) * cbytes > (uint64_t)MTGP_FFT_NOALLOC_SCRATCH_BYTES)
+      return MTGP_ETOOBIG;
+    const int rc = fft_scratch_ptr(&scr);
+    if (rc) return rc;
   }
-  // bit-reversed spectrum in scratch, then permuted into X
-  KDesc kd{};
-  kd.family = FAM_LAT;
-  kd.order = 1;
-  if (f32)
-    LAUNCH_OK(launch_lat_forward<float, float>(src, static_cast<cx<float>*>(scratch),
-                                               static_cast<cx<float>*>(scratch), n, (int)batch,
-                                               log2n, x, 1, 1.0, nullptr, nullptr, nullptr, kd, st));
-  else
-    LAUNCH_OK(launch_lat_forward<double, double>(src, static_cast<cx<double>*>(scratch),
-                                                 static_cast<cx<double>*>(scratch), n, (int)batch,
-                                                 log2n, x, 0, 1.0, nullptr, nullptr, nullptr, kd, st));
-  LAUNCH_OK(launch_lat_natural(scratch, f32, X, batch, log2n, st));
-  return MTGP_OK;
+  return fft_run(x, X, scr, batch, log2n, dtype, bitrev_input, (hipStream_t)stream);
 }
 
 int mtgp_set_data(const mtgp_plan* p, const double* y, void* ws, void* stream) {
