@@ -38,9 +38,18 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane
+# operations/s (one wave64 instruction per CU per clock); FP64 FMA and the
+# integer / conversion instructions of the fused kernels issue at this rate
+# (FP32 vector 157.3 TFLOP/s = 4 flops per lane-op with packed FMA; FP64
+# vector 78.6 TFLOP/s = 2 flops per lane-op)
+CU_COUNT, CLOCK_HZ = 256, 2.4e9
+VALU_LANE_OPS_PEAK = CU_COUNT * 64 * CLOCK_HZ
+GEN_OPS_PER_UNIT = 12.0   # VALU lane ops per (column, element, dimension): generation
+ADJ_OPS_PER_UNIT = 18.5   # the same for the derivative reduction
 COPY_PROBE_BYTES = 1 << 30     # plain streaming kernel used to scale the HBM counters
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_loss_grad_T8_d10_n2e24_mixed.md")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_gen_adj_T8_d10_n2e24_mixed.md")
 
 # phase -> (kernel-name pattern in rocprofv3 output, bound)
 PHASE_KERNELS = {
@@ -145,25 +154,48 @@ def time_evals(plan, theta, steps, warmup, timing=True):
 
 
 def algo_units(w, precision, a_bits=12):
-    """Algorithmic HBM bytes (and FP64 flops for the fused evaluation kernels)
-    per launch of each phase at this workload: P distinct kernel columns of
-    length n, forward working values of wb bytes, spectrum / adjoint weights
-    of sb bytes."""
+    """Algorithmic HBM bytes per launch of each phase at this workload (P
+    distinct kernel columns of length n, forward working values of wb bytes,
+    spectrum / adjoint weights of sb bytes), and for the two fused evaluation
+    kernels their VALU lane operations by the model's per-unit counts: about
+    12 per (column, element, dimension) for the generation and 18.5 for the
+    derivative reduction (9e10 per evaluation at T=8, d=10, n=2^24)."""
     T, d, n, P = w.T, w.d, 1 << w.m[0], 1 + w.T * (w.T - 1) // 2
     wb, sb = {"fp64": (8, 8), "mixed": (8, 4), "f32": (4, 4)}[precision]
     lb = min(a_bits, w.m[0])  # width of the low-bit (LDS) transform pass
     return {
-        # write the low-bit transformed columns; flops: kernel factor 2 FMA +
-        # 1 FMA + product 1 mul per (element, dimension), lb butterfly adds
-        "gen_fwd_low": {"bytes": P * n * wb, "flops": P * n * (7 * d + lb)},
+        "gen_fwd_low": {"bytes": P * n * wb, "ops": GEN_OPS_PER_UNIT * P * n * d},
         "fwd_high": {"bytes": P * n * (wb + sb)},        # read work, write spectrum
         "solve": {"bytes": P * n * 2 * sb + T * n * 8},  # read spectrum + yhat, write weights
         "adj_high": {"bytes": P * n * (sb + wb)},        # read weights, write work
-        # read the partly transformed weights; flops: lb butterflies, kernel factor 6, prefix and
-        # suffix products 2, product with the weight 2, accumulation 2 per dim
         "adj_low_reduce": {"bytes": P * n * (wb if w.m[0] > lb else sb),
-                           "flops": P * n * (12 * d + lb)},
+                           "ops": ADJ_OPS_PER_UNIT * P * n * d},
     }
+
+
+def eval_bytes_model(w, precision):
+    """HBM bytes of one loss + gradient evaluation by the model
+    (8 P b + 8 T) n: two HBM passes per transform direction with column
+    generation fused into the first forward pass and the derivative
+    reduction into the last adjoint pass, b bytes per stored spectrum /
+    weight value, and the FP64 transformed data read once."""
+    T, n, P = w.T, 1 << w.m[0], 1 + w.T * (w.T - 1) // 2
+    b = {"fp64": 8, "mixed": 4, "f32": 4}[precision]
+    return (8 * P * b + 8 * T) * n
+
+
+def load_valu(precision):
+    """VALU counters per launch of the fused evaluation kernels from the
+    committed summary, or None when it is missing or stale."""
+    if precision != "mixed" or not os.path.exists(VALU_FILE):
+        return None
+    txt = open(VALU_FILE).read()
+    if "```json" not in txt:
+        return None
+    blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+    if blob.get("sources_digest") != kernel_sources_digest():
+        return None
+    return blob.get("kernels", {})
 
 
 def load_traffic(precision):
@@ -507,12 +539,18 @@ def run(args):
         extra["fp64_ms_per_step"] = b["ms"]
         extra["fp64_sequential_ms_per_step"] = b["ms_seq"]
         extra["fp64_phases_ms"] = {k: round(v, 4) for k, v in b["phases"].items()}
+        eb64 = eval_bytes_model(w, "fp64")
+        extra["fp64_roofline_eval"] = {
+            "bound": "hbm", "model_bytes": eb64, "achieved": eb64 / (b["ms"] * 1e-3) / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": eb64 / (b["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
     ph = r["phases"]
     units = algo_units(w, primary, r["schedule"][0])
     # the committed counter profile was taken with the default schedule
     from paper_2603_16014_amd import mtgp as _mt
     traffic = (load_traffic(primary)
                if args.m == 24 and tuple(r["schedule"]) == _mt.DEFAULT_SCHEDULE else None)
+    valu = load_valu(primary) if args.m == 24 else None
     kernels = {}
     for k, (pat, bound) in PHASE_KERNELS.items():
         if k not in ph or ph[k] <= 0:
@@ -521,11 +559,17 @@ def run(args):
         e = {"kernel": pat, "ms": round(ph[k], 4), "bound": bound,
              "GB_s": u["bytes"] / (ph[k] * 1e-3) / 1e9}
         e["hbm_frac"] = e["GB_s"] / HBM_PEAK_GBS
-        if "flops" in u:
-            e["TFLOP_s"] = u["flops"] / (ph[k] * 1e-3) / 1e12
-            e["fp64_frac"] = e["TFLOP_s"] / FP64_VALU_PEAK_TFLOPS
+        if "ops" in u:
+            e["Tops_s"] = u["ops"] / (ph[k] * 1e-3) / 1e12
+            e["valu_frac"] = e["Tops_s"] * 1e12 / VALU_LANE_OPS_PEAK
         if traffic and k in traffic:
             e["traffic"] = traffic[k]
+        if valu and pat in valu:
+            # issued VALU instructions (wave64) per launch from the counters,
+            # against one instruction per CU per clock over this launch's time
+            v = valu[pat]
+            e["counters"] = v
+            e["valu_issue_frac"] = v["SQ_INSTS_VALU"] / (ph[k] * 1e-3 * CU_COUNT * CLOCK_HZ)
         kernels[k] = e
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
     kd = kernels[dom]
@@ -533,9 +577,21 @@ def run(args):
         roof = {"bound": "hbm", "kernel": kd["kernel"], "achieved": kd["GB_s"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kd["hbm_frac"]}
     else:
-        roof = {"bound": "alu", "kernel": kd["kernel"], "achieved": kd["TFLOP_s"],
-                "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": kd["fp64_frac"]}
+        roof = {"bound": "alu", "kernel": kd["kernel"], "achieved": kd["Tops_s"],
+                "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "T VALU lane-ops/s",
+                "frac": kd["valu_frac"],
+                "model": f"{ADJ_OPS_PER_UNIT if dom == 'adj_low_reduce' else GEN_OPS_PER_UNIT} "
+                         "lane ops per (column, element, dimension)"}
+        if "valu_issue_frac" in kd:
+            roof["valu_issue_frac"] = kd["valu_issue_frac"]
     roof["traffic"] = kd.get("traffic")
+    eb = eval_bytes_model(w, primary)
+    roof_eval = {"bound": "hbm", "model_bytes": eb, "achieved": eb / (r["ms"] * 1e-3) / 1e9,
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": eb / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 "model": "(8 P b + 8 T) n bytes per evaluation, b = stored spectrum bytes"}
+    if traffic:
+        roof_eval["traffic"] = sum(traffic.values())
     line = {
         "metric": "NLL+grad evals/sec at T=8,n=2^24",
         "value": 1000.0 / r["ms"],
@@ -559,6 +615,7 @@ def run(args):
         "phase_steps_timed": r["nph"],
         "kernels": kernels,
         "roofline": roof,
+        "roofline_eval": roof_eval,
     }
     line.update(extra)
     line["schedule"] = {"pass_a_bits": r["schedule"][0], "pass_b_bits": r["schedule"][1],
@@ -695,6 +752,54 @@ def pmc_summary(fetch_dir, write_dir, trace_dir, cmdline):
     return "\n".join(out)
 
 
+VALU_KERNELS = ("gen_fwd_kernel", "adj_reduce_kernel")
+
+
+def valu_summary(pmc_dirs, trace_dir, cmdline):
+    """Per-launch means of the counters of several rocprofv3 --pmc runs and
+    the launch durations of a trace run, for the two fused evaluation
+    kernels, as markdown with a JSON block read back by the benchmark."""
+    acc = {k: {} for k in VALU_KERNELS}
+    for d in pmc_dirs:
+        for r in _csv_rows(d, "counter_collection.csv"):
+            k = next((k for k in VALU_KERNELS if k in r["Kernel_Name"]), None)
+            if k is None:
+                continue
+            a = acc[k].setdefault(r["Counter_Name"], [0.0, 0])
+            a[0] += float(r["Counter_Value"])
+            a[1] += 1
+    dur = {k: [] for k in VALU_KERNELS}
+    for r in _csv_rows(trace_dir, "kernel_trace.csv"):
+        k = next((k for k in VALU_KERNELS if k in r["Kernel_Name"]), None)
+        if k is not None:
+            dur[k].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    blob = {"sources_digest": kernel_sources_digest(), "kernels": {}}
+    out = ["# VALU counters: fused generation and derivative-reduction kernels, "
+           "T=8, d=10, n=2^24, mixed path", "",
+           "Commands (run from the repository root on one MI355X):", "", "```"]
+    out += cmdline
+    out += ["```", "",
+            "Means per launch (counters summed over the whole GPU by rocprofv3). The issue "
+            f"fraction is SQ_INSTS_VALU / (duration x {CU_COUNT} CUs x {CLOCK_HZ / 1e9} GHz): "
+            "one wave64 VALU instruction per CU per clock is the issue peak (4 SIMDs x 16 "
+            "lanes, 4 clocks per wave64 instruction).", "",
+            "| kernel | us (trace) | counter | per launch |", "|---|---|---|---|"]
+    for k in VALU_KERNELS:
+        if not acc[k]:
+            continue
+        us = sum(dur[k]) / len(dur[k]) if dur[k] else float("nan")
+        e = {c: v[0] / v[1] for c, v in sorted(acc[k].items())}
+        e["us"] = us
+        if "SQ_INSTS_VALU" in e and dur[k]:
+            e["valu_issue_frac"] = e["SQ_INSTS_VALU"] / (us * 1e-6 * CU_COUNT * CLOCK_HZ)
+        blob["kernels"][k] = e
+        for c, v in e.items():
+            if c != "us":
+                out.append(f"| `{k}` | {us:.1f} | {c} | {v:.6g} |")
+    out += ["", "```json", json.dumps(blob, indent=1), "```", ""]
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -718,11 +823,16 @@ def main():
     ap.add_argument("--fits", type=int, default=256, help="fits of the batched leg (0: skip)")
     ap.add_argument("--fit-steps", type=int, default=50)
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "TRACE_DIR"))
+    ap.add_argument("--valu-summary", nargs="+", metavar="DIR",
+                    help="rocprofv3 --pmc output dirs, then the kernel-trace dir")
     ap.add_argument("--pmc-command", action="append", default=[],
                     help="command line recorded in the summary (repeatable)")
     args = ap.parse_args()
     if args.pmc_summary:
         print(pmc_summary(*args.pmc_summary, args.pmc_command))
+        return
+    if args.valu_summary:
+        print(valu_summary(args.valu_summary[:-1], args.valu_summary[-1], args.pmc_command))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the fast MTGP path here runs on a single "

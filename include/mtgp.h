@@ -296,6 +296,26 @@ size_t mtgp_predict_net_scratch_bytes(const mtgp_plan* plan, int32_t m_star);
 int mtgp_predict_net(const mtgp_plan* plan, const double* theta, const uint32_t* shift_star,
                      int32_t m_star, double* mean, void* ws, void* scratch, void* stream);
 
+/* Posterior variance (Eq. MTGP_post_mean_cov, the covariance at (t, x) =
+ * (t', x')) at M arbitrary inputs xs[M][d] (digits): var[M][T],
+ *   var[m][t] = R_tt Q(x_m, x_m) - k(t, x_m)^T Ktilde^-1 k(t, x_m),
+ *   k(t, x) = (R_tu Q(x, x_uk))_{u, k}  (the latent f, without noise).
+ * Per test point the T cross columns Q(x, x_uk) are generated and
+ * transformed like kernel columns (Theorem "Fast MTGP computations":
+ * V^dagger k has blocks R_tu V_u^dagger Q(x, x_u.)), and the quadratic form
+ * runs through the loss's factorisation: per-frequency L D L^H at equal
+ * sizes, forward substitution through the fill-free task-order factor at
+ * nested sizes (MTGP_ELIM_SPARSE; MTGP_ELIM_ALG1 returns MTGP_ENOTSUP).
+ * O(N log N + N T^2) per test point.  Test points are processed `batch` at
+ * a time in `scratch`, a device buffer of
+ * mtgp_predict_var_scratch_bytes(plan, batch) bytes.  Runs one loss
+ * evaluation on ws (data set by mtgp_set_data).  The result is a difference
+ * of two terms of size R_tt Q(x, x): its rounding is relative to that scale,
+ * not to var.  M = 0 does nothing. */
+size_t mtgp_predict_var_scratch_bytes(const mtgp_plan* plan, int32_t batch);
+int mtgp_predict_var(const mtgp_plan* plan, const double* theta, const uint32_t* xs, int64_t M,
+                     int32_t batch, double* var, void* ws, void* scratch, void* stream);
+
 /* GCV loss (Eq. MTGP_MLE_GCV_loss): out3 = (q, s, L_GCV) with
  * q = r^T Ktilde^-2 r, s = tr Ktilde^-1, L_GCV = q / s^2, r = y - E^T tau,
  * and optionally its gradient (device [theta size], same packing as

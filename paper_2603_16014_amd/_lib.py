@@ -49,6 +49,8 @@ SIGNATURES = {
     "mtgp_predict": (ctypes.c_int, [vp, vp, vp, c_i64, vp, vp, vp]),
     "mtgp_predict_net_scratch_bytes": (c_sz, [vp, c_i32]),
     "mtgp_predict_net": (ctypes.c_int, [vp, vp, ctypes.POINTER(c_u32), c_i32, vp, vp, vp, vp]),
+    "mtgp_predict_var_scratch_bytes": (c_sz, [vp, c_i32]),
+    "mtgp_predict_var": (ctypes.c_int, [vp, vp, vp, c_i64, c_i32, vp, vp, vp, vp]),
     "mtgp_status": (ctypes.c_int, [vp, vp, ctypes.POINTER(c_i64)]),
     "mtgp_gcv": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
     "mtgp_cubature": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),

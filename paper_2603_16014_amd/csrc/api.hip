@@ -1187,6 +1187,94 @@ int mtgp_predict_net(const mtgp_plan* p, const double* theta, const uint32_t* sh
   return MTGP_OK;
 }
 
+// scratch of mtgp_predict_var for batches of `batch` test points: the cross
+// spectra (batch x N values, complex for lattices), their shifts, the
+// partial quadratic forms and, at nested sizes, the batch x T stacked
+// right-hand sides of the forward substitution
+struct VarLayout {
+  size_t o_shift, o_part, o_y, bytes;
+  int nbx;
+};
+static VarLayout var_layout(const mtgp_plan* p, int64_t batch) {
+  VarLayout L;
+  const size_t cplx = p->family == MTGP_LAT ? 2 : 1;
+  const int64_t nrow = p->equal ? p->n[0] : p->N;
+  L.nbx = (int)std::min<int64_t>((nrow + 255) / 256, 256);
+  size_t o = align_up((size_t)batch * p->N * sizeof(double) * cplx);
+  L.o_shift = o;
+  o = align_up(o + (size_t)p->T * batch * p->d * sizeof(uint32_t));
+  L.o_part = o;
+  o = align_up(o + (size_t)batch * L.nbx * std::max(16, p->T) * sizeof(double));
+  L.o_y = o;
+  if (!p->equal) o = align_up(o + (size_t)batch * p->T * p->N * sizeof(z2));
+  L.bytes = o;
+  return L;
+}
+
+size_t mtgp_predict_var_scratch_bytes(const mtgp_plan* p, int32_t batch) {
+  if (!p || batch < 1) return 0;
+  return var_layout(p, batch).bytes;
+}
+
+int mtgp_predict_var(const mtgp_plan* p, const double* theta, const uint32_t* xs, int64_t M,
+                     int32_t batch, double* var, void* ws, void* scratch, void* stream) {
+  if (!p || !theta || !ws || M < 0 || batch < 1 || (M > 0 && (!xs || !var || !scratch)))
+    return MTGP_EINVAL;
+  if (!p->equal && p->elim != MTGP_ELIM_SPARSE) return MTGP_ENOTSUP;
+  if (M == 0) return MTGP_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const WsView w = view(p, ws);
+  // loss pass without gradient: the spectrum (equal sizes) or the factor in
+  // the pattern storage (nested sizes) stays in ws
+  int rc = dispatch_loss(p, theta, w.misc, nullptr, nullptr, ws, st, false);
+  if (rc) return rc;
+  const VarLayout L = var_layout(p, batch);
+  unsigned char* sb = static_cast<unsigned char*>(scratch);
+  double* mu = reinterpret_cast<double*>(sb);
+  uint32_t* shd = reinterpret_cast<uint32_t*>(sb + L.o_shift);
+  double* part = reinterpret_cast<double*>(sb + L.o_part);
+  z2* Y = reinterpret_cast<z2*>(sb + L.o_y);
+  const KDesc kd = p->kd();
+  const bool lat = p->family == MTGP_LAT;
+  for (int64_t m0 = 0; m0 < M; m0 += batch) {
+    const int64_t mb = std::min<int64_t>(batch, M - m0);
+    LAUNCH_OK(launch_var_shifts(xs + (size_t)m0 * p->d, mb, p->d_taskshift, p->T, p->d,
+                                p->family, shd, st));
+    // cross spectra of task u: mb columns of length n_u after mb * off[u]
+    for (int u = 0; u < p->T; u++) {
+      const int64_t len = p->n[u];
+      const uint32_t* sh = shd + (size_t)u * mb * p->d;
+      if (lat) {
+        cx<double>* col = reinterpret_cast<cx<double>*>(mu) + (size_t)mb * p->off[u];
+        LAUNCH_OK(launch_lat_forward<double, double>(LAT_SRC_GEN, col, col, len, (int)mb, p->m[u],
+                                                     nullptr, 0, 1.0, p->d_gen, sh, w.P, kd, st));
+      } else {
+        double* col = mu + (size_t)mb * p->off[u];
+        LAUNCH_OK(launch_gen_fwd<double, double>(col, len, (int)mb, p->m[u], p->d_gen, sh, w.P, kd,
+                                                 p->sched, st));
+        LAUNCH_OK(launch_strided<double, double, double>(col, col, col, len, mb, p->m[u],
+                                                         p->sched, st));
+      }
+    }
+    if (p->equal) {
+      const int64_t n = p->n[0];
+      if (p->precision == MTGP_FP64)
+        LAUNCH_OK(launch_var_eq<double>(reinterpret_cast<const double*>(w.cols), n, p->pm,
+                                        p->family, mu, mb, w.P, p->T, part, L.nbx, st));
+      else
+        LAUNCH_OK(launch_var_eq<float>(reinterpret_cast<const float*>(w.cols), n, p->pm,
+                                       p->family, mu, mb, w.P, p->T, part, L.nbx, st));
+      LAUNCH_OK(launch_var_finalize(part, L.nbx, mb, var_tm(p->T), true, w.P, kd,
+                                    var + (size_t)m0 * p->T, st));
+    } else {
+      LAUNCH_OK(launch_var_nested(mu, p->a1, p->family, p->N, mb, w.P, w.a1a, Y, part, L.nbx, st));
+      LAUNCH_OK(launch_var_finalize(part, L.nbx, mb, 0, false, w.P, kd, var + (size_t)m0 * p->T,
+                                    st));
+    }
+  }
+  return MTGP_OK;
+}
+
 int mtgp_gcv(const mtgp_plan* p, const double* theta, double* out3, double* grad,
              double* tau_hat, void* ws, void* stream) {
   if (!p || !theta || !out3 || !ws) return MTGP_EINVAL;

@@ -260,6 +260,19 @@ template <typename SR>
 int launch_cubature(const SR* cols, const CubDesc& cd, const double* ahat, const Params* P,
                     const KDesc& kd, double* mu, double* Sigma, hipStream_t st);
 
+// ---- postvar.hip
+int launch_var_shifts(const uint32_t* xs, int64_t Mb, const uint32_t* taskshift, int T, int d,
+                      int family, uint32_t* out, hipStream_t st);
+template <typename SR>
+int launch_var_eq(const SR* cols, int64_t n, const PairMap& pm, int family, const double* mu,
+                  int64_t Mb, const Params* P, int T, double* partials, int nbx, hipStream_t st);
+int launch_var_nested(const double* mu, const Alg1Desc& A, int family, int64_t N, int64_t Mb,
+                      const Params* P, const z2* S, z2* Y, double* partials, int nbx,
+                      hipStream_t st);
+int launch_var_finalize(const double* partials, int nbx, int64_t Mb, int rowm, bool equal,
+                        const Params* P, const KDesc& kd, double* var, hipStream_t st);
+inline int var_tm(int T) { return T <= 1 ? 1 : T <= 2 ? 2 : T <= 4 ? 4 : T <= 8 ? 8 : 16; }
+
 // ---- optim.hip
 int launch_adam(double* theta, const double* grad, double* m1, double* m2, int64_t n, double lr,
                 double b1, double b2, double eps, int64_t* step, const uint8_t* frozen,

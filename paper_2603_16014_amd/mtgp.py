@@ -192,6 +192,20 @@ class Plan:
                                          _ptr(self.ws), _stream()), "mtgp_predict")
         return mean
 
+    def predict_var(self, theta: torch.Tensor, xs: torch.Tensor, batch: int = 64) -> torch.Tensor:
+        """Posterior variance var[M][T] of the latent f at M test digits."""
+        _need_cuda(theta, torch.float64, "theta")
+        _need_cuda(xs, torch.int32, "xs (uint32 digits stored as int32)")
+        M = xs.shape[0]
+        batch = max(1, min(int(batch), max(M, 1)))
+        nbytes = int(self.lib.mtgp_predict_var_scratch_bytes(self.h, batch))
+        scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+        var = torch.empty((M, self.T), dtype=torch.float64, device="cuda")
+        _lib.check(self.lib.mtgp_predict_var(self.h, _ptr(theta), _ptr(xs), M, batch, _ptr(var),
+                                             _ptr(self.ws), _ptr(scratch), _stream()),
+                   "mtgp_predict_var")
+        return var
+
     def predict_net(self, theta: torch.Tensor, shift_star, m_star: int) -> torch.Tensor:
         _need_cuda(theta, torch.float64, "theta")
         sh = np.ascontiguousarray(shift_star, dtype=np.uint32)

@@ -82,3 +82,36 @@ def test_counter_summary_per_evaluation(tmp_path):
         assert abs(got["hbm_bytes"] - (2.0 * f + 4.0 * w) * 1024.0) < 1e-6, ph
         assert got["launches"] == len(ks)
         assert abs(got["us"] - sum(k + 1 for k in ks)) < 1e-9, ph
+
+
+def test_valu_summary_per_launch(tmp_path):
+    """Counter means per launch of the two fused kernels over several --pmc
+    runs, durations from the trace run, and the issue fraction
+    SQ_INSTS_VALU / (duration x CUs x clock)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    gen = "void mtgp::gen_fwd_kernel<double, double, 2, 10, 16>(double*, long)"
+    adj = "void mtgp::adj_reduce_kernel<double, double, 2, 10>(double const*, long)"
+    other = "void mtgp::solve_eq_kernel<float, 8, true>(float*, long)"
+    cf = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    a = [dict(Dispatch_Id=i, Kernel_Name=n, Counter_Name="SQ_INSTS_VALU", Counter_Value=v)
+         for i, (n, v) in enumerate([(gen, 100.0), (adj, 300.0), (other, 7.0), (gen, 200.0),
+                                     (adj, 500.0)])]
+    b = [dict(Dispatch_Id=i, Kernel_Name=n, Counter_Name="VALUBusy", Counter_Value=v)
+         for i, (n, v) in enumerate([(gen, 40.0), (adj, 60.0)])]
+    _write(str(tmp_path / "a" / "run_counter_collection.csv"), cf, a)
+    _write(str(tmp_path / "b" / "run_counter_collection.csv"), cf, b)
+    _write(str(tmp_path / "kt" / "run_kernel_trace.csv"),
+           ["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+           [dict(Dispatch_Id=0, Kernel_Name=gen, Start_Timestamp=0, End_Timestamp=2000),
+            dict(Dispatch_Id=1, Kernel_Name=adj, Start_Timestamp=0, End_Timestamp=3000),
+            dict(Dispatch_Id=2, Kernel_Name=gen, Start_Timestamp=0, End_Timestamp=4000)])
+    md = bench.valu_summary([str(tmp_path / "a"), str(tmp_path / "b")], str(tmp_path / "kt"),
+                            ["cmd"])
+    blob = json.loads(md.split("```json", 1)[1].split("```", 1)[0])
+    g, r = blob["kernels"]["gen_fwd_kernel"], blob["kernels"]["adj_reduce_kernel"]
+    assert g["SQ_INSTS_VALU"] == 150.0 and r["SQ_INSTS_VALU"] == 400.0
+    assert g["VALUBusy"] == 40.0 and r["VALUBusy"] == 60.0
+    assert abs(g["us"] - 3.0) < 1e-12 and abs(r["us"] - 3.0) < 1e-12
+    assert abs(g["valu_issue_frac"] - 150.0 / (3e-6 * bench.CU_COUNT * bench.CLOCK_HZ)) < 1e-15
+    assert bench.VALU_LANE_OPS_PEAK == 256 * 64 * 2.4e9

@@ -323,3 +323,63 @@ def test_gcv_gradient_central_differences(family, profile, adaptive):
                 vals.append(dense.gcv(w, y, theta=th, X=X)["L"])
             fd = (vals[0] - vals[1]) / (2 * h)
             assert abs(fd - gk[i]) < 1e-5 * max(1.0, abs(gk[i])) + 1e-6 * res["L"], (k, i, fd, gk[i])
+
+
+# ---------------------------------------------------- posterior covariance
+def _joint_posterior_cov(w, X, Xs, t):
+    """Cov[f(t, x*) | y] through the inverse of the full joint covariance of
+    (f(t, x*), y): the noise-free Gram of a design whose task t also holds
+    the test points, with the noise added on the training rows only."""
+    Xa = [np.concatenate([X[u], Xs]) if u == t else X[u] for u in range(w.T)]
+    Ka = dense.gram(w, w.theta, Xa, noise=False)
+    n = [x.shape[0] for x in X]
+    off = np.concatenate([[0], np.cumsum([x.shape[0] for x in Xa])])
+    test = np.arange(off[t] + n[t], off[t + 1])
+    train = np.setdiff1d(np.arange(off[-1]), test)
+    xi = np.asarray(w.theta["xi"], dtype=np.float64)
+    for u in range(w.T):
+        idx = np.arange(off[u], off[u] + n[u])
+        Ka[idx, idx] += xi[u]
+    order = np.concatenate([test, train])
+    J = Ka[np.ix_(order, order)]
+    Ji = np.linalg.inv(J)
+    M = test.size
+    return np.linalg.inv(Ji[:M, :M])
+
+
+@pytest.mark.parametrize("family,m", [("dseq", [4, 4, 3]), ("lat", [4, 3, 3])])
+def test_posterior_cov_is_gaussian_conditioning_of_the_joint(family, m):
+    """Cov[f(t,x), f(t,x') | y] equals the conditioning of the joint
+    Gaussian of the latent values and the data, taken through the inverse of
+    the full joint matrix (not the formula the oracle uses)."""
+    w = tiny(family, 3, m, 2, seed=12)
+    X = pts.task_points(w)
+    Xs = workloads.uniform_digits(np.random.default_rng(3), 6, w.d)
+    for t in range(w.T):
+        ref = _joint_posterior_cov(w, X, Xs, t)
+        got = dense.posterior_cov(w, Xs, Xs, t, t, X=X)
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("family", ["dseq", "lat"])
+def test_posterior_variance_bounds(family):
+    """At a training point of task t the latent variance lies in [0, xi_t]
+    (one noisy observation alone already brings it below xi_t); anywhere it
+    lies in [0, R_tt Q(x, x)]; with the noise taken to 1e8 times the prior
+    scale the data carry no information and it returns to R_tt Q(x, x)."""
+    w = tiny(family, 2, [4, 3], 2, seed=13, xi=1e-4)
+    X = pts.task_points(w)
+    R = dense.task_cov(w.theta)
+    xi = np.asarray(w.theta["xi"])
+    for t in range(2):
+        v = np.diag(dense.posterior_cov(w, X[t], X[t], t, t, X=X))
+        assert v.min() > -1e-12 and v.max() <= xi[t] * (1 + 1e-9), (v.min(), v.max(), xi[t])
+    Xs = workloads.uniform_digits(np.random.default_rng(4), 20, w.d)
+    q0 = np.diag(dense.cross_q(w, w.theta, Xs, Xs))
+    for t in range(2):
+        v = np.diag(dense.posterior_cov(w, Xs, Xs, t, t, X=X))
+        assert v.min() > -1e-12 and (v <= R[t, t] * q0 * (1 + 1e-12)).all()
+    loud = workloads.with_theta(w, xi=np.full(2, 1e8 * R.max() * q0.max()))
+    for t in range(2):
+        v = np.diag(dense.posterior_cov(loud, Xs, Xs, t, t, X=X))
+        np.testing.assert_allclose(v, R[t, t] * q0, rtol=1e-6)
