@@ -390,7 +390,23 @@ def batched_leg(nfits, steps, nstreams=16, eager_steps=3):
     bf.reset()
     eager = np.array(bf.run_eager(eager_steps))
     progress("batched leg: eager loop done")
+    # the library's many-fit launches: one launch per phase for all fits
+    pb = training.PersistentBatchedFits(plans, thetas, lr=0.05)
+    t0 = time.perf_counter()
+    pb.capture()
+    pcap_s = time.perf_counter() - t0
+    pms = np.array(pb.run(steps))
+    pbad = sum(1 for p in plans if p.status()[0] != 0)
+    progress("batched leg: many-fit launches done")
+    persistent = {"fits_steps_per_s": nfits * steps / (pms.sum() * 1e-3),
+                  "step_ms_p50": float(np.percentile(pms, 50)),
+                  "step_ms_p99": float(np.percentile(pms, 99)),
+                  "graph_capture_s": pcap_s, "fits_not_pd": pbad,
+                  "launches_per_step": "prep, forward columns (one per kernel type and "
+                                       "dimension width), elimination, adjoint columns, "
+                                       "chain rule, Adam"}
     return {"fits": nfits, "adam_steps": steps, "streams": nstreams,
+            "many_fit_launches": persistent,
             "fits_steps_per_s": nfits * steps / (ms.sum() * 1e-3),
             "step_ms_p50": float(np.percentile(ms, 50)), "step_ms_p99": float(np.percentile(ms, 99)),
             "graph_capture_s": cap_s, "fits_not_pd": bad,
@@ -433,6 +449,14 @@ def transforms_leg(ncols=29, m=24, reps=5):
         out[name] = {"shape": shape, "ms": ms, "algorithmic_bytes": nbytes,
                      "GB_s": nbytes / (ms * 1e-3) / 1e9,
                      "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        if name.startswith("fwht"):
+            # the passes each read and write every element once: the LDS pass
+            # over the low 12 bits and ceil((m - 12) / 6) register passes
+            passes = 1 + -(-(m - 12) // 6)
+            pb = passes * nbytes
+            out[name].update({"passes": passes, "pass_bytes": pb,
+                              "pass_GB_s": pb / (ms * 1e-3) / 1e9,
+                              "pass_hbm_frac": pb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS})
         del x
         torch.cuda.empty_cache()
     return out
@@ -510,6 +534,7 @@ def run(args):
         progress(f"{prec}: {ms_seq:.3f} ms per loss+gradient without overlap")
         results[prec] = dict(ms=ms, out3=out3, grad=grad, phases=phases, nph=nph, ms_seq=ms_seq,
                              schedule=plan.schedule, overlap=chunks,
+                             fused_occupancy=getattr(plan, "fused_occupancy", 0),
                              tuned=None if tuned is None else
                              {"cached": tuned["cached"],
                               "timings_ms": {k: round(v, 3) for k, v in tuned["timings"].items()}})
@@ -620,6 +645,7 @@ def run(args):
     line.update(extra)
     line["schedule"] = {"pass_a_bits": r["schedule"][0], "pass_b_bits": r["schedule"][1],
                         "pass_b_tile_bytes": r["schedule"][2], "overlap_chunks": r["overlap"],
+                        "fused_occupancy": r["fused_occupancy"],
                         "autotune": r["tuned"]}
     if "train" in results:
         line["training"] = results["train"]

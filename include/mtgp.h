@@ -158,6 +158,14 @@ int mtgp_plan_set_schedule(mtgp_plan* plan, int32_t pass_a_bits, int32_t pass_b_
  * Errors: MTGP_EINVAL (mode), MTGP_ENOTSUP. */
 int mtgp_plan_set_elimination(mtgp_plan* plan, int32_t mode);
 
+/* Digital nets: at most blocks_per_cu workgroups per compute unit of the
+ * fused column-generation and derivative-reduction kernels (1..8; 0, the
+ * default: as many as fit), enforced through their LDS request.  With the
+ * overlapped passes (mtgp_plan_set_overlap) a cap leaves room on each
+ * compute unit for the HBM-bound strided passes running beside them.  A
+ * schedule parameter: results are bitwise the same.  Errors: MTGP_EINVAL. */
+int mtgp_plan_set_fused_occupancy(mtgp_plan* plan, int32_t blocks_per_cu);
+
 /* Overlap of the digital-net passes (tuning only; results are bitwise the
  * same): the columns of each length group are processed in `chunks` chunks
  * (1..32, at most the group's column count; default 4).  The VALU-bound fused passes (generation + low
@@ -323,9 +331,12 @@ int mtgp_predict_var(const mtgp_plan* plan, const double* theta, const uint32_t*
  * profiled, the optimal GCV means (Eq. MTGP_optimal_tau), which for equal
  * sizes are the per-task sample means (written to tau_hat if non-NULL).
  * Equal sizes: two passes over the spectrum (q and s first).  Nested sizes
- * (MTGP_ELIM_SPARSE only): the loss and means through the fill-free
- * elimination, s from the diagonal of its selected inverse; a non-NULL grad
- * returns MTGP_ENOTSUP (the gradient needs Lambda^-2 off Lambda's pattern).
+ * (MTGP_ELIM_SPARSE only; Algorithm 1's elimination returns MTGP_ENOTSUP):
+ * the loss and means through the fill-free elimination, s from the diagonal
+ * of its selected inverse; the gradient runs that elimination in dual
+ * numbers under Lambda + e I, whose derivative parts are -Lambda^-2 on
+ * Lambda's pattern and -Lambda^-2 rhat, then a pass for q and s and one for
+ * the weights W = -(b a^H + a b^H) / s^2 + (2 q / s^3) Lambda^-2.
  * Same workspace as mtgp_nll_grad. */
 int mtgp_gcv(const mtgp_plan* plan, const double* theta, double* out3, double* grad,
              double* tau_hat, void* ws, void* stream);
@@ -348,6 +359,45 @@ int mtgp_cubature(const mtgp_plan* plan, const double* theta, double* mu_hat, do
 int mtgp_nll_grad_batched(int32_t nfits, mtgp_plan* const* plans, const double* const* thetas,
                           double* const* out3, double* const* grads, void* const* ws,
                           void* stream);
+
+/* Many small independent fits with one launch per phase over all of them
+ * (batching of the fitting loop; each fit is the loss and gradient of
+ * mtgp_nll_grad for its own plan: Eq. MTGP_MLE_GCV_loss, Theorem "Fast MTGP
+ * computations").  Phases: parameters; every kernel column of every fit
+ * generated and transformed through all its index bits by one workgroup
+ * (Walsh-Hadamard for nets, decimation in frequency for lattices); one
+ * workgroup per fit for the elimination in task order (the fill-free
+ * factorisation of the nested-size path, which equal sizes also take),
+ * its selected inverse and the adjoint weights; the adjoint transform and
+ * derivative sums per column; the chain rule per fit; optionally Adam.
+ * Column phases are launched once per kernel type and padded dimension
+ * width present in the batch.  Plans may differ in family, T, d, sizes
+ * and kernel; each needs 2^m_1 <= 2^14 points per task and precision
+ * MTGP_FP64 or MTGP_MIXED (else MTGP_ENOTSUP), mtgp_set_data on its own
+ * `ws` beforehand, and the per-fit buffers below (host arrays of device
+ * pointers, fixed at creation so the calls can be captured in a HIP graph
+ * and replayed):
+ *   ws[i]       the fit's workspace (mtgp_workspace_bytes of its plan);
+ *   thetas[i]   theta, read by mtgp_batch_nll_grad, updated by Adam;
+ *   out3[i], grads[i]  outputs as for mtgp_nll_grad;
+ *   adam_m1/m2[i], adam_step[i]  Adam moments (zero before the first
+ *               step) and device step counter, or adam_m1 = NULL for no
+ *               Adam; frozen[i] as for mtgp_adam_step (frozen may be NULL);
+ *   bws         device buffer of mtgp_batch_workspace_bytes(nfits, plans).
+ * The batch keeps the plans' device tables: destroy it before them.
+ * Creation allocates two small device tables; the compute calls allocate
+ * nothing and never synchronise.  A batch must be used from one stream at
+ * a time. */
+typedef struct mtgp_batch mtgp_batch;
+size_t mtgp_batch_workspace_bytes(int32_t nfits, mtgp_plan* const* plans);
+int mtgp_batch_create(int32_t nfits, mtgp_plan* const* plans, void* const* ws,
+                      double* const* thetas, double* const* out3, double* const* grads,
+                      double* const* adam_m1, double* const* adam_m2, int64_t* const* adam_step,
+                      const uint8_t* const* frozen, void* bws, mtgp_batch** out);
+int mtgp_batch_destroy(mtgp_batch* batch);
+int mtgp_batch_nll_grad(const mtgp_batch* batch, void* stream);
+int mtgp_batch_adam_step(const mtgp_batch* batch, double lr, double beta1, double beta2,
+                         double eps, void* stream);
 
 /* One Adam step on the packed theta (device, length n <= 4096) with moments
  * m1, m2 (device, zero before the first step) and a device step counter

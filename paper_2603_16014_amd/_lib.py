@@ -28,6 +28,7 @@ SIGNATURES = {
     "mtgp_plan_set_schedule": (ctypes.c_int, [vp, c_i32, c_i32, c_i64]),
     "mtgp_plan_set_overlap": (ctypes.c_int, [vp, c_i32]),
     "mtgp_plan_set_elimination": (ctypes.c_int, [vp, c_i32]),
+    "mtgp_plan_set_fused_occupancy": (ctypes.c_int, [vp, c_i32]),
     "mtgp_plan_enable_timing": (ctypes.c_int, [vp, c_i32]),
     "mtgp_phase_times": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), c_i32,
                                         ctypes.POINTER(c_i32)]),
@@ -57,6 +58,16 @@ SIGNATURES = {
     "mtgp_nll_grad_batched": (ctypes.c_int, [c_i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                              ctypes.POINTER(vp), ctypes.POINTER(vp),
                                              ctypes.POINTER(vp), vp]),
+    "mtgp_batch_workspace_bytes": (c_sz, [c_i32, ctypes.POINTER(vp)]),
+    "mtgp_batch_create": (ctypes.c_int, [c_i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.POINTER(vp), vp, ctypes.POINTER(vp)]),
+    "mtgp_batch_destroy": (ctypes.c_int, [vp]),
+    "mtgp_batch_nll_grad": (ctypes.c_int, [vp, vp]),
+    "mtgp_batch_adam_step": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, vp]),
     "mtgp_adam_step": (ctypes.c_int, [vp, vp, vp, vp, c_i64, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, vp, vp, vp]),
     "mtgp_strerror": (ctypes.c_char_p, [ctypes.c_int]),

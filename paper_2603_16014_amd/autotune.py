@@ -1,10 +1,11 @@
 """Measured schedule selection for the digital-net transform passes.
 
 `tune(plan, theta)` times mtgp_nll_grad on the caller's plan and data under
-candidate schedules (bits of the LDS pass, bits per high pass, LDS tile size)
-and overlap chunk counts, keeps the fastest, applies it to the plan and
-caches the choice in a JSON file keyed by the design's shape, precision and
-device, so a later plan of the same shape takes it without timing.  Results
+candidate schedules (bits of the LDS pass, bits per high pass, LDS tile
+size), overlap chunk counts and caps on the fused kernels' workgroups per
+CU, keeps the fastest, applies it to the plan and caches the choice in a
+JSON file keyed by the design's shape, precision and device, so a later plan
+of the same shape takes it without timing.  Results
 do not depend on the schedule beyond rounding order; lattice plans have no
 schedule to choose and are left unchanged.
 """
@@ -23,6 +24,9 @@ CANDIDATES = [
 ]
 OVERLAPS = (1, 4, 8, 16)
 FINALISTS = 3  # schedules also timed with each overlap setting
+# caps on workgroups per CU of the fused generation / reduction kernels,
+# tried with the best schedule and the overlapped settings (0: no cap)
+FUSED_CAPS = (3,)
 
 
 def cache_path():
@@ -84,8 +88,10 @@ def tune(plan, theta, reps=3, candidates=None, overlaps=OVERLAPS, use_cache=True
         if hit is not None:
             plan.set_schedule(*hit["schedule"])
             plan.set_overlap(hit["overlap"])
+            plan.set_fused_occupancy(hit.get("fused_occupancy", 0))
             return {"schedule": tuple(hit["schedule"]), "overlap": hit["overlap"], "ms": hit["ms"],
-                    "cached": True, "timings": {}}
+                    "fused_occupancy": hit.get("fused_occupancy", 0), "cached": True,
+                    "timings": {}}
     cands = list(candidates or CANDIDATES)
     timings = {}
     # every schedule with the passes in sequence, then every overlap setting
@@ -113,10 +119,24 @@ def tune(plan, theta, reps=3, candidates=None, overlaps=OVERLAPS, use_cache=True
                 best = (c, ov, ms)
         plan.set_overlap(1)
     plan.set_schedule(*best[0])
+    cap_best = 0
+    for cap in FUSED_CAPS:
+        plan.set_fused_occupancy(cap)
+        for ov in sorted({best[1], 8, 16}):
+            if ov == 1:
+                continue
+            plan.set_overlap(ov)
+            ms = _time(plan, theta, reps)
+            timings[f"{best[0]} overlap {ov} fused cap {cap}"] = ms
+            if ms < best[2]:
+                best = (best[0], ov, ms)
+                cap_best = cap
+    plan.set_fused_occupancy(cap_best)
     plan.set_overlap(best[1])
     if use_cache:
         table = _load(path)
-        table[key] = {"schedule": list(best[0]), "overlap": best[1], "ms": best[2]}
+        table[key] = {"schedule": list(best[0]), "overlap": best[1], "ms": best[2],
+                      "fused_occupancy": cap_best}
         _store(path, table)
-    return {"schedule": best[0], "overlap": best[1], "ms": best[2], "cached": False,
-            "timings": timings}
+    return {"schedule": best[0], "overlap": best[1], "ms": best[2], "fused_occupancy": cap_best,
+            "cached": False, "timings": timings}

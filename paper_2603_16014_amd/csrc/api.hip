@@ -295,7 +295,7 @@ int adjoint_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
       mark(p, 5, st);
       for (const auto& g : p->groups) {
         const int64_t o = p->col_off[g.first];
-        const int nb = 1 << (g.m - p->sched.lb(g.m));
+        const int nb = (int)dseq_adj_rows(g.m, p->sched.lb(g.m));
         const uint32_t* sh = p->d_colshift + (size_t)g.first * p->d;
         double* part = w.ap + (size_t)nadj * adj_nq(p->d);
         if (g.m > p->sched.lb(g.m))
@@ -314,7 +314,7 @@ int adjoint_columns(const mtgp_plan* p, const WsView& w, hipStream_t st) {
     mark(p, 5, st);
     for (const auto& g : p->groups) {
       const int64_t len = (int64_t)1 << g.m;
-      const int nb = 1 << (g.m - p->sched.lb(g.m));
+      const int nb = (int)dseq_adj_rows(g.m, p->sched.lb(g.m));
       const bool high = g.m > p->sched.lb(g.m);
       const int nch = high ? std::min(p->nchunks, g.count) : 1;
       for (int k = 0; k < nch; k++) {
@@ -462,6 +462,37 @@ int run_gcv_nested(const mtgp_plan* p, const double* theta, double* out3, double
   return MTGP_OK;
 }
 
+// GCV loss and gradient at nested sizes: the elimination in dual numbers
+// gives Lambda^-1 and Lambda^-2 on the pattern (and ahat, bhat), the first
+// pass q and s, the second the weights of the adjoint.
+template <typename CR, typename SR>
+int run_gcv_nested_grad(const mtgp_plan* p, const double* theta, double* out3, double* grad,
+                        double* tau_hat, void* ws, hipStream_t st) {
+  const WsView w = view(p, ws);
+  KDesc kd = p->kd();
+  kd.gcv = 1;
+  LAUNCH_OK(launch_prep(theta, w.P, kd, w.status, st));
+  int rc = forward_columns<CR, SR>(p, w, st);
+  if (rc) return rc;
+  SR* spec = reinterpret_cast<SR*>(w.cols);
+  const int64_t nb = zf_final_blocks(p->N);
+  LAUNCH_OK(launch_zerofill_gcv_dual<SR>(spec, p->a1, p->N, w.P, kd.family, w.yhat, w.a1a, w.sp,
+                                         w.status, false, st));
+  LAUNCH_OK(launch_colsum(w.sp, nb, solve_ns(p->T), w.sp2, COLSUM_BLOCKS, st));
+  LAUNCH_OK(launch_finalize(w.sp2, COLSUM_BLOCKS, nullptr, p->d_colinfo, p->ncol, nullptr, 0,
+                            w.yhat, p->n[0], w.P, kd, out3, nullptr, tau_hat, st));
+  LAUNCH_OK(launch_zerofill_gcv_dual<SR>(spec, p->a1, p->N, w.P, kd.family, w.yhat, w.a1a, w.sp,
+                                         w.status, true, st));
+  const int nadj = adjoint_columns<CR, SR>(p, w, st);
+  if (nadj < 0) return nadj;
+  if (nadj != p->nadj_blocks) return MTGP_EINVAL;
+  LAUNCH_OK(launch_colseg(w.ap, p->d_colinfo, p->ncol, adj_nq(p->d), w.ap2, st));
+  LAUNCH_OK(launch_colsum(w.sp, nb, solve_ns(p->T), w.sp2, COLSUM_BLOCKS, st));
+  LAUNCH_OK(launch_finalize(w.sp2, COLSUM_BLOCKS, w.ap2, p->d_colinfo, p->ncol, nullptr, 0,
+                            w.yhat, p->n[0], w.P, kd, out3, grad, tau_hat, st));
+  return MTGP_OK;
+}
+
 int dispatch_loss(const mtgp_plan* p, const double* theta, double* out3, double* grad,
                   double* tau_hat, void* ws, hipStream_t st, bool want_ahat) {
   switch (p->precision) {
@@ -498,7 +529,8 @@ void layout(mtgp_plan* p) {
   // right-hand sides
   const bool a1dense = !p->equal && p->elim == MTGP_ELIM_ALG1;
   const size_t a1 = a1dense ? (size_t)p->N * (size_t)p->a1_ms * sizeof(z2) : 0;
-  const size_t zf = !p->equal && !a1dense ? (size_t)zf_elems(p->a1, p->N) * sizeof(z2) : 0;
+  // (pairs of complex values: the GCV gradient runs the elimination in dual numbers)
+  const size_t zf = !p->equal && !a1dense ? (size_t)zf_elems(p->a1, p->N) * 2 * sizeof(z2) : 0;
   p->o_a1a = o;
   o = align_up(o + (a1dense ? a1 : zf));
   p->o_a1b = o;
@@ -522,7 +554,7 @@ void layout(mtgp_plan* p) {
                                                                       : sizeof(cx<double>)) *
                         g.count;
     else
-      p->nadj_blocks += (1 << (g.m - p->sched.lb(g.m))) * g.count;
+      p->nadj_blocks += dseq_adj_rows(g.m, p->sched.lb(g.m)) * g.count;
   }
   p->o_ap = o;
   o = align_up(o + (size_t)p->nadj_blocks * adj_nq(d) * sizeof(double));
@@ -542,7 +574,7 @@ int upload_colinfo(mtgp_plan* p) {
     const int64_t nb =
         p->family == MTGP_LAT
             ? lat_adj_blocks(g.m, p->precision == MTGP_F32 ? sizeof(cx<float>) : sizeof(cx<double>))
-            : ((int64_t)1 << (g.m - p->sched.lb(g.m)));
+            : dseq_adj_rows(g.m, p->sched.lb(g.m));
     for (int c = g.first; c < g.first + g.count; c++) {
       ci[c].t = p->col_t[c];
       ci[c].u = p->col_u[c];
@@ -844,6 +876,12 @@ int mtgp_plan_set_schedule(mtgp_plan* p, int32_t pass_a_bits, int32_t pass_b_bit
   return upload_colinfo(p);
 }
 
+int mtgp_plan_set_fused_occupancy(mtgp_plan* p, int32_t blocks_per_cu) {
+  if (!p || blocks_per_cu < 0 || blocks_per_cu > 8) return MTGP_EINVAL;
+  p->sched.fused_cap = blocks_per_cu;
+  return MTGP_OK;
+}
+
 int mtgp_plan_set_elimination(mtgp_plan* p, int32_t mode) {
   if (!p || (mode != MTGP_ELIM_SPARSE && mode != MTGP_ELIM_ALG1)) return MTGP_EINVAL;
   if (mode == MTGP_ELIM_ALG1 && !p->equal && p->a1_ms > ALG1_MAX_BLOCK) return MTGP_ENOTSUP;
@@ -961,11 +999,20 @@ int mtgp_fwht(void* x, int64_t batch, int32_t log2n, int32_t dtype, void* stream
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = (int64_t)1 << log2n;
   const Sched sc;
-  if (dtype == MTGP_DTYPE_F64)
-    LAUNCH_OK(launch_fwht<double>(static_cast<double*>(x), n, batch, log2n, sc, st));
-  else if (dtype == MTGP_DTYPE_F32)
-    LAUNCH_OK(launch_fwht<float>(static_cast<float*>(x), n, batch, log2n, sc, st));
-  else return MTGP_EINVAL;
+  const size_t eb = dtype == MTGP_DTYPE_F64 ? sizeof(double) : sizeof(float);
+  // Multi-pass sizes run in groups of at most 128 MiB of vectors, each group
+  // through all its passes before the next: a group's working set then stays
+  // in the 256 MB memory-side cache between passes (measured on [29][2^24]
+  // FP64: 3.7 ms in groups against 5.1 ms for all vectors pass by pass).
+  int64_t grp = batch;
+  if (log2n > sc.a_bits) grp = std::max<int64_t>(1, ((int64_t)128 << 20) / (n * (int64_t)eb));
+  for (int64_t b0 = 0; b0 < batch; b0 += grp) {
+    const int64_t nb = std::min<int64_t>(grp, batch - b0);
+    if (dtype == MTGP_DTYPE_F64)
+      LAUNCH_OK(launch_fwht<double>(static_cast<double*>(x) + b0 * n, n, nb, log2n, sc, st));
+    else
+      LAUNCH_OK(launch_fwht<float>(static_cast<float*>(x) + b0 * n, n, nb, log2n, sc, st));
+  }
   return MTGP_OK;
 }
 
@@ -1278,8 +1325,15 @@ int mtgp_predict_var(const mtgp_plan* p, const double* theta, const uint32_t* xs
 int mtgp_gcv(const mtgp_plan* p, const double* theta, double* out3, double* grad,
              double* tau_hat, void* ws, void* stream) {
   if (!p || !theta || !out3 || !ws) return MTGP_EINVAL;
-  if (!p->equal && (grad || p->elim != MTGP_ELIM_SPARSE)) return MTGP_ENOTSUP;
+  if (!p->equal && p->elim != MTGP_ELIM_SPARSE) return MTGP_ENOTSUP;
   hipStream_t st = (hipStream_t)stream;
+  if (!p->equal && grad) {
+    switch (p->precision) {
+      case MTGP_FP64: return run_gcv_nested_grad<double, double>(p, theta, out3, grad, tau_hat, ws, st);
+      case MTGP_MIXED: return run_gcv_nested_grad<double, float>(p, theta, out3, grad, tau_hat, ws, st);
+      default: return run_gcv_nested_grad<float, float>(p, theta, out3, grad, tau_hat, ws, st);
+    }
+  }
   if (!p->equal) {
     switch (p->precision) {
       case MTGP_FP64: return run_gcv_nested<double, double>(p, theta, out3, tau_hat, ws, st);
@@ -1327,6 +1381,191 @@ int mtgp_nll_grad_batched(int32_t nfits, mtgp_plan* const* plans, const double* 
     const int rc = mtgp_nll_grad(plans[i], thetas[i], out3[i], grads[i], nullptr, ws[i], stream);
     if (rc) return rc;
   }
+  return MTGP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// many fits, one launch per phase
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct mtgp_batch {
+  int nfits = 0;
+  BFit* d_fits = nullptr;
+  BItem* d_items = nullptr;  // column items grouped by (kernel type, width)
+  struct Group {
+    int kt, d, first, count;
+  };
+  std::vector<Group> groups;
+  bool adam = false;
+  int tmax = 0;  // largest T of the batch
+};
+
+namespace {
+
+// per-fit slice of the batch workspace
+struct BSlice {
+  size_t o_S, o_logs, o_sp, o_ap, bytes;
+};
+BSlice batch_slice(const mtgp_plan* p) {
+  BSlice b;
+  size_t o = 0;
+  b.o_S = o;
+  o = align_up(o + (size_t)zf_elems(p->a1, p->N) * sizeof(z2));
+  b.o_logs = o;
+  o = align_up(o + (size_t)p->N * sizeof(double));
+  b.o_sp = o;
+  o = align_up(o + (size_t)BATCH_SOLVE_BLOCKS * solve_ns(p->T) * sizeof(double));
+  b.o_ap = o;
+  o = align_up(o + (size_t)p->ncol * adj_nq(p->d) * sizeof(double));
+  b.bytes = o;
+  return b;
+}
+
+int batch_check(int32_t nfits, mtgp_plan* const* plans) {
+  if (nfits < 0 || (nfits > 0 && !plans)) return MTGP_EINVAL;
+  for (int i = 0; i < nfits; i++) {
+    const mtgp_plan* p = plans[i];
+    if (!p) return MTGP_EINVAL;
+    if (p->precision == MTGP_F32) return MTGP_ENOTSUP;
+    if (p->m[0] > BATCH_MAX_M) return MTGP_ENOTSUP;
+  }
+  return MTGP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mtgp_batch_workspace_bytes(int32_t nfits, mtgp_plan* const* plans) {
+  if (batch_check(nfits, plans) != MTGP_OK) return 0;
+  size_t total = 0;
+  for (int i = 0; i < nfits; i++) total += batch_slice(plans[i]).bytes;
+  return total;
+}
+
+int mtgp_batch_create(int32_t nfits, mtgp_plan* const* plans, void* const* ws,
+                      double* const* thetas, double* const* out3, double* const* grads,
+                      double* const* adam_m1, double* const* adam_m2, int64_t* const* adam_step,
+                      const uint8_t* const* frozen, void* bws, mtgp_batch** out) {
+  if (!out) return MTGP_EINVAL;
+  *out = nullptr;
+  int rc = batch_check(nfits, plans);
+  if (rc) return rc;
+  if (nfits > 0 && (!ws || !thetas || !out3 || !grads || !bws)) return MTGP_EINVAL;
+  const bool adam = adam_m1 != nullptr;
+  if (adam && (!adam_m2 || !adam_step)) return MTGP_EINVAL;
+  std::vector<BFit> fits(nfits);
+  struct Item {
+    int kt, d, fit, col;
+  };
+  std::vector<Item> items;
+  size_t bo = 0;
+  for (int i = 0; i < nfits; i++) {
+    const mtgp_plan* p = plans[i];
+    if (!ws[i] || !thetas[i] || !out3[i] || !grads[i]) return MTGP_EINVAL;
+    if (adam && (!adam_m1[i] || !adam_m2[i] || !adam_step[i])) return MTGP_EINVAL;
+    const WsView w = view(p, ws[i]);
+    const BSlice sl = batch_slice(p);
+    unsigned char* b = static_cast<unsigned char*>(bws) + bo;
+    bo += sl.bytes;
+    BFit& F = fits[i];
+    std::memset(&F, 0, sizeof(F));
+    F.kd = p->kd();
+    F.kd.unequal = 1;
+    F.A = p->a1;
+    F.ncol = p->ncol;
+    F.sr_f32 = p->precision == MTGP_FP64 ? 0 : 1;
+    F.N = p->N;
+    F.gen = p->d_gen;
+    F.colshift = p->d_colshift;
+    F.colinfo = p->d_colinfo;
+    F.theta = thetas[i];
+    F.out3 = out3[i];
+    F.grad = grads[i];
+    F.P = w.P;
+    F.status = w.status;
+    F.cols = w.cols;
+    F.work = reinterpret_cast<double*>(w.work);
+    F.yhat = w.yhat;
+    F.S = reinterpret_cast<z2*>(b + sl.o_S);
+    F.logs = reinterpret_cast<double*>(b + sl.o_logs);
+    F.sp = reinterpret_cast<double*>(b + sl.o_sp);
+    F.ap = reinterpret_cast<double*>(b + sl.o_ap);
+    if (adam) {
+      F.m1 = adam_m1[i];
+      F.m2 = adam_m2[i];
+      F.step = adam_step[i];
+      F.frozen = frozen ? frozen[i] : nullptr;
+    }
+    F.ntheta = theta_size(p);
+    const int kt = kt_of(p->family, p->order, p->adaptive);
+    for (int c = 0; c < p->ncol; c++) items.push_back({kt, p->d, i, c});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+    return a.kt != b.kt ? a.kt < b.kt : a.d < b.d;
+  });
+  mtgp_batch* bt = new (std::nothrow) mtgp_batch();
+  if (!bt) return MTGP_ENOMEM;
+  bt->nfits = nfits;
+  bt->adam = adam;
+  for (int i = 0; i < nfits; i++) bt->tmax = std::max(bt->tmax, plans[i]->T);
+  // one launch per kernel type, at the widest dimension count of its fits
+  // (narrower fits run with padding dimensions whose factor is exactly 1):
+  // the column launches are bound by the latency of their largest columns,
+  // so fewer, fuller launches beat exact widths
+  std::vector<BItem> bi(items.size());
+  for (size_t k = 0; k < items.size(); k++) {
+    bi[k] = {items[k].fit, items[k].col};
+    if (bt->groups.empty() || bt->groups.back().kt != items[k].kt)
+      bt->groups.push_back({items[k].kt, items[k].d, (int)k, 0});
+    bt->groups.back().d = std::max(bt->groups.back().d, items[k].d);
+    bt->groups.back().count++;
+  }
+  if (nfits > 0) {
+    if (hipMalloc(&bt->d_fits, fits.size() * sizeof(BFit)) != hipSuccess ||
+        hipMalloc(&bt->d_items, bi.size() * sizeof(BItem)) != hipSuccess) {
+      mtgp_batch_destroy(bt);
+      return MTGP_ENOMEM;
+    }
+    if (hipMemcpy(bt->d_fits, fits.data(), fits.size() * sizeof(BFit), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(bt->d_items, bi.data(), bi.size() * sizeof(BItem), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+      mtgp_batch_destroy(bt);
+      return MTGP_EHIP;
+    }
+  }
+  *out = bt;
+  return MTGP_OK;
+}
+
+int mtgp_batch_destroy(mtgp_batch* b) {
+  if (!b) return MTGP_OK;
+  if (b->d_fits) (void)hipFree(b->d_fits);
+  if (b->d_items) (void)hipFree(b->d_items);
+  delete b;
+  return MTGP_OK;
+}
+
+int mtgp_batch_nll_grad(const mtgp_batch* b, void* stream) {
+  if (!b) return MTGP_EINVAL;
+  if (b->nfits == 0) return MTGP_OK;
+  hipStream_t st = (hipStream_t)stream;
+  LAUNCH_OK(launch_batch_prep(b->d_fits, b->nfits, st));
+  for (const auto& g : b->groups)
+    LAUNCH_OK(launch_batch_fwd(b->d_fits, b->d_items + g.first, g.count, g.kt, g.d, st));
+  LAUNCH_OK(launch_batch_solve(b->d_fits, b->nfits, b->tmax, st));
+  for (const auto& g : b->groups)
+    LAUNCH_OK(launch_batch_adj(b->d_fits, b->d_items + g.first, g.count, g.kt, g.d, st));
+  LAUNCH_OK(launch_batch_final(b->d_fits, b->nfits, st));
+  return MTGP_OK;
+}
+
+int mtgp_batch_adam_step(const mtgp_batch* b, double lr, double beta1, double beta2, double eps,
+                         void* stream) {
+  if (!b || !b->adam) return MTGP_EINVAL;
+  LAUNCH_OK(launch_batch_adam(b->d_fits, b->nfits, lr, beta1, beta2, eps, (hipStream_t)stream));
   return MTGP_OK;
 }
 

@@ -41,6 +41,17 @@ struct Digits {
       }
     }
   }
+  // block part only, for a new block start i0 (per-thread part unchanged)
+  __device__ inline void set_block(const uint32_t* __restrict__ gen,
+                                   const uint32_t* __restrict__ sh, int d, uint32_t i0, int m) {
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+      const int jj = j < d ? j : 0;
+      const uint32_t keep = j < d ? 0xffffffffu : 0u;
+      if (FAM == FAM_DSEQ) s[j] = (dseq_z(gen + 32 * jj, i0) ^ sh[jj]) & keep;
+      else s[j] = (lat_z(gen[jj], i0, m) + sh[jj]) & keep;
+    }
+  }
   __device__ inline uint32_t u(int j) const { return FAM == FAM_DSEQ ? (a[j] ^ s[j]) : (a[j] + s[j]); }
   // element offset (in units of 256) visited at step k
   __device__ static inline int elem(int k) { return FAM == FAM_DSEQ ? (k ^ (k >> 1)) : k; }

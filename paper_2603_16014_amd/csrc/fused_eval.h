@@ -21,7 +21,7 @@ namespace mtgp {
 // ---------------------------------------------------------------------------
 template <typename Real, typename TOut, int KT, int D, int E>
 __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, int64_t col_stride,
-                                                      int m, int LB,
+                                                      int m, int LB, int G,
                                                       const uint32_t* __restrict__ gen,
                                                       const uint32_t* __restrict__ colshift,
                                                       const Params* __restrict__ P, int d) {
@@ -30,9 +30,9 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
   Real* lds = reinterpret_cast<Real*>(smem);
   const int nb = 1 << LB;
   const int col = blockIdx.y;
-  const uint32_t i0 = (uint32_t)blockIdx.x << LB;
   const uint32_t t = threadIdx.x;
   const int stride = lds_stride(LB);
+  const uint32_t* cs = colshift + (size_t)col * d;
   if constexpr (uses_kap2_table<Real, KT>()) {
     fill_kap2_table(k2tab);
     __syncthreads();
@@ -42,43 +42,51 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
 #pragma unroll
   for (int j = 0; j < D; j++) sc[j] = kscale<Real, KT>(j < d ? RT<Real>::eta(P, j) : (Real)0);
   const Real gam = RT<Real>::gamma(P);
-  if constexpr (E > 0) {
-    // nb == 256 E: thread t owns indices t + 256 e.  Index bits 8 .. 8+log2(E)
-    // are transformed in registers, bits 0 .. 7 in two LDS rounds.
-    Real v[E];
-    dg.init(gen, colshift + (size_t)col * d, d, t, i0, m);
+  // G consecutive blocks of the column per workgroup: the per-thread digit
+  // parts and the table are set up once for all of them
+  for (int g = 0; g < G; g++) {
+    const uint32_t i0 = ((uint32_t)blockIdx.x * G + g) << LB;
+    if (g > 0) __syncthreads();  // the previous block's stores have read the tile
+    if constexpr (E > 0) {
+      // nb == 256 E: thread t owns indices t + 256 e.  Index bits 8 .. 8+log2(E)
+      // are transformed in registers, bits 0 .. 7 in two LDS rounds.
+      Real v[E];
+      if (g == 0) dg.init(gen, cs, d, t, i0, m);
+      else dg.set_block(gen, cs, d, i0, m);
 #pragma unroll
-    for (int k = 0; k < E; k++) {
-      Real c = gam;
-#pragma unroll
-      for (int j = 0; j < D; j++) c *= fma(sc[j], kappa_t<Real, KT>(dg.u(j), P, k2tab), (Real)1);
-      v[Digits<FAM_DSEQ, D>::elem(k)] = c;
-      if (k + 1 < E) dg.advance(gen, d, k);
-    }
-    reg_fwht<Real, E>(v);
-#pragma unroll
-    for (int k = 0; k < E; k++) lds[lds_at(0, stride, (int)t + 256 * k)] = v[k];
-    __syncthreads();
-    lds_round<Real, 4>(lds, 1, LB, 0, stride);
-    __syncthreads();
-    lds_round<Real, 4>(lds, 1, LB, 4, stride);
-    __syncthreads();
-  } else {
-    const int En = nb > 256 ? nb >> 8 : 1;
-    if ((int)t < nb) {
-      dg.init(gen, colshift + (size_t)col * d, d, t, i0, m);
-      for (int k = 0; k < En; k++) {
+      for (int k = 0; k < E; k++) {
         Real c = gam;
 #pragma unroll
         for (int j = 0; j < D; j++) c *= fma(sc[j], kappa_t<Real, KT>(dg.u(j), P, k2tab), (Real)1);
-        lds[lds_at(0, stride, (int)t + 256 * dg.elem(k))] = c;
-        if (k + 1 < En) dg.advance(gen, d, k);
+        v[Digits<FAM_DSEQ, D>::elem(k)] = c;
+        if (k + 1 < E) dg.advance(gen, d, k);
       }
+      reg_fwht<Real, E>(v);
+#pragma unroll
+      for (int k = 0; k < E; k++) lds[lds_at(0, stride, (int)t + 256 * k)] = v[k];
+      __syncthreads();
+      lds_round<Real, 4>(lds, 1, LB, 0, stride);
+      __syncthreads();
+      lds_round<Real, 4>(lds, 1, LB, 4, stride);
+      __syncthreads();
+    } else {
+      const int En = nb > 256 ? nb >> 8 : 1;
+      if ((int)t < nb) {
+        if (g == 0) dg.init(gen, cs, d, t, i0, m);
+        else dg.set_block(gen, cs, d, i0, m);
+        for (int k = 0; k < En; k++) {
+          Real c = gam;
+#pragma unroll
+          for (int j = 0; j < D; j++) c *= fma(sc[j], kappa_t<Real, KT>(dg.u(j), P, k2tab), (Real)1);
+          lds[lds_at(0, stride, (int)t + 256 * dg.elem(k))] = c;
+          if (k + 1 < En) dg.advance(gen, d, k);
+        }
+      }
+      lds_fwht<Real>(lds, 1, LB, stride);
     }
-    lds_fwht<Real>(lds, 1, LB, stride);
+    TOut* out = base + (size_t)col * col_stride + i0;
+    for (int e = t; e < nb; e += 256) out[e] = (TOut)lds[lds_at(0, stride, e)];
   }
-  TOut* out = base + (size_t)col * col_stride + i0;
-  for (int e = t; e < nb; e += 256) out[e] = (TOut)lds[lds_at(0, stride, e)];
 }
 
 // ---------------------------------------------------------------------------
@@ -145,7 +153,7 @@ __device__ inline void adj_element(const Digits<kt_family(KT), D>& dg, Real wv, 
 
 template <typename Real, typename TIn, int KT, int D>
 __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__ base,
-                                                         int64_t col_stride, int m, int LB,
+                                                         int64_t col_stride, int m, int LB, int G,
                                                          const uint32_t* __restrict__ gen,
                                                          const uint32_t* __restrict__ colshift,
                                                          const Params* __restrict__ P, int d,
@@ -159,51 +167,62 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
   Real* lds = reinterpret_cast<Real*>(smem);
   const int nb = 1 << LB;
   const int col = blockIdx.y;
-  const uint32_t i0 = (uint32_t)blockIdx.x << LB;
   const uint32_t t = threadIdx.x;
-  const TIn* w = base + (size_t)col * col_stride + i0;
   const int stride = lds_stride(LB);
+  const uint32_t* cs = colshift + (size_t)col * d;
   // the barriers of the transform below order the table's fill before its use
   if constexpr (uses_kap2_table<Real, KT>()) fill_kap2_table(k2tab);
-  if (LB == 12) {
-    // 16 loads in flight per thread, index bits 8 .. 11 in registers, bits
-    // 0 .. 7 in two LDS rounds
-    Real v[16];
-#pragma unroll
-    for (int k = 0; k < 16; k++) v[k] = (Real)w[t + 256 * k];
-    reg_fwht<Real, 16>(v);
-#pragma unroll
-    for (int k = 0; k < 16; k++) lds[lds_at(0, stride, (int)t + 256 * k)] = v[k];
-    __syncthreads();
-    lds_round<Real, 4>(lds, 1, LB, 0, stride);
-    __syncthreads();
-    lds_round<Real, 4>(lds, 1, LB, 4, stride);
-    __syncthreads();
-  } else {
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) lds[lds_at(0, stride, i)] = (Real)w[i];
-    lds_fwht<Real>(lds, 1, LB, stride);
-  }
-
   Real acc[D + 1];
   Real acc_b[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int j = 0; j <= D; j++) acc[j] = 0;
+  Real sc[D];  // eta K = sc kappa; padding slots: sc = 0
+#pragma unroll
+  for (int j = 0; j < D; j++) sc[j] = kscale<Real, KT>(j < d ? RT<Real>::eta(P, j) : (Real)0);
+  const Real gam = RT<Real>::gamma(P);
+  Digits<FAM, D> dg;
   // the element loop stays rolled: unrolled, its per-element temporaries
   // exceed the register file
   const int En = nb > 256 ? nb >> 8 : 1;
-  if ((int)t < nb) {
-    Real sc[D];  // eta K = sc kappa; padding slots: sc = 0
+  // G consecutive blocks of the column per workgroup: the per-thread digit
+  // parts and the block reduction below are paid once for all of them
+  for (int g = 0; g < G; g++) {
+    const uint32_t i0 = ((uint32_t)blockIdx.x * G + g) << LB;
+    const TIn* w = base + (size_t)col * col_stride + i0;
+    if (g > 0) __syncthreads();  // every read of the previous block's tile is done
+    if (LB == 12) {
+      // 16 loads in flight per thread, index bits 8 .. 11 in registers, bits
+      // 0 .. 7 in two LDS rounds
+      Real v[16];
 #pragma unroll
-    for (int j = 0; j < D; j++) sc[j] = kscale<Real, KT>(j < d ? RT<Real>::eta(P, j) : (Real)0);
-    const Real gam = RT<Real>::gamma(P);
-    Digits<FAM, D> dg;
-    dg.init(gen, colshift + (size_t)col * d, d, t, i0, m);
-    dg.load_columns(gen, d);
-    for (int k = 0; k < En; k++) {
-      const Real wv = lds[lds_at(0, stride, (int)t + 256 * dg.elem(k))];
-      adj_element<Real, KT, D>(dg, wv, gam, sc, P, k2tab, acc, acc_b);
-      if (k + 1 < En) dg.advance_lanes(k);
+      for (int k = 0; k < 16; k++) v[k] = (Real)w[t + 256 * k];
+      reg_fwht<Real, 16>(v);
+#pragma unroll
+      for (int k = 0; k < 16; k++) lds[lds_at(0, stride, (int)t + 256 * k)] = v[k];
+      __syncthreads();
+      lds_round<Real, 4>(lds, 1, LB, 0, stride);
+      __syncthreads();
+      lds_round<Real, 4>(lds, 1, LB, 4, stride);
+      __syncthreads();
+    } else {
+      for (int i = threadIdx.x; i < nb; i += blockDim.x) lds[lds_at(0, stride, i)] = (Real)w[i];
+      lds_fwht<Real>(lds, 1, LB, stride);
     }
+    if ((int)t < nb) {
+      if (g == 0) {
+        dg.init(gen, cs, d, t, i0, m);
+        dg.load_columns(gen, d);
+      } else {
+        dg.set_block(gen, cs, d, i0, m);
+      }
+      for (int k = 0; k < En; k++) {
+        const Real wv = lds[lds_at(0, stride, (int)t + 256 * dg.elem(k))];
+        adj_element<Real, KT, D>(dg, wv, gam, sc, P, k2tab, acc, acc_b);
+        if (k + 1 < En) dg.advance_lanes(k);
+      }
+    }
+  }
+  if ((int)t < nb) {
 #pragma unroll
     for (int j = 0; j < D; j++) acc[j] *= sc[j];  // kappa sums -> dc/dlog eta_j sums
   }
@@ -240,18 +259,18 @@ constexpr bool fused_reg_stages() {
 }
 
 template <typename Real, typename TOut, int KT, int D>
-void gen_fwd_launch_d(dim3 grid, size_t lds, hipStream_t st, bool regs, TOut* base,
+void gen_fwd_launch_d(dim3 grid, size_t lds, hipStream_t st, bool regs, int G, TOut* base,
                       int64_t col_stride, int m, int LB, const uint32_t* gen,
                       const uint32_t* colshift, const Params* P, int d) {
   if constexpr (fused_reg_stages<Real, KT>()) {
     if (regs) {
       hipLaunchKernelGGL((gen_fwd_kernel<Real, TOut, KT, D, 16>), grid, dim3(256), lds, st, base,
-                         col_stride, m, LB, gen, colshift, P, d);
+                         col_stride, m, LB, G, gen, colshift, P, d);
       return;
     }
   }
   hipLaunchKernelGGL((gen_fwd_kernel<Real, TOut, KT, D, 0>), grid, dim3(256), lds, st, base,
-                     col_stride, m, LB, gen, colshift, P, d);
+                     col_stride, m, LB, G, gen, colshift, P, d);
 }
 
 template <typename Real, typename TOut, int KT>
@@ -259,11 +278,14 @@ int launch_gen_fwd_kt(TOut* base, int64_t col_stride, int ncols, int m, const ui
                       const uint32_t* colshift, const Params* P, int d, const Sched& sc,
                       hipStream_t st) {
   const int LB = sc.lb(m);
-  const size_t lds = gen_cols_lds_bytes(LB, sizeof(Real));
-  const dim3 grid(1u << (m - LB), (unsigned)ncols);
+  const size_t lds = sc.fused_lds(gen_cols_lds_bytes(LB, sizeof(Real)));
+  const int64_t nblk = (int64_t)1 << (m - LB);
+  const int G = gen_group(nblk);
+  const dim3 grid((unsigned)(nblk / G), (unsigned)ncols);
   const bool regs = LB == 12;
 #define MTGP_GEN(DD, KTV) \
-  gen_fwd_launch_d<Real, TOut, KTV, DD>(grid, lds, st, regs, base, col_stride, m, LB, gen, colshift, P, d)
+  gen_fwd_launch_d<Real, TOut, KTV, DD>(grid, lds, st, regs, G, base, col_stride, m, LB, gen, \
+                                        colshift, P, d)
   MTGP_DISPATCH_D(d, MTGP_GEN, KT);
 #undef MTGP_GEN
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -274,11 +296,13 @@ int launch_adj_reduce_kt(const TIn* base, int64_t col_stride, int ncols, int m,
                          const uint32_t* gen, const uint32_t* colshift, const Params* P, int d,
                          double* partials, const Sched& sc, hipStream_t st) {
   const int LB = sc.lb(m);
-  const size_t lds = gen_cols_lds_bytes(LB, sizeof(Real));
-  const dim3 grid(1u << (m - LB), (unsigned)ncols);
+  const size_t lds = sc.fused_lds(gen_cols_lds_bytes(LB, sizeof(Real)));
+  const int64_t nblk = (int64_t)1 << (m - LB);
+  const int G = adj_group(nblk);
+  const dim3 grid((unsigned)(nblk / G), (unsigned)ncols);
 #define MTGP_ADJ(DD, KTV)                                                                        \
   hipLaunchKernelGGL((adj_reduce_kernel<Real, TIn, KTV, DD>), grid, dim3(256), lds, st, base,     \
-                     col_stride, m, LB, gen, colshift, P, d, partials)
+                     col_stride, m, LB, G, gen, colshift, P, d, partials)
   MTGP_DISPATCH_D(d, MTGP_ADJ, KT);
 #undef MTGP_ADJ
   return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -53,8 +53,28 @@ struct Sched {
   int a_bits = 12;
   int b_bits = 6;
   size_t b_tile = 36864;
+  // workgroups per CU of the fused generation / reduction kernels (0: as
+  // many as fit), capped through their LDS request so that the strided
+  // passes overlapped with them find room on every CU
+  int fused_cap = 0;
   int lb(int m) const { return m < a_bits ? m : a_bits; }
+  size_t fused_lds(size_t need) const {
+    if (fused_cap <= 0) return need;
+    const size_t cap = ((size_t)160 * 1024) / (size_t)(fused_cap + 1) + 1024;
+    return need > cap ? need : cap;
+  }
 };
+
+// Digital-net adjoint reduction: one workgroup reduces adj_group(nb)
+// consecutive low-bit blocks of a column (of nb), so a column writes
+// nb / adj_group(nb) rows of the adjoint partial table.
+inline int adj_group(int64_t nb) { return nb >= 4 ? 4 : (int)nb; }
+// Digital-net column generation: consecutive low-bit blocks per workgroup.
+inline int gen_group(int64_t nb) { return nb >= 2 ? 2 : (int)nb; }
+inline int64_t dseq_adj_rows(int m, int lb) {
+  const int64_t nb = (int64_t)1 << (m - lb);
+  return nb / adj_group(nb);
+}
 
 // ---- transform.hip
 size_t gen_cols_lds_bytes(int LB, int real_bytes);
@@ -244,6 +264,16 @@ int launch_zerofill(SR* cols, const Alg1Desc& A1, int64_t N, Params* P, int fami
                     const double* yhat, z2* buf, double* logs, double* ahat, double* partials,
                     int* status, hipStream_t st);
 
+// ---- elim_gcv.hip
+// GCV at nested sizes in dual numbers (value, derivative under Lambda + e I):
+// weights = false runs the elimination, the means and the (q, s) pass;
+// weights = true writes the gradient weights (q, s in P).  buf holds
+// zf_elems(A1, N) pairs of complex values.
+template <typename SR>
+int launch_zerofill_gcv_dual(SR* cols, const Alg1Desc& A1, int64_t N, Params* P, int family,
+                             const double* yhat, void* buf, double* partials, int* status,
+                             bool weights, hipStream_t st);
+
 // ---- gcv.hip
 template <typename SR>
 int launch_gcv_eq(SR* cols, int64_t n, const PairMap& pm, const double* yhat, const Params* P,
@@ -272,6 +302,53 @@ int launch_var_nested(const double* mu, const Alg1Desc& A, int family, int64_t N
 int launch_var_finalize(const double* partials, int nbx, int64_t Mb, int rowm, bool equal,
                         const Params* P, const KDesc& kd, double* var, hipStream_t st);
 inline int var_tm(int T) { return T <= 1 ? 1 : T <= 2 ? 2 : T <= 4 ? 4 : T <= 8 ? 8 : 16; }
+
+// ---- batch.hip
+// One fit of a many-fit batch: its plan's tables and workspace regions, the
+// caller's theta / outputs / Adam state, and its slice of the batch
+// workspace (pattern storage of the fill-free elimination, log pivots, the
+// solve's partial row, one adjoint row per column, the log-pivot sum).
+struct BFit {
+  KDesc kd;  // unequal = 1: every fit goes through the fill-free elimination
+  Alg1Desc A;
+  int ncol, sr_f32;
+  int64_t N;
+  const uint32_t* gen;
+  const uint32_t* colshift;
+  const ColInfo* colinfo;
+  const double* theta;
+  double* out3;
+  double* grad;
+  Params* P;
+  int* status;
+  void* cols;    // spectrum / adjoint weights (float when sr_f32, else double)
+  double* work;  // FP64 working values (== cols for FP64 fits)
+  double* yhat;
+  z2* S;
+  double* logs;
+  double* sp;
+  double* ap;
+  double* m1;
+  double* m2;
+  int64_t* step;
+  const uint8_t* frozen;
+  int64_t ntheta;
+};
+struct BItem {
+  int fit, col;
+};
+constexpr int BATCH_MAX_M = 14;  // per-task sizes of the many-fit path: n_t <= 2^14
+constexpr int BATCH_SOLVE_BLOCKS = 64;  // workgroups per fit of each elimination launch
+// launch groups of column items sharing a kernel type and dimension width
+int launch_batch_prep(const BFit* fits, int nfits, hipStream_t st);
+int launch_batch_fwd(const BFit* fits, const BItem* items, int nitems, int kt, int d,
+                     hipStream_t st);
+int launch_batch_solve(const BFit* fits, int nfits, int tmax, hipStream_t st);
+int launch_batch_adj(const BFit* fits, const BItem* items, int nitems, int kt, int d,
+                     hipStream_t st);
+int launch_batch_final(const BFit* fits, int nfits, hipStream_t st);
+int launch_batch_adam(const BFit* fits, int nfits, double lr, double b1, double b2, double eps,
+                      hipStream_t st);
 
 // ---- optim.hip
 int launch_adam(double* theta, const double* grad, double* m1, double* m2, int64_t n, double lr,

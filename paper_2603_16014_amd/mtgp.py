@@ -217,6 +217,12 @@ class Plan:
             _ptr(mean), _ptr(self.ws), _ptr(scratch), _stream()), "mtgp_predict_net")
         return mean
 
+    def set_fused_occupancy(self, blocks_per_cu: int):
+        """Cap on workgroups per CU of the fused digital-net kernels (0 = none)."""
+        _lib.check(self.lib.mtgp_plan_set_fused_occupancy(self.h, int(blocks_per_cu)),
+                   "mtgp_plan_set_fused_occupancy")
+        self.fused_occupancy = int(blocks_per_cu)
+
     def set_overlap(self, chunks: int):
         """Chunks of the overlapped digital-net passes (1 = no overlap)."""
         _lib.check(self.lib.mtgp_plan_set_overlap(self.h, int(chunks)), "mtgp_plan_set_overlap")
@@ -338,3 +344,68 @@ def nll_grad_batched(plans, thetas, out3s, grads):
     G = arr(*[g.data_ptr() for g in grads])
     W = arr(*[p.ws.data_ptr() for p in plans])
     _lib.check(lib.mtgp_nll_grad_batched(k, P, Th, O, G, W, _stream()), "mtgp_nll_grad_batched")
+
+
+class Batch:
+    """Many independent fits with one launch per phase (mtgp_batch_*).
+
+    Holds the plans, the per-fit buffers it was created with (theta, out3,
+    grad and, with ``adam=True``, the Adam moments and step counters) and the
+    batch workspace; ``nll_grad()`` evaluates loss + gradient of every fit,
+    ``adam_step()`` updates every theta.  Both enqueue a fixed sequence of
+    launches on the current stream, so they can be captured in a graph."""
+
+    def __init__(self, plans, thetas, out3s=None, grads=None, adam=False, frozen=None):
+        self.lib = _lib.load()
+        k = len(plans)
+        self.plans = list(plans)
+        self.thetas = [t.contiguous() for t in thetas]
+        for t in self.thetas:
+            _need_cuda(t, torch.float64, "theta")
+        self.out3s = out3s if out3s is not None else [
+            torch.zeros(3, dtype=torch.float64, device="cuda") for _ in range(k)]
+        self.grads = grads if grads is not None else [
+            torch.zeros_like(t) for t in self.thetas]
+        arr = ctypes.c_void_p * max(k, 1)
+        P = arr(*[p.h.value for p in self.plans])
+        nbytes = int(self.lib.mtgp_batch_workspace_bytes(k, P))
+        if k > 0 and nbytes == 0:
+            raise _lib.MTGPError(-5, "mtgp_batch_workspace_bytes")
+        self.bws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+        W = arr(*[p.ws.data_ptr() for p in self.plans])
+        Th = arr(*[t.data_ptr() for t in self.thetas])
+        O = arr(*[o.data_ptr() for o in self.out3s])
+        G = arr(*[g.data_ptr() for g in self.grads])
+        M1 = M2 = S = F = None
+        if adam:
+            self.m1 = [torch.zeros_like(t) for t in self.thetas]
+            self.m2 = [torch.zeros_like(t) for t in self.thetas]
+            self.steps = [torch.zeros(1, dtype=torch.int64, device="cuda") for _ in range(k)]
+            M1 = arr(*[t.data_ptr() for t in self.m1])
+            M2 = arr(*[t.data_ptr() for t in self.m2])
+            S = arr(*[t.data_ptr() for t in self.steps])
+            if frozen is not None:
+                self.frozen = [torch.as_tensor(f, dtype=torch.uint8).cuda().contiguous()
+                               for f in frozen]
+                F = arr(*[f.data_ptr() for f in self.frozen])
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.mtgp_batch_create(k, P, W, Th, O, G, M1, M2, S, F,
+                                              ctypes.c_void_p(self.bws.data_ptr()),
+                                              ctypes.byref(h)), "mtgp_batch_create")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.mtgp_batch_destroy(self.h)
+            self.h = None
+
+    def nll_grad(self):
+        _lib.check(self.lib.mtgp_batch_nll_grad(self.h, _stream()), "mtgp_batch_nll_grad")
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        _lib.check(self.lib.mtgp_batch_adam_step(self.h, float(lr), float(beta1), float(beta2),
+                                                 float(eps), _stream()), "mtgp_batch_adam_step")
+
+    def reset_adam(self):
+        for t in self.m1 + self.m2 + self.steps:
+            t.zero_()

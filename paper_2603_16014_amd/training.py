@@ -197,3 +197,52 @@ class BatchedFits:
             torch.cuda.synchronize()
             out.append((time.perf_counter() - t0) * 1e3)
         return out
+
+
+class PersistentBatchedFits:
+    """Many independent fits advanced by the library's many-fit launches
+    (``mtgp.Batch``): one step of every fit is one launch per phase (loss
+    and gradient of all fits, then Adam of all fits), captured once in a
+    graph and replayed.  Plans need sizes <= 2^14 per task and FP64 or mixed
+    precision."""
+
+    def __init__(self, plans, thetas, lr=0.05, frozen=None):
+        self.lr = float(lr)
+        self.theta0 = [t.detach().clone().contiguous() for t in thetas]
+        if frozen is None:
+            frozen = [frozen_mask(p).numpy() for p in plans]
+        self.batch = mtgp.Batch(plans, [t.clone() for t in self.theta0], adam=True, frozen=frozen)
+        self.graph = None
+
+    @property
+    def thetas(self):
+        return self.batch.thetas
+
+    def step(self):
+        self.batch.nll_grad()
+        self.batch.adam_step(self.lr)
+
+    def reset(self):
+        for t, t0 in zip(self.batch.thetas, self.theta0):
+            t.copy_(t0)
+        self.batch.reset_adam()
+
+    def capture(self):
+        self.step()
+        torch.cuda.synchronize()
+        self.reset()
+        torch.cuda.synchronize()
+        self.graph = _capture(lambda ss: self.step(), [])
+
+    def run(self, steps: int):
+        """Replays the graph `steps` times; returns per-step milliseconds."""
+        if self.graph is None:
+            self.capture()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        st = torch.cuda.current_stream()
+        ev[0].record(st)
+        for k in range(steps):
+            self.graph.replay()
+            ev[k + 1].record(st)
+        torch.cuda.synchronize()
+        return [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]

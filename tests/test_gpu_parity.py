@@ -727,10 +727,12 @@ def test_gcv_against_oracle(family, m, profile, precision):
 @pytest.mark.parametrize("family,m,profile,precision", [
     ("dseq", [7, 5, 4], True, "fp64"), ("dseq", [7, 5, 4], False, "fp64"),
     ("dseq", [8, 8, 6, 3], True, "mixed"), ("lat", [7, 6, 4], True, "fp64"),
-    ("lat", [7, 6, 4], False, "mixed"), ("dseq", [6, 0], True, "fp64")])
+    ("lat", [7, 6, 4], False, "mixed"), ("dseq", [6, 0], True, "fp64"),
+    ("lat", [6, 6, 5, 3], False, "fp64")])
 def test_gcv_nested_loss_against_oracle(family, m, profile, precision):
-    """Nested sizes: GCV loss and GCV means through the fill-free elimination;
-    the gradient is refused."""
+    """Nested sizes: GCV loss, GCV means and the exact GCV gradient (the
+    elimination in dual numbers for Lambda^-2 on the pattern) against the
+    dense oracle; Algorithm 1's elimination refuses the gradient."""
     import workloads as wl
     w = wl.with_theta(tiny(family, len(m), m, 3, seed=53, profile=profile),
                       tau=np.linspace(-0.2, 0.3, len(m)))
@@ -738,17 +740,62 @@ def test_gcv_nested_loss_against_oracle(family, m, profile, precision):
     X = points.task_points(w)
     from oracle import dense
     y = dense.targets(w, np.random.default_rng(w.seed + 1000), X)
-    res = dense.gcv(w, y, X=X)
+    gref, res = dense.gcv_grad(w, y, X=X)
     plan = mt.Plan.from_workload(w, precision)
     plan.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
     theta = plan.pack_theta(w.theta)
-    out3, g, tau = plan.gcv(theta, grad=False)
+    tolL = 1e-10 if precision == "fp64" else 1e-5
+    for want_grad in (False, True):
+        out3, g, tau = plan.gcv(theta, grad=want_grad)
+        torch.cuda.synchronize()
+        assert plan.status()[0] == 0 and (g is None) == (not want_grad)
+        o = out3.cpu().numpy()
+        assert abs(o[2] - res["L"]) < tolL * res["L"], (o, res["L"])
+        assert abs(o[0] - res["q"]) < tolL * res["q"] and abs(o[1] - res["s"]) < tolL * res["s"]
+        np.testing.assert_allclose(tau.cpu().numpy(), res["tau_hat"], rtol=tolL * 100, atol=1e-12)
+    gvec = plan.unpack(g)
+    scale = max(np.abs(np.atleast_1d(v)).max() for v in gref.values())
+    tolg = 1e-7 if precision == "fp64" else 1e-4
+    for k, v in gref.items():
+        e = np.abs(np.atleast_1d(gvec[k]) - np.atleast_1d(v)).max() / scale
+        assert e < tolg, (k, gvec[k], v, e)
+    a1 = mt.Plan.from_workload(w, precision, elimination="alg1")
+    a1.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
+    with pytest.raises(mt._lib.MTGPError):
+        a1.gcv(theta, grad=True)
+
+
+@pytest.mark.parametrize("family,m,profile", [("dseq", [16, 14, 12], True),
+                                              ("lat", [15, 15, 13, 11], False),
+                                              ("dseq", [17, 13], False)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gcv_nested_gradient_against_spectral_oracle_beyond_dense_sizes(family, m, profile,
+                                                                        precision):
+    # nested GCV gradient at N up to 1.7e5 against the class-by-class
+    # spectral oracle (pinned to the dense oracle at small sizes)
+    import workloads as wl
+    from oracle import dense, spectral
+    w = wl.with_theta(tiny(family, len(m), m, 3, seed=97, xi=1e-2, rank=2, profile=profile),
+                      tau=np.linspace(-0.3, 0.4, len(m)))
+    say("gcv nested gradient vs spectral oracle", family, m, precision)
+    key = ("gcvn", w.name, w.seed)
+    if key not in _SPECTRAL_REFS:
+        y = dense.targets(w, np.random.default_rng(w.seed + 1000), points.task_points(w))
+        g, r = spectral.gcv_grad(w, y)
+        _SPECTRAL_REFS[key] = (y, r, g)
+    y, ref, gref = _SPECTRAL_REFS[key]
+    plan = mt.Plan.from_workload(w, precision)
+    plan.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
+    theta = plan.pack_theta(w.theta)
+    out3, g, tau = plan.gcv(theta, grad=True)
     torch.cuda.synchronize()
-    assert plan.status()[0] == 0 and g is None
+    assert plan.status() == (0, -1)
     o = out3.cpu().numpy()
     tolL = 1e-10 if precision == "fp64" else 1e-5
-    assert abs(o[2] - res["L"]) < tolL * res["L"], (o, res["L"])
-    assert abs(o[0] - res["q"]) < tolL * res["q"] and abs(o[1] - res["s"]) < tolL * res["s"]
-    np.testing.assert_allclose(tau.cpu().numpy(), res["tau_hat"], rtol=tolL * 100, atol=1e-12)
-    with pytest.raises(mt._lib.MTGPError):
-        plan.gcv(theta, grad=True)
+    assert abs(o[2] - ref["L"]) < tolL * ref["L"], (o, ref["L"])
+    gvec = plan.unpack(g)
+    scale = max(np.abs(np.atleast_1d(v)).max() for v in gref.values())
+    tolg = 1e-7 if precision == "fp64" else 1e-4
+    for k, v in gref.items():
+        e = np.abs(np.atleast_1d(gvec[k]) - np.atleast_1d(v)).max() / scale
+        assert e < tolg, (k, gvec[k], v, e)
