@@ -69,15 +69,22 @@ def progress(*a):
     print(f"[bench {time.perf_counter() - _T0:7.1f}s]", *a, file=sys.stderr, flush=True)
 
 
+# the sources of the kernels a loss + gradient evaluation of the digital-net
+# workload runs, and of their launch sequence
+HOT_PATH_SOURCES = ("api.hip", "common.h", "kernels.h", "colgen.h", "fused_eval.h",
+                    "fused_gen_o2.hip", "fused_adj_o2.hip", "adjoint.hip", "transform.hip",
+                    "solve.hip", "solve_dev.h")
+
+
 def kernel_sources_digest():
-    """Digest of the HIP sources; a counter summary is stale once it changes."""
+    """Digest of the hot path's HIP sources; a counter summary is stale once
+    it changes."""
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2603_16014_amd", "csrc", "*")))
-    for f in files:
-        if f.endswith((".hip", ".h")):
-            h.update(os.path.basename(f).encode())
-            with open(f, "rb") as fh:
-                h.update(fh.read())
+    for name in HOT_PATH_SOURCES:
+        f = os.path.join(ROOT, "paper_2603_16014_amd", "csrc", name)
+        h.update(name.encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
