@@ -54,9 +54,9 @@ VALU_FILE = os.path.join(ROOT, "profiles", "valu_gen_adj_T8_d10_n2e24_mixed.md")
 # phase -> (kernel-name pattern in rocprofv3 output, bound)
 PHASE_KERNELS = {
     "gen_fwd_low": ("gen_fwd_kernel", "alu"),
-    "fwd_high": ("fwht_reg_buf_kernel (2 passes)", "hbm"),
+    "fwd_high": ("fwht_hi12_kernel (1 pass)", "hbm"),
     "solve": ("solve_eq_kernel", "hbm"),
-    "adj_high": ("fwht_reg_buf_kernel (2 passes)", "hbm"),
+    "adj_high": ("fwht_hi12_kernel (1 pass)", "hbm"),
     "adj_low_reduce": ("adj_reduce_kernel", "alu"),
 }
 
@@ -158,6 +158,15 @@ def time_evals(plan, theta, steps, warmup, timing=True):
     if code != 0:
         raise RuntimeError(f"status {code} at frequency {bad}")
     return ms, out3.cpu().numpy(), grad.cpu().numpy(), tau.cpu().numpy(), phases, done
+
+
+def default_high_passes(r):
+    """HBM passes of the library's default schedule over r high index bits."""
+    n = 0
+    while r > 0:
+        r -= r if r in (8, 10, 12) else min(r, 6)
+        n += 1
+    return n
 
 
 def algo_units(w, precision, a_bits=12):
@@ -458,8 +467,9 @@ def transforms_leg(ncols=29, m=24, reps=5):
                      "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         if name.startswith("fwht"):
             # the passes each read and write every element once: the LDS pass
-            # over the low 12 bits and ceil((m - 12) / 6) register passes
-            passes = 1 + -(-(m - 12) // 6)
+            # over the low 12 bits, then by size one pass over a remainder of
+            # 8, 10 or 12 bits, else register passes of at most 6 bits
+            passes = 1 + default_high_passes(m - 12)
             pb = passes * nbytes
             out[name].update({"passes": passes, "pass_bytes": pb,
                               "pass_GB_s": pb / (ms * 1e-3) / 1e9,
@@ -691,7 +701,7 @@ def _phase_of(name, cur):
         return "prep"
     if "gen_fwd_kernel" in name:
         return "gen_fwd_low"
-    if "fwht_strided_kernel" in name or "fwht_reg_" in name:
+    if "fwht_strided_kernel" in name or "fwht_reg_" in name or "fwht_hi" in name:
         return "fwd_high" if cur in ("gen_fwd_low", "fwd_high") else "adj_high"
     if "solve_eq" in name or "alg1_" in name:
         return "solve"

@@ -130,16 +130,22 @@ int mtgp_plan_destroy(mtgp_plan* plan);
 /* Transform schedule (tuning only; results are the same up to rounding):
  * each length-2^m transform runs as one LDS-resident pass over the low
  * pass_a_bits index bits (1..13; fused with kernel-column generation) and
- * passes over at most pass_b_bits (1..12) further bits each.  Passes of at
- * most 6 bits above bit 8 keep each thread's 2^bits strided values in
- * registers; passes of exactly 8, 10 or 12 bits (above bit 8 - bits/2, with
- * a block's window below 2^30 bytes) go through registers and one LDS tile
- * of 256 x 2^(bits/2) values in a single pass; other wider passes use an LDS
- * tile of about pass_b_tile_bytes (4096..147456).  Changes
- * mtgp_workspace_bytes, so call it before sizing the workspace.  Defaults:
- * 12, 6, 36864 (measured best on MI355X for 2^24-point columns, where the
- * 12-bit single pass halves the HBM traffic of the high bits but holds one
- * block per CU). */
+ * passes over at most pass_b_bits (1..12) further bits each, or, with
+ * pass_b_bits = 0, by size: the whole remainder in one pass when it is 8, 10
+ * or 12 bits (and the one-pass kernel takes it), else passes of at most 6
+ * bits.  Passes of at most 6 bits above bit 8 keep each thread's 2^bits
+ * strided values in registers.  Passes of exactly 8 or 10 bits (above bit
+ * 8 - bits/2, with a block's window below 2^30 bytes) go through registers
+ * and one LDS tile of 256 x 2^(bits/2) values.  A 12-bit pass (above bit 3)
+ * holds 4096 rows of 2, 4 or 8 adjacent columns in registers, the widest
+ * whose exchange grid of 8.6 KiB per column (FP64; half in FP32) fits
+ * pass_b_tile_bytes, and transposes them through that grid in four
+ * quarter-size rounds.  Other wider passes use an LDS tile of about
+ * pass_b_tile_bytes (4096..147456).  Changes mtgp_workspace_bytes, so call
+ * it before sizing the workspace.  Defaults: 12, 0, 73728 (measured on
+ * MI355X: at 2^24-point columns the 12 high bits in one pass of 8 columns
+ * per block, 11.7 -> 10.2 ms per loss + gradient at T=8, d=10 with the
+ * passes in sequence). */
 int mtgp_plan_set_schedule(mtgp_plan* plan, int32_t pass_a_bits, int32_t pass_b_bits,
                            int64_t pass_b_tile_bytes);
 

@@ -16,11 +16,12 @@ import torch
 
 from . import mtgp
 
-# (pass_a_bits, pass_b_bits, pass_b_tile_bytes): register-resident high
-# passes for pass_b_bits <= 6, LDS-tiled ones above
+# (pass_a_bits, pass_b_bits, pass_b_tile_bytes): pass_b_bits 0 picks the
+# high passes by size; register-resident passes for pass_b_bits <= 6,
+# one-pass or LDS-tiled ones above
 CANDIDATES = [
-    (12, 6, 36864), (13, 6, 36864), (12, 5, 36864), (12, 4, 36864), (11, 6, 36864),
-    (10, 7, 36864), (12, 12, 36864),
+    (12, 0, 73728), (12, 6, 36864), (13, 6, 36864), (12, 5, 36864), (12, 4, 36864),
+    (11, 6, 36864), (10, 7, 36864), (12, 12, 36864),
 ]
 OVERLAPS = (1, 4, 8, 16)
 FINALISTS = 3  # schedules also timed with each overlap setting

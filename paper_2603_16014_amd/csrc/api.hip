@@ -866,7 +866,7 @@ int mtgp_plan_create(const mtgp_design* des, int32_t precision, mtgp_plan** out)
 
 int mtgp_plan_set_schedule(mtgp_plan* p, int32_t pass_a_bits, int32_t pass_b_bits,
                            int64_t pass_b_tile_bytes) {
-  if (!p || pass_a_bits < 1 || pass_a_bits > PASS_A_MAX_BITS || pass_b_bits < 1 ||
+  if (!p || pass_a_bits < 1 || pass_a_bits > PASS_A_MAX_BITS || pass_b_bits < 0 ||
       pass_b_bits > 12 || pass_b_tile_bytes < 4096 || pass_b_tile_bytes > 147456)
     return MTGP_EINVAL;
   p->sched.a_bits = pass_a_bits;

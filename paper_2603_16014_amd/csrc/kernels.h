@@ -51,8 +51,10 @@ struct alignas(4) PairMap {
 // most b_bits more, with an LDS tile of about b_tile bytes.
 struct Sched {
   int a_bits = 12;
-  int b_bits = 6;
-  size_t b_tile = 36864;
+  // bits per strided pass; 0: by size (one pass over a remainder of 8, 10
+  // or 12 bits, else register passes of at most 6 bits)
+  int b_bits = 0;
+  size_t b_tile = 73728;
   // workgroups per CU of the fused generation / reduction kernels (0: as
   // many as fit), capped through their LDS request so that the strided
   // passes overlapped with them find room on every CU

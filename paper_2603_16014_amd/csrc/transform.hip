@@ -284,6 +284,90 @@ __global__ __launch_bounds__(256) void fwht_hi_kernel(const TIn* in, TOut* out,
                     ((uint32_t)k << (lo + H1)) * (uint32_t)sizeof(TOut));
 }
 
+// One pass over the 12 high bits [lo, lo + 12) with a quarter-size LDS
+// exchange, so several blocks (and the fused VALU-bound kernels) share a CU.
+// A block takes KC = 4 adjacent low indices c over all 4096 rows
+// h = a + 64 b of one vector; thread (c, u), wave g = u / 16.
+//
+// Phase 1: the thread holds rows a = u, b = 0 .. 63 and transforms over b.
+// Its input block q (b in [16q, 16q + 16)) is negated when popcount(q & g)
+// is odd, which by the XOR-shift rule of the Walsh transform,
+//   sum_s (-1)^{k.s} (-1)^{t.s} x[s] = X[k ^ t],   t = 16 g,
+// leaves frequency b = k ^ 16 g in register slot k: slot block q holds b
+// block q ^ g.  Exchange, rounds r = 0 .. 3: every thread writes its slot
+// block r (b block r ^ g, so the rows b = 16 (r ^ g) + i of a = u) to a
+// 64 x 16 LDS grid per column, and reads back into the same slots the 16
+// values (a = 16 (r ^ g) + j, b = u); the slot indices stay compile-time and
+// each round moves a quarter of the tile.  Phase 2: slot s now holds
+// a = s ^ 16 g, so the transform over the slots gives
+//   (-1)^{popcount((k >> 4) & g)} Y[k]
+// in slot k, the same per-block sign as phase 1's input, undone before the
+// stores of rows k + 64 u.  Blocks that share a 128-byte line sit on one XCD,
+// next to each other in dispatch order (dispatch is round-robin over the 8
+// XCDs).
+constexpr int HI12_AS = 17, HI12_CS = 64 * HI12_AS + 8;
+
+// LDS bytes of fwht_hi12_kernel with KC columns per block
+static size_t hi12_lds_bytes(int KC, size_t tc_bytes) { return (size_t)KC * HI12_CS * tc_bytes; }
+
+// multiplies register block q by (-1)^popcount(q & g) (exact)
+template <typename TC>
+__device__ inline void negate_blocks(TC (&v)[64], int g) {
+#pragma unroll
+  for (int q = 1; q < 4; q++) {
+    const TC sg = (__builtin_popcount(q & g) & 1) ? (TC)-1 : (TC)1;
+#pragma unroll
+    for (int i = 0; i < 16; i++) v[16 * q + i] *= sg;
+  }
+}
+
+template <typename TC, typename TIn, typename TOut, int KC>
+__global__ __launch_bounds__(64 * KC) void fwht_hi12_kernel(const TIn* in, TOut* out,
+                                                            int64_t vec_stride, int lo) {
+  constexpr int KB = KC == 8 ? 3 : KC == 4 ? 2 : 1, AS = HI12_AS, CS = HI12_CS;
+  extern __shared__ __align__(16) unsigned char smem[];
+  TC* X = reinterpret_cast<TC*>(smem);
+  const int ncg = 1 << (lo - KB);
+  int cg = blockIdx.x;
+  if ((ncg & 31) == 0) {
+    const int x = cg & 7, sl = cg >> 3;
+    cg = ((sl >> 2) << 5) + (x << 2) + (sl & 3);
+  }
+  const int64_t vb = (int64_t)blockIdx.y * vec_stride + ((int64_t)cg << KB);
+  const int c = threadIdx.x & (KC - 1), u = threadIdx.x >> KB;
+  // the group u / 16 is wave-uniform for KC >= 4
+  int g = u >> 4;
+  if constexpr (KC >= 4) g = __builtin_amdgcn_readfirstlane(g);
+  const __amdgpu_buffer_rsrc_t ri = buf_rsrc(in + vb, (int)(sizeof(TIn) << (lo + 12)));
+  const __amdgpu_buffer_rsrc_t ro = buf_rsrc(out + vb, (int)(sizeof(TOut) << (lo + 12)));
+  TC v[64];
+  const uint32_t lane_in = ((uint32_t)c + ((uint32_t)u << lo)) * (uint32_t)sizeof(TIn);
+#pragma unroll
+  for (int b = 0; b < 64; b++)
+    v[b] = (TC)buf_load<TIn>(ri, lane_in, ((uint32_t)b << (lo + 6)) * (uint32_t)sizeof(TIn));
+  // all 64 loads in flight before the first butterfly
+  __builtin_amdgcn_sched_barrier(0);
+  negate_blocks<TC>(v, g);
+  reg_fwht_split<TC, 6>(v);
+  TC* Xc = X + c * CS;
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+#pragma unroll
+    for (int i = 0; i < 16; i++) Xc[u * AS + i] = v[16 * r + i];
+    __syncthreads();
+    const TC* src = Xc + (((r ^ g) << 4) * AS) + (u & 15);
+#pragma unroll
+    for (int j = 0; j < 16; j++) v[16 * r + j] = src[j * AS];
+    if (r < 3) __syncthreads();
+  }
+  reg_fwht_split<TC, 6>(v);
+  negate_blocks<TC>(v, g);
+  const uint32_t lane_out = ((uint32_t)c + ((uint32_t)u << (lo + 6))) * (uint32_t)sizeof(TOut);
+#pragma unroll
+  for (int k = 0; k < 64; k++)
+    buf_store<TOut>((TOut)v[k], ro, lane_out, ((uint32_t)k << lo) * (uint32_t)sizeof(TOut));
+}
+
 static size_t fwht_hi_lds_bytes(int H, size_t tc_bytes) {
   const int R = 1 << (H / 2), KC = 256 / R;
   return ((size_t)KC << H) * tc_bytes + (size_t)R * KC * tc_bytes;
@@ -293,20 +377,37 @@ static size_t fwht_hi_lds_bytes(int H, size_t tc_bytes) {
 // block fit in the low part and a block's window stays below 2^30 bytes
 static bool fwht_hi_ok(int lo, int hb, size_t in_bytes, size_t out_bytes) {
   if (hb != 8 && hb != 10 && hb != 12) return false;
-  const int KB = 8 - hb / 2;
+  const int KB = hb == 12 ? 3 : 8 - hb / 2;  // (12 bits: up to 8 columns per block)
   const size_t w = (in_bytes > out_bytes ? in_bytes : out_bytes) << (lo + hb);
   return lo >= KB && w <= ((size_t)1 << 30);
 }
 
+// 12 bits: the widest column group (2, 4 or 8 columns) whose exchange grid
+// fits the schedule's tile budget
+static int hi12_kc(size_t tile, size_t tc_bytes) {
+  return hi12_lds_bytes(8, tc_bytes) <= tile ? 8 : hi12_lds_bytes(4, tc_bytes) <= tile ? 4 : 2;
+}
+
 template <typename TC, typename TIn, typename TOut>
 void launch_hi_pass(const TIn* in, TOut* out, int64_t vec_stride, int nv, int lo, int hb,
-                    hipStream_t st) {
+                    size_t tile, hipStream_t st) {
   const dim3 grid(1u << (lo - (8 - hb / 2)), (unsigned)nv);
   const size_t lds = fwht_hi_lds_bytes(hb, sizeof(TC));
-  if (hb == 12)
-    hipLaunchKernelGGL((fwht_hi_kernel<TC, TIn, TOut, 12>), grid, dim3(256), lds, st, in, out,
-                       vec_stride, lo);
-  else if (hb == 10)
+  if (hb == 12) {
+    const int kc = hi12_kc(tile, sizeof(TC));
+    const size_t l12 = hi12_lds_bytes(kc, sizeof(TC));
+    const int kb = kc == 8 ? 3 : kc == 4 ? 2 : 1;
+    const dim3 g12(1u << (lo - kb), (unsigned)nv);
+    if (kc == 8)
+      hipLaunchKernelGGL((fwht_hi12_kernel<TC, TIn, TOut, 8>), g12, dim3(512), l12, st, in, out,
+                         vec_stride, lo);
+    else if (kc == 4)
+      hipLaunchKernelGGL((fwht_hi12_kernel<TC, TIn, TOut, 4>), g12, dim3(256), l12, st, in, out,
+                         vec_stride, lo);
+    else
+      hipLaunchKernelGGL((fwht_hi12_kernel<TC, TIn, TOut, 2>), g12, dim3(128), l12, st, in, out,
+                         vec_stride, lo);
+  } else if (hb == 10)
     hipLaunchKernelGGL((fwht_hi_kernel<TC, TIn, TOut, 10>), grid, dim3(256), lds, st, in, out,
                        vec_stride, lo);
   else
@@ -363,7 +464,15 @@ int launch_strided(const TIn* first, TC* work, TOut* last, int64_t vec_stride, i
   int lo = sc.lb(m);
   bool is_first = true;
   while (lo < m) {
-    const int hb = (m - lo) < sc.b_bits ? (m - lo) : sc.b_bits;
+    const int r = m - lo;
+    int hb;
+    if (sc.b_bits > 0)
+      hb = r < sc.b_bits ? r : sc.b_bits;
+    else  // by size: the whole remainder in one pass where a one-pass kernel takes it
+      hb = r <= 12 && fwht_hi_ok(lo, r, sizeof(TC) > sizeof(TIn) ? sizeof(TC) : sizeof(TIn),
+                                 sizeof(TC) > sizeof(TOut) ? sizeof(TC) : sizeof(TOut))
+               ? r
+               : (r < 6 ? r : 6);
     const bool is_last = lo + hb >= m;
     if (fwht_hi_ok(lo, hb, sizeof(TC) > sizeof(TIn) ? sizeof(TC) : sizeof(TIn),
                    sizeof(TC) > sizeof(TOut) ? sizeof(TC) : sizeof(TOut))) {
@@ -371,13 +480,13 @@ int launch_strided(const TIn* first, TC* work, TOut* last, int64_t vec_stride, i
         const int nv = (int)((nvec - v0) < 65535 ? (nvec - v0) : 65535);
         const int64_t o = v0 * vec_stride;
         if (is_first && is_last)
-          launch_hi_pass<TC, TIn, TOut>(first + o, last + o, vec_stride, nv, lo, hb, st);
+          launch_hi_pass<TC, TIn, TOut>(first + o, last + o, vec_stride, nv, lo, hb, sc.b_tile, st);
         else if (is_first)
-          launch_hi_pass<TC, TIn, TC>(first + o, work + o, vec_stride, nv, lo, hb, st);
+          launch_hi_pass<TC, TIn, TC>(first + o, work + o, vec_stride, nv, lo, hb, sc.b_tile, st);
         else if (is_last)
-          launch_hi_pass<TC, TC, TOut>(work + o, last + o, vec_stride, nv, lo, hb, st);
+          launch_hi_pass<TC, TC, TOut>(work + o, last + o, vec_stride, nv, lo, hb, sc.b_tile, st);
         else
-          launch_hi_pass<TC, TC, TC>(work + o, work + o, vec_stride, nv, lo, hb, st);
+          launch_hi_pass<TC, TC, TC>(work + o, work + o, vec_stride, nv, lo, hb, sc.b_tile, st);
       }
       is_first = false;
       lo += hb;

@@ -19,7 +19,7 @@ FP64, MIXED, F32 = 0, 1, 2
 FAMILIES = {"dseq": DSEQ, "lat": LAT, DSEQ: DSEQ, LAT: LAT}
 PRECISIONS = {"fp64": FP64, "mixed": MIXED, "f32": F32, FP64: FP64, MIXED: MIXED, F32: F32}
 ELIMINATIONS = {"sparse": 0, "alg1": 1, 0: 0, 1: 1}  # nested unequal sizes
-DEFAULT_SCHEDULE = (12, 6, 36864)  # the library's default transform schedule
+DEFAULT_SCHEDULE = (12, 0, 73728)  # the library's default transform schedule
 LOG_KEYS = ("gamma", "eta", "b", "xi", "zeta")
 
 

@@ -283,8 +283,8 @@ def _spectral_reference(w):
     return _SPECTRAL_REFS[key]
 
 
-def _check_against_spectral(w, y, ref, gref, precision, elimination):
-    plan = mt.Plan.from_workload(w, precision, elimination=elimination)
+def _check_against_spectral(w, y, ref, gref, precision, elimination, schedule=None):
+    plan = mt.Plan.from_workload(w, precision, elimination=elimination, schedule=schedule)
     plan.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
     theta = plan.pack_theta(w.theta)
     out3, grad, tau = plan.nll_grad(theta)
@@ -323,6 +323,20 @@ def test_loss_against_spectral_oracle_beyond_dense_sizes(family, m, T, d, precis
     y, ref, gref = _spectral_reference(w)
     assert abs(spectral.nll_equal(w, y)["L"] - ref["L"]) < 1e-12 * abs(ref["L"])
     _check_against_spectral(w, y, ref, gref, precision, "sparse")
+
+
+@pytest.mark.parametrize("m,sched", [(18, (6, 12, 4096)), (19, (7, 12, 36864)),
+                                     (20, (8, 12, 73728))])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_pass_high_bits_against_spectral_oracle(m, sched, precision):
+    # the 12 high index bits in one pass with the quarter-tile LDS exchange,
+    # 2, 4 and 8 columns per block by the tile budget: at m = 18 the column
+    # groups run in dispatch order, at m = 19 and 20 (32 groups per vector)
+    # the blocks sharing a line sit on one XCD
+    w = tiny("dseq", 3, [m] * 3, 3, seed=71 + m, xi=1e-2, rank=2)
+    say("one-pass high bits vs spectral oracle", m, sched, precision)
+    y, ref, gref = _spectral_reference(w)
+    _check_against_spectral(w, y, ref, gref, precision, "sparse", schedule=sched)
 
 
 NESTED_BEYOND = [
@@ -445,7 +459,8 @@ def test_gcv_gradient_against_spectral_oracle_beyond_dense_sizes(family, m, T, d
 
 
 @pytest.mark.parametrize("m,sched", [(13, (3, 10, 4096)), (16, (6, 10, 4096)), (16, (8, 8, 4096)),
-                                     (19, (7, 12, 36864)), (20, (12, 8, 36864))])
+                                     (18, (6, 12, 4096)), (19, (7, 12, 36864)),
+                                     (20, (8, 12, 73728)), (20, (12, 8, 36864))])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_single_pass_high_bits_match_register_passes(m, sched, precision):
     # the one-pass kernel over 8, 10 or 12 high bits (at m = 19 with the XCD
