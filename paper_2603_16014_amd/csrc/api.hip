@@ -833,14 +833,30 @@ int mtgp_plan_create(const mtgp_design* des, int32_t precision, mtgp_plan** out)
   p->real_bytes = precision == MTGP_FP64 ? sizeof(double) : sizeof(float);
   p->work_bytes = precision == MTGP_MIXED ? sizeof(double) : 0;
   layout(p);
-  // device tables
-  if (hipMalloc(&p->d_gen, p->gen.size() * sizeof(uint32_t)) != hipSuccess ||
+  // device tables; digital sequences append the Gray-code step table of the
+  // fused kernels (row k: z_j(256 gray(k)), the XOR of generating columns
+  // 8 + b of dimension j over the set bits b of gray(k); zero beyond d)
+  std::vector<uint32_t> genx = p->gen;
+  if (p->family == MTGP_DSEQ) {
+    genx.resize((size_t)32 * p->d + (size_t)GRAY_ROWS * GRAY_STRIDE, 0u);
+    uint32_t* gz = genx.data() + (size_t)32 * p->d;
+    for (int k = 0; k < GRAY_ROWS; k++) {
+      const uint32_t gk = (uint32_t)(k ^ (k >> 1));
+      for (int j = 0; j < p->d; j++) {
+        uint32_t z = 0;
+        for (int b = 0; b < 5; b++)
+          if ((gk >> b) & 1u) z ^= p->gen[(size_t)32 * j + 8 + b];
+        gz[(size_t)GRAY_STRIDE * k + j] = z;
+      }
+    }
+  }
+  if (hipMalloc(&p->d_gen, genx.size() * sizeof(uint32_t)) != hipSuccess ||
       hipMalloc(&p->d_colshift, p->col_shift.size() * sizeof(uint32_t)) != hipSuccess ||
       hipMalloc(&p->d_taskshift, p->shift.size() * sizeof(uint32_t)) != hipSuccess) {
     mtgp_plan_destroy(p);
     return MTGP_ENOMEM;
   }
-  if (hipMemcpy(p->d_gen, p->gen.data(), p->gen.size() * sizeof(uint32_t),
+  if (hipMemcpy(p->d_gen, genx.data(), genx.size() * sizeof(uint32_t),
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->d_colshift, p->col_shift.data(), p->col_shift.size() * sizeof(uint32_t),
                 hipMemcpyHostToDevice) != hipSuccess ||

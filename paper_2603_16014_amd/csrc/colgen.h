@@ -94,6 +94,53 @@ struct Digits {
   }
 };
 
+// Digital-sequence digits for the fused kernels, with the block part folded
+// into the per-thread part and the element part read from a table:
+//   u_j(i0 + t + 256 gray(k)) = [z_j(t) ^ z_j(i0) ^ shift_j] ^ z_j(256 gray(k)),
+// where gray(k) = k ^ (k >> 1) is the element visited at step k.  Row k of
+// the table (GRAY_STRIDE words, 0 beyond the d dimensions) holds
+// z_j(256 gray(k)); it depends on the generating matrices only, so one table
+// serves every block and column, and a step costs one XOR per dimension with
+// a wave-uniform (scalar) operand.  The table follows the d x 32 generating
+// columns in the same buffer (gray_table).
+
+template <int D>
+struct FoldedDigits {
+  uint32_t a[D];    // per-thread part with the block part folded in
+  uint32_t blk[D];  // block part z_j(i0) ^ shift_j (uniform)
+  uint32_t s[D];    // element part z_j(256 gray(k)) (uniform)
+
+  __device__ inline void init(const uint32_t* __restrict__ gen, const uint32_t* __restrict__ sh,
+                              int d, uint32_t t, uint32_t i0) {
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+      const int jj = j < d ? j : 0;
+      const uint32_t keep = j < d ? 0xffffffffu : 0u;
+      blk[j] = (dseq_z(gen + 32 * jj, i0) ^ sh[jj]) & keep;
+      a[j] = (dseq_z(gen + 32 * jj, t) & keep) ^ blk[j];
+      s[j] = 0;
+    }
+  }
+  __device__ inline void set_block(const uint32_t* __restrict__ gen,
+                                   const uint32_t* __restrict__ sh, int d, uint32_t i0) {
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+      const int jj = j < d ? j : 0;
+      const uint32_t keep = j < d ? 0xffffffffu : 0u;
+      const uint32_t nb = (dseq_z(gen + 32 * jj, i0) ^ sh[jj]) & keep;
+      a[j] ^= blk[j] ^ nb;
+      blk[j] = nb;
+      s[j] = 0;
+    }
+  }
+  // element part of step k (row 0 is zero)
+  __device__ inline void load(const uint32_t* __restrict__ gz, int k) {
+#pragma unroll
+    for (int j = 0; j < D; j++) s[j] = gz[GRAY_STRIDE * k + j];
+  }
+  __device__ inline uint32_t u(int j) const { return a[j] ^ s[j]; }
+};
+
 // Order-2 DSI kernel in integer-scaled form.  With X = u (the digit as an
 // integer, exact in FP64) and K2(x) = 3/2 - (5/2) t1(x) - beta(x) x,
 //   kappa = 2^32 K2 = (3/2) 2^32 - beta X - (5/2) lead(X),

@@ -37,7 +37,9 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
     fill_kap2_table(k2tab);
     __syncthreads();
   }
-  Digits<FAM_DSEQ, D> dg;
+  Digits<FAM_DSEQ, D> dg;   // blocks below 256 E points (E = 0)
+  FoldedDigits<D> fd;       // E > 0
+  const uint32_t* gz = gray_table(gen, d);
   Real sc[D];  // eta K = sc kappa; padding slots: sc = 0, factor exactly 1
 #pragma unroll
   for (int j = 0; j < D; j++) sc[j] = kscale<Real, KT>(j < d ? RT<Real>::eta(P, j) : (Real)0);
@@ -51,15 +53,15 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
       // nb == 256 E: thread t owns indices t + 256 e.  Index bits 8 .. 8+log2(E)
       // are transformed in registers, bits 0 .. 7 in two LDS rounds.
       Real v[E];
-      if (g == 0) dg.init(gen, cs, d, t, i0, m);
-      else dg.set_block(gen, cs, d, i0, m);
+      if (g == 0) fd.init(gen, cs, d, t, i0);
+      else fd.set_block(gen, cs, d, i0);
 #pragma unroll
       for (int k = 0; k < E; k++) {
+        if (k > 0) fd.load(gz, k);
         Real c = gam;
 #pragma unroll
-        for (int j = 0; j < D; j++) c *= fma(sc[j], kappa_t<Real, KT>(dg.u(j), P, k2tab), (Real)1);
+        for (int j = 0; j < D; j++) c *= fma(sc[j], kappa_t<Real, KT>(fd.u(j), P, k2tab), (Real)1);
         v[Digits<FAM_DSEQ, D>::elem(k)] = c;
-        if (k + 1 < E) dg.advance(gen, d, k);
       }
       reg_fwht<Real, E>(v);
 #pragma unroll
@@ -109,8 +111,8 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
 // Accumulates the derivative sums of one element with weight wv: slot j
 // gets w gamma kappa_j prod_{k != j} f_k (times sc_j at the end this is
 // w dc/dlog eta_j), slot D gets w c, acc_b the adaptive-weight sums.
-template <typename Real, int KT, int D>
-__device__ inline void adj_element(const Digits<kt_family(KT), D>& dg, Real wv, Real gam,
+template <typename Real, int KT, int D, typename Dg>
+__device__ inline void adj_element(const Dg& dg, Real wv, Real gam,
                                    const Real (&sc)[D], const Params* __restrict__ P,
                                    const Kap2Entry* k2tab, Real (&acc)[D + 1],
                                    Real (&acc_b)[4]) {
@@ -180,7 +182,11 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
 #pragma unroll
   for (int j = 0; j < D; j++) sc[j] = kscale<Real, KT>(j < d ? RT<Real>::eta(P, j) : (Real)0);
   const Real gam = RT<Real>::gamma(P);
-  Digits<FAM, D> dg;
+  static_assert(FAM == FAM_DSEQ, "digital-sequence kernels only");
+  FoldedDigits<D> dg;
+  const uint32_t* gz = gray_table(gen, d);
+  // LDS slot of element t + 256 e: lds_at(0, stride, t + 256 e) = wb + 272 e
+  const int wb = (int)t + ((int)t >> 4);
   // the element loop stays rolled: unrolled, its per-element temporaries
   // exceed the register file
   const int En = nb > 256 ? nb >> 8 : 1;
@@ -209,16 +215,12 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
       lds_fwht<Real>(lds, 1, LB, stride);
     }
     if ((int)t < nb) {
-      if (g == 0) {
-        dg.init(gen, cs, d, t, i0, m);
-        dg.load_columns(gen, d);
-      } else {
-        dg.set_block(gen, cs, d, i0, m);
-      }
+      if (g == 0) dg.init(gen, cs, d, t, i0);
+      else dg.set_block(gen, cs, d, i0);
       for (int k = 0; k < En; k++) {
-        const Real wv = lds[lds_at(0, stride, (int)t + 256 * dg.elem(k))];
+        if (k > 0) dg.load(gz, k);
+        const Real wv = lds[wb + 272 * Digits<FAM_DSEQ, D>::elem(k)];
         adj_element<Real, KT, D>(dg, wv, gam, sc, P, k2tab, acc, acc_b);
-        if (k + 1 < En) dg.advance_lanes(k);
       }
     }
   }

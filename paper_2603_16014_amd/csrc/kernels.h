@@ -67,6 +67,14 @@ struct Sched {
   }
 };
 
+// Gray-code step table of the digital-sequence fused kernels, stored after
+// the d x 32 generating columns: row k < GRAY_ROWS holds, per dimension j,
+// z_j(256 gray(k)) with gray(k) = k ^ (k >> 1) (GRAY_STRIDE words per row).
+constexpr int GRAY_ROWS = 32, GRAY_STRIDE = 32;
+__host__ __device__ inline const uint32_t* gray_table(const uint32_t* gen, int d) {
+  return gen + 32 * d;
+}
+
 // Digital-net adjoint reduction: one workgroup reduces adj_group(nb)
 // consecutive low-bit blocks of a column (of nb), so a column writes
 // nb / adj_group(nb) rows of the adjoint partial table.
