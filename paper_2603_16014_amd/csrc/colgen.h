@@ -106,9 +106,8 @@ struct Digits {
 
 template <int D>
 struct FoldedDigits {
-  uint32_t a[D];    // per-thread part with the block part folded in
-  uint32_t blk[D];  // block part z_j(i0) ^ shift_j (uniform)
-  uint32_t s[D];    // element part z_j(256 gray(k)) (uniform)
+  uint32_t a[D];  // per-thread part with the block part folded in
+  uint32_t s[D];  // element part z_j(256 gray(k)) (uniform)
 
   __device__ inline void init(const uint32_t* __restrict__ gen, const uint32_t* __restrict__ sh,
                               int d, uint32_t t, uint32_t i0) {
@@ -116,20 +115,18 @@ struct FoldedDigits {
     for (int j = 0; j < D; j++) {
       const int jj = j < d ? j : 0;
       const uint32_t keep = j < d ? 0xffffffffu : 0u;
-      blk[j] = (dseq_z(gen + 32 * jj, i0) ^ sh[jj]) & keep;
-      a[j] = (dseq_z(gen + 32 * jj, t) & keep) ^ blk[j];
+      a[j] = (dseq_z(gen + 32 * jj, t ^ i0) ^ sh[jj]) & keep;
       s[j] = 0;
     }
   }
-  __device__ inline void set_block(const uint32_t* __restrict__ gen,
-                                   const uint32_t* __restrict__ sh, int d, uint32_t i0) {
+  // from block start i0_old to i0 (the shift cancels: z is XOR-linear)
+  __device__ inline void set_block(const uint32_t* __restrict__ gen, int d, uint32_t i0_old,
+                                   uint32_t i0) {
 #pragma unroll
     for (int j = 0; j < D; j++) {
       const int jj = j < d ? j : 0;
       const uint32_t keep = j < d ? 0xffffffffu : 0u;
-      const uint32_t nb = (dseq_z(gen + 32 * jj, i0) ^ sh[jj]) & keep;
-      a[j] ^= blk[j] ^ nb;
-      blk[j] = nb;
+      a[j] ^= dseq_z(gen + 32 * jj, i0_old ^ i0) & keep;
       s[j] = 0;
     }
   }
@@ -192,6 +189,8 @@ __device__ inline Real kappa(uint32_t u, const Params* __restrict__ P) {
 struct __align__(16) Kap2Entry {
   double c, m;
 };
+// (An 8-byte table of c alone, with the slope converted from r, measured
+// slower: the kernels are bound by VALU issue, not by these LDS reads.)
 __device__ inline void fill_kap2_table(Kap2Entry* tab) {
   for (int i = threadIdx.x; i < 33; i += blockDim.x)
     tab[i] = i == 0 ? Kap2Entry{6442450944.0, 0.0}

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
       // are transformed in registers, bits 0 .. 7 in two LDS rounds.
       Real v[E];
       if (g == 0) fd.init(gen, cs, d, t, i0);
-      else fd.set_block(gen, cs, d, i0);
+      else fd.set_block(gen, d, i0 - (1u << LB), i0);
 #pragma unroll
       for (int k = 0; k < E; k++) {
         if (k > 0) fd.load(gz, k);
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
     }
     if ((int)t < nb) {
       if (g == 0) dg.init(gen, cs, d, t, i0);
-      else dg.set_block(gen, cs, d, i0);
+      else dg.set_block(gen, d, i0 - (1u << LB), i0);
       for (int k = 0; k < En; k++) {
         if (k > 0) dg.load(gz, k);
         const Real wv = lds[wb + 272 * Digits<FAM_DSEQ, D>::elem(k)];

@@ -285,9 +285,11 @@ __global__ __launch_bounds__(256) void fwht_hi_kernel(const TIn* in, TOut* out,
 }
 
 // One pass over the 12 high bits [lo, lo + 12) with a quarter-size LDS
-// exchange, so several blocks (and the fused VALU-bound kernels) share a CU.
-// A block takes KC = 4 adjacent low indices c over all 4096 rows
-// h = a + 64 b of one vector; thread (c, u), wave g = u / 16.
+// exchange.  A block takes KC (2, 4 or 8) adjacent low indices c over all
+// 4096 rows h = a + 64 b of one vector; thread (c, u), group g = u / 16 (a
+// wave or two for KC >= 4).  The rows stay in registers (64 per thread); the
+// LDS only carries one quarter of the transpose at a time, KC x 64 x 16
+// values.
 //
 // Phase 1: the thread holds rows a = u, b = 0 .. 63 and transforms over b.
 // Its input block q (b in [16q, 16q + 16)) is negated when popcount(q & g)
@@ -302,9 +304,10 @@ __global__ __launch_bounds__(256) void fwht_hi_kernel(const TIn* in, TOut* out,
 // a = s ^ 16 g, so the transform over the slots gives
 //   (-1)^{popcount((k >> 4) & g)} Y[k]
 // in slot k, the same per-block sign as phase 1's input, undone before the
-// stores of rows k + 64 u.  Blocks that share a 128-byte line sit on one XCD,
-// next to each other in dispatch order (dispatch is round-robin over the 8
-// XCDs).
+// stores of rows k + 64 u.  Runs of adjacent column groups (about 1 KiB of
+// each row) sit on one XCD, next to each other in dispatch order (dispatch is
+// round-robin over the 8 XCDs), so each row's span reaches the memory
+// channels together.
 constexpr int HI12_AS = 17, HI12_CS = 64 * HI12_AS + 8;
 
 // LDS bytes of fwht_hi12_kernel with KC columns per block
@@ -323,15 +326,16 @@ __device__ inline void negate_blocks(TC (&v)[64], int g) {
 
 template <typename TC, typename TIn, typename TOut, int KC>
 __global__ __launch_bounds__(64 * KC) void fwht_hi12_kernel(const TIn* in, TOut* out,
-                                                            int64_t vec_stride, int lo) {
+                                                            int64_t vec_stride, int lo, int xg) {
   constexpr int KB = KC == 8 ? 3 : KC == 4 ? 2 : 1, AS = HI12_AS, CS = HI12_CS;
   extern __shared__ __align__(16) unsigned char smem[];
   TC* X = reinterpret_cast<TC*>(smem);
   const int ncg = 1 << (lo - KB);
   int cg = blockIdx.x;
-  if ((ncg & 31) == 0) {
+  // XCD x takes runs of 2^xg adjacent column groups (xg < 0: dispatch order)
+  if (xg >= 0) {
     const int x = cg & 7, sl = cg >> 3;
-    cg = ((sl >> 2) << 5) + (x << 2) + (sl & 3);
+    cg = ((sl >> xg) << (xg + 3)) + (x << xg) + (sl & ((1 << xg) - 1));
   }
   const int64_t vb = (int64_t)blockIdx.y * vec_stride + ((int64_t)cg << KB);
   const int c = threadIdx.x & (KC - 1), u = threadIdx.x >> KB;
@@ -398,15 +402,22 @@ void launch_hi_pass(const TIn* in, TOut* out, int64_t vec_stride, int nv, int lo
     const size_t l12 = hi12_lds_bytes(kc, sizeof(TC));
     const int kb = kc == 8 ? 3 : kc == 4 ? 2 : 1;
     const dim3 g12(1u << (lo - kb), (unsigned)nv);
+    // XCD placement: runs of about 1 KiB of input per row on each XCD (measured
+    // at 2^24-point columns: 512 B runs 1.99 ms, 1 KiB 1.70 ms per forward
+    // pass), at most an eighth of the column groups each
+    int xg = 0;
+    while (((size_t)kc * sizeof(TIn) << (xg + 1)) <= 1024) xg++;
+    const int ncg_bits = lo - kb;
+    if (xg > ncg_bits - 3) xg = ncg_bits - 3;
     if (kc == 8)
       hipLaunchKernelGGL((fwht_hi12_kernel<TC, TIn, TOut, 8>), g12, dim3(512), l12, st, in, out,
-                         vec_stride, lo);
+                         vec_stride, lo, xg);
     else if (kc == 4)
       hipLaunchKernelGGL((fwht_hi12_kernel<TC, TIn, TOut, 4>), g12, dim3(256), l12, st, in, out,
-                         vec_stride, lo);
+                         vec_stride, lo, xg);
     else
       hipLaunchKernelGGL((fwht_hi12_kernel<TC, TIn, TOut, 2>), g12, dim3(128), l12, st, in, out,
-                         vec_stride, lo);
+                         vec_stride, lo, xg);
   } else if (hb == 10)
     hipLaunchKernelGGL((fwht_hi_kernel<TC, TIn, TOut, 10>), grid, dim3(256), lds, st, in, out,
                        vec_stride, lo);
