@@ -4,9 +4,9 @@
 
 namespace mtgp {
 template int launch_adj_reduce_kt<double, double, KT_DSI2>(const double*, int64_t, int, int,
-    const uint32_t*, const uint32_t*, const Params*, int, double*, const Sched&, hipStream_t);
+    const uint32_t*, const uint32_t*, const Params*, int, double*, const Sched&, hipStream_t, int);
 template int launch_adj_reduce_kt<double, float, KT_DSI2>(const float*, int64_t, int, int,
-    const uint32_t*, const uint32_t*, const Params*, int, double*, const Sched&, hipStream_t);
+    const uint32_t*, const uint32_t*, const Params*, int, double*, const Sched&, hipStream_t, int);
 template int launch_adj_reduce_kt<float, float, KT_DSI2>(const float*, int64_t, int, int,
-    const uint32_t*, const uint32_t*, const Params*, int, double*, const Sched&, hipStream_t);
+    const uint32_t*, const uint32_t*, const Params*, int, double*, const Sched&, hipStream_t, int);
 }  // namespace mtgp

@@ -153,13 +153,17 @@ __device__ inline void adj_element(const Dg& dg, Real wv, Real gam,
   }
 }
 
+// run != 0: the weights are in the run layout with the halves of the row
+// index swapped (as the one-pass adjoint transform writes them, 4096 rows);
+// a workgroup then takes the blocks h = (b mod 64) + 64 (G (b / 64) + g),
+// whose rows u + 64 k are adjacent, so its reads fill whole lines.
 template <typename Real, typename TIn, int KT, int D>
 __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__ base,
                                                          int64_t col_stride, int m, int LB, int G,
                                                          const uint32_t* __restrict__ gen,
                                                          const uint32_t* __restrict__ colshift,
                                                          const Params* __restrict__ P, int d,
-                                                         double* __restrict__ partials) {
+                                                         double* __restrict__ partials, int run) {
   constexpr int FAM = kt_family(KT);
   constexpr bool ADAPT = KT == KT_DSIA;
   constexpr int NQ = D + 5;
@@ -192,16 +196,28 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
   const int En = nb > 256 ? nb >> 8 : 1;
   // G consecutive blocks of the column per workgroup: the per-thread digit
   // parts and the block reduction below are paid once for all of them
+  const TIn* colp = base + (size_t)col * col_stride;
+  uint32_t i0_prev = 0;
   for (int g = 0; g < G; g++) {
-    const uint32_t i0 = ((uint32_t)blockIdx.x * G + g) << LB;
-    const TIn* w = base + (size_t)col * col_stride + i0;
+    const int b = (int)blockIdx.x;
+    const int h = run ? (b & 63) + 64 * (G * (b >> 6) + g) : b * G + g;
+    const uint32_t i0 = (uint32_t)h << LB;
+    // block h's element e: natural colp[i0 + e], runs colp[run_index(run_swap(h), e)]
+    const TIn* w = run ? colp + ((int64_t)run_swap(h) << 3) : colp + i0;
     if (g > 0) __syncthreads();  // every read of the previous block's tile is done
     if (LB == 12) {
       // 16 loads in flight per thread, index bits 8 .. 11 in registers, bits
       // 0 .. 7 in two LDS rounds
       Real v[16];
+      if (run) {
+        // e = t + 256 k: run_index offset ((t >> 3) + 32 k) 2^15 + (t & 7)
+        const TIn* wt = w + ((int64_t)(t >> 3) << 15) + (t & 7);
 #pragma unroll
-      for (int k = 0; k < 16; k++) v[k] = (Real)w[t + 256 * k];
+        for (int k = 0; k < 16; k++) v[k] = (Real)wt[(int64_t)k << 20];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 16; k++) v[k] = (Real)w[t + 256 * k];
+      }
       reg_fwht<Real, 16>(v);
 #pragma unroll
       for (int k = 0; k < 16; k++) lds[lds_at(0, stride, (int)t + 256 * k)] = v[k];
@@ -211,18 +227,21 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
       lds_round<Real, 4>(lds, 1, LB, 4, stride);
       __syncthreads();
     } else {
-      for (int i = threadIdx.x; i < nb; i += blockDim.x) lds[lds_at(0, stride, i)] = (Real)w[i];
+      for (int i = threadIdx.x; i < nb; i += blockDim.x)
+        lds[lds_at(0, stride, i)] =
+            (Real)(run ? w[((int64_t)(i >> 3) << 15) + (i & 7)] : w[i]);
       lds_fwht<Real>(lds, 1, LB, stride);
     }
     if ((int)t < nb) {
       if (g == 0) dg.init(gen, cs, d, t, i0);
-      else dg.set_block(gen, d, i0 - (1u << LB), i0);
+      else dg.set_block(gen, d, i0_prev, i0);
       for (int k = 0; k < En; k++) {
         if (k > 0) dg.load(gz, k);
         const Real wv = lds[wb + 272 * Digits<FAM_DSEQ, D>::elem(k)];
         adj_element<Real, KT, D>(dg, wv, gam, sc, P, k2tab, acc, acc_b);
       }
     }
+    i0_prev = i0;
   }
   if ((int)t < nb) {
 #pragma unroll
@@ -296,15 +315,18 @@ int launch_gen_fwd_kt(TOut* base, int64_t col_stride, int ncols, int m, const ui
 template <typename Real, typename TIn, int KT>
 int launch_adj_reduce_kt(const TIn* base, int64_t col_stride, int ncols, int m,
                          const uint32_t* gen, const uint32_t* colshift, const Params* P, int d,
-                         double* partials, const Sched& sc, hipStream_t st) {
+                         double* partials, const Sched& sc, hipStream_t st, int run) {
   const int LB = sc.lb(m);
   const size_t lds = sc.fused_lds(gen_cols_lds_bytes(LB, sizeof(Real)));
   const int64_t nblk = (int64_t)1 << (m - LB);
   const int G = adj_group(nblk);
+  // the run layout holds 4096 rows of 8-index groups; the block order pairs
+  // rows within groups of 64 workgroups
+  if (run && (nblk != 4096 || LB < 3 || 64 % G != 0)) return -1;
   const dim3 grid((unsigned)(nblk / G), (unsigned)ncols);
 #define MTGP_ADJ(DD, KTV)                                                                        \
   hipLaunchKernelGGL((adj_reduce_kernel<Real, TIn, KTV, DD>), grid, dim3(256), lds, st, base,     \
-                     col_stride, m, LB, G, gen, colshift, P, d, partials)
+                     col_stride, m, LB, G, gen, colshift, P, d, partials, run)
   MTGP_DISPATCH_D(d, MTGP_ADJ, KT);
 #undef MTGP_ADJ
   return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -92,10 +92,22 @@ template <typename Real>
 int launch_fwht(Real* base, int64_t vec_stride, int64_t nvec, int m, const Sched& sc,
                 hipStream_t st);
 // passes over bits [lb(m), m): first pass reads `first`, last writes `last`,
-// intermediates in `work` (arithmetic in TC)
+// intermediates in `work` (arithmetic in TC).  runs != 0 (only where
+// strided_runs holds): `last` is written in the run layout with the halves
+// of the row index swapped.
 template <typename TC, typename TIn, typename TOut>
 int launch_strided(const TIn* first, TC* work, TOut* last, int64_t vec_stride, int64_t nvec,
-                   int m, const Sched& sc, hipStream_t st);
+                   int m, const Sched& sc, hipStream_t st, int runs = 0);
+// Whether the strided passes of a length-2^m transform are one 12-bit pass
+// with 8 columns per block, which can write the run layout: the 2^lb low
+// indices in groups of 8, each group's 4096 rows x 8 values contiguous
+// (run_index).
+bool strided_runs(const Sched& sc, int m, size_t tc_bytes, size_t in_bytes, size_t out_bytes);
+__host__ __device__ inline int64_t run_index(int h, int l) {
+  return ((int64_t)(l >> 3) << 15) + ((int64_t)h << 3) + (l & 7);
+}
+// the row of block h in the run layout written by the adjoint's one pass
+__host__ __device__ inline int run_swap(int h) { return ((h & 63) << 6) | (h >> 6); }
 // kernel columns generated and transformed over the low index bits
 template <typename Real, typename TOut>
 int launch_gen_fwd(TOut* base, int64_t col_stride, int ncols, int m, const uint32_t* gen,
@@ -109,7 +121,7 @@ int launch_gen_fwd_kt(TOut* base, int64_t col_stride, int ncols, int m, const ui
 template <typename Real, typename TIn, int KT>
 int launch_adj_reduce_kt(const TIn* base, int64_t col_stride, int ncols, int m,
                          const uint32_t* gen, const uint32_t* colshift, const Params* P, int d,
-                         double* partials, const Sched& sc, hipStream_t st);
+                         double* partials, const Sched& sc, hipStream_t st, int run);
 template <typename Real>
 int launch_raw_cols(Real* base, int ncols, int m, const uint32_t* gen, const uint32_t* colshift,
                     const Params* P, const KDesc& kd, hipStream_t st);
@@ -119,10 +131,11 @@ int launch_scale(Real* x, int64_t n, Real s, hipStream_t st);
 // ---- adjoint.hip
 // Number of FP64 partial sums written per block by the derivative reduction.
 __host__ __device__ inline int adj_nq(int d) { return d + 5; }
+// run: the weights are in the run layout with swapped rows (strided_runs)
 template <typename Real, typename TIn>
 int launch_adj_reduce(const TIn* base, int64_t col_stride, int ncols, int m, const uint32_t* gen,
                       const uint32_t* colshift, const Params* P, const KDesc& kd, double* partials,
-                      const Sched& sc, hipStream_t st);
+                      const Sched& sc, hipStream_t st, int run = 0);
 
 // ---- solve.hip
 int launch_clear_status(int* status, hipStream_t st);

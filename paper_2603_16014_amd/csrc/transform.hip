@@ -324,9 +324,15 @@ __device__ inline void negate_blocks(TC (&v)[64], int g) {
   }
 }
 
+// Layouts of a vector: natural (row h of column group cg at cg KC + c + 2^lo h)
+// or, for the output with KC = 8, in runs (the group's 4096 rows x 8 columns
+// contiguous from cg 2^15, run_index) with the halves of the row index
+// swapped (row k + 64 u stored at u + 64 k), so every wave store is 512
+// contiguous values.
 template <typename TC, typename TIn, typename TOut, int KC>
 __global__ __launch_bounds__(64 * KC) void fwht_hi12_kernel(const TIn* in, TOut* out,
-                                                            int64_t vec_stride, int lo, int xg) {
+                                                            int64_t vec_stride, int lo, int xg,
+                                                            int out_run) {
   constexpr int KB = KC == 8 ? 3 : KC == 4 ? 2 : 1, AS = HI12_AS, CS = HI12_CS;
   extern __shared__ __align__(16) unsigned char smem[];
   TC* X = reinterpret_cast<TC*>(smem);
@@ -337,15 +343,19 @@ __global__ __launch_bounds__(64 * KC) void fwht_hi12_kernel(const TIn* in, TOut*
     const int x = cg & 7, sl = cg >> 3;
     cg = ((sl >> xg) << (xg + 3)) + (x << xg) + (sl & ((1 << xg) - 1));
   }
-  const int64_t vb = (int64_t)blockIdx.y * vec_stride + ((int64_t)cg << KB);
+  const int64_t vcol = (int64_t)blockIdx.y * vec_stride;
+  const int64_t vnat = vcol + ((int64_t)cg << KB), vrun = vcol + ((int64_t)cg << (KB + 12));
   const int c = threadIdx.x & (KC - 1), u = threadIdx.x >> KB;
   // the group u / 16 is wave-uniform for KC >= 4
   int g = u >> 4;
   if constexpr (KC >= 4) g = __builtin_amdgcn_readfirstlane(g);
-  const __amdgpu_buffer_rsrc_t ri = buf_rsrc(in + vb, (int)(sizeof(TIn) << (lo + 12)));
-  const __amdgpu_buffer_rsrc_t ro = buf_rsrc(out + vb, (int)(sizeof(TOut) << (lo + 12)));
-  TC v[64];
+  const __amdgpu_buffer_rsrc_t ri = buf_rsrc(in + vnat, (int)(sizeof(TIn) << (lo + 12)));
+  const __amdgpu_buffer_rsrc_t ro =
+      out_run ? buf_rsrc(out + vrun, (int)(sizeof(TOut) << (KB + 12)))
+              : buf_rsrc(out + vnat, (int)(sizeof(TOut) << (lo + 12)));
+  // row h = u + 64 b at c + 2^lo u + 2^(lo+6) b
   const uint32_t lane_in = ((uint32_t)c + ((uint32_t)u << lo)) * (uint32_t)sizeof(TIn);
+  TC v[64];
 #pragma unroll
   for (int b = 0; b < 64; b++)
     v[b] = (TC)buf_load<TIn>(ri, lane_in, ((uint32_t)b << (lo + 6)) * (uint32_t)sizeof(TIn));
@@ -366,10 +376,14 @@ __global__ __launch_bounds__(64 * KC) void fwht_hi12_kernel(const TIn* in, TOut*
   }
   reg_fwht_split<TC, 6>(v);
   negate_blocks<TC>(v, g);
-  const uint32_t lane_out = ((uint32_t)c + ((uint32_t)u << (lo + 6))) * (uint32_t)sizeof(TOut);
+  // row k + 64 u: natural c + 2^(lo+6) u + 2^lo k, in runs (halves swapped)
+  // c + 8 u + 512 k
+  const uint32_t lane_out =
+      ((uint32_t)c + ((uint32_t)u << (out_run ? KB : lo + 6))) * (uint32_t)sizeof(TOut);
+  const int sh_out = out_run ? KB + 6 : lo;
 #pragma unroll
   for (int k = 0; k < 64; k++)
-    buf_store<TOut>((TOut)v[k], ro, lane_out, ((uint32_t)k << lo) * (uint32_t)sizeof(TOut));
+    buf_store<TOut>((TOut)v[k], ro, lane_out, ((uint32_t)k << sh_out) * (uint32_t)sizeof(TOut));
 }
 
 static size_t fwht_hi_lds_bytes(int H, size_t tc_bytes) {
@@ -394,7 +408,7 @@ static int hi12_kc(size_t tile, size_t tc_bytes) {
 
 template <typename TC, typename TIn, typename TOut>
 void launch_hi_pass(const TIn* in, TOut* out, int64_t vec_stride, int nv, int lo, int hb,
-                    size_t tile, hipStream_t st) {
+                    size_t tile, int out_run, hipStream_t st) {
   const dim3 grid(1u << (lo - (8 - hb / 2)), (unsigned)nv);
   const size_t lds = fwht_hi_lds_bytes(hb, sizeof(TC));
   if (hb == 12) {
@@ -411,13 +425,13 @@ void launch_hi_pass(const TIn* in, TOut* out, int64_t vec_stride, int nv, int lo
     if (xg > ncg_bits - 3) xg = ncg_bits - 3;
     if (kc == 8)
       hipLaunchKernelGGL((fwht_hi12_kernel<TC, TIn, TOut, 8>), g12, dim3(512), l12, st, in, out,
-                         vec_stride, lo, xg);
+                         vec_stride, lo, xg, out_run);
     else if (kc == 4)
       hipLaunchKernelGGL((fwht_hi12_kernel<TC, TIn, TOut, 4>), g12, dim3(256), l12, st, in, out,
-                         vec_stride, lo, xg);
+                         vec_stride, lo, xg, 0);
     else
       hipLaunchKernelGGL((fwht_hi12_kernel<TC, TIn, TOut, 2>), g12, dim3(128), l12, st, in, out,
-                         vec_stride, lo, xg);
+                         vec_stride, lo, xg, 0);
   } else if (hb == 10)
     hipLaunchKernelGGL((fwht_hi_kernel<TC, TIn, TOut, 10>), grid, dim3(256), lds, st, in, out,
                        vec_stride, lo);
@@ -469,21 +483,32 @@ size_t gen_cols_lds_bytes(int LB, int real_bytes) { return (size_t)lds_stride(LB
 // Passes over bits [lb(m), m) in TC arithmetic.  The first pass reads `first`
 // (TIn), the last writes `last` (TOut); intermediate results live in `work`
 // (TC).  Any of them may alias when the types agree.
+// bits of the next strided pass from bit lo of a length-2^m transform
+static int next_pass_bits(const Sched& sc, int lo, int m, size_t in_bytes, size_t out_bytes) {
+  const int r = m - lo;
+  if (sc.b_bits > 0) return r < sc.b_bits ? r : sc.b_bits;
+  // by size: the whole remainder in one pass where a one-pass kernel takes it
+  return r <= 12 && fwht_hi_ok(lo, r, in_bytes, out_bytes) ? r : (r < 6 ? r : 6);
+}
+
+bool strided_runs(const Sched& sc, int m, size_t tc_bytes, size_t in_bytes, size_t out_bytes) {
+  const int lo = sc.lb(m);
+  const size_t ib = tc_bytes > in_bytes ? tc_bytes : in_bytes;
+  const size_t ob = tc_bytes > out_bytes ? tc_bytes : out_bytes;
+  return m - lo == 12 && next_pass_bits(sc, lo, m, ib, ob) == 12 && fwht_hi_ok(lo, 12, ib, ob) &&
+         hi12_kc(sc.b_tile, tc_bytes) == 8;
+}
+
 template <typename TC, typename TIn, typename TOut>
 int launch_strided(const TIn* first, TC* work, TOut* last, int64_t vec_stride, int64_t nvec,
-                   int m, const Sched& sc, hipStream_t st) {
+                   int m, const Sched& sc, hipStream_t st, int runs) {
+  if (runs && !strided_runs(sc, m, sizeof(TC), sizeof(TIn), sizeof(TOut))) return -1;
   int lo = sc.lb(m);
   bool is_first = true;
   while (lo < m) {
-    const int r = m - lo;
-    int hb;
-    if (sc.b_bits > 0)
-      hb = r < sc.b_bits ? r : sc.b_bits;
-    else  // by size: the whole remainder in one pass where a one-pass kernel takes it
-      hb = r <= 12 && fwht_hi_ok(lo, r, sizeof(TC) > sizeof(TIn) ? sizeof(TC) : sizeof(TIn),
-                                 sizeof(TC) > sizeof(TOut) ? sizeof(TC) : sizeof(TOut))
-               ? r
-               : (r < 6 ? r : 6);
+    const int hb = next_pass_bits(sc, lo, m,
+                                  sizeof(TC) > sizeof(TIn) ? sizeof(TC) : sizeof(TIn),
+                                  sizeof(TC) > sizeof(TOut) ? sizeof(TC) : sizeof(TOut));
     const bool is_last = lo + hb >= m;
     if (fwht_hi_ok(lo, hb, sizeof(TC) > sizeof(TIn) ? sizeof(TC) : sizeof(TIn),
                    sizeof(TC) > sizeof(TOut) ? sizeof(TC) : sizeof(TOut))) {
@@ -491,13 +516,17 @@ int launch_strided(const TIn* first, TC* work, TOut* last, int64_t vec_stride, i
         const int nv = (int)((nvec - v0) < 65535 ? (nvec - v0) : 65535);
         const int64_t o = v0 * vec_stride;
         if (is_first && is_last)
-          launch_hi_pass<TC, TIn, TOut>(first + o, last + o, vec_stride, nv, lo, hb, sc.b_tile, st);
+          launch_hi_pass<TC, TIn, TOut>(first + o, last + o, vec_stride, nv, lo, hb, sc.b_tile,
+                                        runs, st);
         else if (is_first)
-          launch_hi_pass<TC, TIn, TC>(first + o, work + o, vec_stride, nv, lo, hb, sc.b_tile, st);
+          launch_hi_pass<TC, TIn, TC>(first + o, work + o, vec_stride, nv, lo, hb, sc.b_tile, 0,
+                                     st);
         else if (is_last)
-          launch_hi_pass<TC, TC, TOut>(work + o, last + o, vec_stride, nv, lo, hb, sc.b_tile, st);
+          launch_hi_pass<TC, TC, TOut>(work + o, last + o, vec_stride, nv, lo, hb, sc.b_tile, 0,
+                                       st);
         else
-          launch_hi_pass<TC, TC, TC>(work + o, work + o, vec_stride, nv, lo, hb, sc.b_tile, st);
+          launch_hi_pass<TC, TC, TC>(work + o, work + o, vec_stride, nv, lo, hb, sc.b_tile, 0,
+                                     st);
       }
       is_first = false;
       lo += hb;
@@ -622,13 +651,13 @@ int launch_scale(Real* x, int64_t n, Real s, hipStream_t st) {
 template int launch_fwht<double>(double*, int64_t, int64_t, int, const Sched&, hipStream_t);
 template int launch_fwht<float>(float*, int64_t, int64_t, int, const Sched&, hipStream_t);
 template int launch_strided<double, double, double>(const double*, double*, double*, int64_t,
-                                                    int64_t, int, const Sched&, hipStream_t);
+                                                    int64_t, int, const Sched&, hipStream_t, int);
 template int launch_strided<double, double, float>(const double*, double*, float*, int64_t,
-                                                   int64_t, int, const Sched&, hipStream_t);
+                                                   int64_t, int, const Sched&, hipStream_t, int);
 template int launch_strided<double, float, double>(const float*, double*, double*, int64_t,
-                                                   int64_t, int, const Sched&, hipStream_t);
+                                                   int64_t, int, const Sched&, hipStream_t, int);
 template int launch_strided<float, float, float>(const float*, float*, float*, int64_t, int64_t,
-                                                 int, const Sched&, hipStream_t);
+                                                 int, const Sched&, hipStream_t, int);
 template int launch_gen_fwd<double, double>(double*, int64_t, int, int, const uint32_t*,
                                             const uint32_t*, const Params*, const KDesc&,
                                             const Sched&, hipStream_t);
