@@ -154,9 +154,9 @@ __device__ inline void adj_element(const Dg& dg, Real wv, Real gam,
 }
 
 // run != 0: the weights are in the run layout with the halves of the row
-// index swapped (as the one-pass adjoint transform writes them, 4096 rows);
-// a workgroup then takes the blocks h = (b mod 64) + 64 (G (b / 64) + g),
-// whose rows u + 64 k are adjacent, so its reads fill whole lines.
+// index swapped (as the one-pass adjoint transform writes them, 4096 rows):
+// block h's element e sits at run_index(run_swap(h), e), so each 16-element
+// segment is one 128-byte line.
 template <typename Real, typename TIn, int KT, int D>
 __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__ base,
                                                          int64_t col_stride, int m, int LB, int G,
@@ -199,19 +199,18 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
   const TIn* colp = base + (size_t)col * col_stride;
   uint32_t i0_prev = 0;
   for (int g = 0; g < G; g++) {
-    const int b = (int)blockIdx.x;
-    const int h = run ? (b & 63) + 64 * (G * (b >> 6) + g) : b * G + g;
+    const int h = (int)blockIdx.x * G + g;
     const uint32_t i0 = (uint32_t)h << LB;
     // block h's element e: natural colp[i0 + e], runs colp[run_index(run_swap(h), e)]
-    const TIn* w = run ? colp + ((int64_t)run_swap(h) << 3) : colp + i0;
+    const TIn* w = run ? colp + ((int64_t)run_swap(h) << 4) : colp + i0;
     if (g > 0) __syncthreads();  // every read of the previous block's tile is done
     if (LB == 12) {
       // 16 loads in flight per thread, index bits 8 .. 11 in registers, bits
       // 0 .. 7 in two LDS rounds
       Real v[16];
       if (run) {
-        // e = t + 256 k: run_index offset ((t >> 3) + 32 k) 2^15 + (t & 7)
-        const TIn* wt = w + ((int64_t)(t >> 3) << 15) + (t & 7);
+        // e = t + 256 k: run_index offset ((t >> 4) + 16 k) 2^16 + (t & 15)
+        const TIn* wt = w + ((int64_t)(t >> 4) << 16) + (t & 15);
 #pragma unroll
         for (int k = 0; k < 16; k++) v[k] = (Real)wt[(int64_t)k << 20];
       } else {
@@ -229,7 +228,7 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
     } else {
       for (int i = threadIdx.x; i < nb; i += blockDim.x)
         lds[lds_at(0, stride, i)] =
-            (Real)(run ? w[((int64_t)(i >> 3) << 15) + (i & 7)] : w[i]);
+            (Real)(run ? w[((int64_t)(i >> 4) << 16) + (i & 15)] : w[i]);
       lds_fwht<Real>(lds, 1, LB, stride);
     }
     if ((int)t < nb) {
@@ -320,9 +319,8 @@ int launch_adj_reduce_kt(const TIn* base, int64_t col_stride, int ncols, int m,
   const size_t lds = sc.fused_lds(gen_cols_lds_bytes(LB, sizeof(Real)));
   const int64_t nblk = (int64_t)1 << (m - LB);
   const int G = adj_group(nblk);
-  // the run layout holds 4096 rows of 8-index groups; the block order pairs
-  // rows within groups of 64 workgroups
-  if (run && (nblk != 4096 || LB < 3 || 64 % G != 0)) return -1;
+  // the run layout holds 4096 rows of 16-index groups
+  if (run && (nblk != 4096 || LB < 4)) return -1;
   const dim3 grid((unsigned)(nblk / G), (unsigned)ncols);
 #define MTGP_ADJ(DD, KTV)                                                                        \
   hipLaunchKernelGGL((adj_reduce_kernel<Real, TIn, KTV, DD>), grid, dim3(256), lds, st, base,     \

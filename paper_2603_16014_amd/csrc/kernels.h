@@ -100,11 +100,11 @@ int launch_strided(const TIn* first, TC* work, TOut* last, int64_t vec_stride, i
                    int m, const Sched& sc, hipStream_t st, int runs = 0);
 // Whether the strided passes of a length-2^m transform are one 12-bit pass
 // with 8 columns per block, which can write the run layout: the 2^lb low
-// indices in groups of 8, each group's 4096 rows x 8 values contiguous
-// (run_index).
+// indices in groups of 16, each group's 4096 rows x 16 values contiguous
+// (run_index), so a row of a group is one 128-byte line in FP64.
 bool strided_runs(const Sched& sc, int m, size_t tc_bytes, size_t in_bytes, size_t out_bytes);
 __host__ __device__ inline int64_t run_index(int h, int l) {
-  return ((int64_t)(l >> 3) << 15) + ((int64_t)h << 3) + (l & 7);
+  return ((int64_t)(l >> 4) << 16) + ((int64_t)h << 4) + (l & 15);
 }
 // the row of block h in the run layout written by the adjoint's one pass
 __host__ __device__ inline int run_swap(int h) { return ((h & 63) << 6) | (h >> 6); }

@@ -325,10 +325,12 @@ __device__ inline void negate_blocks(TC (&v)[64], int g) {
 }
 
 // Layouts of a vector: natural (row h of column group cg at cg KC + c + 2^lo h)
-// or, for the output with KC = 8, in runs (the group's 4096 rows x 8 columns
-// contiguous from cg 2^15, run_index) with the halves of the row index
-// swapped (row k + 64 u stored at u + 64 k), so every wave store is 512
-// contiguous values.
+// or, for the output with KC = 8, in runs (groups of 16 low indices, each
+// group's 4096 rows x 16 values contiguous: run_index; the block writes its
+// 8-column half of every row) with the halves of the row index swapped (row
+// k + 64 u stored at u + 64 k), so a wave store covers 8 consecutive rows of
+// the run, 64 bytes each, and the neighbouring block on the same XCD fills
+// the other half of each 128-byte line.
 template <typename TC, typename TIn, typename TOut, int KC>
 __global__ __launch_bounds__(64 * KC) void fwht_hi12_kernel(const TIn* in, TOut* out,
                                                             int64_t vec_stride, int lo, int xg,
@@ -344,14 +346,15 @@ __global__ __launch_bounds__(64 * KC) void fwht_hi12_kernel(const TIn* in, TOut*
     cg = ((sl >> xg) << (xg + 3)) + (x << xg) + (sl & ((1 << xg) - 1));
   }
   const int64_t vcol = (int64_t)blockIdx.y * vec_stride;
-  const int64_t vnat = vcol + ((int64_t)cg << KB), vrun = vcol + ((int64_t)cg << (KB + 12));
+  const int64_t vnat = vcol + ((int64_t)cg << KB);
+  const int64_t vrun = vcol + ((int64_t)(cg >> 1) << 16) + ((cg & 1) << 3);
   const int c = threadIdx.x & (KC - 1), u = threadIdx.x >> KB;
   // the group u / 16 is wave-uniform for KC >= 4
   int g = u >> 4;
   if constexpr (KC >= 4) g = __builtin_amdgcn_readfirstlane(g);
   const __amdgpu_buffer_rsrc_t ri = buf_rsrc(in + vnat, (int)(sizeof(TIn) << (lo + 12)));
   const __amdgpu_buffer_rsrc_t ro =
-      out_run ? buf_rsrc(out + vrun, (int)(sizeof(TOut) << (KB + 12)))
+      out_run ? buf_rsrc(out + vrun, (int)(sizeof(TOut) << 16))
               : buf_rsrc(out + vnat, (int)(sizeof(TOut) << (lo + 12)));
   // row h = u + 64 b at c + 2^lo u + 2^(lo+6) b
   const uint32_t lane_in = ((uint32_t)c + ((uint32_t)u << lo)) * (uint32_t)sizeof(TIn);
@@ -377,10 +380,10 @@ __global__ __launch_bounds__(64 * KC) void fwht_hi12_kernel(const TIn* in, TOut*
   reg_fwht_split<TC, 6>(v);
   negate_blocks<TC>(v, g);
   // row k + 64 u: natural c + 2^(lo+6) u + 2^lo k, in runs (halves swapped)
-  // c + 8 u + 512 k
+  // c + 16 u + 1024 k
   const uint32_t lane_out =
-      ((uint32_t)c + ((uint32_t)u << (out_run ? KB : lo + 6))) * (uint32_t)sizeof(TOut);
-  const int sh_out = out_run ? KB + 6 : lo;
+      ((uint32_t)c + ((uint32_t)u << (out_run ? 4 : lo + 6))) * (uint32_t)sizeof(TOut);
+  const int sh_out = out_run ? 10 : lo;
 #pragma unroll
   for (int k = 0; k < 64; k++)
     buf_store<TOut>((TOut)v[k], ro, lane_out, ((uint32_t)k << sh_out) * (uint32_t)sizeof(TOut));
@@ -495,8 +498,8 @@ bool strided_runs(const Sched& sc, int m, size_t tc_bytes, size_t in_bytes, size
   const int lo = sc.lb(m);
   const size_t ib = tc_bytes > in_bytes ? tc_bytes : in_bytes;
   const size_t ob = tc_bytes > out_bytes ? tc_bytes : out_bytes;
-  return m - lo == 12 && next_pass_bits(sc, lo, m, ib, ob) == 12 && fwht_hi_ok(lo, 12, ib, ob) &&
-         hi12_kc(sc.b_tile, tc_bytes) == 8;
+  return m - lo == 12 && lo >= 4 && next_pass_bits(sc, lo, m, ib, ob) == 12 &&
+         fwht_hi_ok(lo, 12, ib, ob) && hi12_kc(sc.b_tile, tc_bytes) == 8;
 }
 
 template <typename TC, typename TIn, typename TOut>
