@@ -23,7 +23,7 @@ CANDIDATES = [
     (12, 0, 73728), (12, 6, 36864), (13, 6, 36864), (12, 5, 36864), (12, 4, 36864),
     (11, 6, 36864), (10, 7, 36864), (12, 12, 36864),
 ]
-OVERLAPS = (1, 4, 8, 16)
+OVERLAPS = (1, 2, 4, 8, 16)
 FINALISTS = 3  # schedules also timed with each overlap setting
 # caps on workgroups per CU of the fused generation / reduction kernels,
 # tried with the best schedule and the overlapped settings (0: no cap)
@@ -76,7 +76,7 @@ def _time(plan, theta, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def tune(plan, theta, reps=3, candidates=None, overlaps=OVERLAPS, use_cache=True):
+def tune(plan, theta, reps=5, candidates=None, overlaps=OVERLAPS, use_cache=True):
     """Choose and apply the fastest schedule; returns dict(schedule, overlap,
     ms, cached, timings)."""
     if plan.family != mtgp.DSEQ:
@@ -123,7 +123,7 @@ def tune(plan, theta, reps=3, candidates=None, overlaps=OVERLAPS, use_cache=True
     cap_best = 0
     for cap in FUSED_CAPS:
         plan.set_fused_occupancy(cap)
-        for ov in sorted({best[1], 8, 16}):
+        for ov in sorted({best[1], 2, 8}):
             if ov == 1:
                 continue
             plan.set_overlap(ov)
