@@ -653,11 +653,25 @@ int fft_run(const void* x, void* X, void* scratch, int64_t batch, int32_t log2n,
                                                   (int)batch, log2n, st));
     return MTGP_OK;
   }
-  // bit-reversed spectrum in scratch (every entry written before it is
-  // read), then permuted into X
   KDesc kd{};
   kd.family = FAM_LAT;
   kd.order = 1;
+  if (lat_natural_out(log2n)) {
+    // passes in scratch (every entry written before it is read), the last
+    // one writing natural frequency order into X
+    if (f32)
+      LAUNCH_OK(launch_lat_forward<float, float>(src, static_cast<cx<float>*>(scratch),
+                                                 static_cast<cx<float>*>(X), n, (int)batch,
+                                                 log2n, x, 1, 1.0, nullptr, nullptr, nullptr, kd,
+                                                 st, 1));
+    else
+      LAUNCH_OK(launch_lat_forward<double, double>(src, static_cast<cx<double>*>(scratch),
+                                                   static_cast<cx<double>*>(X), n, (int)batch,
+                                                   log2n, x, 0, 1.0, nullptr, nullptr, nullptr,
+                                                   kd, st, 1));
+    return MTGP_OK;
+  }
+  // bit-reversed spectrum in scratch, then permuted into X
   if (f32)
     LAUNCH_OK(launch_lat_forward<float, float>(src, static_cast<cx<float>*>(scratch),
                                                static_cast<cx<float>*>(scratch), n, (int)batch,

@@ -214,7 +214,10 @@ int lat_adj_blocks(int m, size_t cbytes);
 template <typename CR, typename SR>
 int launch_lat_forward(int src, cx<CR>* work, cx<SR>* spec, int64_t vstride, int nvec, int m,
                        const void* y, int y_f32, double scale, const uint32_t* gen, const uint32_t* colshift,
-                       const Params* P, const KDesc& kd, hipStream_t st);
+                       const Params* P, const KDesc& kd, hipStream_t st, int natural = 0);
+// Whether launch_lat_forward can write natural frequency order itself
+// (natural = 1: a multi-pass length whose last pass is the wave pass).
+int lat_natural_out(int m);
 template <typename CR, typename SR>
 int launch_lat_adjoint(int sink, const cx<SR>* spec, cx<CR>* work, double* real_out,
                        int64_t vstride, int nvec, int m, int conj_in, double scale,

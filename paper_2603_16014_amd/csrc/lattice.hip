@@ -27,6 +27,7 @@
 #include <cmath>
 
 #include "colgen.h"
+
 #include "latdev.h"
 
 namespace mtgp {
@@ -582,21 +583,15 @@ struct WavePass {
   }
 };
 
-template <typename CR, typename SR, int L>
-__global__ __launch_bounds__(256) void lat_dif_wave_kernel(const cx<CR>* __restrict__ work,
-                                                           cx<SR>* __restrict__ out,
-                                                           int64_t vstride, double scale) {
+// The decimation-in-frequency rounds of one wave's 2^L-element group: the
+// group is read from `in` in the first round and left in the wave's LDS
+// region `sub` (position i: storage index i of the group), each round ending
+// with a block barrier.
+template <typename CR, int L>
+__device__ inline void wave_dif_rounds(const cx<CR>* __restrict__ in, cx<CR>* sub,
+                                       const cx<CR>* tw, int lane, int stride) {
   using WP = WavePass<L>;
   constexpr int E = WP::E, R = WP::R;
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ cx<double> tmp[96];
-  const int stride = lds_stride(L);
-  cx<CR>* tw = reinterpret_cast<cx<CR>*>(smem);
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  cx<CR>* sub = tw + (1 << (L - 1)) + wv * stride;
-  const int64_t b0 = ((int64_t)blockIdx.x * 4 + wv) << L;
-  const cx<CR>* in = work + (size_t)blockIdx.y * vstride + b0;
-  fill_twiddles<CR>(tw, L, tmp);
   cx<CR> v[E];
   for (int q = 0; q < WP::NR; q++) {
     const int lo = WP::dif_lo(q), r = WP::dif_bits(q);
@@ -622,11 +617,69 @@ __global__ __launch_bounds__(256) void lat_dif_wave_kernel(const cx<CR>* __restr
     for (int k = 0; k < E; k++) sub[lds_at(0, stride, WP::elem(lane, k, lo, r))] = v[k];
     __syncthreads();
   }
+}
+
+template <typename CR, typename SR, int L>
+__global__ __launch_bounds__(256) void lat_dif_wave_kernel(const cx<CR>* __restrict__ work,
+                                                           cx<SR>* __restrict__ out,
+                                                           int64_t vstride, double scale) {
+  using WP = WavePass<L>;
+  constexpr int E = WP::E;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ cx<double> tmp[96];
+  const int stride = lds_stride(L);
+  cx<CR>* tw = reinterpret_cast<cx<CR>*>(smem);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  cx<CR>* sub = tw + (1 << (L - 1)) + wv * stride;
+  const int64_t b0 = ((int64_t)blockIdx.x * 4 + wv) << L;
+  const cx<CR>* in = work + (size_t)blockIdx.y * vstride + b0;
+  fill_twiddles<CR>(tw, L, tmp);
+  wave_dif_rounds<CR, L>(in, sub, tw, lane, stride);
   cx<SR>* o = out + (size_t)blockIdx.y * vstride + b0;
 #pragma unroll
   for (int k = 0; k < E; k++) {
     const cx<CR> val = sub[lds_at(0, stride, lane + 64 * k)];
     o[lane + 64 * k] = {(SR)(val.x * (CR)scale), (SR)(val.y * (CR)scale)};
+  }
+}
+
+// The same pass writing natural frequency order (the standalone transform of
+// a multi-pass length 2^m): a block's NW = 2^B waves take the groups
+// g_j = g0 + j 2^(m-L-B), g0 = blockIdx.x, whose bit-reversed indices differ
+// in their B lowest bits only: bitrev_{m-L}(g_j) = 2^B bitrev_{m-L-B}(g0) +
+// bitrev_B(j).  Position i of group g_j holds frequency
+// bitrev_L(i) 2^(m-L) + bitrev_{m-L}(g_j), so for each i the groups fill NW
+// consecutive frequencies, and a thread writes slot jj of row i from group
+// bitrev_B(jj): one run of NW complex values per row.
+template <typename CR, typename SR, int L, int B>
+__global__ __launch_bounds__(64 << B) void lat_dif_wave_natural_kernel(
+    const cx<CR>* __restrict__ work, cx<SR>* __restrict__ out, int64_t vstride, int m,
+    double scale) {
+  using WP = WavePass<L>;
+  constexpr int E = WP::E, NW = 1 << B;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ cx<double> tmp[96];
+  const int stride = lds_stride(L);
+  cx<CR>* tw = reinterpret_cast<cx<CR>*>(smem);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  cx<CR>* sub0 = tw + (1 << (L - 1));
+  const int gb = m - L - B;  // bits of g0
+  const int64_t g = (int64_t)blockIdx.x + ((int64_t)wv << gb);
+  const cx<CR>* in = work + (size_t)blockIdx.y * vstride + (g << L);
+  fill_twiddles<CR>(tw, L, tmp);
+  wave_dif_rounds<CR, L>(in, sub0 + wv * stride, tw, lane, stride);
+  // every wave's rounds end with a barrier, so all NW groups are in LDS
+  const int64_t base =
+      (int64_t)NW * (int64_t)(gb > 0 ? __brev((unsigned)blockIdx.x) >> (32 - gb) : 0);
+  cx<SR>* o = out + (size_t)blockIdx.y * vstride + base;
+  const int jj = threadIdx.x & (NW - 1);
+  const cx<CR>* src = sub0 + (int)(__brev((unsigned)jj) >> (32 - B)) * stride;
+#pragma unroll
+  for (int k = 0; k < E; k++) {
+    const int i = (threadIdx.x >> B) + 64 * k;  // 64 rows per k, NW slots each
+    const cx<CR> val = src[lds_at(0, stride, i)];
+    const int64_t f = ((int64_t)(__brev((unsigned)i) >> (32 - L)) << (m - L)) + jj;
+    o[f] = {(SR)(val.x * (CR)scale), (SR)(val.y * (CR)scale)};
   }
 }
 
@@ -697,6 +750,49 @@ static void launch_dif_wave(int L, dim3 grid, hipStream_t st, const cx<CR>* work
   else
     hipLaunchKernelGGL((lat_dif_wave_kernel<CR, SR, 10>), grid, dim3(256), lds, st, work, spec,
                        vstride, scale);
+}
+
+// groups per block of the natural-order wave pass: runs of 128 bytes of the
+// output (8 complex FP64 or 16 complex FP32 values; measured on [29][2^24]:
+// FP64 64 / 128 / 256-byte runs 10.6 / 9.8 / 10.1 ms, FP32 64 / 128 bytes
+// 6.6 / 6.3 ms per transform), and the block's LDS (one region per group plus
+// the twiddles) within 160 KB
+template <typename CR, typename SR>
+static int wave_natural_bits(int L, int m) {
+  int B = sizeof(cx<SR>) >= 16 ? 3 : 4;
+  while (B > 0 && (((size_t)lds_stride(L) << B) + (1u << (L - 1))) * sizeof(cx<CR>) > 163840) B--;
+  if (B > m - L) B = m - L;
+  return B;
+}
+
+template <typename CR, typename SR, int B>
+static void launch_dif_wave_natural_b(int L, dim3 grid, hipStream_t st, const cx<CR>* work,
+                                      cx<SR>* X, int64_t vstride, int m, double scale) {
+  const size_t lds = (((size_t)lds_stride(L) << B) + (1u << (L - 1))) * sizeof(cx<CR>);
+  const dim3 block(64 << B);
+  if (L == 8)
+    hipLaunchKernelGGL((lat_dif_wave_natural_kernel<CR, SR, 8, B>), grid, block, lds, st, work,
+                       X, vstride, m, scale);
+  else if (L == 9)
+    hipLaunchKernelGGL((lat_dif_wave_natural_kernel<CR, SR, 9, B>), grid, block, lds, st, work,
+                       X, vstride, m, scale);
+  else
+    hipLaunchKernelGGL((lat_dif_wave_natural_kernel<CR, SR, 10, B>), grid, block, lds, st, work,
+                       X, vstride, m, scale);
+}
+
+template <typename CR, typename SR>
+static void launch_dif_wave_natural(int L, int nvec, hipStream_t st, const cx<CR>* work,
+                                    cx<SR>* X, int64_t vstride, int m, double scale) {
+  const int B = wave_natural_bits<CR, SR>(L, m);
+  const dim3 grid(1u << (m - L - B), nvec);
+  switch (B) {
+    case 4: launch_dif_wave_natural_b<CR, SR, 4>(L, grid, st, work, X, vstride, m, scale); break;
+    case 3: launch_dif_wave_natural_b<CR, SR, 3>(L, grid, st, work, X, vstride, m, scale); break;
+    case 2: launch_dif_wave_natural_b<CR, SR, 2>(L, grid, st, work, X, vstride, m, scale); break;
+    case 1: launch_dif_wave_natural_b<CR, SR, 1>(L, grid, st, work, X, vstride, m, scale); break;
+    default: launch_dif_wave_natural_b<CR, SR, 0>(L, grid, st, work, X, vstride, m, scale); break;
+  }
 }
 
 template <typename CR, typename SR>
@@ -815,8 +911,9 @@ template <typename CR, typename SR>
 int launch_lat_forward(int src, cx<CR>* work, cx<SR>* spec, int64_t vstride, int nvec, int m,
                        const void* y, int y_f32, double scale, const uint32_t* gen,
                        const uint32_t* colshift, const Params* P, const KDesc& kd,
-                       hipStream_t st) {
+                       hipStream_t st, int natural) {
   if (nvec <= 0) return 0;
+  if (natural && !lat_natural_out(m)) return -1;
   const int kt = kt_of(kd.family, kd.order, kd.adaptive);
   const LatSched s = lat_sched(m);
   const LatTab tab = lat_tab();
@@ -849,7 +946,11 @@ int launch_lat_forward(int src, cx<CR>* work, cx<SR>* spec, int64_t vstride, int
     }
   }
   if (s.np > 0 && s.L <= 10) {  // multi-pass: the wave pass over the low bits
-    launch_dif_wave<CR, SR>(s.L, dim3(1u << (m - s.L - 2), nvec), st, work, spec, vstride, scale);
+    if (natural)
+      launch_dif_wave_natural<CR, SR>(s.L, nvec, st, work, spec, vstride, m, scale);
+    else
+      launch_dif_wave<CR, SR>(s.L, dim3(1u << (m - s.L - 2), nvec), st, work, spec, vstride,
+                              scale);
     return hipGetLastError() == hipSuccess ? 0 : -1;
   }
   const dim3 grid2(1u << (m - s.L), nvec);
@@ -977,6 +1078,11 @@ int launch_lat_adjoint(int sink, const cx<SR>* spec, cx<CR>* work, double* real_
 // spectrum that launch_lat_natural permutes.
 int lat_single_pass(int m) { return lat_sched(m).np == 0; }
 
+int lat_natural_out(int m) {
+  const LatSched s = lat_sched(m);
+  return s.np > 0 && s.L <= 10;
+}
+
 // one LDS pass straight into natural frequency order (m <= 12)
 template <typename R>
 int launch_lat_single_natural(int src, const void* x, int x_f32, cx<R>* X, int nvec, int m,
@@ -1062,15 +1168,15 @@ template int launch_lat_single_natural<float>(int, const void*, int, cx<float>*,
 template int launch_lat_forward<double, double>(int, cx<double>*, cx<double>*, int64_t, int, int,
                                                 const void*, int, double, const uint32_t*,
                                                 const uint32_t*, const Params*, const KDesc&,
-                                                hipStream_t);
+                                                hipStream_t, int);
 template int launch_lat_forward<double, float>(int, cx<double>*, cx<float>*, int64_t, int, int,
                                                const void*, int, double, const uint32_t*,
                                                const uint32_t*, const Params*, const KDesc&,
-                                               hipStream_t);
+                                               hipStream_t, int);
 template int launch_lat_forward<float, float>(int, cx<float>*, cx<float>*, int64_t, int, int,
                                               const void*, int, double, const uint32_t*,
                                               const uint32_t*, const Params*, const KDesc&,
-                                              hipStream_t);
+                                              hipStream_t, int);
 template int launch_lat_adjoint<double, double>(int, const cx<double>*, cx<double>*, double*,
                                                 int64_t, int, int, int, double, const uint32_t*,
                                                 const uint32_t*, const Params*, const KDesc&,

@@ -341,6 +341,17 @@ def test_one_pass_high_bits_against_spectral_oracle(m, sched, precision):
     _check_against_spectral(w, y, ref, gref, precision, "sparse", schedule=sched)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_thirteen_bit_low_pass_against_spectral_oracle(precision):
+    # a 13-bit LDS pass (2^13-point blocks: 32 Gray-code steps per thread in
+    # the reduction, the generation's generic block code) and one 6-bit
+    # register pass at m = 19
+    w = tiny("dseq", 3, [19] * 3, 4, seed=97, xi=1e-2, rank=2)
+    say("13-bit low pass vs spectral oracle", precision)
+    y, ref, gref = _spectral_reference(w)
+    _check_against_spectral(w, y, ref, gref, precision, "sparse", schedule=(13, 6, 36864))
+
+
 NESTED_BEYOND = [
     # (family, m, d, order, adaptive): N from 8.6e4 to 1.8e5, classes of 21 to 41 members
     ("dseq", [16, 14, 12], 3, 2, False),
