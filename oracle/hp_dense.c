@@ -256,3 +256,234 @@ int HP_EXPORT(hp_mtgp)(int family, int T, int d, const int* n, const uint32_t* X
   free(v);
   return 0;
 }
+
+/*
+ * Extended-precision spectral route for digital nets of nested sizes
+ * n_t = 2^m_t (test infrastructure only): the steps of the float64 spectral
+ * oracle's MLE, in `real` arithmetic, for sizes the dense twin cannot factor.
+ *   - Theorem "Fast MTGP computations" with the nested-size structure: for
+ *     the pair (t, u) with n_t >= n_u (ties: t <= u), c_tu[i] =
+ *     Q(z_i XOR Delta_t XOR Delta_u), i < n_t, and lambda_tu = H c_tu, the
+ *     unnormalised Sylvester-ordered Walsh-Hadamard transform;
+ *   - yhat_t = H y_t / sqrt(n_t);
+ *   - frequencies fall into residue classes r < n_min; class r has members
+ *     (t, k), k < n_t / n_min, at frequency r + n_min k, and its block
+ *     M_r[(t, k), (u, k mod (n_u / n_min))] = sqrt(n_u / n_t) R_tu
+ *     lambda_tu(r + n_min k) (and its transpose), plus xi_t on the diagonal;
+ *   - profiled means from class 0 (Eq. MTGP_optimal_tau): with A[(t, 0), t]
+ *     = sqrt(n_t), (A^T M_0^-1 A) tau = A^T M_0^-1 yhat(0);
+ *   - L = sum_r rhat_r^T M_r^-1 rhat_r + log det M_r (Eq. MTGP_MLE_GCV_loss),
+ *     rhat_r = yhat_r - [r = 0] A tau, by Cholesky.
+ * z: [n_max][d] unshifted digits (z_i of the oracle's point generator),
+ * shift: [T][d], y: task-major in the oracle's point order.  Classes run on
+ * OpenMP threads; each accumulates its quad and log det in `real`.
+ * Returns 0, -1 (a class block not positive definite) or -2 (bad argument or
+ * allocation failure).
+ */
+static void hp_walsh(real* x, int64_t n) {
+  for (int64_t h = 1; h < n; h <<= 1)
+    for (int64_t i = 0; i < n; i += 2 * h)
+      for (int64_t k = i; k < i + h; k++) {
+        const real a = x[k], b = x[k + h];
+        x[k] = a + b;
+        x[k + h] = a - b;
+      }
+}
+
+/* Cholesky of the c x c block in place (lower, row-major); 0 or -1 */
+static int hp_chol(real* M, int c) {
+  for (int j = 0; j < c; j++) {
+    real dsum = M[(size_t)j * c + j];
+    for (int k = 0; k < j; k++) dsum -= M[(size_t)j * c + k] * M[(size_t)j * c + k];
+    if (!(dsum > 0)) return -1;
+    const real ljj = RSQRT(dsum);
+    M[(size_t)j * c + j] = ljj;
+    for (int i = j + 1; i < c; i++) {
+      real a = M[(size_t)i * c + j];
+      for (int k = 0; k < j; k++) a -= M[(size_t)i * c + k] * M[(size_t)j * c + k];
+      M[(size_t)i * c + j] = a / ljj;
+    }
+  }
+  return 0;
+}
+
+int HP_EXPORT(hp_spectral_nets)(int T, int d, const int* m, const uint32_t* z,
+                                const uint32_t* shift, int order, int adaptive, const double* b,
+                                double gamma, const double* eta, const double* xi, int s,
+                                const double* B, const double* zeta, int profile,
+                                const double* tau_in, const double* y, double* out,
+                                double* tau_hat) {
+  if (T < 1 || T > 64 || d < 1 || d > 64) return -2;
+  kspec ks;
+  ks.family = 0; ks.d = d; ks.order = order; ks.adaptive = adaptive;
+  ks.gamma = gamma;
+  for (int j = 0; j < d; j++) ks.eta[j] = eta[j];
+  for (int a = 0; a < 4; a++) ks.b[a] = adaptive ? b[a] : 0;
+  real R[64 * 64];
+  for (int t = 0; t < T; t++)
+    for (int u = 0; u < T; u++) {
+      real acc = (t == u) ? (real)zeta[t] : 0;
+      for (int k = 0; k < s; k++) acc += (real)B[t * s + k] * (real)B[u * s + k];
+      R[t * T + u] = acc;
+    }
+  int64_t n[64], yoff[65], nmin = INT64_MAX;
+  int size[64], off[65];
+  yoff[0] = 0;
+  for (int t = 0; t < T; t++) {
+    n[t] = (int64_t)1 << m[t];
+    yoff[t + 1] = yoff[t] + n[t];
+    if (n[t] < nmin) nmin = n[t];
+  }
+  off[0] = 0;
+  for (int t = 0; t < T; t++) {
+    size[t] = (int)(n[t] / nmin);
+    off[t + 1] = off[t] + size[t];
+  }
+  const int c = off[T];
+  /* spectra of the columns and of the data */
+  real* lam[64 * 64] = {0};
+  real* yh = (real*)malloc(sizeof(real) * (size_t)yoff[T]);
+  int rc = yh ? 0 : -2;
+  for (int t = 0; t < T && !rc; t++)
+    for (int u = 0; u < T && !rc; u++) {
+      if (!(n[t] > n[u] || (n[t] == n[u] && t <= u))) continue;
+      real* col = (real*)malloc(sizeof(real) * (size_t)n[t]);
+      if (!col) { rc = -2; break; }
+      uint32_t dsh[64];
+      for (int j = 0; j < d; j++) dsh[j] = shift[t * d + j] ^ shift[u * d + j];
+#pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < n[t]; i++) col[i] = qkern(&ks, z + (size_t)i * d, dsh);
+      hp_walsh(col, n[t]);
+      lam[t * T + u] = col;
+    }
+  for (int t = 0; t < T && !rc; t++) {
+    real* v = yh + yoff[t];
+    for (int64_t i = 0; i < n[t]; i++) v[i] = (real)y[yoff[t] + i];
+    hp_walsh(v, n[t]);
+    const real sc = 1 / RSQRT((real)n[t]);
+    for (int64_t i = 0; i < n[t]; i++) v[i] *= sc;
+  }
+  real tau[64];
+  real quad = 0, logdet = 0;
+  if (!rc) {
+    /* class 0: profiled means */
+    real* M0 = (real*)malloc(sizeof(real) * (size_t)c * c);
+    real* X = (real*)malloc(sizeof(real) * (size_t)c * (T + 1));
+    if (!M0 || !X) rc = -2;
+    if (!rc) {
+      memset(M0, 0, sizeof(real) * (size_t)c * c);
+      for (int t = 0; t < T; t++)
+        for (int u = 0; u < T; u++) {
+          const real* L = lam[t * T + u];
+          if (!L) continue;
+          const real f = RSQRT((real)n[u] / (real)n[t]) * R[t * T + u];
+          for (int k = 0; k < size[t]; k++) {
+            const int l = k % size[u];
+            const real v = f * L[(int64_t)nmin * k];
+            M0[(size_t)(off[t] + k) * c + off[u] + l] += v;
+            if (t != u) M0[(size_t)(off[u] + l) * c + off[t] + k] += v;
+          }
+        }
+      for (int t = 0; t < T; t++)
+        for (int k = 0; k < size[t]; k++) M0[(size_t)(off[t] + k) * c + off[t] + k] += (real)xi[t];
+      if (hp_chol(M0, c)) rc = -1;
+    }
+    if (!rc) {
+      for (int q = 0; q <= T; q++) {
+        real* col = X + (size_t)q * c;
+        for (int i = 0; i < c; i++) col[i] = 0;
+        if (q < T) col[off[q]] = RSQRT((real)n[q]);
+        else
+          for (int t = 0; t < T; t++)
+            for (int k = 0; k < size[t]; k++) col[off[t] + k] = yh[yoff[t] + (int64_t)nmin * k];
+        chol_solve(M0, c, col);
+      }
+      real G[64 * 65];
+      for (int t = 0; t < T; t++)
+        for (int q = 0; q <= T; q++) G[t * (T + 1) + q] = RSQRT((real)n[t]) * X[(size_t)q * c + off[t]];
+      for (int cc = 0; cc < T; cc++) {
+        int p = cc;
+        for (int r = cc + 1; r < T; r++) {
+          real a = G[r * (T + 1) + cc], bb = G[p * (T + 1) + cc];
+          if ((a < 0 ? -a : a) > (bb < 0 ? -bb : bb)) p = r;
+        }
+        for (int k = 0; k <= T; k++) {
+          real tmp = G[cc * (T + 1) + k];
+          G[cc * (T + 1) + k] = G[p * (T + 1) + k];
+          G[p * (T + 1) + k] = tmp;
+        }
+        for (int r = cc + 1; r < T; r++) {
+          real f = G[r * (T + 1) + cc] / G[cc * (T + 1) + cc];
+          for (int k = cc; k <= T; k++) G[r * (T + 1) + k] -= f * G[cc * (T + 1) + k];
+        }
+      }
+      for (int cc = T - 1; cc >= 0; cc--) {
+        real acc = G[cc * (T + 1) + T];
+        for (int k = cc + 1; k < T; k++) acc -= G[cc * (T + 1) + k] * tau[k];
+        tau[cc] = acc / G[cc * (T + 1) + cc];
+      }
+      if (!profile)
+        for (int t = 0; t < T; t++) tau[t] = tau_in[t];
+    }
+    free(M0);
+    free(X);
+  }
+  if (!rc) {
+    int bad = 0;
+#pragma omp parallel
+    {
+      real* M = (real*)malloc(sizeof(real) * (size_t)c * c);
+      real* rh = (real*)malloc(sizeof(real) * (size_t)c);
+      real q_loc = 0, ld_loc = 0;
+      int bad_loc = (!M || !rh) ? -2 : 0;
+#pragma omp for schedule(dynamic, 4)
+      for (int64_t r = 0; r < nmin; r++) {
+        if (bad_loc) continue;
+        memset(M, 0, sizeof(real) * (size_t)c * c);
+        for (int t = 0; t < T; t++)
+          for (int u = 0; u < T; u++) {
+            const real* L = lam[t * T + u];
+            if (!L) continue;
+            const real f = RSQRT((real)n[u] / (real)n[t]) * R[t * T + u];
+            for (int k = 0; k < size[t]; k++) {
+              const int l = k % size[u];
+              const real v = f * L[r + (int64_t)nmin * k];
+              M[(size_t)(off[t] + k) * c + off[u] + l] += v;
+              if (t != u) M[(size_t)(off[u] + l) * c + off[t] + k] += v;
+            }
+          }
+        for (int t = 0; t < T; t++)
+          for (int k = 0; k < size[t]; k++) M[(size_t)(off[t] + k) * c + off[t] + k] += (real)xi[t];
+        if (hp_chol(M, c)) { bad_loc = -1; continue; }
+        for (int i = 0; i < c; i++) ld_loc += 2 * RLOG(M[(size_t)i * c + i]);
+        for (int t = 0; t < T; t++)
+          for (int k = 0; k < size[t]; k++) rh[off[t] + k] = yh[yoff[t] + r + (int64_t)nmin * k];
+        if (r == 0)
+          for (int t = 0; t < T; t++) rh[off[t]] -= RSQRT((real)n[t]) * tau[t];
+        for (int i = 0; i < c; i++) {  /* forward substitution L z = rhat */
+          real acc = rh[i];
+          for (int k = 0; k < i; k++) acc -= M[(size_t)i * c + k] * rh[k];
+          rh[i] = acc / M[(size_t)i * c + i];
+          q_loc += rh[i] * rh[i];
+        }
+      }
+#pragma omp critical
+      {
+        quad += q_loc;
+        logdet += ld_loc;
+        if (bad_loc && !bad) bad = bad_loc;
+      }
+      free(M);
+      free(rh);
+    }
+    rc = bad;
+  }
+  for (int i = 0; i < T * T; i++) free(lam[i]);
+  free(yh);
+  if (rc) return rc;
+  out[0] = (double)quad;
+  out[1] = (double)logdet;
+  out[2] = (double)(quad + logdet);
+  for (int t = 0; t < T; t++) tau_hat[t] = (double)tau[t];
+  return 0;
+}

@@ -342,6 +342,18 @@ def test_one_pass_high_bits_against_spectral_oracle(m, sched, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_nested_run_layout_group_against_spectral_oracle(precision):
+    # nested sizes where only the largest length group (m = 18 over a 6-bit
+    # low pass) has its high bits in one 12-bit pass: in the mixed path that
+    # group's adjoint goes through the run layout, the others (m = 16, 13)
+    # through register passes in the natural layout
+    w = tiny("dseq", 3, [18, 16, 13], 3, seed=131, xi=1e-2, rank=2)
+    say("nested run-layout group vs spectral oracle", precision)
+    y, ref, gref = _spectral_reference(w)
+    _check_against_spectral(w, y, ref, gref, precision, "sparse", schedule=(6, 12, 73728))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_thirteen_bit_low_pass_against_spectral_oracle(precision):
     # a 13-bit LDS pass (2^13-point blocks: 32 Gray-code steps per thread in
     # the reduction, the generation's generic block code) and one 6-bit

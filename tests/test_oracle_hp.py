@@ -44,3 +44,26 @@ def test_config1_full_size():
     ref = dense.nll(w, y, X=X)
     ld = hp.mtgp(w, y, X=X)
     assert abs(ld["L"] - ref["L"]) < 1e-13 * (abs(ref["quad"]) + abs(ref["logdet"]))
+
+
+@pytest.mark.parametrize("m,order,adaptive,profile", [
+    ([5, 5], 2, False, True), ([6, 4, 3], 4, False, True), ([5, 5, 2], 2, True, False),
+    ([6, 3, 3, 1], 1, False, True), ([4, 6, 5], 3, False, True)])
+def test_spectral_nets_against_dense_twin(m, order, adaptive, profile):
+    # the long-double spectral route (Walsh transforms, residue-class blocks)
+    # against the long-double dense definitions and the float64 spectral
+    # oracle: two codings of the loss in the same extended precision agree
+    # to the roundoff that precision leaves at this conditioning
+    from oracle import spectral
+    w = tiny("dseq", len(m), m, 3, order=order, adaptive=adaptive, seed=41 + sum(m),
+             profile=profile)
+    X = pts.task_points(w)
+    y = dense.targets(w, np.random.default_rng(7), X)
+    ld = hp.mtgp(w, y, X=X)
+    sp = hp.spectral_nets(w, y)
+    f64 = spectral.mle(w, y)
+    den = abs(ld["quad"]) + abs(ld["logdet"])
+    assert abs(sp["L"] - ld["L"]) < 1e-15 * den, (sp["L"], ld["L"])
+    assert abs(sp["quad"] - ld["quad"]) < 1e-15 * den
+    np.testing.assert_allclose(sp["tau_hat"], ld["tau_hat"], rtol=1e-14, atol=1e-15)
+    assert abs(f64["L"] - sp["L"]) < 1e-12 * den
