@@ -55,27 +55,6 @@ struct Digits {
   __device__ inline uint32_t u(int j) const { return FAM == FAM_DSEQ ? (a[j] ^ s[j]) : (a[j] + s[j]); }
   // element offset (in units of 256) visited at step k
   __device__ static inline int elem(int k) { return FAM == FAM_DSEQ ? (k ^ (k >> 1)) : k; }
-  // Digital sequences: lane q of col[j] holds generating column q of
-  // dimension j (0 for padding slots), so advance_lanes takes the column of
-  // a step from a register with a cross-lane read instead of a scalar load.
-  uint32_t col[FAM == FAM_DSEQ ? D : 1];
-  __device__ inline void load_columns(const uint32_t* __restrict__ gen, int d) {
-    if constexpr (FAM == FAM_DSEQ) {
-      const int lane = threadIdx.x & 31;
-#pragma unroll
-      for (int j = 0; j < D; j++) col[j] = j < d ? gen[32 * j + lane] : 0u;
-    }
-  }
-  __device__ inline void advance_lanes(int k) {
-    if constexpr (FAM == FAM_DSEQ) {
-      const int p = 8 + __ffs(k + 1) - 1;
-#pragma unroll
-      for (int j = 0; j < D; j++) s[j] ^= (uint32_t)__builtin_amdgcn_readlane((int)col[j], p);
-    } else {
-#pragma unroll
-      for (int j = 0; j < D; j++) s[j] += step[j];
-    }
-  }
   // move from step k to step k + 1 (padding slots XOR a masked column of
   // dimension 0, so the update is branch-free and stays in bounds)
   __device__ inline void advance(const uint32_t* __restrict__ gen, int d, int k) {
