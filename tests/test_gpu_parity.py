@@ -341,6 +341,61 @@ def test_one_pass_high_bits_against_spectral_oracle(m, sched, precision):
     _check_against_spectral(w, y, ref, gref, precision, "sparse", schedule=sched)
 
 
+F32_CASES = [("dseq", [8, 8], None, 1e-2), ("lat", [8, 8], None, 1e-2),
+             ("dseq", [9, 7, 5], None, 1e-2), ("lat", [9, 6], None, 1e-2),
+             ("dseq", [16, 16], None, 1e-2), ("dseq", [18, 18], (6, 12, 73728), 1.0)]
+
+
+@pytest.mark.parametrize("family,m,sched,xi", F32_CASES,
+                         ids=[f"{c[0]}-{'_'.join(map(str, c[1]))}" for c in F32_CASES])
+def test_f32_mode_against_oracle(family, m, sched, xi):
+    # the literal FP32 design (columns, transforms and reductions in FP32):
+    # measured errors up to 2e-5 of |quad| + |log det| on L and 4e-4 of the
+    # largest entry on the gradient at these sizes; at m = 18 the 12 high
+    # bits run through the one-pass kernel in FP32 (with xi = 1, since at
+    # xi = 1e-2 FP32 rounding makes Lambda indefinite there: next test)
+    from oracle import dense, points, spectral
+    w = tiny(family, len(m), m, 3, seed=300 + sum(m), xi=xi, rank=2)
+    if w.N <= 4096:
+        ref = oracle_for(w, want_grad=True)
+        y, r, gref = ref["y"], ref["res"], ref["grad"]
+    else:
+        y = dense.targets(w, np.random.default_rng(w.seed + 1000), points.task_points(w))
+        gref, r = spectral.mle_grad(w, y)
+    say("f32 mode vs oracle", family, m, sched)
+    plan = mt.Plan.from_workload(w, "f32", schedule=sched)
+    plan.set_data(torch.from_numpy(np.ascontiguousarray(y)).cuda())
+    out3, grad, _ = plan.nll_grad(plan.pack_theta(w.theta))
+    torch.cuda.synchronize()
+    assert plan.status() == (0, -1)
+    o = out3.cpu().numpy()
+    den = abs(r["quad"]) + abs(r["logdet"])
+    assert abs(o[2] - r["L"]) < 2e-4 * den, (o, r["L"])
+    g = plan.unpack(grad)
+    sc = max(np.abs(np.atleast_1d(v)).max() for v in gref.values())
+    for k, v in gref.items():
+        assert np.abs(np.atleast_1d(g[k]) - np.atleast_1d(v)).max() < 4e-3 * sc, k
+
+
+def test_f32_mode_reports_indefinite_spectrum():
+    # at n = 2^18 per task and xi = 1e-2 the FP32 transform's rounding
+    # exceeds the noise variance and Lambda(f) stops being positive
+    # definite: the call reports MTGP_ENOTPD and the first bad node (the
+    # FP64 and mixed paths factor the same design)
+    w = tiny("dseq", 2, [18, 18], 3, seed=336, xi=1e-2, rank=2)
+    say("f32 mode indefinite report")
+    y = torch.from_numpy(np.random.default_rng(5).normal(size=w.N)).cuda()
+    for precision, ok in (("f32", False), ("mixed", True)):
+        plan = mt.Plan.from_workload(w, precision)
+        plan.set_data(y)
+        plan.nll_grad(plan.pack_theta(w.theta))
+        torch.cuda.synchronize()
+        code, bad = plan.status()
+        assert (code == 0) == ok, (precision, code, bad)
+        if not ok:
+            assert code == -2 and 0 <= bad < w.N
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_nested_run_layout_group_against_spectral_oracle(precision):
     # nested sizes where only the largest length group (m = 18 over a 6-bit
