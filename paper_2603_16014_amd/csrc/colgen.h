@@ -85,16 +85,27 @@ struct Digits {
 
 template <int D>
 struct FoldedDigits {
-  uint32_t a[D];  // per-thread part with the block part folded in
-  uint32_t s[D];  // element part z_j(256 gray(k)) (uniform)
+  uint32_t a[D];   // per-thread part with the block part folded in
+  uint32_t s[D];   // element part z_j(256 gray(k)) of the current step (uniform)
+  uint32_t nx[D];  // element part of the next step, read one step ahead (uniform)
 
+  // t < 256.  z is XOR-linear, so z_j(t ^ i0) = z_j(t) ^ z_j(i0): the block
+  // part z_j(i0) is wave-uniform, and the per-thread part XORs the generating
+  // columns 0 .. 7 selected by t's bits through masks (no per-lane load chain).
   __device__ inline void init(const uint32_t* __restrict__ gen, const uint32_t* __restrict__ sh,
                               int d, uint32_t t, uint32_t i0) {
+    uint32_t msk[8];
+#pragma unroll
+    for (int p = 0; p < 8; p++) msk[p] = 0u - ((t >> p) & 1u);
 #pragma unroll
     for (int j = 0; j < D; j++) {
       const int jj = j < d ? j : 0;
       const uint32_t keep = j < d ? 0xffffffffu : 0u;
-      a[j] = (dseq_z(gen + 32 * jj, t ^ i0) ^ sh[jj]) & keep;
+      const uint32_t* gj = gen + 32 * jj;
+      uint32_t z = dseq_z(gj, i0) ^ sh[jj];
+#pragma unroll
+      for (int p = 0; p < 8; p++) z ^= gj[p] & msk[p];
+      a[j] = z & keep;
       s[j] = 0;
     }
   }
@@ -113,6 +124,26 @@ struct FoldedDigits {
   __device__ inline void load(const uint32_t* __restrict__ gz, int k) {
 #pragma unroll
     for (int j = 0; j < D; j++) s[j] = gz[GRAY_STRIDE * k + j];
+  }
+  // rolled element loops: read row 1 ahead of step 0, then at step k >= 1
+  // take the row read one step earlier and read row k + 1 (k + 1 <= 16 <
+  // GRAY_ROWS for blocks of at most 2^12 points)
+  __device__ inline void ahead(const uint32_t* __restrict__ gz) {
+#pragma unroll
+    for (int j = 0; j < D; j++) nx[j] = gz[GRAY_STRIDE + j];
+  }
+  __device__ inline void step(const uint32_t* __restrict__ gz, int k) {
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+      s[j] = nx[j];
+      nx[j] = gz[GRAY_STRIDE * (k + 1) + j];
+    }
+  }
+  // called at the end of a step's work: the row read by step() is taken
+  // there, so its scalar load is not moved next to its use in the next step
+  __device__ inline void hold() {
+#pragma unroll
+    for (int j = 0; j < D; j++) asm volatile("" : "+s"(nx[j]));
   }
   __device__ inline uint32_t u(int j) const { return a[j] ^ s[j]; }
 };

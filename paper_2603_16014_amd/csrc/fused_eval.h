@@ -234,10 +234,12 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(const TIn* __restrict__
     if ((int)t < nb) {
       if (g == 0) dg.init(gen, cs, d, t, i0);
       else dg.set_block(gen, d, i0_prev, i0);
+      dg.ahead(gz);
       for (int k = 0; k < En; k++) {
-        if (k > 0) dg.load(gz, k);
+        if (k > 0) dg.step(gz, k);
         const Real wv = lds[wb + 272 * Digits<FAM_DSEQ, D>::elem(k)];
         adj_element<Real, KT, D>(dg, wv, gam, sc, P, k2tab, acc, acc_b);
+        dg.hold();
       }
     }
     i0_prev = i0;
