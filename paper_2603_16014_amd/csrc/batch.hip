@@ -91,59 +91,103 @@ __device__ inline double* bcol_work(const BFit& F, int c) {
 // unnormalised Walsh-Hadamard transform.  Lattices: radix-2 decimation in
 // frequency, X at bit-reversed positions; the stage of bit s multiplies the
 // difference by e^{-i pi k / 2^s}, k the index below bit s.
-__device__ inline void block_forward(double* w, int m, bool lat, const BTw& tw) {
-  const int64_t half_n = ((int64_t)1 << m) >> 1;
-  for (int s = m - 1; s >= 0; s--) {
-    const int64_t half = (int64_t)1 << s;
-    for (int64_t g = threadIdx.x; g < half_n; g += blockDim.x) {
-      const int64_t k = g & (half - 1);
-      const int64_t i = ((g >> s) << (s + 1)) | k;
-      if (lat) {
-        const z2 a = {w[2 * i], w[2 * i + 1]}, b = {w[2 * (i + half)], w[2 * (i + half) + 1]};
-        const z2 d = {a.x - b.x, a.y - b.y};
-        const z2 t = btw_at(tw, k, s);
-        w[2 * i] = a.x + b.x;
-        w[2 * i + 1] = a.y + b.y;
-        w[2 * (i + half)] = d.x * t.x - d.y * t.y;
-        w[2 * (i + half) + 1] = d.x * t.y + d.y * t.x;
-      } else {
-        const double a = w[i], b = w[i + half];
-        w[i] = a + b;
-        w[i + half] = a - b;
+//
+// The stages run in rounds of up to 4 bits: a thread loads the 2^R values
+// base + q 2^lo (q < 2^R) of a group, applies the round's stages in the
+// same order and with the same arithmetic as one stage per pass would, and
+// stores them back, so the column crosses the cache once per round, not
+// once per bit.  Within a group, the index below bit lo + s is
+// k = (base mod 2^lo) + (q mod 2^s) 2^lo.
+template <int R, bool FWD>
+__device__ __attribute__((always_inline)) inline void block_round(double* w, int m, int lo, bool lat,
+                                                                 const BTw& tw) {
+  constexpr int Q = 1 << R;
+  const int64_t ngroups = ((int64_t)1 << m) >> R;
+  const int64_t lo_mask = ((int64_t)1 << lo) - 1;
+  for (int64_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
+    const int64_t base = (g & lo_mask) | ((g >> lo) << (lo + R));
+    const int64_t kb = base & lo_mask;
+    if (lat) {
+      z2 v[Q];
+#pragma unroll
+      for (int q = 0; q < Q; q++) {
+        const int64_t i = base + ((int64_t)q << lo);
+        v[q] = {w[2 * i], w[2 * i + 1]};
       }
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        const int sb = FWD ? R - 1 - r : r;  // DIF: high bits first; DIT: low first
+        const int h = 1 << sb;
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+          if (q & h) continue;
+          const z2 t = btw_at(tw, kb + ((int64_t)(q & (h - 1)) << lo), lo + sb);
+          const z2 a = v[q], c = v[q + h];
+          if (FWD) {
+            const z2 d = {a.x - c.x, a.y - c.y};
+            v[q] = {a.x + c.x, a.y + c.y};
+            v[q + h] = {d.x * t.x - d.y * t.y, d.x * t.y + d.y * t.x};
+          } else {
+            const z2 b = {c.x * t.x - c.y * t.y, c.x * t.y + c.y * t.x};
+            v[q] = {a.x + b.x, a.y + b.y};
+            v[q + h] = {a.x - b.x, a.y - b.y};
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < Q; q++) {
+        const int64_t i = base + ((int64_t)q << lo);
+        w[2 * i] = v[q].x;
+        w[2 * i + 1] = v[q].y;
+      }
+    } else {
+      double v[Q];
+#pragma unroll
+      for (int q = 0; q < Q; q++) v[q] = w[base + ((int64_t)q << lo)];
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        const int h = 1 << (FWD ? R - 1 - r : r);
+#pragma unroll
+        for (int q = 0; q < Q; q++) {
+          if (q & h) continue;
+          const double a = v[q], c = v[q + h];
+          v[q] = a + c;
+          v[q + h] = a - c;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < Q; q++) w[base + ((int64_t)q << lo)] = v[q];
     }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
+template <bool FWD>
+__device__ __attribute__((always_inline)) inline void block_rounds(double* w, int m, bool lat, const BTw& tw) {
+  // forward: rounds from the top bits down; adjoint: from bit 0 up
+  for (int done = 0; done < m;) {
+    const int r = min(4, m - done);
+    const int lo = FWD ? m - done - r : done;
+    switch (r) {
+      case 4: block_round<4, FWD>(w, m, lo, lat, tw); break;
+      case 3: block_round<3, FWD>(w, m, lo, lat, tw); break;
+      case 2: block_round<2, FWD>(w, m, lo, lat, tw); break;
+      default: block_round<1, FWD>(w, m, lo, lat, tw); break;
+    }
+    done += r;
+  }
+}
+__device__ __attribute__((always_inline)) inline void block_forward(double* w, int m, bool lat,
+                                                                   const BTw& tw) {
+  block_rounds<true>(w, m, lat, tw);
+}
 // The transposed network: nets the same Walsh-Hadamard transform;
 // lattices decimation in time from bit-reversed input to natural output,
 // u(j) = sum_f omega(f) e^{-2 pi i f j / n} with omega(f) at position
 // bitrev(f).
-__device__ inline void block_adjoint(double* w, int m, bool lat, const BTw& tw) {
-  const int64_t half_n = ((int64_t)1 << m) >> 1;
-  for (int s = 0; s < m; s++) {
-    const int64_t half = (int64_t)1 << s;
-    for (int64_t g = threadIdx.x; g < half_n; g += blockDim.x) {
-      const int64_t k = g & (half - 1);
-      const int64_t i = ((g >> s) << (s + 1)) | k;
-      if (lat) {
-        const z2 a = {w[2 * i], w[2 * i + 1]};
-        const z2 c = {w[2 * (i + half)], w[2 * (i + half) + 1]};
-        const z2 t = btw_at(tw, k, s);
-        const z2 b = {c.x * t.x - c.y * t.y, c.x * t.y + c.y * t.x};
-        w[2 * i] = a.x + b.x;
-        w[2 * i + 1] = a.y + b.y;
-        w[2 * (i + half)] = a.x - b.x;
-        w[2 * (i + half) + 1] = a.y - b.y;
-      } else {
-        const double a = w[i], b = w[i + half];
-        w[i] = a + b;
-        w[i + half] = a - b;
-      }
-    }
-    __syncthreads();
-  }
+__device__ __attribute__((always_inline)) inline void block_adjoint(double* w, int m, bool lat,
+                                                                   const BTw& tw) {
+  block_rounds<false>(w, m, lat, tw);
 }
 
 template <int KT, int D>

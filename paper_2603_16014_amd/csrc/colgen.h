@@ -22,8 +22,13 @@ struct Digits {
   uint32_t s[D];     // block part of the current element (uniform)
   uint32_t step[D];  // lattice increment per element (uniform)
 
+  // t < 256 (the nets' per-thread part XORs the generating columns 0 .. 7
+  // selected by t's bits through masks: no per-lane chain of loads)
   __device__ inline void init(const uint32_t* __restrict__ gen, const uint32_t* __restrict__ sh,
                               int d, uint32_t t, uint32_t i0, int m) {
+    uint32_t msk[8];
+#pragma unroll
+    for (int p = 0; p < 8; p++) msk[p] = 0u - ((t >> p) & 1u);
     // every slot is computed from a valid dimension (padding slots reuse
     // dimension 0) and masked afterwards, so no slot is indexed at run time
 #pragma unroll
@@ -31,7 +36,10 @@ struct Digits {
       const int jj = j < d ? j : 0;
       const uint32_t keep = j < d ? 0xffffffffu : 0u;
       if (FAM == FAM_DSEQ) {
-        a[j] = dseq_z(gen + 32 * jj, t) & keep;
+        uint32_t z = 0;
+#pragma unroll
+        for (int p = 0; p < 8; p++) z ^= gen[32 * jj + p] & msk[p];
+        a[j] = z & keep;
         s[j] = (dseq_z(gen + 32 * jj, i0) ^ sh[jj]) & keep;
         step[j] = 0;
       } else {
