@@ -84,9 +84,11 @@ enum { MTGP_DSEQ = 0, MTGP_LAT = 1 };
  * reductions are FP64 in all of them.
  *   MTGP_FP64:  everything FP64.
  *   MTGP_MIXED: all arithmetic FP64 (kernel columns, transforms, adjoint,
- *               derivative reduction); only the finished spectrum and the
- *               adjoint weights are stored in FP32 (a relative rounding per
- *               entry), which halves the bytes of the solve and of the last
+ *               derivative reduction); only the finished spectrum, the
+ *               adjoint weights and (equal sizes) the copy of the data
+ *               transform that the per-frequency solves read are stored in
+ *               FP32 (a relative rounding per entry; frequency 0 is read in
+ *               FP64), which halves the bytes of the solve and of the last
  *               forward / first adjoint transform pass.  FP32 arithmetic in
  *               the columns or transforms was measured to make Lambda
  *               indefinite on the T=8, d=10, n=2^24 net design (the

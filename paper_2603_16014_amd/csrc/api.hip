@@ -54,8 +54,8 @@ struct mtgp_plan {
   ColInfo* d_colinfo = nullptr;  // per column: task pair, rows of the adjoint partial table
   uint32_t* d_taskshift = nullptr;
   // workspace layout (byte offsets)
-  size_t o_params, o_status, o_cols, o_work, o_yhat, o_ahat, o_sp, o_sp2, o_ap, o_ap2, o_alpha,
-      o_pwork, o_a1a, o_a1b, o_logs, o_lp2, o_misc, ws_bytes;
+  size_t o_params, o_status, o_cols, o_work, o_yhat, o_yh32, o_ahat, o_sp, o_sp2, o_ap, o_ap2,
+      o_alpha, o_pwork, o_a1a, o_a1b, o_logs, o_lp2, o_misc, ws_bytes;
   int nadj_blocks;
   int64_t cols_elems;
   size_t real_bytes;  // bytes of a stored spectrum / adjoint value
@@ -130,6 +130,7 @@ struct WsView {
   unsigned char* cols;
   unsigned char* work;
   double* yhat;
+  float* yh32;  // FP32 copy of yhat for the equal-size solves of FP32-stored spectra
   double* ahat;
   double* sp;
   double* sp2;
@@ -152,6 +153,7 @@ WsView view(const mtgp_plan* p, void* ws) {
   v.cols = b + p->o_cols;
   v.work = p->work_bytes ? b + p->o_work : b + p->o_cols;
   v.yhat = reinterpret_cast<double*>(b + p->o_yhat);
+  v.yh32 = reinterpret_cast<float*>(b + p->o_yh32);
   v.ahat = reinterpret_cast<double*>(b + p->o_ahat);
   v.sp = reinterpret_cast<double*>(b + p->o_sp);
   v.sp2 = reinterpret_cast<double*>(b + p->o_sp2);
@@ -414,12 +416,14 @@ int run_loss(const mtgp_plan* p, const double* theta, double* out3, double* grad
                                   st));
     nsolve = zf_final_blocks(p->N);
   } else if (p->family == MTGP_LAT) {
-    LAUNCH_OK(launch_solve_eq_c<SR>(spec, n, p->pm, w.yhat, w.P, kd, grad != nullptr, w.sp,
-                                    want_ahat ? w.ahat : nullptr, w.status, st));
+    LAUNCH_OK(launch_solve_eq_c<SR>(spec, n, p->pm, solve_yhat<SR>(w), w.yhat, w.P, kd,
+                                    grad != nullptr, w.sp, want_ahat ? w.ahat : nullptr,
+                                    w.status, st));
     nsolve = solve_blocks(n);
   } else {
-    LAUNCH_OK(launch_solve_eq<SR>(spec, n, p->pm, p->ncol, w.yhat, w.P, kd, grad != nullptr, w.sp,
-                                  want_ahat ? w.ahat : nullptr, w.status, st));
+    LAUNCH_OK(launch_solve_eq<SR>(spec, n, p->pm, p->ncol, solve_yhat<SR>(w), w.yhat, w.P, kd,
+                                  grad != nullptr, w.sp, want_ahat ? w.ahat : nullptr, w.status,
+                                  st));
     nsolve = solve_blocks(n);
   }
   mark(p, 4, st);
@@ -534,6 +538,18 @@ int dispatch_loss(const mtgp_plan* p, const double* theta, double* out3, double*
   }
 }
 
+// Equal sizes with FP32 spectrum storage: the per-frequency solves read the
+// data transform from an FP32 copy (rounded once from the FP64 transform,
+// like the spectrum; frequency 0, from which the means are subtracted, is
+// read in FP64), which moves 4 instead of 8 bytes per point and task.
+bool solve_yh32(const mtgp_plan* p) { return p->equal && p->real_bytes == sizeof(float); }
+template <typename SR>
+const SR* solve_yhat(const WsView& w);
+template <>
+const double* solve_yhat<double>(const WsView& w) { return w.yhat; }
+template <>
+const float* solve_yhat<float>(const WsView& w) { return w.yh32; }
+
 // Workspace layout; depends on the schedule through the number of blocks of
 // the adjoint reduction.
 void layout(mtgp_plan* p) {
@@ -550,6 +566,8 @@ void layout(mtgp_plan* p) {
   o = align_up(o + (size_t)p->cols_elems * p->work_bytes * cplx);
   p->o_yhat = o;
   o = align_up(o + (size_t)p->N * sizeof(double) * cplx);
+  p->o_yh32 = o;
+  o = align_up(o + (solve_yh32(p) ? (size_t)p->N * sizeof(float) * cplx : 0));
   p->o_ahat = o;
   o = align_up(o + (size_t)p->N * sizeof(double) * cplx);
   p->o_alpha = o;
@@ -1116,13 +1134,16 @@ int mtgp_set_data(const mtgp_plan* p, const double* y, void* ws, void* stream) {
           reinterpret_cast<cx<double>*>(w.yhat) + p->off[t], p->n[t], nv, p->m[t], y + p->off[t], 0,
           1.0 / std::sqrt((double)p->n[t]), nullptr, nullptr, nullptr, kd, st));
     }
-    return MTGP_OK;
+  } else {
+    HIP_OK(hipMemcpyAsync(w.yhat, y, (size_t)p->N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    for (int t = 0; t < p->T; t++) {
+      LAUNCH_OK(launch_fwht<double>(w.yhat + p->off[t], p->n[t], 1, p->m[t], p->sched, st));
+      LAUNCH_OK(launch_scale<double>(w.yhat + p->off[t], p->n[t],
+                                     1.0 / std::sqrt((double)p->n[t]), st));
+    }
   }
-  HIP_OK(hipMemcpyAsync(w.yhat, y, (size_t)p->N * sizeof(double), hipMemcpyDeviceToDevice, st));
-  for (int t = 0; t < p->T; t++) {
-    LAUNCH_OK(launch_fwht<double>(w.yhat + p->off[t], p->n[t], 1, p->m[t], p->sched, st));
-    LAUNCH_OK(launch_scale<double>(w.yhat + p->off[t], p->n[t], 1.0 / std::sqrt((double)p->n[t]), st));
-  }
+  if (solve_yh32(p))
+    LAUNCH_OK(launch_narrow(w.yhat, w.yh32, p->N * (p->family == MTGP_LAT ? 2 : 1), st));
   return MTGP_OK;
 }
 

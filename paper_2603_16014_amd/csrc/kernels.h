@@ -153,16 +153,19 @@ __host__ __device__ inline int solve_ns(int T) { return 2 + 3 * solve_tm(T); }
 // blocks of the equal-size solves (grid-stride over frequencies beyond)
 inline int64_t solve_blocks(int64_t n) { return (n + 255) / 256; }
 template <typename Real>
-int launch_solve_eq(Real* cols, int64_t n, const PairMap& pm, int ncol, const double* yhat,
-                    const Params* P, const KDesc& kd, bool grad, double* partials, double* ahat,
-                    int* status, hipStream_t st);
+// yhat: the data transform at the spectrum's storage precision; yhat0: the
+// FP64 transform, of which the solves read frequency 0 only
+int launch_solve_eq(Real* cols, int64_t n, const PairMap& pm, int ncol, const Real* yhat,
+                    const double* yhat0, const Params* P, const KDesc& kd, bool grad,
+                    double* partials, double* ahat, int* status, hipStream_t st);
+int launch_narrow(const double* in, float* out, int64_t n, hipStream_t st);
 constexpr int COLSUM_BLOCKS = 256;
 int launch_colsum(const double* in, int64_t nrows, int ncols, double* out, int nblk,
                   hipStream_t st);
 template <typename SR>
-int launch_solve_eq_c(SR* cols, int64_t n, const PairMap& pm, const double* yhat, const Params* P,
-                      const KDesc& kd, bool grad, double* partials, double* ahat, int* status,
-                      hipStream_t st);
+int launch_solve_eq_c(SR* cols, int64_t n, const PairMap& pm, const SR* yhat, const double* yhat0,
+                      const Params* P, const KDesc& kd, bool grad, double* partials, double* ahat,
+                      int* status, hipStream_t st);
 // Kernel column c: the task pair (t, u) it serves (t == u: a diagonal column,
 // whose weights already carry R) and its rows in the adjoint partial table.
 struct ColInfo {

@@ -61,7 +61,8 @@ __device__ constexpr int pk(int i, int j) {
 // measured faster than three without the spill: the kernel is latency-bound.
 template <typename Real, int TM, bool GRAD>
 __global__ __launch_bounds__(256, 4) void solve_eq_kernel(Real* __restrict__ cols, int64_t n,
-                                                       PairMap pm, const double* __restrict__ yhat,
+                                                       PairMap pm, const Real* __restrict__ yhat,
+                                                       const double* __restrict__ yhat0,
                                                        const Params* __restrict__ P, KDesc kd,
                                                        double* __restrict__ partials,
                                                        double* __restrict__ ahat,
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(256, 4) void solve_eq_kernel(Real* __restrict__ col
         const int ci = i < T ? pm.at(j, i) : pm.at(0, 0);
         lv[pk<TM>(i, j)] = cols[(int64_t)ci * n + f];
       }
-      yv[i] = yhat[(int64_t)(i < T ? i : 0) * n + f];
+      yv[i] = (double)yhat[(int64_t)(i < T ? i : 0) * n + f];
     }
     double A[NP], r[TM];
 #pragma unroll
@@ -107,7 +108,8 @@ __global__ __launch_bounds__(256, 4) void solve_eq_kernel(Real* __restrict__ col
         A[pk<TM>(i, j)] = in ? a : (i == j ? 1.0 : 0.0);
       }
       double y = yv[i];
-      if (f == 0) y = kd.profile ? 0.0 : y - sqrt((double)n) * P->tau[i];
+      // frequency 0 from the FP64 transform: the mean is subtracted from it
+      if (f == 0) y = kd.profile ? 0.0 : yhat0[(int64_t)(i < T ? i : 0) * n] - sqrt((double)n) * P->tau[i];
       r[i] = in ? y : 0.0;
     }
     // L D L^T in place: strictly lower part of A becomes L
@@ -205,19 +207,19 @@ __global__ __launch_bounds__(256, 4) void solve_eq_kernel(Real* __restrict__ col
 }
 
 template <typename Real>
-int launch_solve_eq(Real* cols, int64_t n, const PairMap& pm, int ncol, const double* yhat,
-                    const Params* P, const KDesc& kd, bool grad, double* partials, double* ahat,
-                    int* status, hipStream_t st) {
+int launch_solve_eq(Real* cols, int64_t n, const PairMap& pm, int ncol, const Real* yhat,
+                    const double* yhat0, const Params* P, const KDesc& kd, bool grad,
+                    double* partials, double* ahat, int* status, hipStream_t st) {
   (void)ncol;
   const dim3 grid((unsigned)solve_blocks(n)), block(256);
 #define MTGP_SOLVE(TMV)                                                                          \
   do {                                                                                           \
     if (grad)                                                                                    \
       hipLaunchKernelGGL((solve_eq_kernel<Real, TMV, true>), grid, block, 0, st, cols, n, pm,    \
-                         yhat, P, kd, partials, ahat, status);                                   \
+                         yhat, yhat0, P, kd, partials, ahat, status);                            \
     else                                                                                         \
       hipLaunchKernelGGL((solve_eq_kernel<Real, TMV, false>), grid, block, 0, st, cols, n, pm,   \
-                         yhat, P, kd, partials, ahat, status);                                   \
+                         yhat, yhat0, P, kd, partials, ahat, status);                            \
   } while (0)
   if (kd.T <= 1) MTGP_SOLVE(1);
   else if (kd.T <= 2) MTGP_SOLVE(2);
@@ -229,11 +231,24 @@ int launch_solve_eq(Real* cols, int64_t n, const PairMap& pm, int ncol, const do
 }
 
 template int launch_solve_eq<double>(double*, int64_t, const PairMap&, int, const double*,
-                                     const Params*, const KDesc&, bool, double*, double*, int*,
-                                     hipStream_t);
-template int launch_solve_eq<float>(float*, int64_t, const PairMap&, int, const double*,
-                                    const Params*, const KDesc&, bool, double*, double*, int*,
-                                    hipStream_t);
+                                     const double*, const Params*, const KDesc&, bool, double*,
+                                     double*, int*, hipStream_t);
+template int launch_solve_eq<float>(float*, int64_t, const PairMap&, int, const float*,
+                                    const double*, const Params*, const KDesc&, bool, double*,
+                                    double*, int*, hipStream_t);
+
+// FP64 -> storage-precision copy (the data transform read by the solves)
+__global__ void narrow_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+int launch_narrow(const double* in, float* out, int64_t n, hipStream_t st) {
+  if (n <= 0) return 0;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)blocks), dim3(256), 0, st, in, out, n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
 
 // ---------------------------------------------------------------------------
 // Lattices: Lambda(f) is Hermitian, Lambda_tu = R_tu lambda_tu(f) for t < u
@@ -254,7 +269,8 @@ __device__ inline zc zscale(zc a, double s) { return {a.x * s, a.y * s}; }
 template <typename SR, int TM, bool GRAD>
 __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, int64_t n,
                                                          PairMap pm,
-                                                         const double* __restrict__ yhat,
+                                                         const SR* __restrict__ yhat,
+                                                         const double* __restrict__ yhat0,
                                                          const Params* __restrict__ P, KDesc kd,
                                                          double* __restrict__ partials,
                                                          double* __restrict__ ahat,
@@ -288,7 +304,7 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
         lv[pk<TM>(i, j)][1] = cols[at + 1];
       }
       const size_t ay = ((size_t)(i < T ? i : 0) * n + f) * 2;
-      yv[i] = {yhat[ay], yhat[ay + 1]};
+      yv[i] = {(double)yhat[ay], (double)yhat[ay + 1]};
     }
     zc A[NP], r[TM];
 #pragma unroll
@@ -304,7 +320,11 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
         A[pk<TM>(i, j)] = in ? a : zc{i == j ? 1.0 : 0.0, 0.0};
       }
       zc y = yv[i];
-      if (f == 0) y = kd.profile ? zc{0.0, 0.0} : zc{y.x - sqrt((double)n) * P->tau[i], y.y};
+      // frequency 0 from the FP64 transform (real): the mean is subtracted from it
+      if (f == 0)
+        y = kd.profile ? zc{0.0, 0.0}
+                       : zc{yhat0[(size_t)(i < T ? i : 0) * n * 2] - sqrt((double)n) * P->tau[i],
+                            0.0};
       r[i] = in ? y : zc{0.0, 0.0};
     }
     double invD[TM], Dv[TM];
@@ -417,18 +437,18 @@ __global__ __launch_bounds__(256) void solve_eq_c_kernel(SR* __restrict__ cols, 
 }
 
 template <typename SR>
-int launch_solve_eq_c(SR* cols, int64_t n, const PairMap& pm, const double* yhat, const Params* P,
-                      const KDesc& kd, bool grad, double* partials, double* ahat, int* status,
-                      hipStream_t st) {
+int launch_solve_eq_c(SR* cols, int64_t n, const PairMap& pm, const SR* yhat, const double* yhat0,
+                      const Params* P, const KDesc& kd, bool grad, double* partials, double* ahat,
+                      int* status, hipStream_t st) {
   const dim3 grid((unsigned)solve_blocks(n)), block(256);
 #define MTGP_SOLVEC(TMV)                                                                         \
   do {                                                                                           \
     if (grad)                                                                                    \
       hipLaunchKernelGGL((solve_eq_c_kernel<SR, TMV, true>), grid, block, 0, st, cols, n, pm,    \
-                         yhat, P, kd, partials, ahat, status);                                   \
+                         yhat, yhat0, P, kd, partials, ahat, status);                            \
     else                                                                                         \
       hipLaunchKernelGGL((solve_eq_c_kernel<SR, TMV, false>), grid, block, 0, st, cols, n, pm,   \
-                         yhat, P, kd, partials, ahat, status);                                   \
+                         yhat, yhat0, P, kd, partials, ahat, status);                            \
   } while (0)
   if (kd.T <= 1) MTGP_SOLVEC(1);
   else if (kd.T <= 2) MTGP_SOLVEC(2);
@@ -439,11 +459,11 @@ int launch_solve_eq_c(SR* cols, int64_t n, const PairMap& pm, const double* yhat
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 template int launch_solve_eq_c<double>(double*, int64_t, const PairMap&, const double*,
-                                       const Params*, const KDesc&, bool, double*, double*, int*,
-                                       hipStream_t);
-template int launch_solve_eq_c<float>(float*, int64_t, const PairMap&, const double*,
-                                      const Params*, const KDesc&, bool, double*, double*, int*,
-                                      hipStream_t);
+                                       const double*, const Params*, const KDesc&, bool, double*,
+                                       double*, int*, hipStream_t);
+template int launch_solve_eq_c<float>(float*, int64_t, const PairMap&, const float*,
+                                      const double*, const Params*, const KDesc&, bool, double*,
+                                      double*, int*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // finalize: deterministic sums of the block partials and the chain rule
