@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256, 4) void solve_eq_kernel(Real* __restrict__ col
     // diagonal pair uses the one diagonal column.
     const double lam0 = (double)cols[(int64_t)pm.at(0, 0) * n + f];
     Real lv[NP];
-    double yv[TM];
+    Real yv[TM];
 #pragma unroll
     for (int i = 0; i < TM; i++) {
 #pragma unroll
@@ -95,9 +95,9 @@ __global__ __launch_bounds__(256, 4) void solve_eq_kernel(Real* __restrict__ col
         const int ci = i < T ? pm.at(j, i) : pm.at(0, 0);
         lv[pk<TM>(i, j)] = cols[(int64_t)ci * n + f];
       }
-      yv[i] = (double)yhat[(int64_t)(i < T ? i : 0) * n + f];
+      yv[i] = yhat[(int64_t)(i < T ? i : 0) * n + f];
     }
-    double A[NP], r[TM];
+    double A[NP];
 #pragma unroll
     for (int i = 0; i < TM; i++) {
       const bool in = i < T;
@@ -107,10 +107,14 @@ __global__ __launch_bounds__(256, 4) void solve_eq_kernel(Real* __restrict__ col
         const double a = P->R[j * MTGP_MAXT + i] * l + (i == j ? P->xi[i] : 0.0);
         A[pk<TM>(i, j)] = in ? a : (i == j ? 1.0 : 0.0);
       }
-      double y = yv[i];
-      // frequency 0 from the FP64 transform: the mean is subtracted from it
-      if (f == 0) y = kd.profile ? 0.0 : yhat0[(int64_t)(i < T ? i : 0) * n] - sqrt((double)n) * P->tau[i];
-      r[i] = in ? y : 0.0;
+      // right-hand side held at the storage precision until use; frequency 0
+      // is formed from the FP64 transform (the means are subtracted from it)
+      // and rounded once
+      if (f == 0)
+        yv[i] = (Real)(kd.profile ? 0.0
+                                  : yhat0[(int64_t)(i < T ? i : 0) * n] -
+                                        sqrt((double)n) * P->tau[i]);
+      if (!in) yv[i] = (Real)0;
     }
     // L D L^T in place: strictly lower part of A becomes L
     double invD[TM], Dv[TM];
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(256, 4) void solve_eq_kernel(Real* __restrict__ col
     double quad = 0.0;
 #pragma unroll
     for (int i = 0; i < TM; i++) {
-      double v = r[i];
+      double v = (double)yv[i];
 #pragma unroll
       for (int k = 0; k < i; k++) v -= A[pk<TM>(i, k)] * a[k];
       a[i] = v;
@@ -191,8 +195,7 @@ __global__ __launch_bounds__(256, 4) void solve_eq_kernel(Real* __restrict__ col
           const double w = v - a[t] * a[u];
           if (u < T) {
             if (t == u) {
-              vals[2 + t] += w * lam0;
-              vals[2 + TM + t] += w;
+              vals[2 + TM + t] += w;  // times lam0 into vals[2 + t] at the end
               wdiag += P->R[t * MTGP_MAXT + t] * w;
             } else {
               cols[(int64_t)pm.at(t, u) * n + f] = (Real)(2.0 * w);
@@ -201,6 +204,9 @@ __global__ __launch_bounds__(256, 4) void solve_eq_kernel(Real* __restrict__ col
         }
       }
       cols[(int64_t)pm.at(0, 0) * n + f] = (Real)wdiag;
+#pragma unroll
+      for (int t = 0; t < TM; t++)
+        if (t < T) vals[2 + t] = vals[2 + TM + t] * lam0;
     }
   }
   block_sum_store<NR>(vals, NR, red, row);
