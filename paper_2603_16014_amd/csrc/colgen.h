@@ -153,6 +153,12 @@ struct FoldedDigits {
 #pragma unroll
     for (int j = 0; j < D; j++) asm volatile("" : "+s"(nx[j]));
   }
+  // unrolled element loops: the same, and no later row read is hoisted
+  // above it (all rows read up front exceed the scalar register file)
+  __device__ inline void hold_rows() {
+#pragma unroll
+    for (int j = 0; j < D; j++) asm volatile("" : "+s"(nx[j])::"memory");
+  }
   __device__ inline uint32_t u(int j) const { return a[j] ^ s[j]; }
 };
 

@@ -55,13 +55,15 @@ __global__ __launch_bounds__(256) void gen_fwd_kernel(TOut* __restrict__ base, i
       Real v[E];
       if (g == 0) fd.init(gen, cs, d, t, i0);
       else fd.set_block(gen, d, i0 - (1u << LB), i0);
+      fd.ahead(gz);
 #pragma unroll
       for (int k = 0; k < E; k++) {
-        if (k > 0) fd.load(gz, k);
+        if (k > 0) fd.step(gz, k);
         Real c = gam;
 #pragma unroll
         for (int j = 0; j < D; j++) c *= fma(sc[j], kappa_t<Real, KT>(fd.u(j), P, k2tab), (Real)1);
         v[Digits<FAM_DSEQ, D>::elem(k)] = c;
+        fd.hold_rows();
       }
       reg_fwht<Real, E>(v);
 #pragma unroll
