@@ -45,8 +45,17 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # vector 78.6 TFLOP/s = 2 flops per lane-op)
 CU_COUNT, CLOCK_HZ = 256, 2.4e9
 VALU_LANE_OPS_PEAK = CU_COUNT * 64 * CLOCK_HZ
-GEN_OPS_PER_UNIT = 12.0   # VALU lane ops per (column, element, dimension): generation
-ADJ_OPS_PER_UNIT = 18.5   # the same for the derivative reduction
+# Algorithmic VALU lane ops per (column, element, dimension) of the two fused
+# kernels, counted from their arithmetic: generation 7 per dimension (digit
+# XOR, leading-zero count, table offset, u32 -> f64 conversion, kappa FMA,
+# factor FMA, product) plus 12 per element (the Walsh-Hadamard adds of the
+# low bits) spread over d = 10; the reduction 10 per dimension (the
+# same four digit / table steps, kappa and factor FMA, prefix product,
+# suffix combine, suffix product, accumulate) plus 14 per element (12 adds,
+# weight scale, value accumulate).  Set-up, addressing and loop control are
+# not counted.
+GEN_OPS_PER_UNIT = 8.2
+ADJ_OPS_PER_UNIT = 11.4
 COPY_PROBE_BYTES = 1 << 30     # plain streaming kernel used to scale the HBM counters
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_loss_grad_T8_d10_n2e24_mixed.md")
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_gen_adj_T8_d10_n2e24_mixed.md")
@@ -173,9 +182,9 @@ def algo_units(w, precision, a_bits=12):
     """Algorithmic HBM bytes per launch of each phase at this workload (P
     distinct kernel columns of length n, forward working values of wb bytes,
     spectrum / adjoint weights of sb bytes), and for the two fused evaluation
-    kernels their VALU lane operations by the model's per-unit counts: about
-    12 per (column, element, dimension) for the generation and 18.5 for the
-    derivative reduction (9e10 per evaluation at T=8, d=10, n=2^24)."""
+    kernels their algorithmic VALU lane operations: 8.2 per (column, element,
+    dimension) for the generation and 11.4 for the derivative reduction
+    (5.5e10 per evaluation at T=8, d=10, n=2^24)."""
     T, d, n, P = w.T, w.d, 1 << w.m[0], 1 + w.T * (w.T - 1) // 2
     wb, sb = {"fp64": (8, 8), "mixed": (8, 4), "f32": (4, 4)}[precision]
     lb = min(a_bits, w.m[0])  # width of the low-bit (LDS) transform pass
