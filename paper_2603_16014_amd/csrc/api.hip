@@ -674,31 +674,42 @@ int fft_run(const void* x, void* X, void* scratch, int64_t batch, int32_t log2n,
   KDesc kd{};
   kd.family = FAM_LAT;
   kd.order = 1;
-  if (lat_natural_out(log2n)) {
-    // passes in scratch (every entry written before it is read), the last
-    // one writing natural frequency order into X
+  // Multi-pass sizes run in groups of at most 128 MiB of complex values, each
+  // group through all its passes before the next (the scratch reused from
+  // its start), so that a group's intermediate stays in the 256 MB
+  // memory-side cache between passes, as for the Walsh transform.
+  const size_t cbytes = f32 ? sizeof(cx<float>) : sizeof(cx<double>);
+  const int64_t grp = std::max<int64_t>(1, ((int64_t)128 << 20) / (n * (int64_t)cbytes));
+  for (int64_t b0 = 0; b0 < batch; b0 += grp) {
+    const int nb = (int)std::min<int64_t>(grp, batch - b0);
+    const void* xg = static_cast<const unsigned char*>(x) + b0 * n * (int64_t)(cbytes / 2);
+    void* Xg = static_cast<unsigned char*>(X) + b0 * n * (int64_t)cbytes;
+    if (lat_natural_out(log2n)) {
+      // passes in scratch (every entry written before it is read), the last
+      // one writing natural frequency order into X
+      if (f32)
+        LAUNCH_OK(launch_lat_forward<float, float>(src, static_cast<cx<float>*>(scratch),
+                                                   static_cast<cx<float>*>(Xg), n, nb, log2n, xg, 1,
+                                                   1.0, nullptr, nullptr, nullptr, kd, st, 1));
+      else
+        LAUNCH_OK(launch_lat_forward<double, double>(src, static_cast<cx<double>*>(scratch),
+                                                     static_cast<cx<double>*>(Xg), n, nb, log2n,
+                                                     xg, 0, 1.0, nullptr, nullptr, nullptr, kd,
+                                                     st, 1));
+      continue;
+    }
+    // bit-reversed spectrum in scratch, then permuted into X
     if (f32)
       LAUNCH_OK(launch_lat_forward<float, float>(src, static_cast<cx<float>*>(scratch),
-                                                 static_cast<cx<float>*>(X), n, (int)batch,
-                                                 log2n, x, 1, 1.0, nullptr, nullptr, nullptr, kd,
-                                                 st, 1));
+                                                 static_cast<cx<float>*>(scratch), n, nb, log2n,
+                                                 xg, 1, 1.0, nullptr, nullptr, nullptr, kd, st));
     else
       LAUNCH_OK(launch_lat_forward<double, double>(src, static_cast<cx<double>*>(scratch),
-                                                   static_cast<cx<double>*>(X), n, (int)batch,
-                                                   log2n, x, 0, 1.0, nullptr, nullptr, nullptr,
-                                                   kd, st, 1));
-    return MTGP_OK;
+                                                   static_cast<cx<double>*>(scratch), n, nb,
+                                                   log2n, xg, 0, 1.0, nullptr, nullptr, nullptr,
+                                                   kd, st));
+    LAUNCH_OK(launch_lat_natural(scratch, f32, Xg, nb, log2n, st));
   }
-  // bit-reversed spectrum in scratch, then permuted into X
-  if (f32)
-    LAUNCH_OK(launch_lat_forward<float, float>(src, static_cast<cx<float>*>(scratch),
-                                               static_cast<cx<float>*>(scratch), n, (int)batch,
-                                               log2n, x, 1, 1.0, nullptr, nullptr, nullptr, kd, st));
-  else
-    LAUNCH_OK(launch_lat_forward<double, double>(src, static_cast<cx<double>*>(scratch),
-                                                 static_cast<cx<double>*>(scratch), n, (int)batch,
-                                                 log2n, x, 0, 1.0, nullptr, nullptr, nullptr, kd, st));
-  LAUNCH_OK(launch_lat_natural(scratch, f32, X, batch, log2n, st));
   return MTGP_OK;
 }
 

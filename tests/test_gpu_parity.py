@@ -158,7 +158,8 @@ def test_fft_2e27_wide_window_addressing():
 # ---------------------------------------------------------------------- fft
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("log2n,batch", [(0, 2), (3, 3), (9, 2), (12, 2), (13, 2), (14, 2), (15, 1),
-                                          (16, 3), (17, 2), (20, 1), (21, 1), (22, 1), (24, 1)])
+                                          (16, 3), (17, 2), (20, 1), (21, 1), (22, 1), (24, 1),
+                                          (23, 3)])  # 3 vectors: several 128 MiB groups
 @pytest.mark.parametrize("bitrev", [False, True])
 def test_fft_vs_numpy(dtype, log2n, batch, bitrev):
     say("fft", dtype, log2n, batch, bitrev)
