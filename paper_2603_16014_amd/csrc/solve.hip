@@ -57,10 +57,12 @@ __device__ constexpr int pk(int i, int j) {
 // reciprocals and no square roots per frequency.  Per-block sums go to
 // partials[block][solve_ns(T)] in the layout of solve_ns, TM = solve_tm(T)
 // (T padded to 1/2/4/8/16); ahat_t(0) is nonzero in block 0 only.
-// Four waves per SIMD (at most 128 VGPRs, a 20-byte spill per lane at TM = 8)
-// measured faster than three without the spill: the kernel is latency-bound.
+// FP32 storage: four waves per SIMD (at most 128 VGPRs, no spill with the
+// right-hand side held in FP32).  FP64 storage: three (no spill; four spill
+// 28 bytes per lane, which moves 0.9 GB through the caches per 2^24
+// frequencies and measured 2% slower).
 template <typename Real, int TM, bool GRAD>
-__global__ __launch_bounds__(256, 4) void solve_eq_kernel(Real* __restrict__ cols, int64_t n,
+__global__ __launch_bounds__(256, sizeof(Real) == 8 ? 3 : 4) void solve_eq_kernel(Real* __restrict__ cols, int64_t n,
                                                        PairMap pm, const Real* __restrict__ yhat,
                                                        const double* __restrict__ yhat0,
                                                        const Params* __restrict__ P, KDesc kd,
