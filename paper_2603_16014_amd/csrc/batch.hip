@@ -80,6 +80,17 @@ __global__ void batch_prep_kernel(const BFit* __restrict__ fits) {
   prep_device(F.theta, F.P, F.kd, F.status);
 }
 
+// Pointers read from the fit table are generic to the compiler (flat loads
+// and stores, which count against both the vector and the LDS/scalar wait
+// counters); they all point to device global memory, and this view of them
+// lets the loads and stores of the bodies below be global ones.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ inline gptr<T> glb(T* p) {
+  return (gptr<T>)p;
+}
+
 // Column c of fit F, FP64, in the fit's working buffer at the column's
 // offset (complex interleaved for lattices).
 __device__ inline double* bcol_work(const BFit& F, int c) {
@@ -280,12 +291,14 @@ __global__ __launch_bounds__(256) void batch_zf_back_kernel(const BFit* __restri
   const BFit& F = fits[blockIdx.y];
   const int T = F.A.T, t = T - 1 - k;
   if (t < 0) return;
-  z2 *rr = bz_rr(F), *U = bz_U(F);
-  if (T <= 1) zf_back_body<1, true>(F.A, t, F.S, rr, U, F.logs, F.status, bstart(), bstride());
-  else if (T <= 2) zf_back_body<2, true>(F.A, t, F.S, rr, U, F.logs, F.status, bstart(), bstride());
-  else if (T <= 4) zf_back_body<4, true>(F.A, t, F.S, rr, U, F.logs, F.status, bstart(), bstride());
-  else if (T <= 8) zf_back_body<8, true>(F.A, t, F.S, rr, U, F.logs, F.status, bstart(), bstride());
-  else zf_back_body<16, true>(F.A, t, F.S, rr, U, F.logs, F.status, bstart(), bstride());
+  const gptr<z2> S = glb(F.S), rr = glb(bz_rr(F)), U = glb(bz_U(F));
+  const gptr<double> logs = glb(F.logs);
+  const gptr<int> status = glb(F.status);
+  if (T <= 1) zf_back_body<1, true>(F.A, t, S, rr, U, logs, status, bstart(), bstride());
+  else if (T <= 2) zf_back_body<2, true>(F.A, t, S, rr, U, logs, status, bstart(), bstride());
+  else if (T <= 4) zf_back_body<4, true>(F.A, t, S, rr, U, logs, status, bstart(), bstride());
+  else if (T <= 8) zf_back_body<8, true>(F.A, t, S, rr, U, logs, status, bstart(), bstride());
+  else zf_back_body<16, true>(F.A, t, S, rr, U, logs, status, bstart(), bstride());
 }
 
 __global__ __launch_bounds__(256) void batch_zf_tau_kernel(const BFit* __restrict__ fits) {

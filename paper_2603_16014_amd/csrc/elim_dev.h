@@ -29,13 +29,6 @@ __device__ inline int task_of(const int64_t* off, int T, int64_t i) {
   return t;
 }
 
-// Lambda^-1 entry of the pattern between (u, g_u) and (v, g_v), u, v > t,
-// from the overwritten (inverse) pattern storage
-__device__ inline z2 zpair(const Alg1Desc& A, const z2* S, int u, int v, int64_t gu, int64_t gv) {
-  if (u == v) return {S[pidx(A, u, u, gu)].x, 0.0};
-  if (u < v) return zconj(S[pidx(A, u, v, gu)]);
-  return S[pidx(A, v, u, gv)];
-}
 
 }  // namespace
 
@@ -159,48 +152,79 @@ __device__ inline void zf_factor_body(const Alg1Desc& A, int t, int u, int G, z2
   }
 }
 
+// S position of the Lambda^-1 entry between (u, g_u) and (v, g_v), u, v > t,
+// in the overwritten (inverse) pattern storage; zpair_val turns the stored
+// value into the entry (diagonal: its real part; u < v: the conjugate).
+__device__ inline int64_t zpair_idx(const Alg1Desc& A, int u, int v, int64_t gu, int64_t gv) {
+  return u <= v ? pidx(A, u, v, gu) : pidx(A, v, u, gv);
+}
+__device__ inline z2 zpair_val(z2 s, int u, int v) {
+  if (u == v) return {s.x, 0.0};
+  return u < v ? zconj(s) : s;
+}
+
 // Backward stage t over the nodes (t, f): pivot check and log, ahat of the
 // data (and, on residue class 0, of the unit right-hand sides); with GRAD
 // the inverse entries of the column of (t, f), written over it.
-template <int TM, bool GRAD>
-__device__ inline void zf_back_body(const Alg1Desc& A, int t, z2* __restrict__ S,
-                                                      z2* __restrict__ rr, z2* __restrict__ U,
-                                                      double* __restrict__ logs,
-                                                      int* __restrict__ status, int64_t start,
-                                                      int64_t stride) {
+//
+// Every load of a group is issued before its first use, with no branch in
+// between: slots of tasks outside (t, T) read a valid entry (the node's own
+// diagonal or right-hand side) and are skipped in the arithmetic, which
+// runs in the same order as with the slots skipped outright.  (Loads behind
+// branches of their own are waited for one by one.)  ZP, DP and IP are the
+// pointer types (generic, or global for pointers read from memory).
+// complex load / store through generic or global-qualified pointers
+template <typename P>
+__device__ inline z2 zld(P p, int64_t i) {
+  return {p[i].x, p[i].y};
+}
+template <typename P>
+__device__ inline void zst(P p, int64_t i, z2 v) {
+  p[i].x = v.x;
+  p[i].y = v.y;
+}
+
+template <int TM, bool GRAD, typename ZP, typename DP, typename IP>
+__device__ inline void zf_back_body(const Alg1Desc& A, int t, ZP S, ZP rr, ZP U, DP logs,
+                                    IP status, int64_t start, int64_t stride) {
   const int T = A.T;
   const int64_t nt = 1ll << A.m[t];
   const int cs = A.m[T - 1];
   const int64_t ms = A.msz[T - 1];
   for (int64_t f = start; f < nt; f += stride) {
     const int64_t node = A.task_off[t] + f;
-    const double d = S[pidx(A, t, t, f)].x;
-    if (!(d > 0.0) || !isfinite(d)) flag_bad(status, node);
+    const int64_t dix = pidx(A, t, t, f);
+    const double d = zld(S, dix).x;
+    z2 Lr[TM], rv[TM];
+#pragma unroll
+    for (int u = 0; u < TM; u++) {
+      const bool act = u > t && u < T;
+      Lr[u] = zld(S, act ? pidx(A, t, u, f) : dix);
+      rv[u] = zld(rr, act ? A.task_off[u] + (f & ((1ll << A.m[u]) - 1)) : node);
+    }
+    const z2 rn = zld(rr, node);
+    if (!(d > 0.0) || !isfinite(d)) flag_bad((int*)status, node);
     logs[node] = log(d);
     const double di = 1.0 / d;
     z2 L[TM];
 #pragma unroll
-    for (int u = 0; u < TM; u++)
-      L[u] = (u > t && u < T) ? zscale(S[pidx(A, t, u, f)], di) : z2{0.0, 0.0};
+    for (int u = 0; u < TM; u++) L[u] = (u > t && u < T) ? zscale(Lr[u], di) : z2{0.0, 0.0};
     // ahat(t, f) = z / d - sum_u conj(L_u) ahat(u, f mod n_u)
-    z2 a = zscale(rr[node], di);
+    z2 a = zscale(rn, di);
 #pragma unroll
     for (int u = 0; u < TM; u++)
-      if (u > t && u < T) {
-        const z2 p = zmulc(rr[A.task_off[u] + (f & ((1ll << A.m[u]) - 1))], L[u]);
-        a = zsub(a, p);  // conj(L_u) x = x conj(L_u)
-      }
-    rr[node] = a;
+      if (u > t && u < T) a = zsub(a, zmulc(rv[u], L[u]));  // conj(L_u) x = x conj(L_u)
+    zst(rr, node, a);
     if ((f & ((1ll << cs) - 1)) == 0) {
       const int64_t k = f >> cs;
       for (int v = 0; v < T; v++) {
-        z2* Uv = U + (int64_t)v * ms;
-        z2 b = zscale(Uv[A.coff[t] + k], di);
+        ZP Uv = U + (int64_t)v * ms;
+        z2 b = zscale(zld(Uv, A.coff[t] + k), di);
 #pragma unroll
         for (int u = 0; u < TM; u++)
           if (u > t && u < T)
-            b = zsub(b, zmulc(Uv[A.coff[u] + ((f & ((1ll << A.m[u]) - 1)) >> cs)], L[u]));
-        Uv[A.coff[t] + k] = b;
+            b = zsub(b, zmulc(zld(Uv, A.coff[u] + ((f & ((1ll << A.m[u]) - 1)) >> cs)), L[u]));
+        zst(Uv, A.coff[t] + k, b);
       }
     }
     if constexpr (GRAD) {
@@ -211,11 +235,17 @@ __device__ inline void zf_back_body(const Alg1Desc& A, int t, z2* __restrict__ S
         Zc[u] = {0.0, 0.0};
         if (u > t && u < T) {
           const int64_t gu = f & ((1ll << A.m[u]) - 1);
+          z2 zs[TM];
+#pragma unroll
+          for (int v = 0; v < TM; v++) {
+            const bool act = v > t && v < T;
+            zs[v] = zld(S, act ? zpair_idx(A, u, v, gu, f & ((1ll << A.m[v]) - 1)) : dix);
+          }
           z2 acc = {0.0, 0.0};
 #pragma unroll
           for (int v = 0; v < TM; v++)
             if (v > t && v < T) {
-              const z2 p = zmul(zpair(A, S, u, v, gu, f & ((1ll << A.m[v]) - 1)), L[v]);
+              const z2 p = zmul(zpair_val(zs[v], u, v), L[v]);
               acc.x += p.x;
               acc.y += p.y;
             }
@@ -223,10 +253,10 @@ __device__ inline void zf_back_body(const Alg1Desc& A, int t, z2* __restrict__ S
           ztt -= zmulc(L[u], Zc[u]).x;  // Re(conj(Z_u) L_u)
         }
       }
-      S[pidx(A, t, t, f)] = {ztt, 0.0};
+      zst(S, dix, z2{ztt, 0.0});
 #pragma unroll
       for (int u = 0; u < TM; u++)
-        if (u > t && u < T) S[pidx(A, t, u, f)] = Zc[u];
+        if (u > t && u < T) zst(S, pidx(A, t, u, f), Zc[u]);
     }
   }
 }
