@@ -308,13 +308,14 @@ __global__ __launch_bounds__(256) void batch_zf_tau_kernel(const BFit* __restric
 
 template <typename SR>
 __device__ inline void bz_final(const BFit& F) {
-  SR* cols = static_cast<SR*>(F.cols);
+  const gptr<SR> cols = glb(static_cast<SR*>(F.cols));
   const int T = F.A.T;
-  const z2 *rr = bz_rr(F), *U = bz_U(F);
+  const gptr<z2> S = glb(F.S), rr = glb(bz_rr(F)), U = glb(bz_U(F));
   // partial row of this block; the row layout of the chain rule: TM = solve_tm(T)
   double* row = F.sp + (size_t)blockIdx.x * solve_ns(T);
 #define MTGP_BZF(TMV)                                                                          \
-  zf_final_body<SR, TMV>(cols, F.A, F.N, F.P, F.kd.family, 1, F.yhat, F.S, rr, U, nullptr, row, \
+  zf_final_body<SR, TMV>(cols, F.A, F.N, glb((const Params*)F.P), F.kd.family, 1,                \
+                         glb((const double*)F.yhat), S, rr, U, nullptr, row,                    \
                          bstart(), bstride())
   if (T <= 1) MTGP_BZF(1);
   else if (T <= 2) MTGP_BZF(2);

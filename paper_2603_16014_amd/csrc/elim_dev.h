@@ -330,6 +330,24 @@ __device__ inline z2 ahat_at(const Alg1Desc& A, const Params* P, const z2* rr, c
 }
 }  // namespace
 
+// ahat_at through generic or global-qualified pointers
+template <typename PP, typename ZP>
+__device__ inline z2 ahat_at_p(const Alg1Desc& A, PP P, ZP rr, ZP U, int u, int64_t g) {
+  z2 a = zld(rr, A.task_off[u] + g);
+  const int cs = A.m[A.T - 1];
+  if ((g & ((1ll << cs) - 1)) == 0) {
+    const int64_t ms = A.msz[A.T - 1];
+    const int64_t k = A.coff[u] + (g >> cs);
+    for (int v = 0; v < A.T; v++) {
+      const double c = sqrt(ldexp(1.0, A.m[v])) * P->tau_used[v];
+      const z2 e = zld(U, (int64_t)v * ms + k);
+      a.x -= c * e.x;
+      a.y -= c * e.y;
+    }
+  }
+  return a;
+}
+
 // Final pass over all nodes: quad = Re(rhat^H ahat), ahat out, a0; with the
 // gradient W = Lambda^-1 - ahat ahat^H on the pattern, written as adjoint
 // weights over the spectrum (the layout of the unequal-size elimination):
@@ -337,16 +355,13 @@ __device__ inline z2 ahat_at(const Alg1Desc& A, const Params* P, const z2* rr, c
 //   diagonal column of length n_t at f: sum over tasks t2 of that length of
 //   R_{t2 t2} W_{(t2,f),(t2,f)}, formed (with G_tt and sum W_tt) by the
 //   node of the first such task, which alone reads and writes that entry.
-template <typename SR, int TM>
-__device__ inline void zf_final_body(SR* __restrict__ cols, const Alg1Desc& A, int64_t N,
-                                                       const Params* __restrict__ P, int family,
-                                                       int grad, const double* __restrict__ yhat,
-                                                       const z2* __restrict__ S,
-                                                       const z2* __restrict__ rr,
-                                                       const z2* __restrict__ U,
-                                                       double* __restrict__ ahat,
-                                                       double* __restrict__ row,
-                                                       int64_t start, int64_t stride) {
+// CP, PP, YP and ZP are the pointer types (generic, or global for pointers
+// read from memory).
+template <typename SR, int TM, typename CP, typename PP, typename YP, typename ZP>
+__device__ inline void zf_final_body(CP cols, const Alg1Desc& A, int64_t N, PP P, int family,
+                                     int grad, YP yhat, ZP S, ZP rr, ZP U,
+                                     double* __restrict__ ahat, double* __restrict__ row,
+                                     int64_t start, int64_t stride) {
   constexpr int NQ = 2 + 3 * TM;
   __shared__ double red[4 * NQ];
   const int T = A.T;
@@ -359,7 +374,7 @@ __device__ inline void zf_final_body(SR* __restrict__ cols, const Alg1Desc& A, i
     const int64_t yp = A.task_off[t] + spec_pos(family, f, A.m[t]);
     z2 y = family == FAM_DSEQ ? z2{yhat[yp], 0.0} : z2{yhat[2 * yp], yhat[2 * yp + 1]};
     if (f == 0) y.x -= sqrt(ldexp(1.0, A.m[t])) * P->tau_used[t];
-    const z2 a = ahat_at(A, P, rr, U, t, f);
+    const z2 a = ahat_at_p(A, P, rr, U, t, f);
     vals[0] += zmulc(a, y).x;  // Re(conj(rhat) ahat)
     if (ahat) {
       if (family == FAM_DSEQ) {
@@ -377,13 +392,14 @@ __device__ inline void zf_final_body(SR* __restrict__ cols, const Alg1Desc& A, i
     if (!grad) continue;
     if (A.df(t) == t) {
       const int c = A.pc(t, t);
-      const double lam = lam_at<SR>(cols, A, family, c, f).x;
+      const int64_t lp = A.col_off[c] + spec_pos(family, f, A.col_m[c]);
+      const double lam = (double)cols[family == FAM_DSEQ ? lp : 2 * lp];
       double wsum = 0.0;
 #pragma unroll
       for (int i = 0; i < TM; i++) {
         if (i >= t && i < T && A.m[i] == A.m[t]) {
-          const z2 ai = i == t ? a : ahat_at(A, P, rr, U, i, f);
-          const double w = S[pidx(A, i, i, f)].x - (ai.x * ai.x + ai.y * ai.y);
+          const z2 ai = i == t ? a : ahat_at_p(A, P, rr, U, i, f);
+          const double w = zld(S, pidx(A, i, i, f)).x - (ai.x * ai.x + ai.y * ai.y);
           vals[2 + i] += w * lam;
           vals[2 + TM + i] += w;
           wsum += P->R[i * MTGP_MAXT + i] * w;
@@ -398,8 +414,8 @@ __device__ inline void zf_final_body(SR* __restrict__ cols, const Alg1Desc& A, i
       }
     }
     for (int u = t + 1; u < T; u++) {
-      const z2 au = ahat_at(A, P, rr, U, u, f & ((1ll << A.m[u]) - 1));
-      const z2 wtu = zsub(zconj(S[pidx(A, t, u, f)]), zmulc(a, au));
+      const z2 au = ahat_at_p(A, P, rr, U, u, f & ((1ll << A.m[u]) - 1));
+      const z2 wtu = zsub(zconj(zld(S, pidx(A, t, u, f))), zmulc(a, au));
       const double R2 = 2.0 * sqrt(ldexp(1.0, A.m[u] - A.m[t]));
       const int64_t pos = A.col_off[A.pc(t, u)] + spec_pos(family, f, A.m[t]);
       if (family == FAM_DSEQ) {
