@@ -267,12 +267,15 @@ __device__ inline z2* bz_U(const BFit& F) { return F.S + F.A.so[F.A.T] + F.N; }
 
 __global__ __launch_bounds__(256) void batch_zf_init_kernel(const BFit* __restrict__ fits) {
   const BFit& F = fits[blockIdx.y];
+  const gptr<const Params> P = glb((const Params*)F.P);
+  const gptr<const double> yhat = glb((const double*)F.yhat);
+  const gptr<z2> S = glb(F.S), rr = glb(bz_rr(F)), U = glb(bz_U(F));
   if (F.sr_f32)
-    zf_init_body<float>(static_cast<const float*>(F.cols), F.A, F.P, F.kd.family, F.N, F.yhat,
-                        F.S, bz_rr(F), bz_U(F), bstart(), bstride());
+    zf_init_body<float>(glb(static_cast<const float*>(F.cols)), F.A, P, F.kd.family, F.N, yhat, S,
+                        rr, U, bstart(), bstride());
   else
-    zf_init_body<double>(static_cast<const double*>(F.cols), F.A, F.P, F.kd.family, F.N, F.yhat,
-                         F.S, bz_rr(F), bz_U(F), bstart(), bstride());
+    zf_init_body<double>(glb(static_cast<const double*>(F.cols)), F.A, P, F.kd.family, F.N, yhat,
+                         S, rr, U, bstart(), bstride());
 }
 
 // stage t, later task u = t + 1 + blockIdx.z (the targets of different u
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(256) void batch_zf_factor_kernel(const BFit* __rest
   if (u >= F.A.T) return;
   const int64_t K = 1ll << (F.A.m[t] - F.A.m[u]);
   const int G = K >= 64 ? 64 : (int)K;
-  zf_factor_body(F.A, t, u, G, F.S, bz_rr(F), bz_U(F), bstart(), bstride());
+  zf_factor_body(F.A, t, u, G, glb(F.S), glb(bz_rr(F)), glb(bz_U(F)), bstart(), bstride());
 }
 
 // backward stage k of every fit: its task T - 1 - k

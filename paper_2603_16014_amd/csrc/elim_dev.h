@@ -32,14 +32,23 @@ __device__ inline int task_of(const int64_t* off, int T, int64_t i) {
 
 }  // namespace
 
+// complex load / store through generic or global-qualified pointers
+template <typename P>
+__device__ inline z2 zld(P p, int64_t i) {
+  return {p[i].x, p[i].y};
+}
+template <typename P>
+__device__ inline void zst(P p, int64_t i, z2 v) {
+  p[i].x = v.x;
+  p[i].y = v.y;
+}
+
 // Pattern values from the spectrum, yhat in natural frequency order, unit
 // right-hand sides.  Grid-stride over so[T] + N + T ms entries.
-template <typename SR>
-__device__ inline void zf_init_body(const SR* __restrict__ cols, const Alg1Desc& A,
-                                    const Params* __restrict__ P, int family, int64_t N,
-                                    const double* __restrict__ yhat, z2* __restrict__ S,
-                                    z2* __restrict__ rr, z2* __restrict__ U, int64_t start,
-                                    int64_t stride) {
+// (CP, PP, YP, ZP: pointer types, generic or global-qualified.)
+template <typename SR, typename CP, typename PP, typename YP, typename ZP>
+__device__ inline void zf_init_body(CP cols, const Alg1Desc& A, PP P, int family, int64_t N,
+                                    YP yhat, ZP S, ZP rr, ZP U, int64_t start, int64_t stride) {
   const int T = A.T;
   const int64_t nS = A.so[T], ms = A.msz[T - 1];
   const int64_t total = nS + N + (int64_t)T * ms;
@@ -49,25 +58,28 @@ __device__ inline void zf_init_body(const SR* __restrict__ cols, const Alg1Desc&
       const int64_t r = i - A.so[a];
       const int b = a + (int)(r >> A.m[a]);
       const int64_t g = r & ((1ll << A.m[a]) - 1);
-      const z2 l = lam_at<SR>(cols, A, family, A.pc(a, b), g);
+      const int c = A.pc(a, b);
+      const int64_t lp = A.col_off[c] + spec_pos(family, g, A.col_m[c]);
+      const z2 l = family == FAM_DSEQ ? z2{(double)cols[lp], 0.0}
+                                      : z2{(double)cols[2 * lp], (double)cols[2 * lp + 1]};
       if (b == a) {
-        S[i] = {P->R[a * MTGP_MAXT + a] * l.x + P->xi[a], 0.0};
+        zst(S, i, z2{P->R[a * MTGP_MAXT + a] * l.x + P->xi[a], 0.0});
       } else {
         // Lambda_{(a,g),(b,g mod n_b)} = sqrt(n_b / n_a) R_ab lambda_ab(g); the
         // stored entry (row (b, .), column (a, g)) is its conjugate
         const double sc = sqrt(ldexp(1.0, A.m[b] - A.m[a])) * P->R[a * MTGP_MAXT + b];
-        S[i] = zconj(zscale(l, sc));
+        zst(S, i, zconj(zscale(l, sc)));
       }
     } else if (i < nS + N) {
       const int64_t q = i - nS;
       const int t = task_of(A.task_off, T, q);
       const int64_t f = q - A.task_off[t];
       const int64_t yp = A.task_off[t] + spec_pos(family, f, A.m[t]);
-      rr[q] = family == FAM_DSEQ ? z2{yhat[yp], 0.0} : z2{yhat[2 * yp], yhat[2 * yp + 1]};
+      zst(rr, q, family == FAM_DSEQ ? z2{yhat[yp], 0.0} : z2{yhat[2 * yp], yhat[2 * yp + 1]});
     } else {
       const int64_t q = i - nS - N;
       const int64_t v = q / ms, node = q - v * ms;
-      U[q] = {node == A.coff[v] ? 1.0 : 0.0, 0.0};
+      zst(U, q, z2{node == A.coff[v] ? 1.0 : 0.0, 0.0});
     }
   }
 }
@@ -76,9 +88,10 @@ __device__ inline void zf_init_body(const SR* __restrict__ cols, const Alg1Desc&
 // targets rr(u, g) and the T (n_u / n_T) unit targets of class 0.  Each
 // target sums n_t / n_u terms; a group of G lanes (power of two <= 64) of
 // one wave shares a target.
-__device__ inline void zf_factor_body(const Alg1Desc& A, int t, int u, int G, z2* __restrict__ S,
-                                      z2* __restrict__ rr, z2* __restrict__ U, int64_t start,
-                                      int64_t stride) {
+// (ZP: pointer type, generic or global-qualified.)
+template <typename ZP>
+__device__ inline void zf_factor_body(const Alg1Desc& A, int t, int u, int G, ZP S, ZP rr, ZP U,
+                                      int64_t start, int64_t stride) {
   const int T = A.T;
   const int64_t nu = 1ll << A.m[u];
   const int64_t K = 1ll << (A.m[t] - A.m[u]);  // terms per target
@@ -103,8 +116,8 @@ __device__ inline void zf_factor_body(const Alg1Desc& A, int t, int u, int G, z2
         dst = pidx(A, u, v, g);
         for (int64_t j = lane; j < K; j += G) {
           const int64_t f = g + (j << A.m[u]);
-          const double d = S[pidx(A, t, t, f)].x;
-          const z2 p = zmulc(S[pidx(A, t, v, f)], S[pidx(A, t, u, f)]);
+          const double d = zld(S, pidx(A, t, t, f)).x;
+          const z2 p = zmulc(zld(S, pidx(A, t, v, f)), zld(S, pidx(A, t, u, f)));
           acc.x += p.x / d;
           acc.y += p.y / d;
         }
@@ -114,8 +127,8 @@ __device__ inline void zf_factor_body(const Alg1Desc& A, int t, int u, int G, z2
         dst = A.task_off[u] + g;
         for (int64_t j = lane; j < K; j += G) {
           const int64_t f = g + (j << A.m[u]);
-          const double d = S[pidx(A, t, t, f)].x;
-          const z2 p = zmul(S[pidx(A, t, u, f)], rr[A.task_off[t] + f]);
+          const double d = zld(S, pidx(A, t, t, f)).x;
+          const z2 p = zmul(zld(S, pidx(A, t, u, f)), zld(rr, A.task_off[t] + f));
           acc.x += p.x / d;
           acc.y += p.y / d;
         }
@@ -128,8 +141,8 @@ __device__ inline void zf_factor_body(const Alg1Desc& A, int t, int u, int G, z2
         dst = (int64_t)rv * ms + A.coff[u] + k;
         for (int64_t j = lane; j < K; j += G) {
           const int64_t f = g + (j << A.m[u]);
-          const double d = S[pidx(A, t, t, f)].x;
-          const z2 p = zmul(S[pidx(A, t, u, f)], U[(int64_t)rv * ms + A.coff[t] + (f >> cs)]);
+          const double d = zld(S, pidx(A, t, t, f)).x;
+          const z2 p = zmul(zld(S, pidx(A, t, u, f)), zld(U, (int64_t)rv * ms + A.coff[t] + (f >> cs)));
           acc.x += p.x / d;
           acc.y += p.y / d;
         }
@@ -141,12 +154,12 @@ __device__ inline void zf_factor_body(const Alg1Desc& A, int t, int u, int G, z2
     }
     if (live && lane == 0) {
       if (kind == 0) {
-        const z2 s = S[dst];
-        S[dst] = v == u ? z2{s.x - acc.x, 0.0} : zsub(s, acc);
+        const z2 s = zld(S, dst);
+        zst(S, dst, v == u ? z2{s.x - acc.x, 0.0} : zsub(s, acc));
       } else if (kind == 1) {
-        rr[dst] = zsub(rr[dst], acc);
+        zst(rr, dst, zsub(zld(rr, dst), acc));
       } else {
-        U[dst] = zsub(U[dst], acc);
+        zst(U, dst, zsub(zld(U, dst), acc));
       }
     }
   }
@@ -173,17 +186,6 @@ __device__ inline z2 zpair_val(z2 s, int u, int v) {
 // runs in the same order as with the slots skipped outright.  (Loads behind
 // branches of their own are waited for one by one.)  ZP, DP and IP are the
 // pointer types (generic, or global for pointers read from memory).
-// complex load / store through generic or global-qualified pointers
-template <typename P>
-__device__ inline z2 zld(P p, int64_t i) {
-  return {p[i].x, p[i].y};
-}
-template <typename P>
-__device__ inline void zst(P p, int64_t i, z2 v) {
-  p[i].x = v.x;
-  p[i].y = v.y;
-}
-
 template <int TM, bool GRAD, typename ZP, typename DP, typename IP>
 __device__ inline void zf_back_body(const Alg1Desc& A, int t, ZP S, ZP rr, ZP U, DP logs,
                                     IP status, int64_t start, int64_t stride) {
