@@ -483,6 +483,15 @@ def transforms_leg(ncols=29, m=24, reps=5):
             out[name].update({"passes": passes, "pass_bytes": pb,
                               "pass_GB_s": pb / (ms * 1e-3) / 1e9,
                               "pass_hbm_frac": pb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS})
+        elif m == 24:
+            # three passes at 2^24 points: the generating tile over the top
+            # 10 bits (real in, complex out), one 5-bit register pass and the
+            # 9-bit wave pass writing natural order (complex in and out)
+            n_el = ncols << m
+            pb = n_el * (3 * b + 2 * 4 * b)
+            out[name].update({"passes": 3, "pass_bytes": pb,
+                              "pass_GB_s": pb / (ms * 1e-3) / 1e9,
+                              "pass_hbm_frac": pb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS})
         del x
         torch.cuda.empty_cache()
     return out
