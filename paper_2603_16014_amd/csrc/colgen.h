@@ -133,18 +133,20 @@ struct FoldedDigits {
 #pragma unroll
     for (int j = 0; j < D; j++) s[j] = gz[GRAY_STRIDE * k + j];
   }
-  // rolled element loops: read row 1 ahead of step 0, then at step k >= 1
-  // take the row read one step earlier and read row k + 1 (k + 1 <= 16 <
-  // GRAY_ROWS for blocks of at most 2^12 points)
+  // element loops: read row 1 ahead of step 0, then at step k >= 1 take the
+  // row read one step earlier and read row k + 1 (clamped to the table: at
+  // the last step of a 2^13-point block, k + 1 = GRAY_ROWS, the row read is
+  // not used)
   __device__ inline void ahead(const uint32_t* __restrict__ gz) {
 #pragma unroll
     for (int j = 0; j < D; j++) nx[j] = gz[GRAY_STRIDE + j];
   }
   __device__ inline void step(const uint32_t* __restrict__ gz, int k) {
+    const int nr = k + 1 < GRAY_ROWS ? k + 1 : GRAY_ROWS - 1;
 #pragma unroll
     for (int j = 0; j < D; j++) {
       s[j] = nx[j];
-      nx[j] = gz[GRAY_STRIDE * (k + 1) + j];
+      nx[j] = gz[GRAY_STRIDE * nr + j];
     }
   }
   // called at the end of a step's work: the row read by step() is taken
