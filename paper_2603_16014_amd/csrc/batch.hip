@@ -240,8 +240,26 @@ __global__ __launch_bounds__(256) void batch_fwd_kernel(const BFit* __restrict__
     }
   } else {
     btw_fill(tw);
+    // digits of the thread's first point, advanced by one uniform step per
+    // element (natural lattice order); padding dimensions carry eta = 0
+    SiFactor<double, KT> fk[D];
+    uint32_t u[D], step[D];
+#pragma unroll
+    for (int q = 0; q < D; q++) {
+      fk[q].init(q < d ? P->eta[q] : 0.0);
+      const uint32_t g = F.gen[q < d ? q : 0];
+      u[q] = lat_z(g, threadIdx.x, m) + sh[q < d ? q : 0];
+      step[q] = lat_z(g, blockDim.x, m);
+    }
+    const double gam = P->gamma;
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-      w[2 * j] = lat_col_value<double, KT>(F.gen, sh, d, (uint32_t)j, m, P);
+      double v = gam;
+#pragma unroll
+      for (int q = 0; q < D; q++) {
+        v = fma(v, fk[q].eta_k(u[q]), v);
+        u[q] += step[q];
+      }
+      w[2 * j] = v;
       w[2 * j + 1] = 0.0;
     }
   }
